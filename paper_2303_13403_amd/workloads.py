@@ -1,0 +1,147 @@
+"""Seeded synthetic workloads for the Gutzwiller-projection PQMC sweep.
+
+This module only *describes inputs*: lattices (hopping matrix and sublattice
+signs of the Hubbard model, Eq. 2), model parameters, the trial-only on-site
+potential used to close the shell of a doped lattice, and the random draws that
+define a batch of uneven chains.  It contains none of the method's arithmetic
+(no propagation, no Green's function, no Monte Carlo) and is imported both by
+the tests that drive the oracle and by the code that drives the HIP library.
+
+The paper works on the honeycomb lattice; the workloads here are the square
+lattice with periodic boundaries, nearest-neighbour hopping -t, which has the
+same two-sublattice (Neel) structure used by the trial state (Method section,
+Neel mean-field Hamiltonian after Eq. 2).
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Optional
+
+import numpy as np
+
+__all__ = [
+    "square_lattice",
+    "shell_ramp",
+    "Workload",
+    "WORKLOADS",
+    "batch_uneven",
+]
+
+
+def square_lattice(lx: int, ly: int, t: float = 1.0):
+    """Hopping matrix of an lx x ly periodic square lattice.
+
+    Returns ``(K, eps, xy)``: ``K`` is the N x N real symmetric matrix with
+    ``K[i, j] = -t`` for every nearest-neighbour bond (bonds that wrap onto the
+    same pair twice, as on a 2-site-wide torus, accumulate), ``eps`` the
+    sublattice sign (+1 on A, -1 on B: (-1)^(x+y)) and ``xy`` the site
+    coordinates.  Site index is ``i = x + lx * y``.
+    """
+    n = lx * ly
+    K = np.zeros((n, n), dtype=np.float64)
+    xy = np.zeros((n, 2), dtype=np.int64)
+    for y in range(ly):
+        for x in range(lx):
+            i = x + lx * y
+            xy[i] = (x, y)
+            for dx, dy in ((1, 0), (0, 1)):
+                if (dx == 1 and lx == 1) or (dy == 1 and ly == 1):
+                    continue
+                j = (x + dx) % lx + lx * ((y + dy) % ly)
+                K[i, j] -= t
+                K[j, i] -= t
+    eps = np.where((xy[:, 0] + xy[:, 1]) % 2 == 0, 1, -1).astype(np.int8)
+    return K, eps, xy
+
+
+def shell_ramp(lx: int, ly: int, delta: float = 0.1, tilt: float = 0.37):
+    """Trial-only on-site potential delta*(x/lx + tilt*y/ly).
+
+    A doped square lattice (e.g. 16x16 with 112 electrons per spin) has a
+    degenerate Fermi level, so the mean-field trial determinant is not unique.
+    This small potential enters only the trial Hamiltonian (never the
+    Hamiltonian that is simulated), splits the degeneracy and makes the trial
+    state well defined.  The projector estimate is unbiased for any trial state
+    with non-zero overlap with the ground state.
+    """
+    _, _, xy = square_lattice(lx, ly)
+    return delta * (xy[:, 0] / lx + tilt * xy[:, 1] / ly)
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    lx: int
+    ly: int
+    U: float
+    n_up: int
+    n_dn: int
+    dtau: float
+    l_half: int            # slices per side: Theta / dtau
+    m_neel: float
+    g: float
+    stab_interval: int     # slices between QR re-stabilisations
+    delay_rank: int        # sites per block of the delayed submatrix scan
+    precision: str         # "fp64" or "mixed"
+    sweeps: int
+    t: float = 1.0
+    ramp: float = 0.0      # trial-only shell-closing ramp amplitude (0 = none)
+    seed: int = 13403
+
+    @property
+    def n_sites(self) -> int:
+        return self.lx * self.ly
+
+    @property
+    def theta(self) -> float:
+        return self.l_half * self.dtau
+
+    def lattice(self):
+        return square_lattice(self.lx, self.ly, self.t)
+
+    def trial_potential(self) -> Optional[np.ndarray]:
+        if self.ramp == 0.0:
+            return None
+        return shell_ramp(self.lx, self.ly, self.ramp)
+
+    def replace(self, **kw) -> "Workload":
+        return dataclasses.replace(self, **kw)
+
+
+# The five synthetic workloads: a small 4x4 case, a 12x12 half-filled case, the
+# 16x16 doped case whose throughput is the headline figure, a batch of uneven
+# lattices and a 24x24 large case.  Model parameters follow the Gutzwiller
+# optima the paper prints for the Hubbard model (Fig. 1 caption: g=0.55,
+# M_N=0.07 at U=3.5; g=0.6, M_N=0.21 at U=4).
+WORKLOADS = {
+    "4x4": Workload("4x4 U=4 half filling Theta=2", 4, 4, 4.0, 8, 8, 0.1, 20,
+                    0.21, 0.6, 5, 16, "fp64", 200),
+    "12x12": Workload("12x12 U=4 half filling Theta=5", 12, 12, 4.0, 72, 72, 0.1, 50,
+                      0.21, 0.6, 10, 32, "mixed", 500),
+    "16x16": Workload("16x16 U=3.5 n=0.875 Theta=10", 16, 16, 3.5, 112, 112, 0.1, 100,
+                      0.07, 0.55, 5, 32, "mixed", 1000, ramp=0.1),
+    "24x24": Workload("24x24 U=4 half filling Theta=10 dtau=0.05", 24, 24, 4.0, 288, 288,
+                      0.05, 200, 0.21, 0.6, 10, 32, "mixed", 100),
+}
+
+
+def batch_uneven(n_chains: int = 256, seed: int = 13403, l_half: int = 50,
+                 dtau: float = 0.1, precision: str = "mixed", stab_interval: int = 5,
+                 delay_rank: int = 16):
+    """Batch of independent half-filled chains on uneven lattices.
+
+    Each chain draws its linear size uniformly from {6, 8, 10, 12} and U
+    uniformly from [2, 6] (numpy PCG64 stream seeded with ``seed``); every
+    chain uses M_N = 0.21, g = 0.6, Theta = l_half * dtau.
+    """
+    rng = np.random.default_rng(seed)
+    sizes = np.array([6, 8, 10, 12])
+    pick = rng.integers(0, 4, size=n_chains)
+    us = rng.uniform(2.0, 6.0, size=n_chains)
+    out = []
+    for c in range(n_chains):
+        L = int(sizes[pick[c]])
+        out.append(Workload(f"batch chain {c}: {L}x{L} U={us[c]:.3f}", L, L, float(us[c]),
+                            L * L // 2, L * L // 2, dtau, l_half, 0.21, 0.6,
+                            stab_interval, delay_rank, precision, 500, seed=seed))
+    return out

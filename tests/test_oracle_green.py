@@ -1,0 +1,148 @@
+"""Fixed-field pins of the oracle: Green's-function invariants, determinant
+ratios against brute-force determinants, Sherman-Morrison against recompute,
+wrapped sweep against the exact (recompute-everywhere) sweep, and the
+particle-hole symmetry at half filling (no GPU)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import philox, pqmc
+from paper_2303_13403_amd.workloads import square_lattice
+
+
+def _model(L=4, n=None, U=4.0, l_half=4, g=0.6, m=0.21, n_s=3, dtau=0.1, pot=None):
+    K, eps, _ = square_lattice(L, L)
+    n = n if n is not None else L * L // 2
+    return pqmc.Model(K, eps, U=U, n_up=n, n_dn=n, dtau=dtau, l_half=l_half,
+                      m_neel=m, g=g, stab_interval=n_s, potential=pot)
+
+
+def _field(m, seed=7):
+    return philox.initial_field(seed, 0, m.n_slices, m.N)
+
+
+@pytest.mark.parametrize("p", [-1, 0, 3, 4, 9])
+def test_green_invariants(p):
+    m = _model()
+    f = _field(m)
+    for s in pqmc.SPINS:
+        G = pqmc.green_stable(m, f, p, s)
+        assert np.max(np.abs(G @ G - G)) < 1e-12           # 1 - G is a projector
+        assert math.isclose(np.trace(G), m.N - m.n[s], abs_tol=1e-11)
+        # invariance under R -> R T, L -> T' L
+        R = pqmc.right_basis(m, f, p, s)
+        Lt = pqmc.left_basis_T(m, f, p, s)
+        T = np.random.default_rng(1).normal(size=(m.n[s], m.n[s]))
+        G2 = pqmc.green_from_bases(R @ T, Lt @ T.T)
+        assert np.max(np.abs(G2 - G)) < 1e-10
+        assert np.max(np.abs(pqmc.green_from_bases(R, Lt) - G)) < 1e-10
+
+
+def test_ratio_matches_brute_force_determinants():
+    """1 + Delta (1 - G_ii) equals det(L' R')/det(L R) of the full products."""
+    m = _model(l_half=3)
+    f = _field(m, 3)
+    rng = np.random.default_rng(0)
+    for l in [0, 1, 3, 5, m.M + 1]:
+        for i in rng.choice(m.N, 4, replace=False):
+            for s in pqmc.SPINS:
+                # G in the frame where D_l acts
+                R = m.diag(f[l], l, s)[:, None] * pqmc.right_basis(m, f, l - 1, s)
+                Lt = pqmc.left_basis_T(m, f, l, s)
+                if m.is_bulk(l):
+                    Lt = m.Km @ Lt
+                G = pqmc.green_from_bases(R, Lt)
+                delta = m.flip_delta(int(f[l, i]), l, s)
+                r = 1.0 + delta * (1.0 - G[i, i])
+                f2 = f.copy()
+                f2[l, i] *= -1
+                w0, w1 = pqmc.weight(m, f, s), pqmc.weight(m, f2, s)
+                assert math.isclose(r, w1 / w0, rel_tol=1e-10)
+
+
+def test_sherman_morrison_equals_recompute():
+    m = _model(l_half=3)
+    f = _field(m, 5)
+    l, i = 2, 6
+    for s in pqmc.SPINS:
+        R = m.diag(f[l], l, s)[:, None] * pqmc.right_basis(m, f, l - 1, s)
+        Lt = m.Km @ pqmc.left_basis_T(m, f, l, s)
+        G = pqmc.green_from_bases(R, Lt)
+        delta = m.flip_delta(int(f[l, i]), l, s)
+        r = 1 + delta * (1 - G[i, i])
+        e = np.zeros(m.N)
+        e[i] = 1
+        Gsm = G - (delta / r) * np.outer(G[:, i], e - G[i, :])
+        f2 = f.copy()
+        f2[l, i] *= -1
+        R2 = m.diag(f2[l], l, s)[:, None] * pqmc.right_basis(m, f2, l - 1, s)
+        G2 = pqmc.green_from_bases(R2, Lt)
+        assert np.max(np.abs(Gsm - G2)) < 1e-12
+
+
+def test_wrapped_sweep_matches_exact_sweep():
+    """The wrapped/stabilised chain and the recompute-everywhere chain take the
+    same decisions and see the same ratios (both directions)."""
+    m = _model(l_half=3, n_s=2)
+    a = pqmc.Chain(m, seed=11)
+    b = pqmc.Chain(m, seed=11, exact=True)
+    a.record_ratios = b.record_ratios = True
+    a.sweep(2)
+    b.sweep(2)
+    assert np.array_equal(a.field, b.field)
+    assert a.ratios.keys() == b.ratios.keys()
+    for k, va in a.ratios.items():
+        vb = b.ratios[k]
+        assert math.isclose(va[0], vb[0], rel_tol=1e-10, abs_tol=1e-12)
+        assert math.isclose(va[1], vb[1], rel_tol=1e-10, abs_tol=1e-12)
+        assert va[3] == vb[3]
+    accepted = sum(v[3] for v in a.ratios.values())
+    assert 0 < accepted < len(a.ratios)
+    for x, y in zip(a.measurements, b.measurements):
+        assert x[0] == y[0] and math.isclose(x[1], y[1], abs_tol=1e-11)
+
+
+def test_checkpoint_green_matches_fresh_products():
+    m = _model(l_half=4, n_s=3)
+    ch = pqmc.Chain(m, seed=4)
+    ch.record_greens = True
+    ch.sweep(2)
+    assert len(ch.checkpoint_greens) > 4
+    for sweep, p, gu, gd, drift, field in ch.checkpoint_greens:
+        assert np.max(np.abs(gu - pqmc.green_stable(m, field, p, 1))) < 1e-11
+        assert np.max(np.abs(gd - pqmc.green_stable(m, field, p, -1))) < 1e-11
+        assert drift < 1e-10
+    assert ch.sign_mismatches == 0
+
+
+def test_particle_hole_symmetry_half_filling():
+    """Bipartite lattice, half filling, Neel trial: per field configuration
+    G_dn = 1 - S G_up^T S (S = diag(eps)) and r_dn = e^{2 c s} r_up, so the
+    weight is never negative."""
+    m = _model(L=4, l_half=3)
+    S = np.diag(m.eps)
+    for seed in range(3):
+        f = _field(m, seed)
+        for p in (-1, 2, 5, m.M + 1):
+            gu = pqmc.green_stable(m, f, p, 1)
+            gd = pqmc.green_stable(m, f, p, -1)
+            assert np.max(np.abs(gd - (np.eye(m.N) - S @ gu.T @ S))) < 1e-11
+        assert pqmc.weight(m, f, 1) * pqmc.weight(m, f, -1) > 0
+    ch = pqmc.Chain(m, seed=2)
+    ch.record_ratios = True
+    ch.sweep(2)
+    for (sw, l, i), (ru, rd, u, acc) in ch.ratios.items():
+        assert ru * rd > 0
+    assert all(x[0] == 1 for x in ch.measurements)
+
+
+def test_doped_chain_tracks_sign_consistently():
+    """Away from half filling the tracked sign must equal the sign recomputed
+    from the stabilised determinants at every checkpoint."""
+    K, eps, _ = square_lattice(4, 4)
+    m = pqmc.Model(K, eps, U=6.0, n_up=5, n_dn=5, dtau=0.15, l_half=6, m_neel=0.1,
+                   g=0.4, stab_interval=3, potential=np.linspace(0, 0.05, 16))
+    ch = pqmc.Chain(m, seed=9).sweep(6)
+    assert ch.sign_mismatches == 0
+    assert ch.max_drift < 1e-9
