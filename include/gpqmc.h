@@ -1,0 +1,202 @@
+/*
+ * gpqmc.h -- C ABI of the MI355X (gfx950) Gutzwiller-projection PQMC sweep.
+ *
+ * Method: W.-X. Chang and Z.-X. Li, "Boosting quantum Monte Carlo and
+ * alleviating sign problem by Gutzwiller projection", arXiv:2303.13403.
+ *
+ *   <O> = <psi_T| e^{-Theta H} O e^{-Theta H} |psi_T> / <psi_T| e^{-2 Theta H} |psi_T>
+ *   |psi_T> = exp(-g sum_i n_i_up n_i_dn) |psi_N>                 (Method section)
+ *   H = -t sum_<ij>,sigma (c^dag c + h.c.) + U sum_i n_i_up n_i_dn  (Eq. 2)
+ *   |psi_N>: ground state of H_0 + M_N sum_i eps_i (n_i_up - n_i_dn) (Neel trial,
+ *            Hubbard section; eps_i = +1 on sublattice A, -1 on B)
+ *
+ * The projector exp(-g sum n_up n_dn) is decoupled with one Ising field per
+ * site (Eq. 1, used in its exact spin-channel form
+ * exp(-x (n_up-1/2)(n_dn-1/2)) = 1/2 e^{-x/4} sum_s e^{c s (n_up - n_dn)},
+ * cosh c = e^{x/2}) and becomes two boundary slices, ket slice 0 and bra slice
+ * M+1; the Hubbard term is decoupled the same way (x = dtau U) on the M = 2
+ * l_half bulk slices, B_l = e^{-dtau K} e^{V(s_l)}.  One sweep is one pass over
+ * the M + 2 slices (upward on even sweep indices, downward on odd ones)
+ * proposing a flip of every field with the determinant ratio
+ * 1 + Delta (1 - G_ii) and Metropolis acceptance on |r_up r_dn|.
+ *
+ * Conventions of every entry point:
+ *  - All functions return a gpqmc_status; no exception or abort crosses the ABI.
+ *    After an error, gpqmc_last_error() describes it.
+ *  - Host arrays passed in are read during the call and copied; the library
+ *    keeps no pointer to them.  Output arrays are caller-owned host buffers.
+ *  - Device memory is owned by the caller: gpqmc_workspace_bytes() gives the
+ *    size and gpqmc_bind_workspace() hands it over; it must stay allocated and
+ *    untouched until gpqmc_destroy().  The library allocates no device memory.
+ *  - All device work is enqueued on the HIP stream given at creation, in call
+ *    order.  Functions marked "synchronises" wait for that stream.
+ *  - A context is not thread-safe; use one context per host thread.
+ *  - Matrices are row-major; sites are indexed 0 .. N-1; spin 0 is up, 1 down.
+ */
+#ifndef GPQMC_H
+#define GPQMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GPQMC_OK = 0,
+  GPQMC_EINVAL = -1,      /* invalid argument (message in gpqmc_last_error) */
+  GPQMC_ENOMEM = -2,      /* host allocation failed, or workspace too small */
+  GPQMC_EHIP = -3,        /* a HIP runtime call failed */
+  GPQMC_EDEGENERATE = -4, /* trial state not unique: single-particle gap below 1e-6 */
+  GPQMC_EUNSTABLE = -5,   /* a chain flagged drift, NaN, singular L R or a sign mismatch */
+  GPQMC_ESTATE = -6       /* call out of order (e.g. sweep before init_trial) */
+} gpqmc_status;
+
+/* GPQMC_FP64: every step in FP64 (FP64 MFMA for the contractions).
+ * GPQMC_MIXED: the Green's-function work of every slice (kinetic wrap, delayed
+ *   flush, submatrix scan) in FP32 on FP32 MFMA with FP32 accumulation; basis
+ *   propagation, QR, (L R)^{-1}, the fresh Green's function, log|det| and sign
+ *   in FP64.
+ * GPQMC_MIXED_FP32_BASIS: as GPQMC_MIXED but the basis propagation e^{-dtau K}
+ *   e^{V} U also in FP32 (its fresh Green's function carries an error of order
+ *   eps_fp32 cond(L R), about 1e-5 on a 12 x 12 lattice). */
+typedef enum { GPQMC_FP64 = 0, GPQMC_MIXED = 1, GPQMC_MIXED_FP32_BASIS = 2 } gpqmc_precision;
+
+/* One Markov chain.  All chains of one context must share l_half,
+ * stab_interval, delay_rank and precision; lattices, fillings and couplings
+ * may differ per chain. */
+typedef struct {
+  int32_t n_sites;            /* N, 1 .. 1024 */
+  int32_t n_up, n_dn;         /* particles per spin, 1 .. N */
+  const double* hopping;      /* N x N symmetric hopping matrix K (K_ij = -t per bond) */
+  const int8_t* sublattice;   /* N signs eps_i (+1 / -1) of the Neel trial */
+  const double* trial_potential; /* N extra on-site energies of the trial
+                                    Hamiltonian only (NULL = none) */
+  double U;                   /* Hubbard repulsion, >= 0 */
+  double dtau;                /* Trotter step, > 0 */
+  double g;                   /* Gutzwiller parameter, >= 0 */
+  double m_neel;              /* Neel order parameter M_N of the trial */
+  int32_t l_half;             /* slices per side, Theta / dtau (>= 0) */
+  int32_t stab_interval;      /* n_s: slices between QR re-stabilisations (>= 1) */
+  int32_t delay_rank;         /* k: sites per block of the delayed scan (1 .. 32) */
+  int32_t precision;          /* gpqmc_precision */
+  uint64_t seed;              /* Philox key; words (lo32(seed), hi32(seed) ^ tag) */
+  uint64_t chain_id;          /* counter word 0 of every draw of this chain */
+  int32_t trace;              /* nonzero: record ratios and checkpoint Green's
+                                 functions of the last pass (testing; large) */
+} gpqmc_chain_desc;
+
+typedef struct {
+  int32_t meas_capacity;      /* measurement records kept per chain (default 4096) */
+  int32_t use_graph;          /* capture each pass in a HIP graph (default 1) */
+  double drift_tol;           /* drift above this flags a chain (default 1e-3 mixed,
+                                 1e-6 fp64) */
+} gpqmc_options;
+
+typedef struct {
+  int32_t sign;               /* current sign of W_up W_dn */
+  int32_t flags;              /* sticky error bits: 1 drift, 2 NaN, 4 singular L R,
+                                 8 sign mismatch, 16 measurement buffer full */
+  int32_t n_meas;             /* stored measurement records */
+  int32_t sign_mismatch;      /* checkpoints where tracked and recomputed signs differed */
+  int32_t sweep;              /* passes done since init_trial */
+  float max_drift;            /* max |G_wrapped - G_fresh| over checkpoints */
+  float last_drift;
+  int64_t accepted, proposed; /* Metropolis counters */
+} gpqmc_chain_info;
+
+typedef struct gpqmc_ctx gpqmc_ctx;
+
+/* Create a context for n_chains chains (host only; no device work).
+ * Validates the descriptors, builds e^{-+dtau K} and the Neel trial orbitals
+ * (lowest n_sigma eigenvectors of K + sigma M_N diag(eps) + diag(trial_potential),
+ * Hubbard section) with the library's own symmetric eigensolver, and fixes the
+ * workspace layout.  hip_stream is a hipStream_t (NULL = default stream).
+ * opts may be NULL.  Errors: EINVAL, EDEGENERATE, ENOMEM. */
+gpqmc_status gpqmc_create(int32_t n_chains, const gpqmc_chain_desc* chains,
+                          const gpqmc_options* opts, void* hip_stream, gpqmc_ctx** out);
+
+/* Device workspace size in bytes (256-byte aligned start required). */
+gpqmc_status gpqmc_workspace_bytes(const gpqmc_ctx* ctx, size_t* bytes);
+
+/* Hand over the caller-owned device workspace; uploads the static matrices
+ * (synchronises).  Errors: ENOMEM if bytes is too small, EINVAL if misaligned. */
+gpqmc_status gpqmc_bind_workspace(gpqmc_ctx* ctx, void* device_ptr, size_t bytes);
+
+/* Initialise every chain: draw the initial field from Philox (tag 0, counter
+ * (chain_id, 0, l, i): s = +1 iff bit 0 of word 0 is set) unless one was set
+ * with gpqmc_set_field, build the stack of orthonormal bases of
+ * L_p = P^T S_{M+1} ... S_{p+1} downward from the bra, and compute the Green's
+ * function G = 1 - R (L R)^{-1} L at position -1.  Resets sweep counters,
+ * measurements and flags.  Synchronises.  Errors: ESTATE before bind. */
+gpqmc_status gpqmc_init_trial(gpqmc_ctx* ctx);
+
+/* Run n_sweeps passes.  measure != 0 records (sign, E/N, D) at tau = Theta
+ * once per pass from the freshly recomputed Green's function.  Enqueue only.
+ * Errors: ESTATE before init_trial. */
+gpqmc_status gpqmc_sweep(gpqmc_ctx* ctx, int32_t n_sweeps, int32_t measure);
+
+/* Sign-weighted estimates over the stored records of one chain
+ * (chain = -1: all chains pooled), error by jackknife over bins of
+ * 10 records: energy per site E/N = <s E>/<s> (Eq. 2 with U n_up n_dn),
+ * double occupancy <s D>/<s>, average sign <s>.  Synchronises.
+ * Errors: EINVAL (chain out of range or fewer than 20 records). */
+gpqmc_status gpqmc_measure_energy(gpqmc_ctx* ctx, int32_t chain, double* mean, double* err);
+gpqmc_status gpqmc_measure_double_occupancy(gpqmc_ctx* ctx, int32_t chain, double* mean,
+                                            double* err);
+gpqmc_status gpqmc_measure_sign(gpqmc_ctx* ctx, int32_t chain, double* mean, double* err);
+
+/* Raw records (sign, E/N, D) of one chain, oldest first; *n_out receives the
+ * number written (<= capacity).  Synchronises. */
+gpqmc_status gpqmc_get_measurements(gpqmc_ctx* ctx, int32_t chain, double* out,
+                                    int32_t capacity, int32_t* n_out);
+
+/* Clear the measurement records of every chain (enqueue only). */
+gpqmc_status gpqmc_reset_measurements(gpqmc_ctx* ctx);
+
+/* Field of one chain, (M+2) x N int8 (+1 / -1), slice-major.  set_field
+ * requires a following gpqmc_init_trial.  Synchronise. */
+gpqmc_status gpqmc_set_field(gpqmc_ctx* ctx, int32_t chain, const int8_t* field);
+gpqmc_status gpqmc_get_field(gpqmc_ctx* ctx, int32_t chain, int8_t* field);
+
+/* Last freshly recomputed FP64 Green's function G_ij = <c_i c_j^dag> of one
+ * chain and spin (N x N): after init_trial or a sweep it is at position -1
+ * (after a downward pass) or M+1 (after an upward pass).  Synchronises. */
+gpqmc_status gpqmc_get_green(gpqmc_ctx* ctx, int32_t chain, int32_t spin, double* G);
+
+/* Status record of one chain.  Synchronises. */
+gpqmc_status gpqmc_get_chain_info(gpqmc_ctx* ctx, int32_t chain, gpqmc_chain_info* info);
+
+/* Testing hooks (off the hot path).
+ * set_debug: bit 0 = reject every proposal (fixed-field parity runs).
+ * get_trace: for a chain created with trace != 0, the ratios (r_up, r_dn) of
+ * every proposal of the last pass ((M+2) x N x 2, slice-major), the FP64
+ * Green's functions at the checkpoints of the last pass (n_ck x 2 x N x N, in
+ * pass order) and their drifts (n_ck); any pointer may be NULL.  n_ck is
+ * returned in *n_checkpoints.  Synchronises. */
+gpqmc_status gpqmc_set_debug(gpqmc_ctx* ctx, int32_t flags);
+gpqmc_status gpqmc_get_trace(gpqmc_ctx* ctx, int32_t chain, double* ratios, double* greens,
+                             double* drifts, int32_t* n_checkpoints);
+
+/* Batched-GEMM self test on caller device memory: C = op(A) B with the
+ * library's MFMA tile kernel (precision GPQMC_FP64 or GPQMC_MIXED = FP32),
+ * A M x K row-major (or K x M when trans_a), B K x N, C M x N.  Synchronises. */
+gpqmc_status gpqmc_debug_gemm(int32_t precision, int32_t M, int32_t N, int32_t K,
+                              int32_t trans_a, const void* A, int32_t lda, const void* B,
+                              int32_t ldb, void* C, int32_t ldc, void* hip_stream);
+
+/* Status of one chain: GPQMC_OK or GPQMC_EUNSTABLE if any flag is set.
+ * Synchronises. */
+gpqmc_status gpqmc_chain_status(gpqmc_ctx* ctx, int32_t chain);
+
+const char* gpqmc_last_error(const gpqmc_ctx* ctx);
+
+/* Release host resources (the caller frees the workspace afterwards). */
+void gpqmc_destroy(gpqmc_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GPQMC_H */

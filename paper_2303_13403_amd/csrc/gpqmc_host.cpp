@@ -1,0 +1,1056 @@
+// Host side of the Gutzwiller-projection PQMC library: validation, the
+// symmetric eigensolver for e^{-+dtau K} and the Neel trial, the workspace
+// layout, the slice schedule of a pass (captured as a HIP graph) and the
+// C ABI declared in include/gpqmc.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/gpqmc.h"
+#include "gpqmc_internal.h"
+
+namespace gpqmc {
+hipError_t launch_gemm(int bulk_fp32, int mode, const GemmEntry* e, const TileRef* t, int n,
+                       GemmArgs a, hipStream_t s);
+hipError_t launch_gemm_plain(int fp32, int transA, const GemmEntry* e, const TileRef* t, int n,
+                             GemmArgs a, hipStream_t s);
+hipError_t launch_scan(int fp32, const ChainDev* c, int nc, const Ctl* ctl, int l, int M, int kblk,
+                       hipStream_t s);
+hipError_t launch_qr(int fp32, const ChainDev* c, int nc, int parity, hipStream_t s);
+hipError_t launch_lu_solve(const ChainDev* c, int nc, int slot, int dir, hipStream_t s);
+hipError_t launch_finalize(const ChainDev* c, int nc, const Ctl* ctl, int slot, int mode,
+                           int measure_here, int ck_index, hipStream_t s);
+hipError_t launch_put_trial(int fp32, const ChainDev* c, int nc, int slot, int set_active,
+                            hipStream_t s);
+hipError_t launch_dscale_u(int fp32, const ChainDev* c, int nc, int l, int M, int parity,
+                           hipStream_t s);
+hipError_t launch_pass_end(const ChainDev* c, int nc, hipStream_t s);
+hipError_t launch_set_ctl(Ctl* ctl, int measure, int force_reject, float drift_tol, hipStream_t s);
+}  // namespace gpqmc
+
+using namespace gpqmc;
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// cyclic Jacobi eigensolver for a real symmetric matrix (row-major, n x n):
+// rotations annihilate A_pq until the off-diagonal norm is negligible.
+// Returns ascending eigenvalues w and eigenvectors as the columns of V.
+// ---------------------------------------------------------------------------
+void jacobi_eigh(int n, const double* a_in, std::vector<double>& w, std::vector<double>& V) {
+  std::vector<double> A(a_in, a_in + (size_t)n * n);
+  V.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
+  double total = 0.0;
+  for (size_t i = 0; i < A.size(); ++i) total += A[i] * A[i];
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) off += A[(size_t)p * n + q] * A[(size_t)p * n + q];
+    if (off <= 1e-32 * total || off == 0.0) break;
+    for (int p = 0; p < n; ++p) {
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = A[(size_t)p * n + q];
+        if (apq == 0.0) continue;
+        const double app = A[(size_t)p * n + p], aqq = A[(size_t)q * n + q];
+        if (std::fabs(apq) < 1e-300) continue;
+        const double theta = (aqq - app) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        // A <- J^T A J with J the rotation in the (p, q) plane
+        for (int k = 0; k < n; ++k) {
+          const double akp = A[(size_t)k * n + p], akq = A[(size_t)k * n + q];
+          A[(size_t)k * n + p] = c * akp - s * akq;
+          A[(size_t)k * n + q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double apk = A[(size_t)p * n + k], aqk = A[(size_t)q * n + k];
+          A[(size_t)p * n + k] = c * apk - s * aqk;
+          A[(size_t)q * n + k] = s * apk + c * aqk;
+        }
+        A[(size_t)p * n + q] = 0.0;
+        A[(size_t)q * n + p] = 0.0;
+        for (int k = 0; k < n; ++k) {
+          const double vkp = V[(size_t)k * n + p], vkq = V[(size_t)k * n + q];
+          V[(size_t)k * n + p] = c * vkp - s * vkq;
+          V[(size_t)k * n + q] = s * vkp + c * vkq;
+        }
+      }
+    }
+  }
+  std::vector<int> ord(n);
+  for (int i = 0; i < n; ++i) ord[i] = i;
+  std::stable_sort(ord.begin(), ord.end(),
+                   [&](int x, int y) { return A[(size_t)x * n + x] < A[(size_t)y * n + y]; });
+  w.resize(n);
+  std::vector<double> Vs((size_t)n * n);
+  for (int j = 0; j < n; ++j) {
+    w[j] = A[(size_t)ord[j] * n + ord[j]];
+    for (int i = 0; i < n; ++i) Vs[(size_t)i * n + j] = V[(size_t)i * n + ord[j]];
+  }
+  V.swap(Vs);
+}
+
+struct Lattice {   // shared by chains with identical hopping and dtau
+  int N;
+  std::vector<double> K, Km, Kp;
+  size_t off_K = 0, off_Km = 0, off_Kp = 0, off_Kmb = 0;  // Kmb: e^{-dtau K} in basis precision
+};
+
+struct Trial {     // shared by chains with identical trial Hamiltonian
+  int N, n;
+  std::vector<double> P;
+  size_t off = 0;
+};
+
+struct ChainHost {
+  int N, n[2];
+  int lat, trial[2];
+  double U, dtau, g, m_neel, alpha, lam;
+  uint64_t seed, chain_id;
+  bool trace;
+  bool field_set = false;
+  std::vector<int8_t> field;
+  // workspace offsets
+  size_t G[2], Gtmp[2], U2[2][2], Z[2], Xg[2], Yg[2], T1[2], scan_ws[2];
+  size_t stack[2], slot_log[2], slot_sgn[2], Hw[2], Qc[2], Xm[2], Ym[2], piv[2], G64[2];
+  size_t field_off, Flist, st, meas, tr_ratio = 0, tr_green = 0, tr_drift = 0;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+std::string key_bytes(const void* p, size_t n) { return std::string((const char*)p, n); }
+
+}  // namespace
+
+struct gpqmc_ctx {
+  int n_chains = 0;
+  hipStream_t stream = nullptr;
+  int fp32 = 0;            // Green's-function (wrap, flush, scan) precision: 1 = FP32, 0 = FP64
+  int fp32b = 0;           // basis propagation precision: 1 = FP32, 0 = FP64
+  int l_half = 0, M = 0, n_s = 1, kblk = 16, n_slices = 2;
+  int meas_cap = 4096;
+  bool use_graph = true;
+  float drift_tol = 1e-3f;
+  std::vector<int> ckpts;          // sorted checkpoint positions
+  std::map<int, int> slot_of;      // position -> slot
+  std::vector<Lattice> lats;
+  std::vector<Trial> trials;
+  std::vector<ChainHost> ch;
+  // layout
+  size_t bytes = 0;
+  size_t off_chains = 0, off_ctl = 0;
+  size_t off_ent[9] = {0};
+  size_t off_tiles_NN = 0, off_tiles_Nn = 0, off_tiles_nn = 0;
+  std::vector<TileRef> tiles_NN, tiles_Nn, tiles_nn;
+  char* ws = nullptr;
+  bool bound = false, initialized = false;
+  long long sweeps_done = 0;       // passes enqueued since init_trial (mirrors the device counter)
+  int debug_flags = 0;
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  hipGraph_t graph_def[2] = {nullptr, nullptr};
+  std::string err;
+
+  template <class T>
+  T* at(size_t off) const { return (T*)(ws + off); }
+  int slot(int p) const { return slot_of.at(p); }
+  bool is_ck(int p) const { return slot_of.count(p) != 0; }
+  int n_ck_pass() const { return (int)ckpts.size() - 1; }
+};
+
+namespace {
+
+enum EntryKind { E_WRAP1_UP = 0, E_WRAP2_UP, E_WRAP1_DN, E_WRAP2_DN, E_T1, E_FLUSH, E_PROP, E_XMAT,
+                 E_GFRESH };
+
+gpqmc_status fail(gpqmc_ctx* c, gpqmc_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+gpqmc_status hip_fail(gpqmc_ctx* c, hipError_t e, const char* where) {
+  return fail(c, GPQMC_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(call, where)                       \
+  do {                                            \
+    hipError_t e_ = (call);                       \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, where); \
+  } while (0)
+
+const GemmEntry* ents(const gpqmc_ctx* ctx, int kind) {
+  return ctx->at<GemmEntry>(ctx->off_ent[kind]);
+}
+
+// ----------------------------------------------------------------------------
+// schedule of one pass
+// ----------------------------------------------------------------------------
+struct Launcher {
+  gpqmc_ctx* ctx;
+  const ChainDev* chains;
+  const Ctl* ctl;
+  int nc;
+  hipStream_t s;
+
+  GemmArgs args() const {
+    GemmArgs a;
+    a.scale_slice = -1;
+    a.scale_inverse = 0;
+    a.bscale_slice = -1;
+    a.parity = 0;
+    a.slot = 0;
+    a.dir = 0;
+    a.n_bulk_last = ctx->M;
+    a.check_drift = 0;
+    return a;
+  }
+  hipError_t gemm(int kind, int mode, const std::vector<TileRef>& tl, size_t tl_off, GemmArgs a) {
+    const int f32 = (mode == GM_PROPB || mode == GM_PROPR) ? ctx->fp32b : ctx->fp32;
+    return launch_gemm(f32, mode, ents(ctx, kind), ctx->at<TileRef>(tl_off), (int)tl.size(), a, s);
+  }
+  hipError_t nn(int kind, int mode, GemmArgs a) { return gemm(kind, mode, ctx->tiles_NN, ctx->off_tiles_NN, a); }
+
+  // checkpoint at position p: orthonormalise the active basis, recompute G
+  hipError_t checkpoint(int p, int dir, int parity, int next_scale, int measure, int ck_index,
+                        int mode) {
+    hipError_t e;
+    if ((e = launch_qr(ctx->fp32b, chains, nc, parity, s)) != hipSuccess) return e;
+    const int sl = ctx->slot(p);
+    if (mode == 2) return launch_finalize(chains, nc, ctl, sl, 2, 0, -1, s);
+    GemmArgs a = args();
+    a.slot = sl;
+    a.dir = dir;
+    if ((e = gemm(E_XMAT, GM_XMAT, ctx->tiles_nn, ctx->off_tiles_nn, a)) != hipSuccess) return e;
+    if ((e = launch_lu_solve(chains, nc, sl, dir, s)) != hipSuccess) return e;
+    a.scale_slice = next_scale;
+    a.check_drift = (mode == 0);
+    if ((e = nn(E_GFRESH, GM_GFRESH, a)) != hipSuccess) return e;
+    return launch_finalize(chains, nc, ctl, sl, mode, measure, ck_index, s);
+  }
+
+  hipError_t scan_and_flush(int l, int scale_slice, int inverse) {
+    hipError_t e;
+    if ((e = launch_scan(ctx->fp32, chains, nc, ctl, l, ctx->M, ctx->kblk, s)) != hipSuccess) return e;
+    GemmArgs a = args();
+    if ((e = nn(E_T1, GM_T1, a)) != hipSuccess) return e;
+    a.scale_slice = scale_slice;
+    a.scale_inverse = inverse;
+    return nn(E_FLUSH, GM_FLUSH, a);
+  }
+
+  hipError_t up_pass() {
+    hipError_t e;
+    const int M = ctx->M;
+    if ((e = launch_put_trial(ctx->fp32b, chains, nc, ctx->slot(-1), 1, s)) != hipSuccess) return e;
+    int parity = 0, ck = 0;
+    for (int l = 0; l <= M + 1; ++l) {
+      const bool bulk = (l >= 1 && l <= M);
+      const bool ckl = ctx->is_ck(l);
+      if ((e = scan_and_flush(l, (!bulk && l == 0 && !ckl) ? 1 : -1, 0)) != hipSuccess) return e;
+      if (bulk) {
+        GemmArgs a = args();
+        if ((e = nn(E_WRAP1_UP, GM_STORE, a)) != hipSuccess) return e;
+        a.scale_slice = ckl ? -1 : l + 1;
+        if ((e = nn(E_WRAP2_UP, GM_WRAP, a)) != hipSuccess) return e;
+        GemmArgs b = args();
+        b.bscale_slice = l;
+        b.parity = parity;
+        if ((e = gemm(E_PROP, GM_PROPB, ctx->tiles_Nn, ctx->off_tiles_Nn, b)) != hipSuccess) return e;
+        parity ^= 1;
+      } else {
+        if ((e = launch_dscale_u(ctx->fp32b, chains, nc, l, M, parity, s)) != hipSuccess) return e;
+      }
+      if (ckl) {
+        if ((e = checkpoint(l, 0, parity, l <= M ? l + 1 : -1, l == ctx->l_half, ck++, 0)) != hipSuccess)
+          return e;
+      }
+    }
+    return launch_pass_end(chains, nc, s);
+  }
+
+  hipError_t down_pass() {
+    hipError_t e;
+    const int M = ctx->M;
+    if ((e = launch_put_trial(ctx->fp32b, chains, nc, ctx->slot(M + 1), 1, s)) != hipSuccess) return e;
+    int parity = 0, ck = 0;
+    for (int l = M + 1; l >= 0; --l) {
+      const bool bulk = (l >= 1 && l <= M);
+      if (bulk) {
+        GemmArgs a = args();
+        if ((e = nn(E_WRAP1_DN, GM_STORE, a)) != hipSuccess) return e;
+        if ((e = nn(E_WRAP2_DN, GM_WRAP, a)) != hipSuccess) return e;
+      }
+      if ((e = scan_and_flush(l, l, 1)) != hipSuccess) return e;
+      if (bulk) {
+        GemmArgs b = args();
+        b.scale_slice = l;
+        b.parity = parity;
+        if ((e = gemm(E_PROP, GM_PROPR, ctx->tiles_Nn, ctx->off_tiles_Nn, b)) != hipSuccess) return e;
+        parity ^= 1;
+      } else {
+        if ((e = launch_dscale_u(ctx->fp32b, chains, nc, l, M, parity, s)) != hipSuccess) return e;
+      }
+      const int p = l - 1;
+      if (ctx->is_ck(p)) {
+        if ((e = checkpoint(p, 1, parity, p == -1 ? 0 : -1, p == ctx->l_half, ck++, 0)) != hipSuccess)
+          return e;
+      }
+    }
+    return launch_pass_end(chains, nc, s);
+  }
+
+  hipError_t init_pass() {
+    hipError_t e;
+    const int M = ctx->M;
+    if ((e = launch_put_trial(ctx->fp32b, chains, nc, ctx->slot(M + 1), 1, s)) != hipSuccess) return e;
+    if ((e = launch_put_trial(ctx->fp32b, chains, nc, ctx->slot(-1), 0, s)) != hipSuccess) return e;
+    int parity = 0;
+    for (int l = M + 1; l >= 0; --l) {
+      const bool bulk = (l >= 1 && l <= M);
+      if (bulk) {
+        GemmArgs b = args();
+        b.scale_slice = l;
+        b.parity = parity;
+        if ((e = gemm(E_PROP, GM_PROPR, ctx->tiles_Nn, ctx->off_tiles_Nn, b)) != hipSuccess) return e;
+        parity ^= 1;
+      } else {
+        if ((e = launch_dscale_u(ctx->fp32b, chains, nc, l, M, parity, s)) != hipSuccess) return e;
+      }
+      const int p = l - 1;
+      if (ctx->is_ck(p)) {
+        if ((e = checkpoint(p, 1, parity, p == -1 ? 0 : -1, 0, -1, p >= 0 ? 2 : 1)) != hipSuccess)
+          return e;
+      }
+    }
+    return hipSuccess;
+  }
+};
+
+Launcher make_launcher(gpqmc_ctx* ctx) {
+  Launcher L;
+  L.ctx = ctx;
+  L.chains = ctx->at<ChainDev>(ctx->off_chains);
+  L.ctl = ctx->at<Ctl>(ctx->off_ctl);
+  L.nc = ctx->n_chains;
+  L.s = ctx->stream;
+  return L;
+}
+
+void build_tiles(std::vector<TileRef>& out, const std::vector<std::pair<int, int>>& mn) {
+  out.clear();
+  for (size_t e = 0; e < mn.size(); ++e) {
+    const int tm = (mn[e].first + kTile - 1) / kTile, tn = (mn[e].second + kTile - 1) / kTile;
+    for (int a = 0; a < tm; ++a)
+      for (int b = 0; b < tn; ++b) out.push_back(TileRef{(int)e, a, b, 0});
+  }
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+extern "C" {
+
+gpqmc_status gpqmc_create(int32_t n_chains, const gpqmc_chain_desc* chains,
+                          const gpqmc_options* opts, void* hip_stream, gpqmc_ctx** out) {
+  if (!out) return GPQMC_EINVAL;
+  *out = nullptr;
+  std::unique_ptr<gpqmc_ctx> ctx(new (std::nothrow) gpqmc_ctx());
+  if (!ctx) return GPQMC_ENOMEM;
+  gpqmc_ctx* c = ctx.get();
+  // on error the context is still returned so that gpqmc_last_error() can
+  // describe the problem; the caller destroys it
+  auto bad = [&](gpqmc_status code, const std::string& msg) {
+    c->err = msg;
+    *out = ctx.release();
+    return code;
+  };
+  if (n_chains <= 0 || !chains) return bad(GPQMC_EINVAL, "n_chains <= 0 or chains == NULL");
+  c->n_chains = n_chains;
+  c->stream = (hipStream_t)hip_stream;
+  const gpqmc_chain_desc& d0 = chains[0];
+  c->l_half = d0.l_half;
+  c->n_s = d0.stab_interval;
+  c->kblk = d0.delay_rank;
+  c->fp32 = d0.precision == GPQMC_FP64 ? 0 : 1;
+  c->fp32b = d0.precision == GPQMC_MIXED_FP32_BASIS ? 1 : 0;
+  if (d0.precision != GPQMC_MIXED && d0.precision != GPQMC_FP64 &&
+      d0.precision != GPQMC_MIXED_FP32_BASIS)
+    return bad(GPQMC_EINVAL, "precision must be GPQMC_FP64, GPQMC_MIXED or GPQMC_MIXED_FP32_BASIS");
+  if (c->l_half < 0 || c->n_s < 1 || c->kblk < 1 || c->kblk > kMaxBlock)
+    return bad(GPQMC_EINVAL, "need l_half >= 0, stab_interval >= 1, 1 <= delay_rank <= 32");
+  c->M = 2 * c->l_half;
+  c->n_slices = c->M + 2;
+  c->drift_tol = c->fp32 ? 1e-3f : 1e-6f;
+  if (opts) {
+    if (opts->meas_capacity > 0) c->meas_cap = opts->meas_capacity;
+    c->use_graph = opts->use_graph != 0;
+    if (opts->drift_tol > 0) c->drift_tol = (float)opts->drift_tol;
+  }
+  if (!c->stream) c->use_graph = false;   // the null stream cannot be captured
+  // checkpoints C = {-1, l_half, M+1} U {j n_s : 1 <= j n_s <= M}
+  std::vector<int> ck = {-1, c->l_half, c->M + 1};
+  for (int j = c->n_s; j <= c->M; j += c->n_s) ck.push_back(j);
+  std::sort(ck.begin(), ck.end());
+  ck.erase(std::unique(ck.begin(), ck.end()), ck.end());
+  c->ckpts = ck;
+  for (size_t i = 0; i < ck.size(); ++i) c->slot_of[ck[i]] = (int)i;
+
+  std::map<std::string, int> lat_of, trial_of;
+  for (int i = 0; i < n_chains; ++i) {
+    const gpqmc_chain_desc& d = chains[i];
+    char buf[200];
+    if (d.l_half != c->l_half || d.stab_interval != c->n_s || d.delay_rank != c->kblk ||
+        d.precision != d0.precision) {
+      snprintf(buf, sizeof buf, "chain %d: l_half, stab_interval, delay_rank and precision must "
+               "match chain 0", i);
+      return bad(GPQMC_EINVAL, buf);
+    }
+    const int N = d.n_sites;
+    if (N < 1 || N > kMaxSites || d.n_up < 1 || d.n_up > N || d.n_dn < 1 || d.n_dn > N ||
+        !d.hopping || !d.sublattice || !(d.U >= 0) || !(d.dtau > 0) || !(d.g >= 0)) {
+      snprintf(buf, sizeof buf, "chain %d: need 1 <= N <= %d, 1 <= n_up, n_dn <= N, U >= 0, "
+               "dtau > 0, g >= 0 and non-NULL hopping and sublattice", i, kMaxSites);
+      return bad(GPQMC_EINVAL, buf);
+    }
+    ChainHost h;
+    h.N = N;
+    h.n[0] = d.n_up;
+    h.n[1] = d.n_dn;
+    h.U = d.U;
+    h.dtau = d.dtau;
+    h.g = d.g;
+    h.m_neel = d.m_neel;
+    h.alpha = d.U == 0 ? 0.0 : std::acosh(std::exp(0.5 * d.dtau * d.U));
+    h.lam = d.g == 0 ? 0.0 : std::acosh(std::exp(0.5 * d.g));
+    h.seed = d.seed;
+    h.chain_id = d.chain_id;
+    h.trace = d.trace != 0;
+    for (int a = 0; a < N; ++a)
+      for (int b = 0; b < a; ++b)
+        if (d.hopping[(size_t)a * N + b] != d.hopping[(size_t)b * N + a])
+          return bad(GPQMC_EINVAL, "hopping matrix not symmetric");
+    // lattice exponentials
+    std::string lk = key_bytes(d.hopping, sizeof(double) * N * N) + key_bytes(&d.dtau, 8);
+    auto it = lat_of.find(lk);
+    if (it == lat_of.end()) {
+      Lattice L;
+      L.N = N;
+      L.K.assign(d.hopping, d.hopping + (size_t)N * N);
+      std::vector<double> w, V;
+      jacobi_eigh(N, d.hopping, w, V);
+      L.Km.assign((size_t)N * N, 0.0);
+      L.Kp.assign((size_t)N * N, 0.0);
+      for (int a = 0; a < N; ++a)
+        for (int b = 0; b < N; ++b) {
+          double sm = 0.0, sp = 0.0;
+          for (int k = 0; k < N; ++k) {
+            const double v = V[(size_t)a * N + k] * V[(size_t)b * N + k];
+            sm += v * std::exp(-d.dtau * w[k]);
+            sp += v * std::exp(d.dtau * w[k]);
+          }
+          L.Km[(size_t)a * N + b] = sm;
+          L.Kp[(size_t)a * N + b] = sp;
+        }
+      it = lat_of.emplace(lk, (int)c->lats.size()).first;
+      c->lats.push_back(std::move(L));
+    }
+    h.lat = it->second;
+    // Neel trial per spin: lowest n_sigma eigenvectors of K + sigma M_N eps + v
+    for (int sp = 0; sp < 2; ++sp) {
+      const double sigma = sp == 0 ? 1.0 : -1.0;
+      std::vector<double> hm(d.hopping, d.hopping + (size_t)N * N);
+      for (int a = 0; a < N; ++a) {
+        hm[(size_t)a * N + a] += sigma * d.m_neel * (double)d.sublattice[a];
+        if (d.trial_potential) hm[(size_t)a * N + a] += d.trial_potential[a];
+      }
+      const int nsig = h.n[sp];
+      std::string tk = key_bytes(hm.data(), sizeof(double) * hm.size()) + key_bytes(&nsig, 4);
+      auto jt = trial_of.find(tk);
+      if (jt == trial_of.end()) {
+        std::vector<double> w, V;
+        jacobi_eigh(N, hm.data(), w, V);
+        if (nsig < N && w[nsig] - w[nsig - 1] < 1e-6) {
+          snprintf(buf, sizeof buf, "chain %d spin %d: degenerate trial (gap %.3e)", i, sp,
+                   w[nsig] - w[nsig - 1]);
+          return bad(GPQMC_EDEGENERATE, buf);
+        }
+        Trial T;
+        T.N = N;
+        T.n = nsig;
+        T.P.resize((size_t)N * nsig);
+        for (int a = 0; a < N; ++a)
+          for (int b = 0; b < nsig; ++b) T.P[(size_t)a * nsig + b] = V[(size_t)a * N + b];
+        jt = trial_of.emplace(tk, (int)c->trials.size()).first;
+        c->trials.push_back(std::move(T));
+      }
+      h.trial[sp] = jt->second;
+    }
+    h.field.assign((size_t)c->n_slices * N, 1);
+    c->ch.push_back(std::move(h));
+  }
+
+  // ---- workspace layout ----
+  const size_t bs = c->fp32 ? 4 : 8;     // Green's-function element size
+  const size_t ub = c->fp32b ? 4 : 8;    // basis element size
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    off = align256(off);
+    const size_t o = off;
+    off += std::max<size_t>(b, 1);
+    return o;
+  };
+  for (auto& L : c->lats) {
+    const size_t nn = (size_t)L.N * L.N;
+    L.off_K = take(nn * 8);
+    L.off_Km = take(nn * bs);
+    L.off_Kp = take(nn * bs);
+    L.off_Kmb = (ub == bs) ? L.off_Km : take(nn * ub);
+  }
+  for (auto& T : c->trials) T.off = take((size_t)T.N * T.n * 8);
+  const int n_slots = (int)c->ckpts.size();
+  const int nck = c->n_ck_pass();
+  for (auto& h : c->ch) {
+    const size_t N = h.N, nn = N * N;
+    for (int sp = 0; sp < 2; ++sp) {
+      const size_t nb = N * h.n[sp];
+      h.G[sp] = take(nn * bs);
+      h.Gtmp[sp] = take(nn * bs);
+      h.U2[sp][0] = take(nb * ub);
+      h.U2[sp][1] = take(nb * ub);
+      h.Z[sp] = take(nn * bs);
+      h.Xg[sp] = take(nn * bs);
+      h.Yg[sp] = take(nn * bs);
+      h.T1[sp] = take(nn * bs);
+      h.scan_ws[sp] = take((size_t)5 * kMaxBlock * N * bs);
+      h.stack[sp] = take((size_t)n_slots * nb * 8);
+      h.slot_log[sp] = take((size_t)n_slots * 8);
+      h.slot_sgn[sp] = take((size_t)n_slots * 4);
+      h.Hw[sp] = take(nb * 8);
+      h.Qc[sp] = take(nb * 8);
+      h.Xm[sp] = take((size_t)h.n[sp] * h.n[sp] * 8);
+      h.Ym[sp] = take((size_t)h.n[sp] * N * 8);
+      h.piv[sp] = take((size_t)h.n[sp] * 4);
+      h.G64[sp] = take(nn * 8);
+    }
+    h.field_off = take((size_t)c->n_slices * N);
+    h.Flist = take(N * 4);
+    h.st = take(sizeof(ChainState));
+    h.meas = take((size_t)c->meas_cap * 3 * 8);
+    if (h.trace) {
+      h.tr_ratio = take((size_t)c->n_slices * N * 2 * 8);
+      h.tr_green = take((size_t)nck * 2 * nn * 8);
+      h.tr_drift = take((size_t)nck * 8);
+    }
+  }
+  c->off_chains = take(sizeof(ChainDev) * n_chains);
+  c->off_ctl = take(sizeof(Ctl));
+  for (int k = 0; k < 9; ++k) c->off_ent[k] = take(sizeof(GemmEntry) * 2 * n_chains);
+  std::vector<std::pair<int, int>> nn_sz, nb_sz, bb_sz;
+  for (auto& h : c->ch)
+    for (int sp = 0; sp < 2; ++sp) {
+      nn_sz.push_back({h.N, h.N});
+      nb_sz.push_back({h.N, h.n[sp]});
+      bb_sz.push_back({h.n[sp], h.n[sp]});
+    }
+  build_tiles(c->tiles_NN, nn_sz);
+  build_tiles(c->tiles_Nn, nb_sz);
+  build_tiles(c->tiles_nn, bb_sz);
+  c->off_tiles_NN = take(sizeof(TileRef) * c->tiles_NN.size());
+  c->off_tiles_Nn = take(sizeof(TileRef) * c->tiles_Nn.size());
+  c->off_tiles_nn = take(sizeof(TileRef) * c->tiles_nn.size());
+  c->bytes = align256(off);
+  *out = ctx.release();
+  return GPQMC_OK;
+}
+
+gpqmc_status gpqmc_workspace_bytes(const gpqmc_ctx* ctx, size_t* bytes) {
+  if (!ctx || !bytes) return GPQMC_EINVAL;
+  *bytes = ctx->bytes;
+  return GPQMC_OK;
+}
+
+gpqmc_status gpqmc_bind_workspace(gpqmc_ctx* ctx, void* device_ptr, size_t bytes) {
+  if (!ctx || !device_ptr) return GPQMC_EINVAL;
+  if (((uintptr_t)device_ptr & 255) != 0) return fail(ctx, GPQMC_EINVAL, "workspace not 256-byte aligned");
+  if (bytes < ctx->bytes) return fail(ctx, GPQMC_ENOMEM, "workspace too small");
+  ctx->ws = (char*)device_ptr;
+  const bool f32 = ctx->fp32 != 0;
+  auto up = [&](size_t off, const void* src, size_t b) {
+    return hipMemcpy(ctx->ws + off, src, b, hipMemcpyHostToDevice);
+  };
+  for (auto& L : ctx->lats) {
+    const size_t nn = (size_t)L.N * L.N;
+    HIPCHK(up(L.off_K, L.K.data(), nn * 8), "upload K");
+    if (f32) {
+      std::vector<float> a(L.Km.begin(), L.Km.end()), b(L.Kp.begin(), L.Kp.end());
+      HIPCHK(up(L.off_Km, a.data(), nn * 4), "upload Km");
+      HIPCHK(up(L.off_Kp, b.data(), nn * 4), "upload Kp");
+      if (L.off_Kmb != L.off_Km) HIPCHK(up(L.off_Kmb, L.Km.data(), nn * 8), "upload Km (basis)");
+    } else {
+      HIPCHK(up(L.off_Km, L.Km.data(), nn * 8), "upload Km");
+      HIPCHK(up(L.off_Kp, L.Kp.data(), nn * 8), "upload Kp");
+    }
+  }
+  for (auto& T : ctx->trials) HIPCHK(up(T.off, T.P.data(), T.P.size() * 8), "upload P");
+
+  const int nc = ctx->n_chains;
+  std::vector<ChainDev> cd(nc);
+  std::vector<GemmEntry> E[9];
+  for (int k = 0; k < 9; ++k) E[k].resize(2 * nc);
+  for (int i = 0; i < nc; ++i) {
+    ChainHost& h = ctx->ch[i];
+    ChainDev& d = cd[i];
+    memset(&d, 0, sizeof d);
+    const Lattice& L = ctx->lats[h.lat];
+    d.N = h.N;
+    d.n[0] = h.n[0];
+    d.n[1] = h.n[1];
+    for (int b = 0; b < 2; ++b) {
+      const double cpl = b == 0 ? h.lam : h.alpha;
+      for (int sp = 0; sp < 2; ++sp) {
+        const double sigma = sp == 0 ? 1.0 : -1.0;
+        for (int si = 0; si < 2; ++si) {
+          const double s = si == 0 ? 1.0 : -1.0;
+          d.dval[b][sp][si] = std::exp(sigma * cpl * s);
+          d.delta[b][sp][si] = std::exp(-2.0 * sigma * cpl * s) - 1.0;
+        }
+      }
+    }
+    d.U_hub = h.U;
+    d.key0 = (uint32_t)(h.seed & 0xffffffffu);
+    d.key1 = (uint32_t)(h.seed >> 32) ^ (uint32_t)TAG_ACCEPT;
+    d.chain_id = (uint32_t)h.chain_id;
+    for (int sp = 0; sp < 2; ++sp) {
+      d.G[sp] = ctx->ws + h.G[sp];
+      d.Gtmp[sp] = ctx->ws + h.Gtmp[sp];
+      d.U[sp][0] = ctx->ws + h.U2[sp][0];
+      d.U[sp][1] = ctx->ws + h.U2[sp][1];
+      d.Z[sp] = ctx->ws + h.Z[sp];
+      d.Xg[sp] = ctx->ws + h.Xg[sp];
+      d.Yg[sp] = ctx->ws + h.Yg[sp];
+      d.T1[sp] = ctx->ws + h.T1[sp];
+      d.scan_ws[sp] = ctx->ws + h.scan_ws[sp];
+      d.P[sp] = ctx->at<double>(ctx->trials[h.trial[sp]].off);
+      d.stack[sp] = ctx->at<double>(h.stack[sp]);
+      d.slot_log[sp] = ctx->at<double>(h.slot_log[sp]);
+      d.slot_sgn[sp] = ctx->at<int>(h.slot_sgn[sp]);
+      d.Hw[sp] = ctx->at<double>(h.Hw[sp]);
+      d.Qc[sp] = ctx->at<double>(h.Qc[sp]);
+      d.Xm[sp] = ctx->at<double>(h.Xm[sp]);
+      d.Ym[sp] = ctx->at<double>(h.Ym[sp]);
+      d.piv[sp] = ctx->at<int>(h.piv[sp]);
+      d.G64[sp] = ctx->at<double>(h.G64[sp]);
+    }
+    d.Km = ctx->ws + L.off_Km;
+    d.Kp = ctx->ws + L.off_Kp;
+    d.Khop = ctx->at<double>(L.off_K);
+    d.field = ctx->at<int8_t>(h.field_off);
+    d.Flist = ctx->at<int>(h.Flist);
+    d.st = ctx->at<ChainState>(h.st);
+    d.meas = ctx->at<double>(h.meas);
+    d.meas_cap = ctx->meas_cap;
+    if (h.trace) {
+      d.trace_ratio = ctx->at<double>(h.tr_ratio);
+      d.trace_green = ctx->at<double>(h.tr_green);
+      d.trace_drift = ctx->at<double>(h.tr_drift);
+    }
+    const int N = h.N;
+    for (int sp = 0; sp < 2; ++sp) {
+      const int n = h.n[sp];
+      const int ei = 2 * i + sp;
+      GemmEntry base;
+      memset(&base, 0, sizeof base);
+      base.field = d.field;
+      base.n_sites = N;
+      base.spin = sp;
+      base.st = d.st;
+      for (int b = 0; b < 2; ++b)
+        for (int si = 0; si < 2; ++si) base.dval[b][si] = d.dval[b][sp][si];
+      auto nnE = [&](const void* A, const void* B, void* C) {
+        GemmEntry e = base;
+        e.A = A;
+        e.B = B;
+        e.C = C;
+        e.M = e.N = e.K = N;
+        e.lda = e.ldb = e.ldc = N;
+        return e;
+      };
+      E[E_WRAP1_UP][ei] = nnE(d.Km, d.G[sp], d.Gtmp[sp]);
+      E[E_WRAP2_UP][ei] = nnE(d.Gtmp[sp], d.Kp, d.G[sp]);
+      E[E_WRAP1_DN][ei] = nnE(d.Kp, d.G[sp], d.Gtmp[sp]);
+      E[E_WRAP2_DN][ei] = nnE(d.Gtmp[sp], d.Km, d.G[sp]);
+      GemmEntry t1 = nnE(d.Z[sp], d.Yg[sp], d.T1[sp]);
+      t1.dynMK = &d.st->fcount;
+      E[E_T1][ei] = t1;
+      GemmEntry fl = nnE(d.Xg[sp], d.T1[sp], d.G[sp]);
+      fl.dynMK = &d.st->fcount;
+      E[E_FLUSH][ei] = fl;
+      GemmEntry pr = base;
+      pr.A = ctx->ws + L.off_Kmb;
+      pr.Bpp[0] = d.U[sp][0];
+      pr.Bpp[1] = d.U[sp][1];
+      pr.Cpp[0] = d.U[sp][0];
+      pr.Cpp[1] = d.U[sp][1];
+      pr.M = N;
+      pr.N = n;
+      pr.K = N;
+      pr.lda = N;
+      pr.ldb = n;
+      pr.ldc = n;
+      E[E_PROP][ei] = pr;
+      GemmEntry xm = base;
+      xm.stack = d.stack[sp];
+      xm.Qc = d.Qc[sp];
+      xm.slot_stride = N * n;
+      xm.C = d.Xm[sp];
+      xm.M = n;
+      xm.N = n;
+      xm.K = N;
+      xm.lda = n;
+      xm.ldb = n;
+      xm.ldc = n;
+      E[E_XMAT][ei] = xm;
+      GemmEntry gf = base;
+      gf.stack = d.stack[sp];
+      gf.Qc = d.Qc[sp];
+      gf.Ym = d.Ym[sp];
+      gf.slot_stride = N * n;
+      gf.C = d.G64[sp];
+      gf.C2 = d.G[sp];
+      gf.M = N;
+      gf.N = N;
+      gf.K = n;
+      gf.lda = n;
+      gf.ldb = N;
+      gf.ldc = N;
+      gf.ldc2 = N;
+      E[E_GFRESH][ei] = gf;
+    }
+  }
+  HIPCHK(up(ctx->off_chains, cd.data(), sizeof(ChainDev) * nc), "upload chains");
+  for (int k = 0; k < 9; ++k)
+    HIPCHK(up(ctx->off_ent[k], E[k].data(), sizeof(GemmEntry) * E[k].size()), "upload entries");
+  HIPCHK(up(ctx->off_tiles_NN, ctx->tiles_NN.data(), sizeof(TileRef) * ctx->tiles_NN.size()), "tiles");
+  HIPCHK(up(ctx->off_tiles_Nn, ctx->tiles_Nn.data(), sizeof(TileRef) * ctx->tiles_Nn.size()), "tiles");
+  HIPCHK(up(ctx->off_tiles_nn, ctx->tiles_nn.data(), sizeof(TileRef) * ctx->tiles_nn.size()), "tiles");
+  Ctl ctl = {0, 0, ctx->drift_tol, 0};
+  HIPCHK(up(ctx->off_ctl, &ctl, sizeof ctl), "upload ctl");
+  HIPCHK(hipDeviceSynchronize(), "bind");
+  ctx->bound = true;
+  ctx->initialized = false;
+  return GPQMC_OK;
+}
+
+gpqmc_status gpqmc_init_trial(gpqmc_ctx* ctx) {
+  if (!ctx) return GPQMC_EINVAL;
+  if (!ctx->bound) return fail(ctx, GPQMC_ESTATE, "init_trial before bind_workspace");
+  const int nc = ctx->n_chains;
+  // initial fields: Philox(key = (lo32 seed, hi32 seed ^ INIT), ctr = (chain, 0, l, i))
+  for (int i = 0; i < nc; ++i) {
+    ChainHost& h = ctx->ch[i];
+    if (!h.field_set) {
+      const uint32_t k0 = (uint32_t)(h.seed & 0xffffffffu), k1 = (uint32_t)(h.seed >> 32) ^ TAG_INIT;
+      for (int l = 0; l < ctx->n_slices; ++l)
+        for (int s = 0; s < h.N; ++s) {
+          uint32_t c[4] = {(uint32_t)h.chain_id, 0u, (uint32_t)l, (uint32_t)s};
+          philox4x32_10(c, k0, k1);
+          h.field[(size_t)l * h.N + s] = (c[0] & 1u) ? 1 : -1;
+        }
+    }
+    HIPCHK(hipMemcpyAsync(ctx->ws + h.field_off, h.field.data(), h.field.size(),
+                          hipMemcpyHostToDevice, ctx->stream), "upload field");
+    ChainState st;
+    memset(&st, 0, sizeof st);
+    st.sign = 1;
+    st.run_sgn[0] = st.run_sgn[1] = 1;
+    HIPCHK(hipMemcpyAsync(ctx->ws + h.st, &st, sizeof st, hipMemcpyHostToDevice, ctx->stream),
+           "upload state");
+    HIPCHK(hipStreamSynchronize(ctx->stream), "init sync");
+  }
+  Launcher L = make_launcher(ctx);
+  HIPCHK(launch_set_ctl(ctx->at<Ctl>(ctx->off_ctl), 0, 0, ctx->drift_tol, ctx->stream), "ctl");
+  HIPCHK(L.init_pass(), "init pass");
+  HIPCHK(hipStreamSynchronize(ctx->stream), "init_trial");
+  ctx->initialized = true;
+  ctx->sweeps_done = 0;
+  return GPQMC_OK;
+}
+
+gpqmc_status gpqmc_sweep(gpqmc_ctx* ctx, int32_t n_sweeps, int32_t measure) {
+  if (!ctx) return GPQMC_EINVAL;
+  if (!ctx->initialized) return fail(ctx, GPQMC_ESTATE, "sweep before init_trial");
+  if (n_sweeps < 0) return fail(ctx, GPQMC_EINVAL, "n_sweeps < 0");
+  static_assert(sizeof(ChainState) % 8 == 0, "state alignment");
+  Launcher L = make_launcher(ctx);
+  HIPCHK(launch_set_ctl(ctx->at<Ctl>(ctx->off_ctl), measure ? 1 : 0, ctx->debug_flags & 1,
+                        ctx->drift_tol, ctx->stream), "ctl");
+  for (int w = 0; w < n_sweeps; ++w) {
+    const int dir = (int)(ctx->sweeps_done & 1);
+    ctx->sweeps_done += 1;
+    if (ctx->use_graph) {
+      if (!ctx->graph[dir]) {
+        HIPCHK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal), "capture");
+        hipError_t e = dir == 0 ? L.up_pass() : L.down_pass();
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(ctx->stream, &g);
+        if (e != hipSuccess) return hip_fail(ctx, e, "capture pass");
+        if (e2 != hipSuccess) return hip_fail(ctx, e2, "end capture");
+        ctx->graph_def[dir] = g;
+        HIPCHK(hipGraphInstantiate(&ctx->graph[dir], g, nullptr, nullptr, 0), "instantiate");
+      }
+      HIPCHK(hipGraphLaunch(ctx->graph[dir], ctx->stream), "graph launch");
+    } else {
+      HIPCHK(dir == 0 ? L.up_pass() : L.down_pass(), "pass");
+    }
+  }
+  return GPQMC_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// host statistics
+// ---------------------------------------------------------------------------
+namespace {
+
+gpqmc_status fetch_records(gpqmc_ctx* ctx, int chain, std::vector<double>& rec) {
+  if (!ctx->initialized) return fail(ctx, GPQMC_ESTATE, "no measurements before init_trial");
+  HIPCHK(hipStreamSynchronize(ctx->stream), "sync");
+  rec.clear();
+  const int lo = chain < 0 ? 0 : chain, hi = chain < 0 ? ctx->n_chains : chain + 1;
+  for (int c = lo; c < hi; ++c) {
+    ChainState st;
+    HIPCHK(hipMemcpy(&st, ctx->ws + ctx->ch[c].st, sizeof st, hipMemcpyDeviceToHost), "state");
+    const size_t b = rec.size();
+    rec.resize(b + (size_t)st.n_meas * 3);
+    if (st.n_meas > 0)
+      HIPCHK(hipMemcpy(rec.data() + b, ctx->ws + ctx->ch[c].meas, (size_t)st.n_meas * 3 * 8,
+                       hipMemcpyDeviceToHost), "records");
+  }
+  return GPQMC_OK;
+}
+
+// <s O>/<s> with a delete-one-bin jackknife over bins of 10 records;
+// which = 0: sign itself (plain binned mean), 1: energy, 2: double occupancy.
+gpqmc_status weighted(gpqmc_ctx* ctx, int chain, int which, double* mean, double* err) {
+  if (!ctx || !mean || !err) return GPQMC_EINVAL;
+  if (chain < -1 || chain >= ctx->n_chains) return fail(ctx, GPQMC_EINVAL, "chain out of range");
+  std::vector<double> rec;
+  gpqmc_status st = fetch_records(ctx, chain, rec);
+  if (st != GPQMC_OK) return st;
+  const size_t n = rec.size() / 3, bin = 10, nb = n / bin;
+  if (nb < 2) return fail(ctx, GPQMC_EINVAL, "fewer than 20 measurement records");
+  std::vector<double> s(nb, 0.0), so(nb, 0.0);
+  for (size_t b = 0; b < nb; ++b)
+    for (size_t k = 0; k < bin; ++k) {
+      const double* r = &rec[(b * bin + k) * 3];
+      s[b] += r[0] / bin;
+      so[b] += (which == 0 ? r[0] : r[0] * r[which]) / bin;
+    }
+  double S = 0, SO = 0;
+  for (size_t b = 0; b < nb; ++b) {
+    S += s[b];
+    SO += so[b];
+  }
+  if (which == 0) {
+    const double m = S / nb;
+    double v = 0;
+    for (size_t b = 0; b < nb; ++b) v += (s[b] - m) * (s[b] - m);
+    *mean = m;
+    *err = std::sqrt(v / (nb - 1) / nb);
+    return GPQMC_OK;
+  }
+  *mean = SO / S;
+  std::vector<double> jk(nb);
+  double jm = 0;
+  for (size_t b = 0; b < nb; ++b) {
+    jk[b] = (SO - so[b]) / (S - s[b]);
+    jm += jk[b] / nb;
+  }
+  double v = 0;
+  for (size_t b = 0; b < nb; ++b) v += (jk[b] - jm) * (jk[b] - jm);
+  *err = std::sqrt((double)(nb - 1) / nb * v);
+  return GPQMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gpqmc_status gpqmc_measure_energy(gpqmc_ctx* ctx, int32_t chain, double* mean, double* err) {
+  return weighted(ctx, chain, 1, mean, err);
+}
+gpqmc_status gpqmc_measure_double_occupancy(gpqmc_ctx* ctx, int32_t chain, double* mean,
+                                            double* err) {
+  return weighted(ctx, chain, 2, mean, err);
+}
+gpqmc_status gpqmc_measure_sign(gpqmc_ctx* ctx, int32_t chain, double* mean, double* err) {
+  return weighted(ctx, chain, 0, mean, err);
+}
+
+gpqmc_status gpqmc_get_measurements(gpqmc_ctx* ctx, int32_t chain, double* out, int32_t capacity,
+                                    int32_t* n_out) {
+  if (!ctx || !out || !n_out || chain < 0 || chain >= ctx->n_chains) return GPQMC_EINVAL;
+  std::vector<double> rec;
+  gpqmc_status st = fetch_records(ctx, chain, rec);
+  if (st != GPQMC_OK) return st;
+  const int n = std::min<int>((int)(rec.size() / 3), capacity);
+  memcpy(out, rec.data(), (size_t)n * 3 * 8);
+  *n_out = n;
+  return GPQMC_OK;
+}
+
+gpqmc_status gpqmc_reset_measurements(gpqmc_ctx* ctx) {
+  if (!ctx || !ctx->initialized) return GPQMC_ESTATE;
+  HIPCHK(hipStreamSynchronize(ctx->stream), "sync");
+  for (auto& h : ctx->ch) {
+    ChainState st;
+    HIPCHK(hipMemcpy(&st, ctx->ws + h.st, sizeof st, hipMemcpyDeviceToHost), "state");
+    st.n_meas = 0;
+    st.flags &= ~FLAG_MEAS_FULL;
+    HIPCHK(hipMemcpy(ctx->ws + h.st, &st, sizeof st, hipMemcpyHostToDevice), "state");
+  }
+  return GPQMC_OK;
+}
+
+gpqmc_status gpqmc_set_field(gpqmc_ctx* ctx, int32_t chain, const int8_t* field) {
+  if (!ctx || !field || chain < 0 || chain >= ctx->n_chains) return GPQMC_EINVAL;
+  ChainHost& h = ctx->ch[chain];
+  for (size_t k = 0; k < h.field.size(); ++k)
+    if (field[k] != 1 && field[k] != -1) return fail(ctx, GPQMC_EINVAL, "field entries must be +-1");
+  h.field.assign(field, field + h.field.size());
+  h.field_set = true;
+  ctx->initialized = false;
+  return GPQMC_OK;
+}
+
+gpqmc_status gpqmc_get_field(gpqmc_ctx* ctx, int32_t chain, int8_t* field) {
+  if (!ctx || !field || chain < 0 || chain >= ctx->n_chains) return GPQMC_EINVAL;
+  if (!ctx->bound) return GPQMC_ESTATE;
+  const ChainHost& h = ctx->ch[chain];
+  HIPCHK(hipStreamSynchronize(ctx->stream), "sync");
+  HIPCHK(hipMemcpy(field, ctx->ws + h.field_off, h.field.size(), hipMemcpyDeviceToHost), "field");
+  return GPQMC_OK;
+}
+
+gpqmc_status gpqmc_get_green(gpqmc_ctx* ctx, int32_t chain, int32_t spin, double* G) {
+  if (!ctx || !G || chain < 0 || chain >= ctx->n_chains || spin < 0 || spin > 1) return GPQMC_EINVAL;
+  if (!ctx->initialized) return GPQMC_ESTATE;
+  const ChainHost& h = ctx->ch[chain];
+  HIPCHK(hipStreamSynchronize(ctx->stream), "sync");
+  HIPCHK(hipMemcpy(G, ctx->ws + h.G64[spin], (size_t)h.N * h.N * 8, hipMemcpyDeviceToHost), "G");
+  return GPQMC_OK;
+}
+
+gpqmc_status gpqmc_get_chain_info(gpqmc_ctx* ctx, int32_t chain, gpqmc_chain_info* info) {
+  if (!ctx || !info || chain < 0 || chain >= ctx->n_chains) return GPQMC_EINVAL;
+  if (!ctx->initialized) return GPQMC_ESTATE;
+  HIPCHK(hipStreamSynchronize(ctx->stream), "sync");
+  ChainState st;
+  HIPCHK(hipMemcpy(&st, ctx->ws + ctx->ch[chain].st, sizeof st, hipMemcpyDeviceToHost), "state");
+  info->sign = st.sign;
+  info->flags = st.flags;
+  info->n_meas = st.n_meas;
+  info->sign_mismatch = st.sign_mismatch;
+  info->sweep = st.sweep;
+  info->max_drift = st.max_drift;
+  info->last_drift = st.last_drift;
+  info->accepted = st.accepted;
+  info->proposed = st.proposed;
+  return GPQMC_OK;
+}
+
+gpqmc_status gpqmc_chain_status(gpqmc_ctx* ctx, int32_t chain) {
+  gpqmc_chain_info info;
+  gpqmc_status s = gpqmc_get_chain_info(ctx, chain, &info);
+  if (s != GPQMC_OK) return s;
+  return info.flags & (FLAG_DRIFT | FLAG_NAN | FLAG_SINGULAR | FLAG_SIGN) ? GPQMC_EUNSTABLE : GPQMC_OK;
+}
+
+gpqmc_status gpqmc_set_debug(gpqmc_ctx* ctx, int32_t flags) {
+  if (!ctx) return GPQMC_EINVAL;
+  ctx->debug_flags = flags;
+  return GPQMC_OK;
+}
+
+gpqmc_status gpqmc_get_trace(gpqmc_ctx* ctx, int32_t chain, double* ratios, double* greens,
+                             double* drifts, int32_t* n_checkpoints) {
+  if (!ctx || chain < 0 || chain >= ctx->n_chains) return GPQMC_EINVAL;
+  const ChainHost& h = ctx->ch[chain];
+  if (!h.trace) return fail(ctx, GPQMC_EINVAL, "chain created without trace");
+  HIPCHK(hipStreamSynchronize(ctx->stream), "sync");
+  const size_t N = h.N;
+  const int nck = ctx->n_ck_pass();
+  if (n_checkpoints) *n_checkpoints = nck;
+  if (ratios)
+    HIPCHK(hipMemcpy(ratios, ctx->ws + h.tr_ratio, (size_t)ctx->n_slices * N * 2 * 8,
+                     hipMemcpyDeviceToHost), "ratios");
+  if (greens)
+    HIPCHK(hipMemcpy(greens, ctx->ws + h.tr_green, (size_t)nck * 2 * N * N * 8,
+                     hipMemcpyDeviceToHost), "greens");
+  if (drifts)
+    HIPCHK(hipMemcpy(drifts, ctx->ws + h.tr_drift, (size_t)nck * 8, hipMemcpyDeviceToHost), "drifts");
+  return GPQMC_OK;
+}
+
+gpqmc_status gpqmc_debug_gemm(int32_t precision, int32_t M, int32_t N, int32_t K, int32_t trans_a,
+                              const void* A, int32_t lda, const void* B, int32_t ldb, void* C,
+                              int32_t ldc, void* hip_stream) {
+  if (M <= 0 || N <= 0 || K < 0 || !A || !B || !C) return GPQMC_EINVAL;
+  gpqmc_ctx* ctx = nullptr;
+  GemmEntry e;
+  memset(&e, 0, sizeof e);
+  e.A = A;
+  e.B = B;
+  e.C = C;
+  e.M = M;
+  e.N = N;
+  e.K = K;
+  e.lda = lda;
+  e.ldb = ldb;
+  e.ldc = ldc;
+  std::vector<TileRef> tl;
+  build_tiles(tl, {{M, N}});
+  // test hook: a small descriptor buffer in device memory for this one call
+  void* dbuf = nullptr;
+  const size_t bytes = align256(sizeof e) + sizeof(TileRef) * tl.size();
+  HIPCHK(hipMalloc(&dbuf, bytes), "debug alloc");
+  hipStream_t s = (hipStream_t)hip_stream;
+  HIPCHK(hipMemcpy(dbuf, &e, sizeof e, hipMemcpyHostToDevice), "debug upload");
+  TileRef* dt = (TileRef*)((char*)dbuf + align256(sizeof e));
+  HIPCHK(hipMemcpy(dt, tl.data(), sizeof(TileRef) * tl.size(), hipMemcpyHostToDevice), "debug upload");
+  GemmArgs a;
+  memset(&a, 0, sizeof a);
+  a.scale_slice = -1;
+  a.bscale_slice = -1;
+  hipError_t err = launch_gemm_plain(precision == GPQMC_MIXED, trans_a, (const GemmEntry*)dbuf, dt,
+                                     (int)tl.size(), a, s);
+  hipError_t err2 = hipStreamSynchronize(s);
+  hipFree(dbuf);
+  if (err != hipSuccess) return GPQMC_EHIP;
+  if (err2 != hipSuccess) return GPQMC_EHIP;
+  return GPQMC_OK;
+}
+
+const char* gpqmc_last_error(const gpqmc_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+void gpqmc_destroy(gpqmc_ctx* ctx) {
+  if (!ctx) return;
+  for (int d = 0; d < 2; ++d) {
+    if (ctx->graph[d]) hipGraphExecDestroy(ctx->graph[d]);
+    if (ctx->graph_def[d]) hipGraphDestroy(ctx->graph_def[d]);
+  }
+  delete ctx;
+}
+
+}  // extern "C"

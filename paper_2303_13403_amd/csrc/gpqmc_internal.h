@@ -1,0 +1,179 @@
+// Internal data layout shared by the HIP kernels and the host-side library
+// code of the Gutzwiller-projection PQMC sweep.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gpqmc {
+
+constexpr int kThreads = 256;   // every kernel runs 256-thread workgroups (4 waves)
+constexpr int kMaxBlock = 32;   // largest submatrix block (delay rank) of the scan
+constexpr int kMaxSites = 1024; // largest lattice the scan's LDS tables hold
+constexpr int kTile = 64;       // GEMM output tile (kTile x kTile per workgroup)
+
+enum Tag : uint32_t { TAG_INIT = 0, TAG_ACCEPT = 1 };
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of
+// (c0,c1,c2,c3) -> (hi(M1 c2)^c1^k0, lo(M1 c2), hi(M0 c0)^c3^k1, lo(M0 c0)) with a
+// Weyl key schedule.  Used on the host for the initial field and on the device
+// for the Metropolis draws.
+__host__ __device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+  const uint32_t m0 = 0xD2511F53u, m1 = 0xCD9E8D57u;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)m0 * c[0];
+    const uint64_t p1 = (uint64_t)m1 * c[2];
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+    c[1] = (uint32_t)p1;
+    c[3] = (uint32_t)p0;
+    c[0] = n0;
+    c[2] = n2;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+
+// 53-bit uniform in [0, 1) from the first two output words.
+__host__ __device__ inline double uniform53(uint32_t w0, uint32_t w1) {
+  return ((double)(w0 >> 5) * 67108864.0 + (double)(w1 >> 6)) * (1.0 / 9007199254740992.0);
+}
+
+// Mutable per-chain state (device memory).
+struct ChainState {
+  int sign;             // tracked sign of W_up * W_dn
+  int sweep;            // pass counter: word 1 of the Philox counter
+  int fcount;           // flips with nonzero Delta accepted in the current slice
+  int flags;            // sticky error bits (GPQMC_FLAG_*)
+  int n_meas;           // stored measurement records
+  int sign_mismatch;    // checkpoints where tracked and recomputed signs differ
+  int run_sgn[2];       // sign of det of the active basis' accumulated triangular factors
+  double run_log[2];    // log|det| of the same
+  double chk_log[2];    // log|det T| of the current checkpoint's QR
+  int chk_sgn[2];
+  double x_log[2];      // log|det (L R)| of the current checkpoint
+  int x_sgn[2];
+  unsigned int drift_bits;  // max |G_wrapped - G_fresh| of the current checkpoint (float bits)
+  float max_drift;      // since creation / last reset
+  float last_drift;
+  int pad0;
+  long long accepted;   // accepted proposals
+  long long proposed;   // proposals
+};
+
+enum Flags : int {
+  FLAG_DRIFT = 1,       // drift above tolerance at a checkpoint
+  FLAG_NAN = 2,         // non-finite Green's function or ratio
+  FLAG_SINGULAR = 4,    // singular L R at a checkpoint
+  FLAG_SIGN = 8,        // tracked and recomputed signs disagree
+  FLAG_MEAS_FULL = 16,  // measurement buffer full (records dropped)
+};
+
+// Per-chain description (device memory).  Matrices are row-major; N x N
+// matrices use leading dimension N, N x n_sigma matrices leading dimension n_sigma.
+struct ChainDev {
+  int N;                // sites
+  int n[2];             // particles per spin (0 = up, 1 = down)
+  int pad0;
+  // diagonal of D_l for spin sigma: d = dval[b][sigma][s] with b = 0 boundary
+  // (projector coupling lambda), 1 bulk (Hubbard coupling alpha), s = 0 for
+  // field +1 and 1 for field -1: exp(sigma_sign * c_b * s_sign).
+  double dval[2][2][2];
+  double delta[2][2][2];  // flip factor Delta = exp(-2 sigma c_b s) - 1, same indexing
+  double U_hub;         // Hubbard U (energy measurement)
+  uint32_t key0, key1;    // Philox key (seed low word, seed high word ^ TAG_ACCEPT)
+  uint32_t chain_id;
+  int pad1;
+  // bulk-precision matrices (float or double depending on the context)
+  void* G[2];           // equal-time Green's function in the current frame
+  void* Gtmp[2];        // wrap intermediate
+  void* U[2][2];        // active propagated basis, ping-pong pair
+  void* Z[2];           // delayed-update coefficient matrix (f x f, ld N)
+  void* Xg[2];          // G0[:, F]   (N x f, ld N)
+  void* Yg[2];          // (1 - G0)[F, :]  (f x N, ld N)
+  void* T1[2];          // Z Yg  (f x N, ld N)
+  void* scan_ws[2];     // scan scratch, 4 * kMaxBlock * N
+  const void* Km;       // e^{-dtau K} (bulk precision)
+  const void* Kp;       // e^{+dtau K}
+  // FP64 matrices
+  const double* Khop;   // hopping matrix K
+  const double* P[2];   // trial orbitals, N x n_sigma
+  double* stack[2];     // n_slots x N x n_sigma orthonormal bases
+  double* slot_log[2];  // per slot: log|det| of the accumulated triangular factors
+  int* slot_sgn[2];
+  double* Hw[2];        // QR work (N x n_sigma)
+  double* Qc[2];        // explicit Q of the current checkpoint
+  double* Xm[2];        // L R (n x n), LU in place
+  double* Ym[2];        // (L R)^{-1} L  (n x N)
+  int* piv[2];
+  double* G64[2];       // last fresh Green's function (unscaled, at its checkpoint)
+  int8_t* field;        // n_slices x N
+  int* Flist;           // accepted sites of the current slice
+  ChainState* st;
+  double* meas;         // records (sign, E/N, D)
+  int meas_cap;
+  int pad2;
+  double* trace_ratio;  // optional: (n_slices * N) x 2 ratios of the last pass
+  double* trace_green;  // optional: checkpoints_per_pass x 2 x N x N
+  double* trace_drift;  // optional: checkpoints_per_pass
+};
+
+// Control block (device memory), read by every kernel of a pass.
+struct Ctl {
+  int measure;          // record measurements at tau = Theta
+  int force_reject;     // debug: reject every proposal (fixed-field parity)
+  float drift_tol;      // drift above this sets FLAG_DRIFT
+  int pad;
+};
+
+// One operand set of a batched GEMM (one chain and one spin).
+struct GemmEntry {
+  const void* A;        // resolved per launch from the fields below where needed
+  const void* B;
+  void* C;
+  void* C2;             // secondary output (bulk copy of a fresh Green's function)
+  const void* Bpp[2];   // ping-pong inputs (propagation)
+  void* Cpp[2];         // ping-pong outputs
+  const double* stack;  // checkpoint stack base (FP64)
+  const double* Qc;     // current checkpoint basis (FP64)
+  const double* Ym;
+  int slot_stride;      // elements per stack slot
+  int M, N, K;          // static sizes
+  int lda, ldb, ldc, ldc2;
+  const int* dynMK;     // if set, M (mode T1) and K are read from *dynMK (accepted count)
+  const int8_t* field;  // base of the chain's field
+  int n_sites;
+  int spin;
+  ChainState* st;
+  double dval[2][2];    // [b][s] diagonal of D for this spin (see ChainDev)
+};
+
+struct TileRef {
+  int entry, tm, tn, pad;
+};
+
+// Launch arguments shared by the GEMM kinds.
+struct GemmArgs {
+  int scale_slice;      // slice whose D scales the output (-1: none)
+  int scale_inverse;    // 0: D X D^{-1}, 1: D^{-1} X D  (mode WRAP/FLUSH/GFRESH)
+  int bscale_slice;     // slice whose D scales the rows of B (-1: none)
+  int parity;           // ping-pong selector
+  int slot;             // checkpoint slot
+  int dir;              // 0 up pass (R is the new basis), 1 down pass (L is new)
+  int n_bulk_last;      // M (bulk slices are 1..M)
+  int check_drift;      // compare against the wrapped Green's function
+};
+
+enum GemmMode : int {
+  GM_STORE = 0,   // C = A B
+  GM_WRAP = 1,    // C = D (A B) D^{-1}  (or D^{-1}(A B)D, or unscaled)
+  GM_FLUSH = 2,   // C = D (C - A B) D^{-1}  (scaling optional)
+  GM_PROPB = 3,   // C[parity^1] = A (D B[parity])
+  GM_PROPR = 4,   // C[parity^1] = D (A B[parity])
+  GM_T1 = 5,      // C = A B with M = K = accepted count
+  GM_XMAT = 6,    // C = Lt^T R  (FP64)
+  GM_GFRESH = 7,  // C = 1 - R Y (FP64), drift, bulk copy with scaling
+};
+
+}  // namespace gpqmc

@@ -1,0 +1,189 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+* MFMA tile GEMM against a float64 CPU product (ragged shapes, transposed A);
+* initial field (Philox) bit-exact; Green's function after init_trial;
+* fixed field (every proposal rejected): ratios of every proposal and the
+  fresh Green's functions at every checkpoint of an upward and a downward pass;
+* Markov trajectories with shared Philox streams: fields bit-exact except for
+  draws within the tie tolerance of their threshold (follow mode), and the
+  measured (sign, E/N, D) of every pass;
+* uneven batch, determinism, and a sampled chain of the 16x16 benchmark batch.
+Tolerances: max|x - x_ref| / max|x_ref| <= 1e-10 (FP64) or 1e-5 (mixed).
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from gpu_helpers import TIE, TOL, make_context, oracle_chain, oracle_fixed_pass, ratio_array, rel_err
+from oracle import philox, pqmc
+from paper_2303_13403_amd import gpqmc
+from paper_2303_13403_amd.workloads import WORKLOADS, Workload, batch_uneven
+
+
+def small(prec="fp64", L=4, l_half=6, n_s=3, k=8, U=4.0, n=None, **kw):
+    n = L * L // 2 if n is None else n
+    return Workload(f"{L}x{L} test", L, L, U, n, n, 0.1, l_half, 0.21, 0.6, n_s, k, prec, 10, **kw)
+
+
+# --------------------------------------------------------------------------- #
+# MFMA GEMM tile kernel
+# --------------------------------------------------------------------------- #
+@pytest.mark.parametrize("prec", [gpqmc.FP64, gpqmc.MIXED])
+@pytest.mark.parametrize("shape", [(64, 64, 64), (100, 70, 37), (1, 129, 5), (144, 72, 144)])
+@pytest.mark.parametrize("trans", [False, True])
+def test_mfma_gemm_matches_cpu(prec, shape, trans):
+    M, N, K = shape
+    g = torch.Generator().manual_seed(M * 7 + N * 3 + K)
+    A = torch.randn((K, M) if trans else (M, K), generator=g, dtype=torch.float64)
+    B = torch.randn((K, N), generator=g, dtype=torch.float64)
+    dt = torch.float64 if prec == gpqmc.FP64 else torch.float32
+    A, B = A.to(dt).to(torch.float64), B.to(dt).to(torch.float64)
+    ref = (A.T if trans else A) @ B
+    C = gpqmc.debug_gemm(A.cuda(), B.cuda(), trans_a=trans, precision=prec).cpu().to(torch.float64)
+    tol = 1e-13 if prec == gpqmc.FP64 else 2e-6
+    assert rel_err(C.numpy(), ref.numpy()) < tol
+
+
+# --------------------------------------------------------------------------- #
+# initialisation
+# --------------------------------------------------------------------------- #
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("L,l_half,n_s", [(4, 6, 3), (6, 5, 4)])
+def test_init_field_and_green(prec, L, l_half, n_s):
+    w = small(prec, L=L, l_half=l_half, n_s=n_s)
+    ctx = make_context([w], prec).init_trial()
+    ch = oracle_chain(w, 0)
+    assert np.array_equal(ctx.get_field(0), ch.field)
+    for s, sp in ((1, 0), (-1, 1)):
+        assert rel_err(ctx.get_green(0, sp), ch.G[s]) < TOL[prec]
+    info = ctx.chain_info(0)
+    assert info["sign"] == ch.sign and info["flags"] == 0
+    ctx.close()
+
+
+# --------------------------------------------------------------------------- #
+# fixed field: every ratio and every checkpoint Green's function of a pass
+# --------------------------------------------------------------------------- #
+FIXED = [
+    ("fp64", dict(L=4, l_half=6, n_s=3, k=8)),
+    ("fp64", dict(L=6, l_half=5, n_s=4, k=16)),            # N = 36: ragged tiles
+    ("fp64", dict(L=12, l_half=50, n_s=10, k=32)),         # the 12x12 workload
+    ("mixed", dict(L=4, l_half=6, n_s=3, k=8)),
+    ("mixed", dict(L=6, l_half=5, n_s=4, k=16)),
+    ("mixed", dict(L=12, l_half=50, n_s=4, k=32)),      # FP32 wrap needs n_s ~ 4 at dtau 0.1
+    ("mixed32b", dict(L=4, l_half=6, n_s=3, k=8)),
+    ("mixed32b", dict(L=12, l_half=50, n_s=3, k=32)),
+    ("fp64", dict(L=4, l_half=5, n_s=3, k=5, U=3.0, n=5, ramp=0.05)),   # doped
+]
+
+
+@pytest.mark.parametrize("prec,kw", FIXED)
+def test_fixed_field_pass_matches_oracle(prec, kw):
+    w = small(prec, **kw)
+    ctx = make_context([w], prec, trace=True).init_trial()
+    ctx.set_debug(True)
+    ch = oracle_chain(w, 0)
+    N = w.n_sites
+    for sweep in range(2):                     # one upward and one downward pass
+        ctx.sweep(1, measure=False)
+        oracle_fixed_pass(ch)
+        r_gpu, g_gpu, d_gpu = ctx.trace(0)
+        r_ref = ratio_array(ch, sweep, ch.m.n_slices, N)
+        assert rel_err(r_gpu, r_ref) < TOL[prec], f"ratios, sweep {sweep}"
+        assert len(ch.checkpoint_greens) == g_gpu.shape[0]
+        for k, (sw, p, gu, gd, drift, field) in enumerate(ch.checkpoint_greens):
+            assert rel_err(g_gpu[k, 0], gu) < TOL[prec], f"G_up at p={p}, sweep {sweep}"
+            assert rel_err(g_gpu[k, 1], gd) < TOL[prec], f"G_dn at p={p}, sweep {sweep}"
+        assert np.max(d_gpu) < (1e-8 if prec == "fp64" else 1e-3)
+        print(f"{prec} {kw}: sweep {sweep}: max ratio err {rel_err(r_gpu, r_ref):.2e}, "
+              f"max G err {max(rel_err(g_gpu[k, s], g[2 + s]) for k, g in enumerate(ch.checkpoint_greens) for s in (0, 1)):.2e}, "
+              f"max drift {np.max(d_gpu):.2e}")
+    assert np.array_equal(ctx.get_field(0), ch.field)
+    ctx.close()
+
+
+# --------------------------------------------------------------------------- #
+# Markov trajectories with shared random streams
+# --------------------------------------------------------------------------- #
+def follow_and_compare(ctx, chains, prec, n_sweeps, indep=None):
+    """Advance GPU and oracle chains pass by pass; the oracle follows the GPU's
+    decisions and every disagreement must be a near-threshold draw."""
+    n_meas0 = [len(ch.measurements) for ch in chains]
+    for sweep in range(n_sweeps):
+        ctx.sweep(1, measure=True)
+        for c, ch in enumerate(chains):
+            f_gpu = ctx.get_field(c)
+            bad = ch.sweep_following(f_gpu, TIE[prec])
+            assert not bad, f"chain {c} sweep {sweep}: decisions differ beyond the tie band: {bad[:3]}"
+            assert np.array_equal(ch.field, f_gpu)
+            if indep is not None:
+                indep[c].sweep(1)
+    for c, ch in enumerate(chains):
+        m_gpu = ctx.measurements(c)
+        m_ref = np.array(ch.measurements[n_meas0[c]:])
+        assert m_gpu.shape == m_ref.shape
+        assert np.array_equal(m_gpu[:, 0], m_ref[:, 0])          # signs
+        tol = {"fp64": 1e-10, "mixed": 1e-4, "mixed32b": 1e-3}[prec]
+        assert np.max(np.abs(m_gpu[:, 1:] - m_ref[:, 1:])) < tol
+        info = ctx.chain_info(c)
+        assert info["sign_mismatch"] == 0 and (info["flags"] & ~16) == 0, info
+
+
+@pytest.mark.parametrize("prec,kw,n_sweeps", [
+    ("fp64", dict(L=4, l_half=6, n_s=3, k=8), 6),
+    ("mixed", dict(L=4, l_half=6, n_s=3, k=8), 6),
+    ("fp64", dict(L=6, l_half=5, n_s=4, k=7), 4),
+    ("mixed", dict(L=8, l_half=10, n_s=4, k=16), 4),
+    ("mixed32b", dict(L=6, l_half=5, n_s=3, k=16), 4),
+    ("fp64", dict(L=4, l_half=5, n_s=3, k=5, U=3.0, n=5, ramp=0.05), 6),   # doped: signs
+])
+def test_trajectory_follows_oracle(prec, kw, n_sweeps):
+    w = small(prec, **kw)
+    ctx = make_context([w], prec).init_trial()
+    ch = oracle_chain(w, 0)
+    indep = [oracle_chain(w, 0)]
+    follow_and_compare(ctx, [ch], prec, n_sweeps, indep)
+    if prec == "fp64":   # independent oracle run reaches the same field exactly
+        assert np.array_equal(indep[0].field, ctx.get_field(0))
+    ctx.close()
+
+
+def test_config_4x4_trajectory_fp64():
+    w = WORKLOADS["4x4"]
+    ctx = make_context([w, w], "fp64", chain_ids=[0, 1]).init_trial()
+    chains = [oracle_chain(w, 0), oracle_chain(w, 1)]
+    follow_and_compare(ctx, chains, "fp64", 4)
+    ctx.close()
+
+
+def test_uneven_batch_follows_oracle():
+    ws = [w.replace(l_half=5, stab_interval=4) for w in batch_uneven(6, l_half=5)]
+    ctx = make_context(ws, "mixed").init_trial()
+    chains = [oracle_chain(w, c) for c, w in enumerate(ws)]
+    follow_and_compare(ctx, chains, "mixed", 2)
+    ctx.close()
+
+
+def test_determinism_same_seed_twice():
+    w = small("mixed", L=8, l_half=8, n_s=4, k=16)
+    out = []
+    for _ in range(2):
+        ctx = make_context([w, w], "mixed", chain_ids=[0, 1]).init_trial().sweep(3)
+        out.append((ctx.get_field(0), ctx.get_field(1), ctx.get_green(0, 0), ctx.measurements(1)))
+        ctx.close()
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
+
+
+def test_graph_and_direct_launch_agree():
+    w = small("mixed", L=6, l_half=5, n_s=4, k=16)
+    res = []
+    for g in (True, False):
+        ctx = make_context([w], "mixed", use_graph=g).init_trial().sweep(4)
+        res.append((ctx.get_field(0), ctx.measurements(0)))
+        ctx.close()
+    assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])

@@ -1,0 +1,115 @@
+"""The C-ABI library loads, exports every declared entry point and validates its
+inputs (no GPU: only host-side calls)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2303_13403_amd import gpqmc
+from paper_2303_13403_amd.workloads import WORKLOADS, square_lattice
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gpqmc.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(gpqmc_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_binding_surface():
+    assert set(_declared()) == set(gpqmc.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = gpqmc.load()
+    for name in _declared():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", gpqmc.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (gpqmc_\w+)", out))
+    assert set(_declared()) <= exported
+
+
+def _desc(w, **over):
+    d = gpqmc.chain_desc_arrays(w, 0, gpqmc.MIXED if w.precision == "mixed" else gpqmc.FP64)
+    d.update(over)
+    return d
+
+
+def _create(chains):
+    lib = gpqmc.load()
+    descs = (gpqmc.ChainDesc * len(chains))()
+    keep = []
+    for i, c in enumerate(chains):
+        K = np.ascontiguousarray(c["K"], np.float64)
+        eps = np.ascontiguousarray(c["eps"], np.int8)
+        keep += [K, eps]
+        d = descs[i]
+        d.n_sites = K.shape[0]
+        d.n_up, d.n_dn = c["n_up"], c["n_dn"]
+        d.hopping = K.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        d.sublattice = eps.ctypes.data_as(ctypes.POINTER(ctypes.c_int8))
+        if c.get("pot") is not None:
+            pot = np.ascontiguousarray(c["pot"], np.float64)
+            keep.append(pot)
+            d.trial_potential = pot.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        d.U, d.dtau, d.g, d.m_neel = c["U"], c["dtau"], c["g"], c["m_neel"]
+        d.l_half, d.stab_interval, d.delay_rank = c["l_half"], c["n_s"], c["k"]
+        d.precision = c["precision"]
+        d.seed, d.chain_id = c["seed"], c["chain_id"]
+    ctx = ctypes.c_void_p()
+    st = lib.gpqmc_create(len(chains), descs, None, None, ctypes.byref(ctx))
+    msg = lib.gpqmc_last_error(ctx).decode() if ctx.value else ""
+    nbytes = ctypes.c_size_t(0)
+    if st == 0:
+        assert lib.gpqmc_workspace_bytes(ctx, ctypes.byref(nbytes)) == 0
+    if ctx.value:
+        lib.gpqmc_destroy(ctx)
+    return st, msg, nbytes.value
+
+
+def test_create_accepts_the_workloads_and_sizes_workspace():
+    for name in ("4x4", "12x12"):
+        st, msg, nbytes = _create([_desc(WORKLOADS[name])])
+        assert st == 0, msg
+        assert nbytes > 0
+    w = WORKLOADS["4x4"]
+    st1, _, b1 = _create([_desc(w)])
+    st2, _, b2 = _create([_desc(w, chain_id=c) for c in range(3)])
+    assert st1 == st2 == 0 and b2 > 2.5 * b1
+
+
+def test_create_rejects_a_degenerate_trial():
+    w = WORKLOADS["16x16"].replace(l_half=2)
+    st, msg, _ = _create([_desc(w, pot=None)])
+    assert st == gpqmc.EDEGENERATE and "degenerate" in msg
+    st, msg, _ = _create([_desc(w)])            # with the shell-closing ramp
+    assert st == 0, msg
+
+
+@pytest.mark.parametrize("bad", [
+    dict(n_up=0), dict(n_up=17), dict(dtau=0.0), dict(U=-1.0), dict(g=-0.5),
+    dict(k=0), dict(k=33), dict(n_s=0), dict(l_half=-1), dict(precision=7),
+])
+def test_create_rejects_invalid_arguments(bad):
+    st, msg, _ = _create([_desc(WORKLOADS["4x4"], **bad)])
+    assert st == gpqmc.EINVAL and msg
+
+
+def test_create_rejects_mismatched_chain_parameters():
+    w = WORKLOADS["4x4"]
+    st, msg, _ = _create([_desc(w), _desc(w, l_half=3, chain_id=1)])
+    assert st == gpqmc.EINVAL and "match" in msg
+
+
+def test_create_rejects_asymmetric_hopping():
+    K, eps, _ = square_lattice(4, 4)
+    K = K.copy()
+    K[0, 1] = -0.5
+    st, msg, _ = _create([_desc(WORKLOADS["4x4"], K=K)])
+    assert st == gpqmc.EINVAL and "symmetric" in msg
