@@ -1,0 +1,209 @@
+"""Throughput benchmark of the Gutzwiller-projection PQMC sweep on one MI355X.
+
+Workload (the configuration the headline metric is quoted on): 16x16 periodic
+Hubbard model, t = 1, U = 3.5, 112 + 112 electrons (<n> = 0.875), dtau = 0.1,
+Theta = 10 (l_half = 100 slices per side, M + 2 = 202 slices), Neel trial
+M_N = 0.07 with Gutzwiller g = 0.55 and the trial-only shell-closing ramp,
+mixed precision (FP32-MFMA Green's-function work, FP64 bases and
+stabilisation), a batch of independent chains.
+
+One step = one sweep (one pass over all 202 slices) of every chain of the
+batch; value = HS-field updates (proposals) per second over the timed steps,
+inputs resident in HBM.  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--chains B] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "HS-field updates/sec at 16×16, L=100; mixed vs FP64 GPU at 1e-5 rel G error"
+UNIT = "HS-field updates/s"
+PEAK_FP32_MFMA = 157.3e12   # MI355X dense FP32 matrix, FLOP/s
+PEAK_FP64_MFMA = 78.6e12
+KERNEL_SRC = os.path.join(ROOT, "paper_2303_13403_amd", "csrc", "gpqmc_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_wrap_gemm_16x16_b512.txt")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_sha() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def read_traffic(chains: int):
+    """HBM bytes per launch of the wrap GEMM from the committed PMC summary, if
+    it was taken on the current kernel source and the same batch size."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha") != kernel_sha() or int(kv.get("chains", -1)) != chains:
+        return None
+    return float(kv["hbm_bytes_per_launch"])
+
+
+def workload(args):
+    from paper_2303_13403_amd.workloads import WORKLOADS
+
+    return WORKLOADS["16x16"].replace(stab_interval=args.ns, delay_rank=args.k)
+
+
+def run_gpu(args, precision_name, steps, warmup):
+    import torch
+
+    from paper_2303_13403_amd import gpqmc
+
+    prec = {"mixed": gpqmc.MIXED, "fp64": gpqmc.FP64, "mixed32b": gpqmc.MIXED_FP32_BASIS}[precision_name]
+    w = workload(args)
+    t0 = time.time()
+    chains = [gpqmc.chain_desc_arrays(w, c, prec) for c in range(args.chains)]
+    ctx = gpqmc.Context(chains, device="cuda:0", meas_capacity=max(64, steps + warmup + 4))
+    ctx.init_trial()
+    log(f"[{precision_name}] context + init_trial: {time.time() - t0:.1f} s, "
+        f"workspace {ctx.workspace_bytes / 2**30:.2f} GiB")
+    ctx.sweep(warmup, measure=True)
+    ctx.synchronize()
+    log(f"[{precision_name}] warmup {warmup} sweeps done")
+    acc0 = sum(ctx.chain_info(c)["accepted"] for c in range(args.chains))
+    prop0 = sum(ctx.chain_info(c)["proposed"] for c in range(args.chains))
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(ctx.stream)
+    w0 = time.time()
+    ctx.sweep(steps, measure=True)
+    ev1.record(ctx.stream)
+    torch.cuda.synchronize()
+    wall = time.time() - w0
+    ms = ev0.elapsed_time(ev1)
+    infos = [ctx.chain_info(c) for c in range(args.chains)]
+    acc = sum(i["accepted"] for i in infos) - acc0
+    prop = sum(i["proposed"] for i in infos) - prop0
+    n_updates = (2 * w.l_half + 2) * w.n_sites * args.chains * steps
+    assert prop == n_updates, (prop, n_updates)
+    wrap_ms = ctx.time_kernel(0, reps=10)
+    prop_ms = ctx.time_kernel(1, reps=10)
+    res = dict(ms=ms, wall=wall, updates=n_updates, accept=acc / max(prop, 1),
+               max_drift=max(i["max_drift"] for i in infos),
+               flags=sorted({i["flags"] for i in infos}),
+               sign_mismatch=sum(i["sign_mismatch"] for i in infos),
+               wrap_ms=wrap_ms, prop_ms=prop_ms,
+               sign=ctx.measure_sign(-1) if args.chains * (steps + warmup) >= 20 else None)
+    log(f"[{precision_name}] {steps} sweeps: {ms:.1f} ms (wall {wall * 1e3:.1f} ms), "
+        f"{n_updates / (ms / 1e3):.4g} updates/s, acceptance {res['accept']:.3f}, "
+        f"wrap GEMM {wrap_ms:.3f} ms/launch, max drift {res['max_drift']:.2e}, flags {res['flags']}")
+    ctx.close()
+    del ctx
+    torch.cuda.empty_cache()
+    return res
+
+
+def cpu_baseline(args, budget_s=30.0):
+    """The oracle on the host: one chain of the same workload, BLAS on one
+    thread, timed over whole sweeps after its initialisation."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import pqmc
+
+    w = workload(args)
+    with threadpool_limits(limits=1):
+        ch = pqmc.Chain(pqmc.Model.from_workload(w), seed=w.seed, chain_id=0)
+        t0 = time.time()
+        n = 0
+        while True:
+            ch.sweep(1, measure=True)
+            n += 1
+            if time.time() - t0 > budget_s / 3 or n >= 3:
+                break
+        dt = time.time() - t0
+    upd = (2 * w.l_half + 2) * w.n_sites * n
+    return {"value": upd / dt, "unit": UNIT, "cores": 1, "kind": "oracle",
+            "sample": f"{n} sweep(s) of one 16x16 chain (202 slices x 256 sites), "
+                      f"serial FP64 NumPy, BLAS threads = 1, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=6)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--chains", type=int, default=512)
+    ap.add_argument("--ns", type=int, default=5)
+    ap.add_argument("--k", type=int, default=32)
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64", "mixed32b"])
+    ap.add_argument("--fp64-steps", type=int, default=2,
+                    help="sweeps of the plain FP64 GPU path timed for comparison (0 = skip)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): the chains of a "
+              "multi-GPU run are independent, so a node's throughput is N times one GPU's.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+
+    w = workload(args)
+    N, M = w.n_sites, 2 * w.l_half
+    main_res = run_gpu(args, args.precision, args.steps, args.warmup)
+    fp64_res = None
+    if args.fp64_steps > 0 and args.precision != "fp64":
+        fp64_res = run_gpu(args, "fp64", args.fp64_steps, 1)
+
+    value = main_res["updates"] / (main_res["ms"] / 1e3)
+    # dominant kernel: the kinetic-wrap GEMM e^{-dtau K} G; one launch covers
+    # every chain and both spins: 2 * chains * 2 N^3 flops
+    flops = 2.0 * args.chains * 2.0 * N ** 3
+    peak = PEAK_FP32_MFMA if args.precision != "fp64" else PEAK_FP64_MFMA
+    achieved = flops / (main_res["wrap_ms"] / 1e3)
+    traffic = read_traffic(args.chains)
+    out = {
+        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": main_res["ms"] / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"16x16 periodic Hubbard, U=3.5, 112+112 electrons, dtau=0.1, "
+                        f"Theta=10 (l_half=100, {M + 2} slices), Neel M_N=0.07 + Gutzwiller "
+                        f"g=0.55, batch of {args.chains} chains",
+            "chains": args.chains, "precision": args.precision, "stab_interval": args.ns,
+            "delay_rank": args.k, "acceptance": round(main_res["accept"], 4),
+            "max_drift": main_res["max_drift"], "flags": main_res["flags"],
+        },
+        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
+                     "kernel": "k_gemm<float, GM_STORE> (e^{-dtau K} G, all chains x 2 spins)",
+                     "ms_per_launch": main_res["wrap_ms"]},
+    }
+    if fp64_res is not None:
+        out["fp64_gpu"] = {"value": fp64_res["updates"] / (fp64_res["ms"] / 1e3), "unit": UNIT,
+                           "steps": args.fp64_steps,
+                           "wrap_gemm_ms_per_launch": fp64_res["wrap_ms"]}
+        out["mixed_over_fp64"] = value / out["fp64_gpu"]["value"]
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -186,6 +186,14 @@ gpqmc_status gpqmc_debug_gemm(int32_t precision, int32_t M, int32_t N, int32_t K
                               int32_t trans_a, const void* A, int32_t lda, const void* B,
                               int32_t ldb, void* C, int32_t ldc, void* hip_stream);
 
+/* Average duration (ms) of one launch of a hot-path kernel for all chains,
+ * timed with HIP events on the context's stream over reps back-to-back
+ * launches on the chains' current data: kernel 0 = the kinetic-wrap GEMM
+ * e^{-dtau K} G (every chain and spin), 1 = the basis-propagation GEMM.
+ * Writes only scratch that every pass rebuilds.  Synchronises.
+ * Errors: ESTATE before init_trial. */
+gpqmc_status gpqmc_time_kernel(gpqmc_ctx* ctx, int32_t kernel, int32_t reps, float* ms_per_launch);
+
 /* Status of one chain: GPQMC_OK or GPQMC_EUNSTABLE if any flag is set.
  * Synchronises. */
 gpqmc_status gpqmc_chain_status(gpqmc_ctx* ctx, int32_t chain);

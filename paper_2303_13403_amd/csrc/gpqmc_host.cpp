@@ -1042,6 +1042,33 @@ gpqmc_status gpqmc_debug_gemm(int32_t precision, int32_t M, int32_t N, int32_t K
   return GPQMC_OK;
 }
 
+gpqmc_status gpqmc_time_kernel(gpqmc_ctx* ctx, int32_t kernel, int32_t reps, float* ms_per_launch) {
+  if (!ctx || !ms_per_launch || reps < 1 || kernel < 0 || kernel > 1) return GPQMC_EINVAL;
+  if (!ctx->initialized) return fail(ctx, GPQMC_ESTATE, "time_kernel before init_trial");
+  Launcher L = make_launcher(ctx);
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0), "event");
+  HIPCHK(hipEventCreate(&e1), "event");
+  // both kernels write only scratch that every pass rebuilds before reading it
+  auto one = [&]() -> hipError_t {
+    GemmArgs a = L.args();
+    if (kernel == 0) return L.nn(E_WRAP1_UP, GM_STORE, a);        // Gtmp = e^{-dtau K} G
+    a.parity = 0;                                                  // U[1] = e^{-dtau K} U[0]
+    return L.gemm(E_PROP, GM_PROPB, ctx->tiles_Nn, ctx->off_tiles_Nn, a);
+  };
+  HIPCHK(one(), "warm");
+  HIPCHK(hipEventRecord(e0, ctx->stream), "event");
+  for (int r = 0; r < reps; ++r) HIPCHK(one(), "time");
+  HIPCHK(hipEventRecord(e1, ctx->stream), "event");
+  HIPCHK(hipEventSynchronize(e1), "event");
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, e0, e1), "event");
+  HIPCHK(hipEventDestroy(e0), "event");
+  HIPCHK(hipEventDestroy(e1), "event");
+  *ms_per_launch = ms / reps;
+  return GPQMC_OK;
+}
+
 const char* gpqmc_last_error(const gpqmc_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
 void gpqmc_destroy(gpqmc_ctx* ctx) {

@@ -59,7 +59,7 @@ EXPORTS = [
     "gpqmc_measure_sign", "gpqmc_get_measurements", "gpqmc_reset_measurements",
     "gpqmc_set_field", "gpqmc_get_field", "gpqmc_get_green", "gpqmc_get_chain_info",
     "gpqmc_set_debug", "gpqmc_get_trace", "gpqmc_debug_gemm", "gpqmc_chain_status",
-    "gpqmc_last_error", "gpqmc_destroy",
+    "gpqmc_time_kernel", "gpqmc_last_error", "gpqmc_destroy",
 ]
 
 
@@ -92,6 +92,7 @@ def load():
         "gpqmc_get_trace": [VP, I32, P(D), P(D), P(D), P(I32)],
         "gpqmc_debug_gemm": [I32, I32, I32, I32, I32, VP, I32, VP, I32, VP, I32, VP],
         "gpqmc_chain_status": [VP, I32],
+        "gpqmc_time_kernel": [VP, I32, I32, P(ctypes.c_float)],
         "gpqmc_last_error": [VP],
         "gpqmc_destroy": [VP],
     }
@@ -263,6 +264,12 @@ class Context:
         d = np.zeros(nck.value, np.float64)
         self._call("gpqmc_get_trace", chain, _dptr(r), _dptr(g), _dptr(d), ctypes.byref(nck))
         return r, g, d
+
+    def time_kernel(self, kernel: int = 0, reps: int = 20) -> float:
+        """Average ms per launch of the wrap GEMM (0) or propagation GEMM (1)."""
+        ms = ctypes.c_float()
+        self._call("gpqmc_time_kernel", kernel, reps, ctypes.byref(ms))
+        return ms.value
 
     def close(self):
         if getattr(self, "ctx", None) is not None and self.ctx.value:
