@@ -29,7 +29,7 @@ METRIC = "HS-field updates/sec at 16×16, L=100; mixed vs FP64 GPU at 1e-5 rel G
 UNIT = "HS-field updates/s"
 PEAK_FP32_MFMA = 157.3e12   # MI355X dense FP32 matrix, FLOP/s
 PEAK_FP64_MFMA = 78.6e12
-KERNEL_SRC = os.path.join(ROOT, "paper_2303_13403_amd", "csrc", "gpqmc_kernels.hip")
+KERNEL_SRC = os.path.join(ROOT, "paper_2303_13403_amd", "csrc", "gpqmc_gemm.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_wrap_gemm_16x16_b512.txt")
 
 
@@ -144,7 +144,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--chains", type=int, default=512)
     ap.add_argument("--ns", type=int, default=5)
-    ap.add_argument("--k", type=int, default=32)
+    ap.add_argument("--k", type=int, default=64)
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64", "mixed32b"])
     ap.add_argument("--fp64-steps", type=int, default=2,
                     help="sweeps of the plain FP64 GPU path timed for comparison (0 = skip)")

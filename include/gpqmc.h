@@ -194,6 +194,16 @@ gpqmc_status gpqmc_debug_gemm(int32_t precision, int32_t M, int32_t N, int32_t K
  * Errors: ESTATE before init_trial. */
 gpqmc_status gpqmc_time_kernel(gpqmc_ctx* ctx, int32_t kernel, int32_t reps, float* ms_per_launch);
 
+/* Debugging hooks (off the hot path; synchronise).  debug_step runs one
+ * stage of slice l on every chain: 0 = the flip scan of sites [s0, s1),
+ * 1 = T1 = Z Yg, 2 = the flush G -= Xg T1 (no frame change).  debug_read copies
+ * an internal buffer of one chain and spin as doubles: 0 = G, 1 = Z (ld 128),
+ * 2 = Xg (ld 128), 3 = Yg (ld N), 4 = T1 (ld N), 5 = (accepted count of the
+ * last segment, sign, accepted total). */
+gpqmc_status gpqmc_debug_step(gpqmc_ctx* ctx, int32_t stage, int32_t l, int32_t s0, int32_t s1);
+gpqmc_status gpqmc_debug_read(gpqmc_ctx* ctx, int32_t chain, int32_t what, int32_t spin, double* out,
+                              int64_t count);
+
 /* Status of one chain: GPQMC_OK or GPQMC_EUNSTABLE if any flag is set.
  * Synchronises. */
 gpqmc_status gpqmc_chain_status(gpqmc_ctx* ctx, int32_t chain);

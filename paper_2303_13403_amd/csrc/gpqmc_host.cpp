@@ -18,19 +18,20 @@
 #include "gpqmc_internal.h"
 
 namespace gpqmc {
-hipError_t launch_gemm(int bulk_fp32, int mode, const GemmEntry* e, const TileRef* t, int n,
+hipError_t launch_gemm(int fp32, int g_fp32, int mode, const GemmEntry* e, const TileRef* t, int n,
                        GemmArgs a, hipStream_t s);
 hipError_t launch_gemm_plain(int fp32, int transA, const GemmEntry* e, const TileRef* t, int n,
                              GemmArgs a, hipStream_t s);
-hipError_t launch_scan(int fp32, const ChainDev* c, int nc, const Ctl* ctl, int l, int M, int kblk,
-                       hipStream_t s);
-hipError_t launch_qr(int fp32, const ChainDev* c, int nc, int parity, hipStream_t s);
-hipError_t launch_lu_solve(const ChainDev* c, int nc, int slot, int dir, hipStream_t s);
-hipError_t launch_finalize(const ChainDev* c, int nc, const Ctl* ctl, int slot, int mode,
-                           int measure_here, int ck_index, hipStream_t s);
-hipError_t launch_put_trial(int fp32, const ChainDev* c, int nc, int slot, int set_active,
+hipError_t launch_scan(int fp32, const ChainDev* c, int nc, const Ctl* ctl, int l, int M, int s0,
+                       int s1, hipStream_t s);
+hipError_t launch_chol_inv(const ChainDev* c, int nc, int which, hipStream_t s);
+hipError_t launch_gj_inv(const ChainDev* c, int nc, hipStream_t s);
+hipError_t launch_basis_to_fp64(int fp32b, const ChainDev* c, int nc, int parity, hipStream_t s);
+hipError_t launch_finalize(int fp32b, const ChainDev* c, int nc, const Ctl* ctl, int slot, int mode,
+                           int measure_here, int ck_index, int parity, hipStream_t s);
+hipError_t launch_put_trial(int fp32b, const ChainDev* c, int nc, int slot, int set_active,
                             hipStream_t s);
-hipError_t launch_dscale_u(int fp32, const ChainDev* c, int nc, int l, int M, int parity,
+hipError_t launch_dscale_u(int fp32b, const ChainDev* c, int nc, int l, int M, int parity,
                            hipStream_t s);
 hipError_t launch_pass_end(const ChainDev* c, int nc, hipStream_t s);
 hipError_t launch_set_ctl(Ctl* ctl, int measure, int force_reject, float drift_tol, hipStream_t s);
@@ -121,8 +122,8 @@ struct ChainHost {
   std::vector<int8_t> field;
   // workspace offsets
   size_t G[2], Gtmp[2], U2[2][2], Z[2], Xg[2], Yg[2], T1[2], scan_ws[2];
-  size_t stack[2], slot_log[2], slot_sgn[2], Hw[2], Qc[2], Xm[2], Ym[2], piv[2], G64[2];
-  size_t field_off, Flist, st, meas, tr_ratio = 0, tr_green = 0, tr_drift = 0;
+  size_t stack[2], slot_log[2], slot_sgn[2], Hw[2], Qc[2], Wm[2], Rinv[2], Xm[2], Ym[2], G64[2];
+  size_t field_off, st, meas, tr_ratio = 0, tr_green = 0, tr_drift = 0;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -136,7 +137,8 @@ struct gpqmc_ctx {
   hipStream_t stream = nullptr;
   int fp32 = 0;            // Green's-function (wrap, flush, scan) precision: 1 = FP32, 0 = FP64
   int fp32b = 0;           // basis propagation precision: 1 = FP32, 0 = FP64
-  int l_half = 0, M = 0, n_s = 1, kblk = 16, n_slices = 2;
+  int l_half = 0, M = 0, n_s = 1, kseg = 64, n_slices = 2;  // kseg: delay rank (sites per flush)
+  int n_max = 0;                   // largest lattice of the batch
   int meas_cap = 4096;
   bool use_graph = true;
   float drift_tol = 1e-3f;
@@ -148,9 +150,10 @@ struct gpqmc_ctx {
   // layout
   size_t bytes = 0;
   size_t off_chains = 0, off_ctl = 0;
-  size_t off_ent[9] = {0};
-  size_t off_tiles_NN = 0, off_tiles_Nn = 0, off_tiles_nn = 0;
-  std::vector<TileRef> tiles_NN, tiles_Nn, tiles_nn;
+  size_t off_ent[14] = {0};
+  // tile lists: N x N, N x n, n x n, n x N and (delay rank) x N outputs
+  std::vector<TileRef> tiles[5];
+  size_t off_tiles[5] = {0};
   char* ws = nullptr;
   bool bound = false, initialized = false;
   long long sweeps_done = 0;       // passes enqueued since init_trial (mirrors the device counter)
@@ -168,8 +171,9 @@ struct gpqmc_ctx {
 
 namespace {
 
-enum EntryKind { E_WRAP1_UP = 0, E_WRAP2_UP, E_WRAP1_DN, E_WRAP2_DN, E_T1, E_FLUSH, E_PROP, E_XMAT,
-                 E_GFRESH };
+enum EntryKind { E_WRAP1_UP = 0, E_WRAP2_UP, E_WRAP1_DN, E_WRAP2_DN, E_T1, E_FLUSH, E_PROP,
+                 E_GRAM_U, E_APPLY1, E_GRAM_H, E_APPLY2, E_XMAT, E_YMAT, E_GFRESH, E_COUNT };
+enum TileKind { T_NN = 0, T_Nn, T_nn, T_nN, T_sN };
 
 gpqmc_status fail(gpqmc_ctx* c, gpqmc_status s, const std::string& msg) {
   if (c) c->err = msg;
@@ -212,38 +216,55 @@ struct Launcher {
     a.check_drift = 0;
     return a;
   }
-  hipError_t gemm(int kind, int mode, const std::vector<TileRef>& tl, size_t tl_off, GemmArgs a) {
+  hipError_t gemm(int kind, int mode, int tk, GemmArgs a) {
     const int f32 = (mode == GM_PROPB || mode == GM_PROPR) ? ctx->fp32b : ctx->fp32;
-    return launch_gemm(f32, mode, ents(ctx, kind), ctx->at<TileRef>(tl_off), (int)tl.size(), a, s);
+    return launch_gemm(f32, ctx->fp32, mode, ents(ctx, kind), ctx->at<TileRef>(ctx->off_tiles[tk]),
+                       (int)ctx->tiles[tk].size(), a, s);
   }
-  hipError_t nn(int kind, int mode, GemmArgs a) { return gemm(kind, mode, ctx->tiles_NN, ctx->off_tiles_NN, a); }
 
-  // checkpoint at position p: orthonormalise the active basis, recompute G
+  // checkpoint at position p: re-orthonormalise the active basis U[parity]
+  // (Cholesky QR twice), recompute G = 1 - R (L R)^{-1} L from the stored
+  // opposite-side basis, check the sign, store the new basis.
   hipError_t checkpoint(int p, int dir, int parity, int next_scale, int measure, int ck_index,
                         int mode) {
     hipError_t e;
-    if ((e = launch_qr(ctx->fp32b, chains, nc, parity, s)) != hipSuccess) return e;
-    const int sl = ctx->slot(p);
-    if (mode == 2) return launch_finalize(chains, nc, ctl, sl, 2, 0, -1, s);
     GemmArgs a = args();
+    a.parity = parity;
+    if (ctx->fp32b && (e = launch_basis_to_fp64(1, chains, nc, parity, s)) != hipSuccess) return e;
+    if ((e = gemm(E_GRAM_U, GM_GRAM, T_nn, a)) != hipSuccess) return e;
+    if ((e = launch_chol_inv(chains, nc, 0, s)) != hipSuccess) return e;
+    if ((e = gemm(E_APPLY1, GM_APPLY, T_Nn, a)) != hipSuccess) return e;
+    if ((e = gemm(E_GRAM_H, GM_GRAM, T_nn, a)) != hipSuccess) return e;
+    if ((e = launch_chol_inv(chains, nc, 1, s)) != hipSuccess) return e;
+    if ((e = gemm(E_APPLY2, GM_APPLY, T_Nn, a)) != hipSuccess) return e;
+    const int sl = ctx->slot(p);
+    if (mode == 2) return launch_finalize(ctx->fp32b, chains, nc, ctl, sl, 2, 0, -1, parity, s);
     a.slot = sl;
     a.dir = dir;
-    if ((e = gemm(E_XMAT, GM_XMAT, ctx->tiles_nn, ctx->off_tiles_nn, a)) != hipSuccess) return e;
-    if ((e = launch_lu_solve(chains, nc, sl, dir, s)) != hipSuccess) return e;
+    if ((e = gemm(E_XMAT, GM_XMAT, T_nn, a)) != hipSuccess) return e;
+    if ((e = launch_gj_inv(chains, nc, s)) != hipSuccess) return e;
+    if ((e = gemm(E_YMAT, GM_YMAT, T_nN, a)) != hipSuccess) return e;
     a.scale_slice = next_scale;
     a.check_drift = (mode == 0);
-    if ((e = nn(E_GFRESH, GM_GFRESH, a)) != hipSuccess) return e;
-    return launch_finalize(chains, nc, ctl, sl, mode, measure, ck_index, s);
+    if ((e = gemm(E_GFRESH, GM_GFRESH, T_NN, a)) != hipSuccess) return e;
+    return launch_finalize(ctx->fp32b, chains, nc, ctl, sl, mode, measure, ck_index, parity, s);
   }
 
+  // all proposals of slice l, segment by segment; each segment is flushed into
+  // G by a delayed rank-|F| update; the last flush applies the frame change
   hipError_t scan_and_flush(int l, int scale_slice, int inverse) {
     hipError_t e;
-    if ((e = launch_scan(ctx->fp32, chains, nc, ctl, l, ctx->M, ctx->kblk, s)) != hipSuccess) return e;
-    GemmArgs a = args();
-    if ((e = nn(E_T1, GM_T1, a)) != hipSuccess) return e;
-    a.scale_slice = scale_slice;
-    a.scale_inverse = inverse;
-    return nn(E_FLUSH, GM_FLUSH, a);
+    for (int s0 = 0; s0 < ctx->n_max; s0 += ctx->kseg) {
+      const bool last = s0 + ctx->kseg >= ctx->n_max;
+      if ((e = launch_scan(ctx->fp32, chains, nc, ctl, l, ctx->M, s0, s0 + ctx->kseg, s)) != hipSuccess)
+        return e;
+      GemmArgs a = args();
+      if ((e = gemm(E_T1, GM_T1, T_sN, a)) != hipSuccess) return e;
+      a.scale_slice = last ? scale_slice : -1;
+      a.scale_inverse = inverse;
+      if ((e = gemm(E_FLUSH, GM_FLUSH, T_NN, a)) != hipSuccess) return e;
+    }
+    return hipSuccess;
   }
 
   hipError_t up_pass() {
@@ -257,13 +278,13 @@ struct Launcher {
       if ((e = scan_and_flush(l, (!bulk && l == 0 && !ckl) ? 1 : -1, 0)) != hipSuccess) return e;
       if (bulk) {
         GemmArgs a = args();
-        if ((e = nn(E_WRAP1_UP, GM_STORE, a)) != hipSuccess) return e;
+        if ((e = gemm(E_WRAP1_UP, GM_STORE, T_NN, a)) != hipSuccess) return e;
         a.scale_slice = ckl ? -1 : l + 1;
-        if ((e = nn(E_WRAP2_UP, GM_WRAP, a)) != hipSuccess) return e;
+        if ((e = gemm(E_WRAP2_UP, GM_WRAP, T_NN, a)) != hipSuccess) return e;
         GemmArgs b = args();
         b.bscale_slice = l;
         b.parity = parity;
-        if ((e = gemm(E_PROP, GM_PROPB, ctx->tiles_Nn, ctx->off_tiles_Nn, b)) != hipSuccess) return e;
+        if ((e = gemm(E_PROP, GM_PROPB, T_Nn, b)) != hipSuccess) return e;
         parity ^= 1;
       } else {
         if ((e = launch_dscale_u(ctx->fp32b, chains, nc, l, M, parity, s)) != hipSuccess) return e;
@@ -285,15 +306,15 @@ struct Launcher {
       const bool bulk = (l >= 1 && l <= M);
       if (bulk) {
         GemmArgs a = args();
-        if ((e = nn(E_WRAP1_DN, GM_STORE, a)) != hipSuccess) return e;
-        if ((e = nn(E_WRAP2_DN, GM_WRAP, a)) != hipSuccess) return e;
+        if ((e = gemm(E_WRAP1_DN, GM_STORE, T_NN, a)) != hipSuccess) return e;
+        if ((e = gemm(E_WRAP2_DN, GM_WRAP, T_NN, a)) != hipSuccess) return e;
       }
       if ((e = scan_and_flush(l, l, 1)) != hipSuccess) return e;
       if (bulk) {
         GemmArgs b = args();
         b.scale_slice = l;
         b.parity = parity;
-        if ((e = gemm(E_PROP, GM_PROPR, ctx->tiles_Nn, ctx->off_tiles_Nn, b)) != hipSuccess) return e;
+        if ((e = gemm(E_PROP, GM_PROPR, T_Nn, b)) != hipSuccess) return e;
         parity ^= 1;
       } else {
         if ((e = launch_dscale_u(ctx->fp32b, chains, nc, l, M, parity, s)) != hipSuccess) return e;
@@ -319,7 +340,7 @@ struct Launcher {
         GemmArgs b = args();
         b.scale_slice = l;
         b.parity = parity;
-        if ((e = gemm(E_PROP, GM_PROPR, ctx->tiles_Nn, ctx->off_tiles_Nn, b)) != hipSuccess) return e;
+        if ((e = gemm(E_PROP, GM_PROPR, T_Nn, b)) != hipSuccess) return e;
         parity ^= 1;
       } else {
         if ((e = launch_dscale_u(ctx->fp32b, chains, nc, l, M, parity, s)) != hipSuccess) return e;
@@ -380,14 +401,14 @@ gpqmc_status gpqmc_create(int32_t n_chains, const gpqmc_chain_desc* chains,
   const gpqmc_chain_desc& d0 = chains[0];
   c->l_half = d0.l_half;
   c->n_s = d0.stab_interval;
-  c->kblk = d0.delay_rank;
+  c->kseg = d0.delay_rank;
   c->fp32 = d0.precision == GPQMC_FP64 ? 0 : 1;
   c->fp32b = d0.precision == GPQMC_MIXED_FP32_BASIS ? 1 : 0;
   if (d0.precision != GPQMC_MIXED && d0.precision != GPQMC_FP64 &&
       d0.precision != GPQMC_MIXED_FP32_BASIS)
     return bad(GPQMC_EINVAL, "precision must be GPQMC_FP64, GPQMC_MIXED or GPQMC_MIXED_FP32_BASIS");
-  if (c->l_half < 0 || c->n_s < 1 || c->kblk < 1 || c->kblk > kMaxBlock)
-    return bad(GPQMC_EINVAL, "need l_half >= 0, stab_interval >= 1, 1 <= delay_rank <= 32");
+  if (c->l_half < 0 || c->n_s < 1 || c->kseg < 1 || c->kseg > kSegMax)
+    return bad(GPQMC_EINVAL, "need l_half >= 0, stab_interval >= 1, 1 <= delay_rank <= 128");
   c->M = 2 * c->l_half;
   c->n_slices = c->M + 2;
   c->drift_tol = c->fp32 ? 1e-3f : 1e-6f;
@@ -409,7 +430,7 @@ gpqmc_status gpqmc_create(int32_t n_chains, const gpqmc_chain_desc* chains,
   for (int i = 0; i < n_chains; ++i) {
     const gpqmc_chain_desc& d = chains[i];
     char buf[200];
-    if (d.l_half != c->l_half || d.stab_interval != c->n_s || d.delay_rank != c->kblk ||
+    if (d.l_half != c->l_half || d.stab_interval != c->n_s || d.delay_rank != c->kseg ||
         d.precision != d0.precision) {
       snprintf(buf, sizeof buf, "chain %d: l_half, stab_interval, delay_rank and precision must "
                "match chain 0", i);
@@ -527,23 +548,23 @@ gpqmc_status gpqmc_create(int32_t n_chains, const gpqmc_chain_desc* chains,
       h.Gtmp[sp] = take(nn * bs);
       h.U2[sp][0] = take(nb * ub);
       h.U2[sp][1] = take(nb * ub);
-      h.Z[sp] = take(nn * bs);
-      h.Xg[sp] = take(nn * bs);
-      h.Yg[sp] = take(nn * bs);
-      h.T1[sp] = take(nn * bs);
-      h.scan_ws[sp] = take((size_t)5 * kMaxBlock * N * bs);
+      h.Z[sp] = take((size_t)kSegMax * kSegMax * bs);
+      h.Xg[sp] = take(N * kSegMax * bs);
+      h.Yg[sp] = take(N * kSegMax * bs);
+      h.T1[sp] = take(N * kSegMax * bs);
+      h.scan_ws[sp] = take((size_t)5 * kBlock * kSegMax * bs);
       h.stack[sp] = take((size_t)n_slots * nb * 8);
       h.slot_log[sp] = take((size_t)n_slots * 8);
       h.slot_sgn[sp] = take((size_t)n_slots * 4);
       h.Hw[sp] = take(nb * 8);
       h.Qc[sp] = take(nb * 8);
+      h.Wm[sp] = take((size_t)h.n[sp] * h.n[sp] * 8);
+      h.Rinv[sp] = take((size_t)h.n[sp] * h.n[sp] * 8);
       h.Xm[sp] = take((size_t)h.n[sp] * h.n[sp] * 8);
       h.Ym[sp] = take((size_t)h.n[sp] * N * 8);
-      h.piv[sp] = take((size_t)h.n[sp] * 4);
       h.G64[sp] = take(nn * 8);
     }
     h.field_off = take((size_t)c->n_slices * N);
-    h.Flist = take(N * 4);
     h.st = take(sizeof(ChainState));
     h.meas = take((size_t)c->meas_cap * 3 * 8);
     if (h.trace) {
@@ -554,20 +575,22 @@ gpqmc_status gpqmc_create(int32_t n_chains, const gpqmc_chain_desc* chains,
   }
   c->off_chains = take(sizeof(ChainDev) * n_chains);
   c->off_ctl = take(sizeof(Ctl));
-  for (int k = 0; k < 9; ++k) c->off_ent[k] = take(sizeof(GemmEntry) * 2 * n_chains);
-  std::vector<std::pair<int, int>> nn_sz, nb_sz, bb_sz;
-  for (auto& h : c->ch)
+  for (int k = 0; k < E_COUNT; ++k) c->off_ent[k] = take(sizeof(GemmEntry) * 2 * n_chains);
+  std::vector<std::pair<int, int>> sz[5];
+  for (auto& h : c->ch) {
+    c->n_max = std::max(c->n_max, h.N);
     for (int sp = 0; sp < 2; ++sp) {
-      nn_sz.push_back({h.N, h.N});
-      nb_sz.push_back({h.N, h.n[sp]});
-      bb_sz.push_back({h.n[sp], h.n[sp]});
+      sz[T_NN].push_back({h.N, h.N});
+      sz[T_Nn].push_back({h.N, h.n[sp]});
+      sz[T_nn].push_back({h.n[sp], h.n[sp]});
+      sz[T_nN].push_back({h.n[sp], h.N});
+      sz[T_sN].push_back({std::min(c->kseg, h.N), h.N});
     }
-  build_tiles(c->tiles_NN, nn_sz);
-  build_tiles(c->tiles_Nn, nb_sz);
-  build_tiles(c->tiles_nn, bb_sz);
-  c->off_tiles_NN = take(sizeof(TileRef) * c->tiles_NN.size());
-  c->off_tiles_Nn = take(sizeof(TileRef) * c->tiles_Nn.size());
-  c->off_tiles_nn = take(sizeof(TileRef) * c->tiles_nn.size());
+  }
+  for (int t = 0; t < 5; ++t) {
+    build_tiles(c->tiles[t], sz[t]);
+    c->off_tiles[t] = take(sizeof(TileRef) * c->tiles[t].size());
+  }
   c->bytes = align256(off);
   *out = ctx.release();
   return GPQMC_OK;
@@ -605,8 +628,8 @@ gpqmc_status gpqmc_bind_workspace(gpqmc_ctx* ctx, void* device_ptr, size_t bytes
 
   const int nc = ctx->n_chains;
   std::vector<ChainDev> cd(nc);
-  std::vector<GemmEntry> E[9];
-  for (int k = 0; k < 9; ++k) E[k].resize(2 * nc);
+  std::vector<GemmEntry> E[E_COUNT];
+  for (int k = 0; k < E_COUNT; ++k) E[k].resize(2 * nc);
   for (int i = 0; i < nc; ++i) {
     ChainHost& h = ctx->ch[i];
     ChainDev& d = cd[i];
@@ -646,16 +669,16 @@ gpqmc_status gpqmc_bind_workspace(gpqmc_ctx* ctx, void* device_ptr, size_t bytes
       d.slot_sgn[sp] = ctx->at<int>(h.slot_sgn[sp]);
       d.Hw[sp] = ctx->at<double>(h.Hw[sp]);
       d.Qc[sp] = ctx->at<double>(h.Qc[sp]);
+      d.Wm[sp] = ctx->at<double>(h.Wm[sp]);
+      d.Rinv[sp] = ctx->at<double>(h.Rinv[sp]);
       d.Xm[sp] = ctx->at<double>(h.Xm[sp]);
       d.Ym[sp] = ctx->at<double>(h.Ym[sp]);
-      d.piv[sp] = ctx->at<int>(h.piv[sp]);
       d.G64[sp] = ctx->at<double>(h.G64[sp]);
     }
     d.Km = ctx->ws + L.off_Km;
     d.Kp = ctx->ws + L.off_Kp;
     d.Khop = ctx->at<double>(L.off_K);
     d.field = ctx->at<int8_t>(h.field_off);
-    d.Flist = ctx->at<int>(h.Flist);
     d.st = ctx->at<ChainState>(h.st);
     d.meas = ctx->at<double>(h.meas);
     d.meas_cap = ctx->meas_cap;
@@ -676,73 +699,69 @@ gpqmc_status gpqmc_bind_workspace(gpqmc_ctx* ctx, void* device_ptr, size_t bytes
       base.st = d.st;
       for (int b = 0; b < 2; ++b)
         for (int si = 0; si < 2; ++si) base.dval[b][si] = d.dval[b][sp][si];
-      auto nnE = [&](const void* A, const void* B, void* C) {
+      auto mk = [&](const void* A0, const void* A1, const void* B0, const void* B1, void* C0,
+                    void* C1, int M_, int N_, int K_, int lda, int ldb, int ldc) {
         GemmEntry e = base;
-        e.A = A;
-        e.B = B;
-        e.C = C;
-        e.M = e.N = e.K = N;
-        e.lda = e.ldb = e.ldc = N;
+        e.A[0] = A0;
+        e.A[1] = A1;
+        e.B[0] = B0;
+        e.B[1] = B1;
+        e.C[0] = C0;
+        e.C[1] = C1;
+        e.M = M_;
+        e.N = N_;
+        e.K = K_;
+        e.lda = lda;
+        e.ldb = ldb;
+        e.ldc = ldc;
         return e;
+      };
+      auto nnE = [&](const void* A, const void* B, void* C) {
+        return mk(A, A, B, B, C, C, N, N, N, N, N, N);
       };
       E[E_WRAP1_UP][ei] = nnE(d.Km, d.G[sp], d.Gtmp[sp]);
       E[E_WRAP2_UP][ei] = nnE(d.Gtmp[sp], d.Kp, d.G[sp]);
       E[E_WRAP1_DN][ei] = nnE(d.Kp, d.G[sp], d.Gtmp[sp]);
       E[E_WRAP2_DN][ei] = nnE(d.Gtmp[sp], d.Km, d.G[sp]);
-      GemmEntry t1 = nnE(d.Z[sp], d.Yg[sp], d.T1[sp]);
+      GemmEntry t1 = mk(d.Z[sp], d.Z[sp], d.Yg[sp], d.Yg[sp], d.T1[sp], d.T1[sp],
+                        std::min(ctx->kseg, N), N, 0, kSegMax, N, N);
       t1.dynMK = &d.st->fcount;
       E[E_T1][ei] = t1;
-      GemmEntry fl = nnE(d.Xg[sp], d.T1[sp], d.G[sp]);
+      GemmEntry fl = mk(d.Xg[sp], d.Xg[sp], d.T1[sp], d.T1[sp], d.G[sp], d.G[sp], N, N, 0, kSegMax, N, N);
       fl.dynMK = &d.st->fcount;
       E[E_FLUSH][ei] = fl;
-      GemmEntry pr = base;
-      pr.A = ctx->ws + L.off_Kmb;
-      pr.Bpp[0] = d.U[sp][0];
-      pr.Bpp[1] = d.U[sp][1];
-      pr.Cpp[0] = d.U[sp][0];
-      pr.Cpp[1] = d.U[sp][1];
-      pr.M = N;
-      pr.N = n;
-      pr.K = N;
-      pr.lda = N;
-      pr.ldb = n;
-      pr.ldc = n;
-      E[E_PROP][ei] = pr;
-      GemmEntry xm = base;
+      const void* Kmb = ctx->ws + L.off_Kmb;
+      E[E_PROP][ei] = mk(Kmb, Kmb, d.U[sp][0], d.U[sp][1], d.U[sp][0], d.U[sp][1], N, n, N, N, n, n);
+      // checkpoint: Cholesky QR of U[parity] (or of its FP64 copy in Qc)
+      const void* src0 = ctx->fp32b ? (const void*)d.Qc[sp] : d.U[sp][0];
+      const void* src1 = ctx->fp32b ? (const void*)d.Qc[sp] : d.U[sp][1];
+      E[E_GRAM_U][ei] = mk(src0, src1, nullptr, nullptr, d.Wm[sp], d.Wm[sp], n, n, N, n, n, n);
+      E[E_APPLY1][ei] = mk(src0, src1, d.Rinv[sp], d.Rinv[sp], d.Hw[sp], d.Hw[sp], N, n, n, n, n, n);
+      E[E_GRAM_H][ei] = mk(d.Hw[sp], d.Hw[sp], nullptr, nullptr, d.Wm[sp], d.Wm[sp], n, n, N, n, n, n);
+      E[E_APPLY2][ei] = mk(d.Hw[sp], d.Hw[sp], d.Rinv[sp], d.Rinv[sp], d.Qc[sp], d.Qc[sp], N, n, n, n, n, n);
+      GemmEntry xm = mk(nullptr, nullptr, nullptr, nullptr, d.Xm[sp], d.Xm[sp], n, n, N, n, n, n);
       xm.stack = d.stack[sp];
       xm.Qc = d.Qc[sp];
       xm.slot_stride = N * n;
-      xm.C = d.Xm[sp];
-      xm.M = n;
-      xm.N = n;
-      xm.K = N;
-      xm.lda = n;
-      xm.ldb = n;
-      xm.ldc = n;
       E[E_XMAT][ei] = xm;
-      GemmEntry gf = base;
+      GemmEntry ym = mk(d.Xm[sp], d.Xm[sp], nullptr, nullptr, d.Ym[sp], d.Ym[sp], n, N, n, n, n, N);
+      ym.stack = d.stack[sp];
+      ym.Qc = d.Qc[sp];
+      ym.slot_stride = N * n;
+      E[E_YMAT][ei] = ym;
+      GemmEntry gf = mk(nullptr, nullptr, d.Ym[sp], d.Ym[sp], d.G64[sp], d.G[sp], N, N, n, n, N, N);
+      gf.ldc2 = N;
       gf.stack = d.stack[sp];
       gf.Qc = d.Qc[sp];
-      gf.Ym = d.Ym[sp];
       gf.slot_stride = N * n;
-      gf.C = d.G64[sp];
-      gf.C2 = d.G[sp];
-      gf.M = N;
-      gf.N = N;
-      gf.K = n;
-      gf.lda = n;
-      gf.ldb = N;
-      gf.ldc = N;
-      gf.ldc2 = N;
       E[E_GFRESH][ei] = gf;
     }
   }
   HIPCHK(up(ctx->off_chains, cd.data(), sizeof(ChainDev) * nc), "upload chains");
-  for (int k = 0; k < 9; ++k)
+  for (int k = 0; k < E_COUNT; ++k)
     HIPCHK(up(ctx->off_ent[k], E[k].data(), sizeof(GemmEntry) * E[k].size()), "upload entries");
-  HIPCHK(up(ctx->off_tiles_NN, ctx->tiles_NN.data(), sizeof(TileRef) * ctx->tiles_NN.size()), "tiles");
-  HIPCHK(up(ctx->off_tiles_Nn, ctx->tiles_Nn.data(), sizeof(TileRef) * ctx->tiles_Nn.size()), "tiles");
-  HIPCHK(up(ctx->off_tiles_nn, ctx->tiles_nn.data(), sizeof(TileRef) * ctx->tiles_nn.size()), "tiles");
+  for (int t = 0; t < 5; ++t)
+    HIPCHK(up(ctx->off_tiles[t], ctx->tiles[t].data(), sizeof(TileRef) * ctx->tiles[t].size()), "tiles");
   Ctl ctl = {0, 0, ctx->drift_tol, 0};
   HIPCHK(up(ctx->off_ctl, &ctl, sizeof ctl), "upload ctl");
   HIPCHK(hipDeviceSynchronize(), "bind");
@@ -1010,9 +1029,9 @@ gpqmc_status gpqmc_debug_gemm(int32_t precision, int32_t M, int32_t N, int32_t K
   gpqmc_ctx* ctx = nullptr;
   GemmEntry e;
   memset(&e, 0, sizeof e);
-  e.A = A;
-  e.B = B;
-  e.C = C;
+  e.A[0] = e.A[1] = A;
+  e.B[0] = e.B[1] = B;
+  e.C[0] = e.C[1] = C;
   e.M = M;
   e.N = N;
   e.K = K;
@@ -1036,7 +1055,8 @@ gpqmc_status gpqmc_debug_gemm(int32_t precision, int32_t M, int32_t N, int32_t K
   hipError_t err = launch_gemm_plain(precision == GPQMC_MIXED, trans_a, (const GemmEntry*)dbuf, dt,
                                      (int)tl.size(), a, s);
   hipError_t err2 = hipStreamSynchronize(s);
-  hipFree(dbuf);
+  const hipError_t err3 = hipFree(dbuf);
+  if (err3 != hipSuccess) return GPQMC_EHIP;
   if (err != hipSuccess) return GPQMC_EHIP;
   if (err2 != hipSuccess) return GPQMC_EHIP;
   return GPQMC_OK;
@@ -1052,9 +1072,9 @@ gpqmc_status gpqmc_time_kernel(gpqmc_ctx* ctx, int32_t kernel, int32_t reps, flo
   // both kernels write only scratch that every pass rebuilds before reading it
   auto one = [&]() -> hipError_t {
     GemmArgs a = L.args();
-    if (kernel == 0) return L.nn(E_WRAP1_UP, GM_STORE, a);        // Gtmp = e^{-dtau K} G
+    if (kernel == 0) return L.gemm(E_WRAP1_UP, GM_STORE, T_NN, a);  // Gtmp = e^{-dtau K} G
     a.parity = 0;                                                  // U[1] = e^{-dtau K} U[0]
-    return L.gemm(E_PROP, GM_PROPB, ctx->tiles_Nn, ctx->off_tiles_Nn, a);
+    return L.gemm(E_PROP, GM_PROPB, T_Nn, a);
   };
   HIPCHK(one(), "warm");
   HIPCHK(hipEventRecord(e0, ctx->stream), "event");
@@ -1069,13 +1089,59 @@ gpqmc_status gpqmc_time_kernel(gpqmc_ctx* ctx, int32_t kernel, int32_t reps, flo
   return GPQMC_OK;
 }
 
+gpqmc_status gpqmc_debug_step(gpqmc_ctx* ctx, int32_t stage, int32_t l, int32_t s0, int32_t s1) {
+  if (!ctx || !ctx->initialized || l < 0 || l > ctx->M + 1) return GPQMC_EINVAL;
+  Launcher L = make_launcher(ctx);
+  HIPCHK(launch_set_ctl(ctx->at<Ctl>(ctx->off_ctl), 0, ctx->debug_flags & 1, ctx->drift_tol,
+                        ctx->stream), "ctl");
+  GemmArgs a = L.args();
+  hipError_t e = hipErrorInvalidValue;
+  if (stage == 0) e = launch_scan(ctx->fp32, L.chains, L.nc, L.ctl, l, ctx->M, s0, s1, ctx->stream);
+  if (stage == 1) e = L.gemm(E_T1, GM_T1, T_sN, a);
+  if (stage == 2) e = L.gemm(E_FLUSH, GM_FLUSH, T_NN, a);
+  HIPCHK(e, "debug step");
+  HIPCHK(hipStreamSynchronize(ctx->stream), "debug step");
+  return GPQMC_OK;
+}
+
+gpqmc_status gpqmc_debug_read(gpqmc_ctx* ctx, int32_t chain, int32_t what, int32_t spin, double* out,
+                              int64_t count) {
+  if (!ctx || !out || chain < 0 || chain >= ctx->n_chains || spin < 0 || spin > 1 || count < 0)
+    return GPQMC_EINVAL;
+  const ChainHost& h = ctx->ch[chain];
+  size_t off = 0, elem = ctx->fp32 ? 4 : 8;
+  switch (what) {
+    case 0: off = h.G[spin]; break;
+    case 1: off = h.Z[spin]; break;
+    case 2: off = h.Xg[spin]; break;
+    case 3: off = h.Yg[spin]; break;
+    case 4: off = h.T1[spin]; break;
+    case 5: off = h.st; elem = 0; break;
+    default: return GPQMC_EINVAL;
+  }
+  HIPCHK(hipStreamSynchronize(ctx->stream), "sync");
+  if (elem == 0) {
+    ChainState st;
+    HIPCHK(hipMemcpy(&st, ctx->ws + off, sizeof st, hipMemcpyDeviceToHost), "state");
+    out[0] = st.fcount;
+    out[1] = st.sign;
+    out[2] = (double)st.accepted;
+    return GPQMC_OK;
+  }
+  std::vector<char> buf((size_t)count * elem);
+  HIPCHK(hipMemcpy(buf.data(), ctx->ws + off, buf.size(), hipMemcpyDeviceToHost), "read");
+  for (int64_t i = 0; i < count; ++i)
+    out[i] = elem == 4 ? (double)((float*)buf.data())[i] : ((double*)buf.data())[i];
+  return GPQMC_OK;
+}
+
 const char* gpqmc_last_error(const gpqmc_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
 void gpqmc_destroy(gpqmc_ctx* ctx) {
   if (!ctx) return;
   for (int d = 0; d < 2; ++d) {
-    if (ctx->graph[d]) hipGraphExecDestroy(ctx->graph[d]);
-    if (ctx->graph_def[d]) hipGraphDestroy(ctx->graph_def[d]);
+    if (ctx->graph[d]) (void)hipGraphExecDestroy(ctx->graph[d]);
+    if (ctx->graph_def[d]) (void)hipGraphDestroy(ctx->graph_def[d]);
   }
   delete ctx;
 }

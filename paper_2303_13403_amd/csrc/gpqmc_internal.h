@@ -8,9 +8,11 @@
 namespace gpqmc {
 
 constexpr int kThreads = 256;   // every kernel runs 256-thread workgroups (4 waves)
-constexpr int kMaxBlock = 32;   // largest submatrix block (delay rank) of the scan
-constexpr int kMaxSites = 1024; // largest lattice the scan's LDS tables hold
+constexpr int kBlock = 32;      // submatrix block of the flip scan (sites)
+constexpr int kSegMax = 128;    // largest delay rank: sites per scan segment / flush
+constexpr int kMaxSites = 1024; // largest lattice
 constexpr int kTile = 64;       // GEMM output tile (kTile x kTile per workgroup)
+constexpr int kLdsDense = 128;  // small dense factorisations run in LDS up to this order
 
 enum Tag : uint32_t { TAG_INIT = 0, TAG_ACCEPT = 1 };
 
@@ -44,8 +46,8 @@ __host__ __device__ inline double uniform53(uint32_t w0, uint32_t w1) {
 struct ChainState {
   int sign;             // tracked sign of W_up * W_dn
   int sweep;            // pass counter: word 1 of the Philox counter
-  int fcount;           // flips with nonzero Delta accepted in the current slice
-  int flags;            // sticky error bits (GPQMC_FLAG_*)
+  int fcount;           // flips with nonzero Delta accepted in the current scan segment
+  int flags;            // sticky error bits (FLAG_*)
   int n_meas;           // stored measurement records
   int sign_mismatch;    // checkpoints where tracked and recomputed signs differ
   int run_sgn[2];       // sign of det of the active basis' accumulated triangular factors
@@ -55,7 +57,7 @@ struct ChainState {
   double x_log[2];      // log|det (L R)| of the current checkpoint
   int x_sgn[2];
   unsigned int drift_bits;  // max |G_wrapped - G_fresh| of the current checkpoint (float bits)
-  float max_drift;      // since creation / last reset
+  float max_drift;      // since initialisation
   float last_drift;
   int pad0;
   long long accepted;   // accepted proposals
@@ -64,14 +66,15 @@ struct ChainState {
 
 enum Flags : int {
   FLAG_DRIFT = 1,       // drift above tolerance at a checkpoint
-  FLAG_NAN = 2,         // non-finite Green's function or ratio
-  FLAG_SINGULAR = 4,    // singular L R at a checkpoint
+  FLAG_NAN = 2,         // non-finite Green's function
+  FLAG_SINGULAR = 4,    // singular L R, or a basis Gram matrix not positive definite
   FLAG_SIGN = 8,        // tracked and recomputed signs disagree
   FLAG_MEAS_FULL = 16,  // measurement buffer full (records dropped)
 };
 
 // Per-chain description (device memory).  Matrices are row-major; N x N
-// matrices use leading dimension N, N x n_sigma matrices leading dimension n_sigma.
+// matrices use leading dimension N, N x n matrices (n = particles of the spin)
+// leading dimension n.
 struct ChainDev {
   int N;                // sites
   int n[2];             // particles per spin (0 = up, 1 = down)
@@ -81,35 +84,36 @@ struct ChainDev {
   // field +1 and 1 for field -1: exp(sigma_sign * c_b * s_sign).
   double dval[2][2][2];
   double delta[2][2][2];  // flip factor Delta = exp(-2 sigma c_b s) - 1, same indexing
-  double U_hub;         // Hubbard U (energy measurement)
+  double U_hub;           // Hubbard U (energy measurement)
   uint32_t key0, key1;    // Philox key (seed low word, seed high word ^ TAG_ACCEPT)
   uint32_t chain_id;
   int pad1;
-  // bulk-precision matrices (float or double depending on the context)
+  // Green's-function precision (float or double)
   void* G[2];           // equal-time Green's function in the current frame
   void* Gtmp[2];        // wrap intermediate
-  void* U[2][2];        // active propagated basis, ping-pong pair
-  void* Z[2];           // delayed-update coefficient matrix (f x f, ld N)
-  void* Xg[2];          // G0[:, F]   (N x f, ld N)
+  void* Z[2];           // delayed-update coefficients of a segment (f x f, ld kSegMax)
+  void* Xg[2];          // G0[:, F]  (N x f, ld kSegMax)
   void* Yg[2];          // (1 - G0)[F, :]  (f x N, ld N)
   void* T1[2];          // Z Yg  (f x N, ld N)
-  void* scan_ws[2];     // scan scratch, 4 * kMaxBlock * N
-  const void* Km;       // e^{-dtau K} (bulk precision)
+  void* scan_ws[2];     // scan scratch, 5 * kBlock * kSegMax elements
+  const void* Km;       // e^{-dtau K}
   const void* Kp;       // e^{+dtau K}
-  // FP64 matrices
+  // basis precision (float or double)
+  void* U[2][2];        // active propagated basis, ping-pong pair
+  // FP64
   const double* Khop;   // hopping matrix K
-  const double* P[2];   // trial orbitals, N x n_sigma
-  double* stack[2];     // n_slots x N x n_sigma orthonormal bases
+  const double* P[2];   // trial orbitals, N x n
+  double* stack[2];     // n_slots x N x n orthonormal bases
   double* slot_log[2];  // per slot: log|det| of the accumulated triangular factors
   int* slot_sgn[2];
-  double* Hw[2];        // QR work (N x n_sigma)
-  double* Qc[2];        // explicit Q of the current checkpoint
-  double* Xm[2];        // L R (n x n), LU in place
+  double* Hw[2];        // QR work (N x n)
+  double* Qc[2];        // orthonormal basis of the current checkpoint (N x n)
+  double* Wm[2];        // Gram matrix (n x n)
+  double* Rinv[2];      // inverse Cholesky factor (n x n, upper)
+  double* Xm[2];        // L R (n x n), inverted in place
   double* Ym[2];        // (L R)^{-1} L  (n x N)
-  int* piv[2];
   double* G64[2];       // last fresh Green's function (unscaled, at its checkpoint)
   int8_t* field;        // n_slices x N
-  int* Flist;           // accepted sites of the current slice
   ChainState* st;
   double* meas;         // records (sign, E/N, D)
   int meas_cap;
@@ -127,21 +131,18 @@ struct Ctl {
   int pad;
 };
 
-// One operand set of a batched GEMM (one chain and one spin).
+// One operand set of a batched GEMM (one chain and one spin).  Pointer pairs
+// are selected by the launch's parity where the mode ping-pongs.
 struct GemmEntry {
-  const void* A;        // resolved per launch from the fields below where needed
-  const void* B;
-  void* C;
-  void* C2;             // secondary output (bulk copy of a fresh Green's function)
-  const void* Bpp[2];   // ping-pong inputs (propagation)
-  void* Cpp[2];         // ping-pong outputs
+  const void* A[2];
+  const void* B[2];
+  void* C[2];
   const double* stack;  // checkpoint stack base (FP64)
   const double* Qc;     // current checkpoint basis (FP64)
-  const double* Ym;
   int slot_stride;      // elements per stack slot
   int M, N, K;          // static sizes
   int lda, ldb, ldc, ldc2;
-  const int* dynMK;     // if set, M (mode T1) and K are read from *dynMK (accepted count)
+  const int* dynMK;     // if set, K (and M in mode GM_T1) = *dynMK (accepted count)
   const int8_t* field;  // base of the chain's field
   int n_sites;
   int spin;
@@ -169,11 +170,14 @@ enum GemmMode : int {
   GM_STORE = 0,   // C = A B
   GM_WRAP = 1,    // C = D (A B) D^{-1}  (or D^{-1}(A B)D, or unscaled)
   GM_FLUSH = 2,   // C = D (C - A B) D^{-1}  (scaling optional)
-  GM_PROPB = 3,   // C[parity^1] = A (D B[parity])
-  GM_PROPR = 4,   // C[parity^1] = D (A B[parity])
+  GM_PROPB = 3,   // C[p^1] = A (D B[p])
+  GM_PROPR = 4,   // C[p^1] = D (A B[p])
   GM_T1 = 5,      // C = A B with M = K = accepted count
-  GM_XMAT = 6,    // C = Lt^T R  (FP64)
-  GM_GFRESH = 7,  // C = 1 - R Y (FP64), drift, bulk copy with scaling
+  GM_GRAM = 6,    // C = A[p]^T A[p]  (FP64)
+  GM_APPLY = 7,   // C = A[p] B       (FP64)
+  GM_XMAT = 8,    // C = Lt^T R       (FP64)
+  GM_YMAT = 9,    // C = Xinv Lt^T    (FP64)
+  GM_GFRESH = 10, // C = 1 - R Y (FP64), drift, bulk copy with scaling
 };
 
 }  // namespace gpqmc

@@ -59,7 +59,8 @@ EXPORTS = [
     "gpqmc_measure_sign", "gpqmc_get_measurements", "gpqmc_reset_measurements",
     "gpqmc_set_field", "gpqmc_get_field", "gpqmc_get_green", "gpqmc_get_chain_info",
     "gpqmc_set_debug", "gpqmc_get_trace", "gpqmc_debug_gemm", "gpqmc_chain_status",
-    "gpqmc_time_kernel", "gpqmc_last_error", "gpqmc_destroy",
+    "gpqmc_time_kernel", "gpqmc_debug_step", "gpqmc_debug_read", "gpqmc_last_error",
+    "gpqmc_destroy",
 ]
 
 
@@ -93,6 +94,8 @@ def load():
         "gpqmc_debug_gemm": [I32, I32, I32, I32, I32, VP, I32, VP, I32, VP, I32, VP],
         "gpqmc_chain_status": [VP, I32],
         "gpqmc_time_kernel": [VP, I32, I32, P(ctypes.c_float)],
+        "gpqmc_debug_step": [VP, I32, I32, I32, I32],
+        "gpqmc_debug_read": [VP, I32, I32, I32, P(D), I64],
         "gpqmc_last_error": [VP],
         "gpqmc_destroy": [VP],
     }
@@ -270,6 +273,14 @@ class Context:
         ms = ctypes.c_float()
         self._call("gpqmc_time_kernel", kernel, reps, ctypes.byref(ms))
         return ms.value
+
+    def debug_step(self, stage: int, l: int, s0: int = 0, s1: int = 0):
+        self._call("gpqmc_debug_step", stage, l, s0, s1)
+
+    def debug_read(self, chain: int, what: int, spin: int, count: int) -> np.ndarray:
+        out = np.zeros(count, np.float64)
+        self._call("gpqmc_debug_read", chain, what, spin, _dptr(out), count)
+        return out
 
     def close(self):
         if getattr(self, "ctx", None) is not None and self.ctx.value:

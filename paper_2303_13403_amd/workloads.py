@@ -81,7 +81,7 @@ class Workload:
     m_neel: float
     g: float
     stab_interval: int     # slices between QR re-stabilisations
-    delay_rank: int        # sites per block of the delayed submatrix scan
+    delay_rank: int        # delay rank: sites per scan segment (one delayed flush each)
     precision: str         # "fp64" or "mixed"
     sweeps: int
     t: float = 1.0
@@ -117,17 +117,17 @@ WORKLOADS = {
     "4x4": Workload("4x4 U=4 half filling Theta=2", 4, 4, 4.0, 8, 8, 0.1, 20,
                     0.21, 0.6, 5, 16, "fp64", 200),
     "12x12": Workload("12x12 U=4 half filling Theta=5", 12, 12, 4.0, 72, 72, 0.1, 50,
-                      0.21, 0.6, 10, 32, "mixed", 500),
+                      0.21, 0.6, 10, 64, "mixed", 500),
     "16x16": Workload("16x16 U=3.5 n=0.875 Theta=10", 16, 16, 3.5, 112, 112, 0.1, 100,
-                      0.07, 0.55, 5, 32, "mixed", 1000, ramp=0.1),
+                      0.07, 0.55, 5, 64, "mixed", 1000, ramp=0.1),
     "24x24": Workload("24x24 U=4 half filling Theta=10 dtau=0.05", 24, 24, 4.0, 288, 288,
-                      0.05, 200, 0.21, 0.6, 10, 32, "mixed", 100),
+                      0.05, 200, 0.21, 0.6, 10, 64, "mixed", 100),
 }
 
 
 def batch_uneven(n_chains: int = 256, seed: int = 13403, l_half: int = 50,
                  dtau: float = 0.1, precision: str = "mixed", stab_interval: int = 5,
-                 delay_rank: int = 16):
+                 delay_rank: int = 64):
     """Batch of independent half-filled chains on uneven lattices.
 
     Each chain draws its linear size uniformly from {6, 8, 10, 12} and U
