@@ -1,8 +1,11 @@
 // Checkpoint (re-stabilisation) and bookkeeping kernels of the PQMC sweep
-// (gfx950).  At a checkpoint the propagated N x n basis is re-orthonormalised
-// in FP64 by Cholesky QR applied twice (Gram matrix and the triangular-factor
-// products are batched MFMA GEMMs; the n x n Cholesky factorisation and the
-// inverse of its factor run here, in LDS), the fresh Green's function
+// (gfx950).  At a checkpoint the propagated N x n basis U is re-orthonormalised
+// in FP64 by Cholesky QR: U = Q T with T the Cholesky factor of U^T U and
+// Q = U T^{-1} (the Gram matrix and Q are batched MFMA GEMMs; the n x n
+// Cholesky factorisation and T^{-1} run here, in LDS).  Only span(Q) and the
+// exact factorisation U = Q T matter (the Green's function is invariant under
+// R -> R T), so one pass suffices: Q is orthonormal to O(eps cond(U)^2).  The
+// fresh Green's function
 // G = 1 - R (L R)^{-1} L follows from the inverse of the n x n overlap L R
 // (Gauss-Jordan with partial pivoting, in LDS) and two more GEMMs; log|det|
 // and the sign of each factor are accumulated for the sign check.
@@ -14,188 +17,214 @@
 
 namespace gpqmc {
 
-// LDS copy of an n x n matrix when n <= kLdsDense, else work in place in global
-// memory (leading dimension n either way).
-__device__ inline double* dense_buffer(double* lds, double* global, int n) {
-  if (n > kLdsDense) return global;
-  for (int idx = threadIdx.x; idx < n * n; idx += kThreads) lds[idx] = global[idx];
+// The n x n factorisations below run with kDenseThreads threads (16 waves), so
+// that one workgroup per CU (the LDS copy takes up to 130 KB) still hides LDS
+// latency.  Loops are two-dimensional (wave -> rows, lane -> columns): no
+// integer division in the inner loops.
+constexpr int kDenseThreads = 1024;
+constexpr int kDenseWaves = kDenseThreads / 64;
+
+// Work copy of an n x n matrix: in LDS with an odd leading dimension n + 1 when
+// n <= kLdsDense, else in place in global memory (leading dimension n).
+struct Dense {
+  double* a;
+  int ld;
+};
+
+__device__ inline Dense dense_load(double* lds, double* global, int n) {
+  if (n > kLdsDense) return Dense{global, n};
+  const int ld = n + 1, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int r = wave; r < n; r += kDenseWaves)
+    for (int c = lane; c < n; c += 64) lds[r * ld + c] = global[(size_t)r * n + c];
   __syncthreads();
-  return lds;
+  return Dense{lds, ld};
 }
 
-// Cholesky W = R^T R (R upper) of the Gram matrix, then R^{-1} in place.
-// which = 0: first pass (sets the checkpoint's log|det T|), 1: second (adds).
-__global__ __launch_bounds__(kThreads) void k_chol_inv(const ChainDev* __restrict__ chains,
-                                                       int which) {
-  const int lg = xcd_remap(blockIdx.x, gridDim.x);
-  const ChainDev& C = chains[lg >> 1];
-  const int sp = lg & 1, n = C.n[sp], tid = threadIdx.x;
-  __shared__ double lds[kLdsDense * kLdsDense];
-  __shared__ double tmp[kMaxSites];
-  __shared__ int bad;
-  if (tid == 0) bad = 0;
-  double* A = dense_buffer(lds, C.Wm[sp], n);
-  for (int j = 0; j < n; ++j) {
-    const double d2 = A[j * n + j];
-    __syncthreads();
-    if (!(d2 > 0.0)) {   // not positive definite (or NaN): flag, keep going finitely
-      if (tid == 0) {
-        bad = 1;
-        A[j * n + j] = 1.0;
+__device__ inline void dense_store(const Dense& A, double* global, int n, bool upper_only) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int r = wave; r < n; r += kDenseWaves)
+    for (int c = lane; c < n; c += 64)
+      global[(size_t)r * n + c] = (upper_only && c < r) ? 0.0 : A.a[r * A.ld + c];
+}
+
+// In-place Gauss-Jordan inversion with partial (row) pivoting; the column
+// interchanges are undone in reverse order at the end.  triangular: the input
+// is upper triangular with nonzero diagonal (no pivoting; elimination only
+// touches rows above the pivot and columns from it on).  Returns log|det| and
+// the sign of det (0 if singular) to every thread.
+__device__ void gj_invert(const Dense& D, int n, bool triangular, double* colk, int* piv,
+                          double* rv, int* ri, double& logabs, int& sgn) {
+  double* A = D.a;
+  const int ld = D.ld;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  logabs = 0.0;
+  sgn = 1;
+  for (int k = 0; k < n; ++k) {
+    int p = k;
+    if (!triangular) {
+      double best = -1.0;
+      int bi = k;
+      for (int i = k + tid; i < n; i += kDenseThreads) {
+        const double v = fabs(A[i * ld + k]);
+        if (v > best) {
+          best = v;
+          bi = i;
+        }
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o, 64);
+        const int oi = __shfl_xor(bi, o, 64);
+        if (ob > best || (ob == best && oi < bi)) {
+          best = ob;
+          bi = oi;
+        }
+      }
+      if (lane == 0) {
+        rv[wave] = best;
+        ri[wave] = bi;
       }
       __syncthreads();
-      continue;
-    }
-    const double d = sqrt(d2);
-    for (int c = j + 1 + tid; c < n; c += kThreads) A[j * n + c] /= d;
-    if (tid == 0) A[j * n + j] = d;
-    __syncthreads();
-    const int m = n - j - 1;
-    for (int idx = tid; idx < m * m; idx += kThreads) {
-      const int r = j + 1 + idx / m, c = j + 1 + idx % m;
-      if (c >= r) A[r * n + c] -= A[j * n + r] * A[j * n + c];
-    }
-    __syncthreads();
-  }
-  if (tid == 0) {
-    double lsum = 0.0;
-    for (int j = 0; j < n; ++j) lsum += log(A[j * n + j]);
-    if (which == 0) {
-      C.st->chk_log[sp] = lsum;
-      C.st->chk_sgn[sp] = 1;
-    } else {
-      C.st->chk_log[sp] += lsum;
-    }
-    if (bad) atomicOr(&C.st->flags, (int)FLAG_SINGULAR);
-  }
-  // in-place inverse of the upper-triangular factor, column by column:
-  // Rinv[0:j, j] = -Rinv[j][j] * Rinv[0:j, 0:j] R[0:j, j]
-  for (int j = 0; j < n; ++j) {
-    for (int k = tid; k < j; k += kThreads) tmp[k] = A[k * n + j];
-    __syncthreads();
-    const double inv = 1.0 / A[j * n + j];
-    for (int i = tid; i < j; i += kThreads) {
-      double y = 0.0;
-      for (int k = i; k < j; ++k) y += A[i * n + k] * tmp[k];
-      A[i * n + j] = -inv * y;
-    }
-    __syncthreads();
-    if (tid == 0) A[j * n + j] = inv;
-    __syncthreads();
-  }
-  double* out = C.Rinv[sp];
-  for (int idx = tid; idx < n * n; idx += kThreads) {
-    const int r = idx / n, c = idx - r * n;
-    out[idx] = (c >= r) ? A[idx] : 0.0;
-  }
-}
-
-// Inverse of X = L R (n x n) in place by Gauss-Jordan elimination with partial
-// (row) pivoting; the column interchanges are undone in reverse order at the
-// end.  log|det X| and its sign go to the chain state.
-__global__ __launch_bounds__(kThreads) void k_gj_inv(const ChainDev* __restrict__ chains) {
-  const int lg = xcd_remap(blockIdx.x, gridDim.x);
-  const ChainDev& C = chains[lg >> 1];
-  const int sp = lg & 1, n = C.n[sp], tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  __shared__ double lds[kLdsDense * kLdsDense];
-  __shared__ double colk[kMaxSites];
-  __shared__ int piv[kMaxSites];
-  __shared__ double rv[4];
-  __shared__ int ri[4];
-  double* A = dense_buffer(lds, C.Xm[sp], n);
-  double logabs = 0.0;
-  int sgn = 1;
-  bool singular = false;
-  for (int k = 0; k < n; ++k) {
-    double best = -1.0;
-    int bi = k;
-    for (int i = k + tid; i < n; i += kThreads) {
-      const double v = fabs(A[i * n + k]);
-      if (v > best) {
-        best = v;
-        bi = i;
+      p = ri[0];
+      double pb = rv[0];
+      for (int w = 1; w < kDenseWaves; ++w)
+        if (rv[w] > pb || (rv[w] == pb && ri[w] < p)) {
+          pb = rv[w];
+          p = ri[w];
+        }
+      if (p != k) {
+        for (int c = tid; c < n; c += kDenseThreads) {
+          const double t = A[k * ld + c];
+          A[k * ld + c] = A[p * ld + c];
+          A[p * ld + c] = t;
+        }
+        sgn = -sgn;
       }
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      const double ob = __shfl_xor(best, o, 64);
-      const int oi = __shfl_xor(bi, o, 64);
-      if (ob > best || (ob == best && oi < bi)) {
-        best = ob;
-        bi = oi;
-      }
-    }
-    if (lane == 0) {
-      rv[wave] = best;
-      ri[wave] = bi;
-    }
-    __syncthreads();
-    int p = ri[0];
-    double pb = rv[0];
-    for (int w = 1; w < 4; ++w)
-      if (rv[w] > pb || (rv[w] == pb && ri[w] < p)) {
-        pb = rv[w];
-        p = ri[w];
-      }
-    if (p != k) {
-      for (int c = tid; c < n; c += kThreads) {
-        const double t = A[k * n + c];
-        A[k * n + c] = A[p * n + c];
-        A[p * n + c] = t;
-      }
-      sgn = -sgn;
     }
     if (tid == 0) piv[k] = p;
     __syncthreads();
-    const double pv = A[k * n + k];
+    const double pv = A[k * ld + k];
     if (pv == 0.0 || pv != pv) {
-      singular = true;
-      break;
+      sgn = 0;
+      return;
     }
     logabs += log(fabs(pv));
     if (pv < 0) sgn = -sgn;
     const double ipv = 1.0 / pv;
     __syncthreads();
-    for (int c = tid; c < n; c += kThreads) A[k * n + c] = (c == k) ? ipv : A[k * n + c] * ipv;
-    for (int i = tid; i < n; i += kThreads) colk[i] = A[i * n + k];
+    const int c0 = triangular ? k : 0;
+    for (int c = c0 + tid; c < n; c += kDenseThreads) A[k * ld + c] = (c == k) ? ipv : A[k * ld + c] * ipv;
+    const int rend = triangular ? k : n;
+    for (int i = tid; i < rend; i += kDenseThreads) colk[i] = (i == k) ? 0.0 : A[i * ld + k];
     __syncthreads();
-    for (int idx = tid; idx < n * n; idx += kThreads) {
-      const int i = idx / n, c = idx - i * n;
+    for (int i = wave; i < rend; i += kDenseWaves) {
       if (i == k) continue;
       const double t = colk[i];
-      A[idx] = (c == k) ? -t * ipv : A[idx] - t * A[k * n + c];
+      if (t == 0.0) continue;
+      for (int c = c0 + lane; c < n; c += 64)
+        A[i * ld + c] = (c == k) ? -t * ipv : A[i * ld + c] - t * A[k * ld + c];
     }
     __syncthreads();
   }
-  if (!singular) {
+  if (!triangular)
     for (int k = n - 1; k >= 0; --k) {
       const int p = piv[k];
       if (p != k)
-        for (int r = tid; r < n; r += kThreads) {
-          const double t = A[r * n + k];
-          A[r * n + k] = A[r * n + p];
-          A[r * n + p] = t;
+        for (int r = tid; r < n; r += kDenseThreads) {
+          const double t = A[r * ld + k];
+          A[r * ld + k] = A[r * ld + p];
+          A[r * ld + p] = t;
         }
       __syncthreads();
     }
-    if (A != C.Xm[sp])
-      for (int idx = tid; idx < n * n; idx += kThreads) C.Xm[sp][idx] = A[idx];
+}
+
+// Cholesky W = R^T R (R upper) of the Gram matrix of the basis, then R^{-1}.
+// log|det R| is the checkpoint's log|det T| (R has a positive diagonal).
+__global__ __launch_bounds__(kDenseThreads) void k_chol_inv(const ChainDev* __restrict__ chains) {
+  const int lg = xcd_remap(blockIdx.x, gridDim.x);
+  const ChainDev& C = chains[lg >> 1];
+  const int sp = lg & 1, n = C.n[sp], tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ double lds[kLdsDense * (kLdsDense + 1)];
+  __shared__ double colk[kMaxSites];
+  __shared__ int piv[kMaxSites];
+  __shared__ double rv[kDenseWaves];
+  __shared__ int ri[kDenseWaves];
+  __shared__ int bad;
+  if (tid == 0) bad = 0;
+  const Dense D = dense_load(lds, C.Wm[sp], n);
+  double* A = D.a;
+  const int ld = D.ld;
+  for (int j = 0; j < n; ++j) {
+    const double d2 = A[j * ld + j];
+    __syncthreads();
+    if (!(d2 > 0.0)) {   // not positive definite (or NaN): flag, keep going finitely
+      if (tid == 0) {
+        bad = 1;
+        A[j * ld + j] = 1.0;
+      }
+      __syncthreads();
+      continue;
+    }
+    const double d = sqrt(d2);
+    for (int c = j + 1 + tid; c < n; c += kDenseThreads) A[j * ld + c] /= d;
+    if (tid == 0) A[j * ld + j] = d;
+    __syncthreads();
+    for (int r = j + 1 + wave; r < n; r += kDenseWaves) {
+      const double ajr = A[j * ld + r];
+      for (int c = r + lane; c < n; c += 64) A[r * ld + c] -= ajr * A[j * ld + c];
+    }
+    __syncthreads();
   }
+  for (int r = wave; r < n; r += kDenseWaves)   // clear the lower triangle
+    for (int c = lane; c < r; c += 64) A[r * ld + c] = 0.0;
+  __syncthreads();
+  if (tid == 0) {
+    double lsum = 0.0;
+    for (int j = 0; j < n; ++j) lsum += log(A[j * ld + j]);
+    C.st->chk_log[sp] = lsum;
+    C.st->chk_sgn[sp] = 1;
+    if (bad) atomicOr(&C.st->flags, (int)FLAG_SINGULAR);
+  }
+  double la;
+  int sg;
+  gj_invert(D, n, true, colk, piv, rv, ri, la, sg);
+  __syncthreads();
+  dense_store(D, C.Rinv[sp], n, true);
+}
+
+// Inverse of X = L R (n x n) in place; log|det X| and its sign go to the
+// chain state.
+__global__ __launch_bounds__(kDenseThreads) void k_gj_inv(const ChainDev* __restrict__ chains) {
+  const int lg = xcd_remap(blockIdx.x, gridDim.x);
+  const ChainDev& C = chains[lg >> 1];
+  const int sp = lg & 1, n = C.n[sp], tid = threadIdx.x;
+  __shared__ double lds[kLdsDense * (kLdsDense + 1)];
+  __shared__ double colk[kMaxSites];
+  __shared__ int piv[kMaxSites];
+  __shared__ double rv[kDenseWaves];
+  __shared__ int ri[kDenseWaves];
+  const Dense D = dense_load(lds, C.Xm[sp], n);
+  double logabs;
+  int sgn;
+  gj_invert(D, n, false, colk, piv, rv, ri, logabs, sgn);
+  __syncthreads();
+  if (sgn != 0 && D.a != C.Xm[sp]) dense_store(D, C.Xm[sp], n, false);
   if (tid == 0) {
     C.st->x_log[sp] = logabs;
-    C.st->x_sgn[sp] = singular ? 0 : sgn;
-    if (singular) atomicOr(&C.st->flags, (int)FLAG_SINGULAR);
+    C.st->x_sgn[sp] = sgn;
+    if (sgn == 0) atomicOr(&C.st->flags, (int)FLAG_SINGULAR);
   }
 }
 
-// FP32 basis variant: the checkpoint starts from an FP64 copy of the basis.
+// FP32 basis variant: the checkpoint starts from an FP64 copy (in Hw) of the basis.
 template <typename Tu>
 __global__ __launch_bounds__(kThreads) void k_basis_to_fp64(const ChainDev* __restrict__ chains,
                                                             int parity) {
   const ChainDev& C = chains[xcd_remap(blockIdx.x, gridDim.x)];
   for (int sp = 0; sp < 2; ++sp) {
     const Tu* u = (const Tu*)C.U[sp][parity];
-    for (int idx = threadIdx.x; idx < C.N * C.n[sp]; idx += kThreads) C.Qc[sp][idx] = (double)u[idx];
+    for (int idx = threadIdx.x; idx < C.N * C.n[sp]; idx += kThreads) C.Hw[sp][idx] = (double)u[idx];
   }
 }
 
@@ -345,13 +374,13 @@ __global__ void k_set_ctl(Ctl* ctl, int measure, int force_reject, float drift_t
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-hipError_t launch_chol_inv(const ChainDev* c, int nc, int which, hipStream_t s) {
-  hipLaunchKernelGGL(k_chol_inv, dim3(2 * nc), dim3(kThreads), 0, s, c, which);
+hipError_t launch_chol_inv(const ChainDev* c, int nc, hipStream_t s) {
+  hipLaunchKernelGGL(k_chol_inv, dim3(2 * nc), dim3(kDenseThreads), 0, s, c);
   return hipGetLastError();
 }
 
 hipError_t launch_gj_inv(const ChainDev* c, int nc, hipStream_t s) {
-  hipLaunchKernelGGL(k_gj_inv, dim3(2 * nc), dim3(kThreads), 0, s, c);
+  hipLaunchKernelGGL(k_gj_inv, dim3(2 * nc), dim3(kDenseThreads), 0, s, c);
   return hipGetLastError();
 }
 

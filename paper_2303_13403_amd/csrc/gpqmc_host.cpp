@@ -24,7 +24,7 @@ hipError_t launch_gemm_plain(int fp32, int transA, const GemmEntry* e, const Til
                              GemmArgs a, hipStream_t s);
 hipError_t launch_scan(int fp32, const ChainDev* c, int nc, const Ctl* ctl, int l, int M, int s0,
                        int s1, hipStream_t s);
-hipError_t launch_chol_inv(const ChainDev* c, int nc, int which, hipStream_t s);
+hipError_t launch_chol_inv(const ChainDev* c, int nc, hipStream_t s);
 hipError_t launch_gj_inv(const ChainDev* c, int nc, hipStream_t s);
 hipError_t launch_basis_to_fp64(int fp32b, const ChainDev* c, int nc, int parity, hipStream_t s);
 hipError_t launch_finalize(int fp32b, const ChainDev* c, int nc, const Ctl* ctl, int slot, int mode,
@@ -150,7 +150,7 @@ struct gpqmc_ctx {
   // layout
   size_t bytes = 0;
   size_t off_chains = 0, off_ctl = 0;
-  size_t off_ent[14] = {0};
+  size_t off_ent[16] = {0};
   // tile lists: N x N, N x n, n x n, n x N and (delay rank) x N outputs
   std::vector<TileRef> tiles[5];
   size_t off_tiles[5] = {0};
@@ -172,7 +172,7 @@ struct gpqmc_ctx {
 namespace {
 
 enum EntryKind { E_WRAP1_UP = 0, E_WRAP2_UP, E_WRAP1_DN, E_WRAP2_DN, E_T1, E_FLUSH, E_PROP,
-                 E_GRAM_U, E_APPLY1, E_GRAM_H, E_APPLY2, E_XMAT, E_YMAT, E_GFRESH, E_COUNT };
+                 E_GRAM_U, E_APPLY1, E_XMAT, E_YMAT, E_GFRESH, E_COUNT };
 enum TileKind { T_NN = 0, T_Nn, T_nn, T_nN, T_sN };
 
 gpqmc_status fail(gpqmc_ctx* c, gpqmc_status s, const std::string& msg) {
@@ -223,7 +223,7 @@ struct Launcher {
   }
 
   // checkpoint at position p: re-orthonormalise the active basis U[parity]
-  // (Cholesky QR twice), recompute G = 1 - R (L R)^{-1} L from the stored
+  // (Cholesky QR), recompute G = 1 - R (L R)^{-1} L from the stored
   // opposite-side basis, check the sign, store the new basis.
   hipError_t checkpoint(int p, int dir, int parity, int next_scale, int measure, int ck_index,
                         int mode) {
@@ -232,11 +232,8 @@ struct Launcher {
     a.parity = parity;
     if (ctx->fp32b && (e = launch_basis_to_fp64(1, chains, nc, parity, s)) != hipSuccess) return e;
     if ((e = gemm(E_GRAM_U, GM_GRAM, T_nn, a)) != hipSuccess) return e;
-    if ((e = launch_chol_inv(chains, nc, 0, s)) != hipSuccess) return e;
+    if ((e = launch_chol_inv(chains, nc, s)) != hipSuccess) return e;
     if ((e = gemm(E_APPLY1, GM_APPLY, T_Nn, a)) != hipSuccess) return e;
-    if ((e = gemm(E_GRAM_H, GM_GRAM, T_nn, a)) != hipSuccess) return e;
-    if ((e = launch_chol_inv(chains, nc, 1, s)) != hipSuccess) return e;
-    if ((e = gemm(E_APPLY2, GM_APPLY, T_Nn, a)) != hipSuccess) return e;
     const int sl = ctx->slot(p);
     if (mode == 2) return launch_finalize(ctx->fp32b, chains, nc, ctl, sl, 2, 0, -1, parity, s);
     a.slot = sl;
@@ -732,13 +729,11 @@ gpqmc_status gpqmc_bind_workspace(gpqmc_ctx* ctx, void* device_ptr, size_t bytes
       E[E_FLUSH][ei] = fl;
       const void* Kmb = ctx->ws + L.off_Kmb;
       E[E_PROP][ei] = mk(Kmb, Kmb, d.U[sp][0], d.U[sp][1], d.U[sp][0], d.U[sp][1], N, n, N, N, n, n);
-      // checkpoint: Cholesky QR of U[parity] (or of its FP64 copy in Qc)
-      const void* src0 = ctx->fp32b ? (const void*)d.Qc[sp] : d.U[sp][0];
-      const void* src1 = ctx->fp32b ? (const void*)d.Qc[sp] : d.U[sp][1];
+      // checkpoint: Cholesky QR of U[parity] (or of its FP64 copy in Hw)
+      const void* src0 = ctx->fp32b ? (const void*)d.Hw[sp] : d.U[sp][0];
+      const void* src1 = ctx->fp32b ? (const void*)d.Hw[sp] : d.U[sp][1];
       E[E_GRAM_U][ei] = mk(src0, src1, nullptr, nullptr, d.Wm[sp], d.Wm[sp], n, n, N, n, n, n);
-      E[E_APPLY1][ei] = mk(src0, src1, d.Rinv[sp], d.Rinv[sp], d.Hw[sp], d.Hw[sp], N, n, n, n, n, n);
-      E[E_GRAM_H][ei] = mk(d.Hw[sp], d.Hw[sp], nullptr, nullptr, d.Wm[sp], d.Wm[sp], n, n, N, n, n, n);
-      E[E_APPLY2][ei] = mk(d.Hw[sp], d.Hw[sp], d.Rinv[sp], d.Rinv[sp], d.Qc[sp], d.Qc[sp], N, n, n, n, n, n);
+      E[E_APPLY1][ei] = mk(src0, src1, d.Rinv[sp], d.Rinv[sp], d.Qc[sp], d.Qc[sp], N, n, n, n, n, n);
       GemmEntry xm = mk(nullptr, nullptr, nullptr, nullptr, d.Xm[sp], d.Xm[sp], n, n, N, n, n, n);
       xm.stack = d.stack[sp];
       xm.Qc = d.Qc[sp];

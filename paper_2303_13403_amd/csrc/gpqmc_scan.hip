@@ -46,7 +46,7 @@ __global__ __launch_bounds__(kThreads) void k_scan(const ChainDev* __restrict__ 
   __shared__ T Hs[2][kBlock][KP];
   __shared__ T Gt[2][kBlock][KP];
   __shared__ T Zb[2][kBlock][KP];
-  __shared__ T colb[2][kBlock], rowb[2][kBlock], uvec[2][kBlock], vvec[2][kBlock];
+  __shared__ T rowb[2][kBlock], uvec[2][kBlock], vvec[2][kBlock];
   __shared__ T Rsf[kBlock * kSegMax];
   __shared__ int Fb[kBlock];
   __shared__ int sh_f, sh_fb, sh_sign, sh_acc;
@@ -87,10 +87,8 @@ __global__ __launch_bounds__(kThreads) void k_scan(const ChainDev* __restrict__ 
     // ---- W1 = G0[S, F] Z  (kb x f), one spin at a time through LDS ----
     if (f > 0) {
       for (int s = 0; s < 2; ++s) {
-        for (int idx = tid; idx < kb * f; idx += kThreads) {
-          const int a = idx / f, p = idx - a * f;
-          Rsf[a * f + p] = G0[s][(size_t)(b0 + a) * N + Fs[p]];
-        }
+        for (int a = wave; a < kb; a += 4)
+          for (int p = lane; p < f; p += 64) Rsf[a * f + p] = G0[s][(size_t)(b0 + a) * N + Fs[p]];
         __syncthreads();
         for (int q = tid; q < f; q += kThreads) {
           T acc[kBlock];
@@ -110,17 +108,26 @@ __global__ __launch_bounds__(kThreads) void k_scan(const ChainDev* __restrict__ 
       }
     }
     // ---- block of the current Green's function: G[S,S] = G0[S,S] + W1 G0[F,S] ----
-    for (int idx = tid; idx < 2 * kb * kb; idx += kThreads) {
-      const int s = idx / (kb * kb), r = idx - s * kb * kb, a = r / kb, bb = r - a * kb;
-      T acc = G0[s][(size_t)(b0 + a) * N + b0 + bb];
-      for (int q = 0; q < f; ++q) acc += W1[s][(size_t)a * LDZ + q] * G0[s][(size_t)Fs[q] * N + b0 + bb];
-      Gt[s][a][bb] = acc;
-      Hs[s][a][bb] = acc;
+    // rows (spin, a) over waves and lane halves, columns over lanes 0..31
+    {
+      const int half = lane >> 5, c = lane & 31;
+      for (int row = 2 * wave + half; row < 2 * kb; row += 8) {
+        const int s = row >= kb ? 1 : 0, a = row - s * kb;
+        if (c < kb) {
+          T acc = G0[s][(size_t)(b0 + a) * N + b0 + c];
+          for (int q = 0; q < f; ++q)
+            acc += W1[s][(size_t)a * LDZ + q] * G0[s][(size_t)Fs[q] * N + b0 + c];
+          Gt[s][a][c] = acc;
+          Hs[s][a][c] = acc;
+        }
+      }
     }
     __syncthreads();
 
     // ---- sequential proposals of the block: one wave, rank-1 updates ----
+    // lane = (spin s, row a): colb/rowb, u/v and the row-wise updates
     if (wave == 0) {
+      const int s = lane >> 5, a = lane & 31;
       int fb = 0, sign = sh_sign, nacc = 0;
       for (int j = 0; j < kb; ++j) {
         const int li = b0 + j - s0;
@@ -135,33 +142,35 @@ __global__ __launch_bounds__(kThreads) void k_scan(const ChainDev* __restrict__ 
         }
         if (!accept) continue;
         if (!zero_delta) {
-          const int s = lane >> 5, a = lane & 31;
+          T col = T(0);
           if (a < kb) {
-            colb[s][a] = Gt[s][a][j];
+            col = Gt[s][a][j];
             rowb[s][a] = (a == j ? T(1) : T(0)) - Gt[s][j][a];
           }
-          if (a <= fb) {
-            T uu = (a == fb) ? T(1) : T(0), vv = uu;
-            if (a < fb) {   // row/column fb of Zb is the new (still zero) one
-              for (int c = 0; c < fb; ++c) {
-                uu += Zb[s][a][c] * Hs[s][Fb[c]][j];
-                vv += Zb[s][c][a] * Hs[s][j][Fb[c]];
-              }
+          T uu = (a == fb) ? T(1) : T(0), vv = uu;
+          if (a < fb) {   // row/column fb of Zb is the new (still zero) one
+            for (int c = 0; c < fb; ++c) {
+              uu += Zb[s][a][c] * Hs[s][Fb[c]][j];
+              vv += Zb[s][c][a] * Hs[s][j][Fb[c]];
             }
+          }
+          if (a <= fb) {
             uvec[s][a] = uu;
             vvec[s][a] = vv;
           }
           wave_sync();
-          const T coef[2] = {(T)(du / ru), (T)(dd / rd)};
-          for (int idx = lane; idx < 2 * kb * kb; idx += 64) {
-            const int s2 = idx / (kb * kb), r = idx - s2 * kb * kb, a2 = r / kb, bb = r - a2 * kb;
-            Gt[s2][a2][bb] -= coef[s2] * colb[s2][a2] * rowb[s2][bb];
+          const T coef = (T)((s == 0 ? du : dd) / (s == 0 ? ru : rd));
+          if (a < kb) {
+            const T cc = coef * col;
+            for (int bb = 0; bb < kb; ++bb) Gt[s][a][bb] -= cc * rowb[s][bb];
           }
           const int fb1 = fb + 1;
-          for (int idx = lane; idx < 2 * fb1 * fb1; idx += 64) {
-            const int s2 = idx / (fb1 * fb1), r = idx - s2 * fb1 * fb1, p = r / fb1, q = r - p * fb1;
-            const T base = (p < fb && q < fb) ? Zb[s2][p][q] : T(0);
-            Zb[s2][p][q] = base + coef[s2] * uvec[s2][p] * vvec[s2][q];
+          if (a < fb1) {
+            const T cu = coef * uu;
+            for (int q = 0; q < fb1; ++q) {
+              const T base = (a < fb && q < fb) ? Zb[s][a][q] : T(0);
+              Zb[s][a][q] = base + cu * vvec[s][q];
+            }
           }
           if (lane == 0) Fb[fb] = j;
           fb = fb1;
@@ -180,60 +189,60 @@ __global__ __launch_bounds__(kThreads) void k_scan(const ChainDev* __restrict__ 
     __syncthreads();
 
     // ---- merge the block's Zb into Z ----
+    //   Z <- [[Z + P Zb Q, P Zb], [Zb Q, Zb]],  P = Z G0[F,Fb], Q = G0[Fb,F] Z
     const int fb = sh_fb;
     if (fb > 0) {
       if (f > 0) {
-        const int tot = f * fb;
-        for (int idx = tid; idx < 4 * tot; idx += kThreads) {
-          const int s = idx / (2 * tot), r0 = idx - s * 2 * tot;
-          if (r0 < tot) {  // P[p][c] = sum_q Z[p][q] G0[F_q][Fb_c]
-            const int p = r0 / fb, c = r0 - p * fb;
-            const int col = b0 + Fb[c];
-            T acc = 0;
-            for (int q = 0; q < f; ++q) acc += Z[s][(size_t)p * LDZ + q] * G0[s][(size_t)Fs[q] * N + col];
-            Pm[s][p * kBlock + c] = acc;
-          } else {         // Q[c][q] = sum_p G0[Fb_c][F_p] Z[p][q]
-            const int r = r0 - tot, c = r / f, q = r - c * f;
+        for (int s = 0; s < 2; ++s) {
+          // P (f x fb): rows over waves, columns over lanes; Q (fb x f) likewise
+          for (int p = wave; p < f; p += 4)
+            for (int c = lane; c < fb; c += 64) {
+              const int col = b0 + Fb[c];
+              T acc = 0;
+              for (int q = 0; q < f; ++q) acc += Z[s][(size_t)p * LDZ + q] * G0[s][(size_t)Fs[q] * N + col];
+              Pm[s][p * kBlock + c] = acc;
+            }
+          for (int c = wave; c < fb; c += 4) {
             const T* row = G0[s] + (size_t)(b0 + Fb[c]) * N;
-            T acc = 0;
-            for (int p = 0; p < f; ++p) acc += row[Fs[p]] * Z[s][(size_t)p * LDZ + q];
-            Qm[s][c * LDZ + q] = acc;
+            for (int q = lane; q < f; q += 64) {
+              T acc = 0;
+              for (int p = 0; p < f; ++p) acc += row[Fs[p]] * Z[s][(size_t)p * LDZ + q];
+              Qm[s][c * LDZ + q] = acc;
+            }
           }
         }
         __syncthreads();
-        for (int idx = tid; idx < 4 * tot; idx += kThreads) {
-          const int s = idx / (2 * tot), r0 = idx - s * 2 * tot;
-          if (r0 < tot) {  // PZb[p][c]
-            const int p = r0 / fb, c = r0 - p * fb;
-            T acc = 0;
-            for (int d = 0; d < fb; ++d) acc += Pm[s][p * kBlock + d] * Zb[s][d][c];
-            PZ[s][p * kBlock + c] = acc;
-          } else {         // ZbQ[c][q]
-            const int r = r0 - tot, c = r / f, q = r - c * f;
-            T acc = 0;
-            for (int d = 0; d < fb; ++d) acc += Zb[s][c][d] * Qm[s][d * LDZ + q];
-            ZQ[s][c * LDZ + q] = acc;
-          }
+        for (int s = 0; s < 2; ++s) {
+          for (int p = wave; p < f; p += 4)
+            for (int c = lane; c < fb; c += 64) {
+              T acc = 0;
+              for (int d = 0; d < fb; ++d) acc += Pm[s][p * kBlock + d] * Zb[s][d][c];
+              PZ[s][p * kBlock + c] = acc;
+            }
+          for (int c = wave; c < fb; c += 4)
+            for (int q = lane; q < f; q += 64) {
+              T acc = 0;
+              for (int d = 0; d < fb; ++d) acc += Zb[s][c][d] * Qm[s][d * LDZ + q];
+              ZQ[s][c * LDZ + q] = acc;
+            }
         }
         __syncthreads();
-        for (int idx = tid; idx < 2 * f * f; idx += kThreads) {
-          const int s = idx / (f * f), r = idx - s * f * f, p = r / f, q = r - p * f;
-          T acc = Z[s][(size_t)p * LDZ + q];
-          for (int c = 0; c < fb; ++c) acc += PZ[s][p * kBlock + c] * Qm[s][c * LDZ + q];
-          Z[s][(size_t)p * LDZ + q] = acc;
-        }
-        for (int idx = tid; idx < 2 * tot; idx += kThreads) {
-          const int s = idx / tot, r = idx - s * tot;
-          const int p = r / fb, c = r - p * fb;
-          Z[s][(size_t)p * LDZ + f + c] = PZ[s][p * kBlock + c];
-          const int c2 = r / f, q = r - c2 * f;
-          Z[s][(size_t)(f + c2) * LDZ + q] = ZQ[s][c2 * LDZ + q];
+        for (int s = 0; s < 2; ++s) {
+          for (int p = wave; p < f; p += 4)
+            for (int q = lane; q < f; q += 64) {
+              T acc = Z[s][(size_t)p * LDZ + q];
+              for (int c = 0; c < fb; ++c) acc += PZ[s][p * kBlock + c] * Qm[s][c * LDZ + q];
+              Z[s][(size_t)p * LDZ + q] = acc;
+            }
+          for (int p = wave; p < f; p += 4)
+            for (int c = lane; c < fb; c += 64) Z[s][(size_t)p * LDZ + f + c] = PZ[s][p * kBlock + c];
+          for (int c = wave; c < fb; c += 4)
+            for (int q = lane; q < f; q += 64) Z[s][(size_t)(f + c) * LDZ + q] = ZQ[s][c * LDZ + q];
         }
       }
-      for (int idx = tid; idx < 2 * fb * fb; idx += kThreads) {
-        const int s = idx / (fb * fb), r = idx - s * fb * fb, c = r / fb, d = r - c * fb;
-        Z[s][(size_t)(f + c) * LDZ + f + d] = Zb[s][c][d];
-      }
+      for (int s = 0; s < 2; ++s)
+        for (int c = wave; c < fb; c += 4)
+          for (int d = lane; d < fb; d += 64) Z[s][(size_t)(f + c) * LDZ + f + d] = Zb[s][c][d];
       if (tid < fb) Fs[f + tid] = b0 + Fb[tid];
       __syncthreads();
       if (tid == 0) sh_f = f + fb;
@@ -243,16 +252,16 @@ __global__ __launch_bounds__(kThreads) void k_scan(const ChainDev* __restrict__ 
 
   // operands of the flush: Xg = G0[:, F] (ld LDZ), Yg = (1 - G0)[F, :]
   const int f = sh_f;
-  T* Xg[2] = {(T*)C.Xg[0], (T*)C.Xg[1]};
-  T* Yg[2] = {(T*)C.Yg[0], (T*)C.Yg[1]};
-  for (int idx = tid; idx < 2 * N * f; idx += kThreads) {
-    const int s = idx / (N * f), r = idx - s * N * f, i = r / f, p = r - i * f;
-    Xg[s][(size_t)i * LDZ + p] = G0[s][(size_t)i * N + Fs[p]];
-  }
-  for (int idx = tid; idx < 2 * N * f; idx += kThreads) {
-    const int s = idx / (N * f), r = idx - s * N * f, p = r / N, j = r - p * N;
-    const int site = Fs[p];
-    Yg[s][(size_t)p * N + j] = (site == j ? T(1) : T(0)) - G0[s][(size_t)site * N + j];
+  for (int s = 0; s < 2; ++s) {
+    T* Xg = (T*)C.Xg[s];
+    T* Yg = (T*)C.Yg[s];
+    for (int i = wave; i < N; i += 4)
+      for (int p = lane; p < f; p += 64) Xg[(size_t)i * LDZ + p] = G0[s][(size_t)i * N + Fs[p]];
+    for (int p = wave; p < f; p += 4) {
+      const int site = Fs[p];
+      const T* src = G0[s] + (size_t)site * N;
+      for (int j = lane; j < N; j += 64) Yg[(size_t)p * N + j] = (site == j ? T(1) : T(0)) - src[j];
+    }
   }
   for (int i = tid; i < nseg; i += kThreads) frow[s0 + i] = fs[i];
   if (tid == 0) {
