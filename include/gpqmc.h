@@ -79,7 +79,8 @@ typedef struct {
   double m_neel;              /* Neel order parameter M_N of the trial */
   int32_t l_half;             /* slices per side, Theta / dtau (>= 0) */
   int32_t stab_interval;      /* n_s: slices between QR re-stabilisations (>= 1) */
-  int32_t delay_rank;         /* k: sites per block of the delayed scan (1 .. 32) */
+  int32_t delay_rank;         /* k: sites per segment of the delayed scan (1 .. 128); each
+                                 segment ends with one rank-(accepted) update of G */
   int32_t precision;          /* gpqmc_precision */
   uint64_t seed;              /* Philox key; words (lo32(seed), hi32(seed) ^ tag) */
   uint64_t chain_id;          /* counter word 0 of every draw of this chain */
@@ -196,10 +197,12 @@ gpqmc_status gpqmc_time_kernel(gpqmc_ctx* ctx, int32_t kernel, int32_t reps, flo
 
 /* Debugging hooks (off the hot path; synchronise).  debug_step runs one
  * stage of slice l on every chain: 0 = the flip scan of sites [s0, s1),
- * 1 = T1 = Z Yg, 2 = the flush G -= Xg T1 (no frame change).  debug_read copies
- * an internal buffer of one chain and spin as doubles: 0 = G, 1 = Z (ld 128),
- * 2 = Xg (ld 128), 3 = Yg (ld N), 4 = T1 (ld N), 5 = (accepted count of the
- * last segment, sign, accepted total). */
+ * 1 = the delayed-update flush of that segment into G (no frame change).
+ * debug_read copies at most `count` elements of an internal buffer of one
+ * chain and spin as doubles: 0 = G (N x N), 1 = Z (128 x 128), 2 = the
+ * accepted sites of the last segment (128), 3 = Yg (rows of 1 - G, ld N),
+ * 5 = (accepted count of the last segment, sign, accepted total).  A count
+ * beyond the buffer is GPQMC_EINVAL. */
 gpqmc_status gpqmc_debug_step(gpqmc_ctx* ctx, int32_t stage, int32_t l, int32_t s0, int32_t s1);
 gpqmc_status gpqmc_debug_read(gpqmc_ctx* ctx, int32_t chain, int32_t what, int32_t spin, double* out,
                               int64_t count);

@@ -217,6 +217,295 @@ __global__ __launch_bounds__(kDenseThreads) void k_gj_inv(const ChainDev* __rest
   }
 }
 
+// ---------------------------------------------------------------------------
+// Register-tiled variants for n <= 16 NB (the usual case).  One 256-thread
+// workgroup per matrix; thread t owns the elements (ti + 16 a, tj + 16 b),
+// ti = t / 16, tj = t % 16, in m[a][b], so a row segment is 16 consecutive
+// lanes (coalesced loads).  Every elimination step publishes the rows and the
+// column it needs in double-buffered LDS vectors and updates the registers.
+// ---------------------------------------------------------------------------
+constexpr int kRtMax = 128;
+
+template <int NB>
+struct RegTile {
+  double m[NB][NB];
+  int ti, tj, n;
+  __device__ void load(const double* __restrict__ g, int n_) {
+    n = n_;
+    ti = threadIdx.x >> 4;
+    tj = threadIdx.x & 15;
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int r = ti + 16 * a, c = tj + 16 * b;
+        m[a][b] = (r < n && c < n) ? g[(size_t)r * n + c] : 0.0;
+      }
+  }
+  // row r (owned by ti == r % 16) into v[c]; column c (tj == c % 16) into v[r]
+  __device__ void put_row(int r, double* v) const {
+    if (ti != (r & 15)) return;
+    const int ar = r >> 4;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      double x = 0.0;
+#pragma unroll
+      for (int a = 0; a < NB; ++a) x = (a == ar) ? m[a][b] : x;
+      const int c = tj + 16 * b;
+      if (c < n) v[c] = x;
+    }
+  }
+  __device__ void put_col(int c, double* v) const {
+    if (tj != (c & 15)) return;
+    const int bc = c >> 4;
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+      double x = 0.0;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) x = (b == bc) ? m[a][b] : x;
+      const int r = ti + 16 * a;
+      if (r < n) v[r] = x;
+    }
+  }
+  // one Gauss-Jordan step at pivot k with the pivot row taken from row p:
+  // rk = old row k, rp = old row p, ck = old column k (all in LDS).  The
+  // vector entries are loaded first, the update is branch-free.
+  __device__ void gj_step(int k, int p, double inv, const double* rk, const double* rp,
+                          const double* ck) {
+    double prc[NB], rkc[NB], ckr[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      prc[b] = rp[tj + 16 * b];
+      rkc[b] = rk[tj + 16 * b];
+    }
+#pragma unroll
+    for (int a = 0; a < NB; ++a) ckr[a] = ck[ti + 16 * a];
+    const double fpk = rk[k];   // column-k entry of the row that moves to p
+#pragma unroll
+    for (int b = 0; b < NB; ++b) prc[b] = (tj + 16 * b == k) ? inv : prc[b] * inv;
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+      const int r = ti + 16 * a;
+      const bool isk = r == k, isp = (r == p) & (p != k);
+      const double fr = isp ? fpk : ckr[a];
+      const double nfi = -fr * inv;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const bool colk = tj + 16 * b == k;
+        const double src = isp ? rkc[b] : m[a][b];
+        const double upd = colk ? nfi : fma(-fr, prc[b], src);
+        m[a][b] = isk ? prc[b] : upd;
+      }
+    }
+  }
+};
+
+// In-place inverse.  triangular: upper triangular input, no pivoting.  Returns
+// log|det| (to thread 0) and the sign (0: singular, the tile is then
+// unusable; to every thread);
+// colmap receives, for every column of the eliminated matrix, its column in
+// the inverse.
+template <int NB>
+__device__ void rt_invert(RegTile<NB>& T, bool triangular, double (*rk)[kRtMax],
+                          double (*rp)[kRtMax], double (*ck)[kRtMax], double (*cv)[16],
+                          int (*ci)[16], int* piv, int* colmap, double& logabs, int& sgn) {
+  const int n = T.n, tid = threadIdx.x;
+  logabs = 0.0;
+  sgn = 1;
+  if (tid == 0)
+    for (int c = 0; c < n; ++c) colmap[c] = c;   // ordered by the first step's barrier
+  for (int k = 0; k < n; ++k) {
+    const int kb = k & 1;
+    T.put_row(k, rk[kb]);
+    T.put_col(k, ck[kb]);
+    int p = k;
+    if (!triangular) {
+      // candidates of the owners of column k, one per row residue
+      if (T.tj == (k & 15)) {
+        double best = -1.0;
+        int bi = k;
+        const int bc = k >> 4;
+#pragma unroll
+        for (int a = 0; a < NB; ++a) {
+          double x = 0.0;
+#pragma unroll
+          for (int b = 0; b < NB; ++b) x = (b == bc) ? T.m[a][b] : x;
+          const int r = T.ti + 16 * a;
+          const bool take = (r >= k) & (r < n) & (fabs(x) > best);
+          best = take ? fabs(x) : best;
+          bi = take ? r : bi;
+        }
+        cv[kb][T.ti] = best;
+        ci[kb][T.ti] = bi;
+      }
+      __syncthreads();
+      double vq[16];
+      int iq[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        vq[q] = cv[kb][q];
+        iq[q] = ci[kb][q];
+      }
+      double best = -1.0;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const bool take = (vq[q] > best) | ((vq[q] == best) & (iq[q] < p));
+        best = take ? vq[q] : best;
+        p = take ? iq[q] : p;
+      }
+      if (p != k) T.put_row(p, rp[kb]);
+    }
+    __syncthreads();
+    const double* prow = (p == k) ? rk[kb] : rp[kb];
+    const double pv = prow[k];
+    if (pv == 0.0 || pv != pv) {
+      sgn = 0;
+      return;
+    }
+    if (tid == 0) {
+      logabs += log(fabs(pv));
+      piv[k] = p;
+    }
+    if (pv < 0) sgn = -sgn;
+    if (p != k) sgn = -sgn;
+    T.gj_step(k, p, 1.0 / pv, rk[kb], prow, ck[kb]);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    // columns of the result: undo the row interchanges as column
+    // interchanges in reverse order; colmap[c] = destination of column c
+    if (!triangular)
+      for (int k = n - 1; k >= 0; --k) {
+        const int q = piv[k];
+        const int t = colmap[k];
+        colmap[k] = colmap[q];
+        colmap[q] = t;
+      }
+    // colmap now holds the source column of each destination; invert it
+    for (int c = 0; c < n; ++c) piv[colmap[c]] = c;
+    for (int c = 0; c < n; ++c) colmap[c] = piv[c];
+  }
+  __syncthreads();
+}
+
+template <int NB>
+__device__ void rt_store(const RegTile<NB>& T, double* __restrict__ g, const int* colmap,
+                         bool upper_only) {
+#pragma unroll
+  for (int a = 0; a < NB; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int r = T.ti + 16 * a, c = T.tj + 16 * b;
+      if (r < T.n && c < T.n) {
+        const int cd = colmap[c];
+        g[(size_t)r * T.n + cd] = (upper_only && cd < r) ? 0.0 : T.m[a][b];
+      }
+    }
+}
+
+// the step vectors are read at every residue, including entries beyond n
+__device__ inline void rt_clear(double (*rk)[kRtMax], double (*rp)[kRtMax], double (*ck)[kRtMax]) {
+  for (int i = threadIdx.x; i < 2 * kRtMax; i += kThreads) {
+    rk[i / kRtMax][i % kRtMax] = 0.0;
+    rp[i / kRtMax][i % kRtMax] = 0.0;
+    ck[i / kRtMax][i % kRtMax] = 0.0;
+  }
+}
+
+#define GPQMC_RT_SHARED                                 \
+  __shared__ double rk[2][kRtMax], rp[2][kRtMax], ck[2][kRtMax]; \
+  __shared__ double cv[2][16];                          \
+  __shared__ int ci[2][16];                             \
+  __shared__ int piv[kRtMax], colmap[kRtMax];
+
+// Cholesky W = R^T R (R upper) of the Gram matrix, then R^{-1}, in registers.
+template <int NB>
+__global__ __launch_bounds__(kThreads) void k_chol_inv_rt(const ChainDev* __restrict__ chains) {
+  const int lg = xcd_remap(blockIdx.x, gridDim.x);
+  const ChainDev& C = chains[lg >> 1];
+  const int sp = lg & 1, n = C.n[sp], tid = threadIdx.x;
+  GPQMC_RT_SHARED
+  rt_clear(rk, rp, ck);
+  RegTile<NB> T;
+  T.load(C.Wm[sp], n);
+  double lsum = 0.0;
+  bool bad = false;
+  for (int j = 0; j < n; ++j) {
+    const int jb = j & 1;
+    T.put_row(j, rk[jb]);
+    __syncthreads();
+    const double d2 = rk[jb][j];
+    if (!(d2 > 0.0)) {   // not positive definite (or NaN): flag, keep going finitely
+      bad = true;
+#pragma unroll
+      for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+          if (T.ti + 16 * a == j && T.tj + 16 * b == j) T.m[a][b] = 1.0;
+      continue;
+    }
+    const double d = sqrt(d2), id = 1.0 / d;
+    if (tid == 0) lsum += log(d);
+    double rc[NB], rr[NB];   // normalised row j at the thread's columns and rows
+#pragma unroll
+    for (int b = 0; b < NB; ++b) rc[b] = rk[jb][T.tj + 16 * b] * id;
+#pragma unroll
+    for (int a = 0; a < NB; ++a) rr[a] = rk[jb][T.ti + 16 * a] * id;
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+      const int r = T.ti + 16 * a;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int c = T.tj + 16 * b;
+        const double x = T.m[a][b];
+        const double rowj = (c == j) ? d : rc[b];
+        const double trail = fma(-rr[a], rc[b], x);
+        T.m[a][b] = (r == j) ? ((c >= j) ? rowj : x) : (((r > j) & (c >= r)) ? trail : x);
+      }
+    }
+  }
+  // clear the lower triangle
+#pragma unroll
+  for (int a = 0; a < NB; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+      if (T.tj + 16 * b < T.ti + 16 * a) T.m[a][b] = 0.0;
+  if (tid == 0) {
+    C.st->chk_log[sp] = lsum;
+    C.st->chk_sgn[sp] = 1;
+    if (bad) atomicOr(&C.st->flags, (int)FLAG_SINGULAR);
+  }
+  double la;
+  int sg;
+  rt_invert<NB>(T, true, rk, rp, ck, cv, ci, piv, colmap, la, sg);
+  if (sg != 0)
+    rt_store<NB>(T, C.Rinv[sp], colmap, true);
+  else if (tid == 0)
+    atomicOr(&C.st->flags, (int)FLAG_SINGULAR);
+}
+
+// Inverse of X = L R (n x n) in place, partial pivoting; log|det X| and its
+// sign go to the chain state.
+template <int NB>
+__global__ __launch_bounds__(kThreads) void k_gj_inv_rt(const ChainDev* __restrict__ chains) {
+  const int lg = xcd_remap(blockIdx.x, gridDim.x);
+  const ChainDev& C = chains[lg >> 1];
+  const int sp = lg & 1, n = C.n[sp], tid = threadIdx.x;
+  GPQMC_RT_SHARED
+  rt_clear(rk, rp, ck);
+  RegTile<NB> T;
+  T.load(C.Xm[sp], n);
+  double logabs;
+  int sgn;
+  rt_invert<NB>(T, false, rk, rp, ck, cv, ci, piv, colmap, logabs, sgn);
+  if (sgn != 0) rt_store<NB>(T, C.Xm[sp], colmap, false);
+  if (tid == 0) {
+    C.st->x_log[sp] = logabs;
+    C.st->x_sgn[sp] = sgn;
+    if (sgn == 0) atomicOr(&C.st->flags, (int)FLAG_SINGULAR);
+  }
+}
+
 // FP32 basis variant: the checkpoint starts from an FP64 copy (in Hw) of the basis.
 template <typename Tu>
 __global__ __launch_bounds__(kThreads) void k_basis_to_fp64(const ChainDev* __restrict__ chains,
@@ -374,14 +663,43 @@ __global__ void k_set_ctl(Ctl* ctl, int measure, int force_reject, float drift_t
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-hipError_t launch_chol_inv(const ChainDev* c, int nc, hipStream_t s) {
-  hipLaunchKernelGGL(k_chol_inv, dim3(2 * nc), dim3(kDenseThreads), 0, s, c);
+// n_part: the largest particle number of the batch; register tiles up to
+// kRtMax, the LDS / global kernels beyond
+template <int NB>
+static hipError_t launch_rt(bool chol, const ChainDev* c, int nc, hipStream_t s) {
+  if (chol)
+    hipLaunchKernelGGL(k_chol_inv_rt<NB>, dim3(2 * nc), dim3(kThreads), 0, s, c);
+  else
+    hipLaunchKernelGGL(k_gj_inv_rt<NB>, dim3(2 * nc), dim3(kThreads), 0, s, c);
   return hipGetLastError();
 }
 
-hipError_t launch_gj_inv(const ChainDev* c, int nc, hipStream_t s) {
-  hipLaunchKernelGGL(k_gj_inv, dim3(2 * nc), dim3(kDenseThreads), 0, s, c);
+static hipError_t launch_dense(bool chol, const ChainDev* c, int nc, int n_part, hipStream_t s) {
+  switch ((n_part + 15) / 16) {
+    case 0:
+    case 1: return launch_rt<1>(chol, c, nc, s);
+    case 2: return launch_rt<2>(chol, c, nc, s);
+    case 3: return launch_rt<3>(chol, c, nc, s);
+    case 4: return launch_rt<4>(chol, c, nc, s);
+    case 5: return launch_rt<5>(chol, c, nc, s);
+    case 6: return launch_rt<6>(chol, c, nc, s);
+    case 7: return launch_rt<7>(chol, c, nc, s);
+    case 8: return launch_rt<8>(chol, c, nc, s);
+    default: break;
+  }
+  if (chol)
+    hipLaunchKernelGGL(k_chol_inv, dim3(2 * nc), dim3(kDenseThreads), 0, s, c);
+  else
+    hipLaunchKernelGGL(k_gj_inv, dim3(2 * nc), dim3(kDenseThreads), 0, s, c);
   return hipGetLastError();
+}
+
+hipError_t launch_chol_inv(const ChainDev* c, int nc, int n_part, hipStream_t s) {
+  return launch_dense(true, c, nc, n_part, s);
+}
+
+hipError_t launch_gj_inv(const ChainDev* c, int nc, int n_part, hipStream_t s) {
+  return launch_dense(false, c, nc, n_part, s);
 }
 
 hipError_t launch_basis_to_fp64(int fp32b, const ChainDev* c, int nc, int parity, hipStream_t s) {

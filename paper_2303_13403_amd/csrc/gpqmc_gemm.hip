@@ -1,6 +1,5 @@
 // Batched MFMA GEMM of the PQMC sweep (gfx950), one 64 x 64 output tile per
 // workgroup, with the epilogues that fuse the sweep's elementwise work:
-//   the delayed-update flush            G <- D (G - Xg T1) D^{-1}
 //   the kinetic wrap                    G <- D_{l+1} (Gtmp e^{dtau K}) D_{l+1}^{-1}
 //   the basis propagation               U <- e^{-dtau K} (D_l U)   /  D_l (e^{-dtau K} U)
 //   the checkpoint products (FP64)      U^T U, U R^{-1}, L^T R, (L R)^{-1} L, 1 - R Y
@@ -22,15 +21,9 @@ __global__ __launch_bounds__(kThreads) void k_gemm(const GemmEntry* __restrict__
   if (bid >= n_tiles) return;
   const TileRef tr = tiles[bid];
   const GemmEntry& e = ents[tr.entry];
-  int M = e.M, N = e.N, K = e.K;
-  if (e.dynMK) {
-    const int f = *e.dynMK;
-    K = f;
-    if (MODE == GM_T1) M = f;
-  }
+  const int M = e.M, N = e.N, K = e.K;
   const int m0 = tr.tm * kTile, n0 = tr.tn * kTile;
   if (m0 >= M || n0 >= N) return;
-  if (MODE == GM_FLUSH && K == 0 && args.scale_slice < 0) return;   // nothing to apply
 
   const int p = args.parity;
   const T* A = (const T*)e.A[0];
@@ -149,16 +142,29 @@ __global__ __launch_bounds__(kThreads) void k_gemm(const GemmEntry* __restrict__
   }
   const bool inv = args.scale_inverse != 0;
   float dmax = 0.f;
+  // the drift check reads the wrapped Green's function it replaces: all of
+  // those loads are issued before the first store of the tile
+  Tb prev[16];
+  int ix = 0;
+  if (MODE == GM_GFRESH && args.check_drift) {
+    const Tb* Cb = (const Tb*)e.C[1];
+    wt.each(wm, wn, lane, [&](int li, int lj, T) {
+      const int i = m0 + li, j = n0 + lj;
+      prev[ix++] = (i < M && j < N) ? Cb[(size_t)i * e.ldc2 + j] : Tb(0);
+    });
+  }
+  ix = 0;
   wt.each(wm, wn, lane, [&](int li, int lj, T acc) {
     const int i = m0 + li, j = n0 + lj;
+    const int k = ix++;
     if (i >= M || j >= N) return;
     const size_t o = (size_t)i * ldc + j;
     if (MODE == GM_PROPR) {
       T v = acc;
       if (sfield) v *= (T)dfac(e.dval, sbnd, sfield[i], false);
       C[o] = v;
-    } else if (MODE == GM_WRAP || MODE == GM_FLUSH) {
-      T v = (MODE == GM_FLUSH) ? C[o] - acc : acc;
+    } else if (MODE == GM_WRAP) {
+      T v = acc;
       if (sfield)
         v *= (T)(dfac(e.dval, sbnd, sfield[i], inv) * dfac(e.dval, sbnd, sfield[j], !inv));
       C[o] = v;
@@ -168,7 +174,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm(const GemmEntry* __restrict__
       Tb* Cb = (Tb*)e.C[1];
       const size_t o2 = (size_t)i * e.ldc2 + j;
       if (args.check_drift) {
-        const float d = (float)fabs((double)Cb[o2] - g);
+        const float d = (float)fabs((double)prev[k] - g);
         dmax = (d != d) ? __builtin_inff() : fmaxf(dmax, d);
       }
       double v = g;
@@ -198,7 +204,7 @@ static hipError_t gemm_t(const GemmEntry* e, const TileRef* t, int n, GemmArgs a
 }
 
 // fp32: arithmetic type of the modes that follow the Green's function or the
-// basis precision (STORE/WRAP/FLUSH/T1/PROP*); the checkpoint modes are FP64
+// basis precision (STORE/WRAP/PROP*); the checkpoint modes are FP64
 // and write their bulk copy (GFRESH) in the Green's-function precision g_fp32.
 hipError_t launch_gemm(int fp32, int g_fp32, int mode, const GemmEntry* e, const TileRef* t, int n,
                        GemmArgs a, hipStream_t s) {
@@ -216,19 +222,15 @@ hipError_t launch_gemm(int fp32, int g_fp32, int mode, const GemmEntry* e, const
     switch (mode) {
       case GM_STORE: return gemm_t<float, GM_STORE, false, false, float>(e, t, n, a, s);
       case GM_WRAP: return gemm_t<float, GM_WRAP, false, false, float>(e, t, n, a, s);
-      case GM_FLUSH: return gemm_t<float, GM_FLUSH, false, false, float>(e, t, n, a, s);
       case GM_PROPB: return gemm_t<float, GM_PROPB, false, false, float>(e, t, n, a, s);
       case GM_PROPR: return gemm_t<float, GM_PROPR, false, false, float>(e, t, n, a, s);
-      case GM_T1: return gemm_t<float, GM_T1, false, false, float>(e, t, n, a, s);
     }
   } else {
     switch (mode) {
       case GM_STORE: return gemm_t<double, GM_STORE, false, false, double>(e, t, n, a, s);
       case GM_WRAP: return gemm_t<double, GM_WRAP, false, false, double>(e, t, n, a, s);
-      case GM_FLUSH: return gemm_t<double, GM_FLUSH, false, false, double>(e, t, n, a, s);
       case GM_PROPB: return gemm_t<double, GM_PROPB, false, false, double>(e, t, n, a, s);
       case GM_PROPR: return gemm_t<double, GM_PROPR, false, false, double>(e, t, n, a, s);
-      case GM_T1: return gemm_t<double, GM_T1, false, false, double>(e, t, n, a, s);
     }
   }
   return hipErrorInvalidValue;

@@ -24,8 +24,10 @@ hipError_t launch_gemm_plain(int fp32, int transA, const GemmEntry* e, const Til
                              GemmArgs a, hipStream_t s);
 hipError_t launch_scan(int fp32, const ChainDev* c, int nc, const Ctl* ctl, int l, int M, int s0,
                        int s1, hipStream_t s);
-hipError_t launch_chol_inv(const ChainDev* c, int nc, hipStream_t s);
-hipError_t launch_gj_inv(const ChainDev* c, int nc, hipStream_t s);
+hipError_t launch_flush(int fp32, const ChainDev* c, int nc, int n_max, int kseg, int scale_slice,
+                        int scale_inverse, int M, hipStream_t s);
+hipError_t launch_chol_inv(const ChainDev* c, int nc, int n_part, hipStream_t s);
+hipError_t launch_gj_inv(const ChainDev* c, int nc, int n_part, hipStream_t s);
 hipError_t launch_basis_to_fp64(int fp32b, const ChainDev* c, int nc, int parity, hipStream_t s);
 hipError_t launch_finalize(int fp32b, const ChainDev* c, int nc, const Ctl* ctl, int slot, int mode,
                            int measure_here, int ck_index, int parity, hipStream_t s);
@@ -121,7 +123,7 @@ struct ChainHost {
   bool field_set = false;
   std::vector<int8_t> field;
   // workspace offsets
-  size_t G[2], Gtmp[2], U2[2][2], Z[2], Xg[2], Yg[2], T1[2], scan_ws[2];
+  size_t G[2], Gtmp[2], U2[2][2], Z[2], Yg[2], scan_ws[2], flist;
   size_t stack[2], slot_log[2], slot_sgn[2], Hw[2], Qc[2], Wm[2], Rinv[2], Xm[2], Ym[2], G64[2];
   size_t field_off, st, meas, tr_ratio = 0, tr_green = 0, tr_drift = 0;
 };
@@ -139,6 +141,7 @@ struct gpqmc_ctx {
   int fp32b = 0;           // basis propagation precision: 1 = FP32, 0 = FP64
   int l_half = 0, M = 0, n_s = 1, kseg = 64, n_slices = 2;  // kseg: delay rank (sites per flush)
   int n_max = 0;                   // largest lattice of the batch
+  int n_part = 0;                  // largest particle number (either spin) of the batch
   int meas_cap = 4096;
   bool use_graph = true;
   float drift_tol = 1e-3f;
@@ -171,9 +174,9 @@ struct gpqmc_ctx {
 
 namespace {
 
-enum EntryKind { E_WRAP1_UP = 0, E_WRAP2_UP, E_WRAP1_DN, E_WRAP2_DN, E_T1, E_FLUSH, E_PROP,
-                 E_GRAM_U, E_APPLY1, E_XMAT, E_YMAT, E_GFRESH, E_COUNT };
-enum TileKind { T_NN = 0, T_Nn, T_nn, T_nN, T_sN };
+enum EntryKind { E_WRAP1_UP = 0, E_WRAP2_UP, E_WRAP1_DN, E_WRAP2_DN, E_PROP, E_GRAM_U, E_APPLY1,
+                 E_XMAT, E_YMAT, E_GFRESH, E_COUNT };
+enum TileKind { T_NN = 0, T_Nn, T_nn, T_nN, T_COUNT };
 
 gpqmc_status fail(gpqmc_ctx* c, gpqmc_status s, const std::string& msg) {
   if (c) c->err = msg;
@@ -232,14 +235,14 @@ struct Launcher {
     a.parity = parity;
     if (ctx->fp32b && (e = launch_basis_to_fp64(1, chains, nc, parity, s)) != hipSuccess) return e;
     if ((e = gemm(E_GRAM_U, GM_GRAM, T_nn, a)) != hipSuccess) return e;
-    if ((e = launch_chol_inv(chains, nc, s)) != hipSuccess) return e;
+    if ((e = launch_chol_inv(chains, nc, ctx->n_part, s)) != hipSuccess) return e;
     if ((e = gemm(E_APPLY1, GM_APPLY, T_Nn, a)) != hipSuccess) return e;
     const int sl = ctx->slot(p);
     if (mode == 2) return launch_finalize(ctx->fp32b, chains, nc, ctl, sl, 2, 0, -1, parity, s);
     a.slot = sl;
     a.dir = dir;
     if ((e = gemm(E_XMAT, GM_XMAT, T_nn, a)) != hipSuccess) return e;
-    if ((e = launch_gj_inv(chains, nc, s)) != hipSuccess) return e;
+    if ((e = launch_gj_inv(chains, nc, ctx->n_part, s)) != hipSuccess) return e;
     if ((e = gemm(E_YMAT, GM_YMAT, T_nN, a)) != hipSuccess) return e;
     a.scale_slice = next_scale;
     a.check_drift = (mode == 0);
@@ -255,11 +258,9 @@ struct Launcher {
       const bool last = s0 + ctx->kseg >= ctx->n_max;
       if ((e = launch_scan(ctx->fp32, chains, nc, ctl, l, ctx->M, s0, s0 + ctx->kseg, s)) != hipSuccess)
         return e;
-      GemmArgs a = args();
-      if ((e = gemm(E_T1, GM_T1, T_sN, a)) != hipSuccess) return e;
-      a.scale_slice = last ? scale_slice : -1;
-      a.scale_inverse = inverse;
-      if ((e = gemm(E_FLUSH, GM_FLUSH, T_NN, a)) != hipSuccess) return e;
+      if ((e = launch_flush(ctx->fp32, chains, nc, ctx->n_max, ctx->kseg, last ? scale_slice : -1, inverse,
+                            ctx->M, s)) != hipSuccess)
+        return e;
     }
     return hipSuccess;
   }
@@ -546,9 +547,7 @@ gpqmc_status gpqmc_create(int32_t n_chains, const gpqmc_chain_desc* chains,
       h.U2[sp][0] = take(nb * ub);
       h.U2[sp][1] = take(nb * ub);
       h.Z[sp] = take((size_t)kSegMax * kSegMax * bs);
-      h.Xg[sp] = take(N * kSegMax * bs);
       h.Yg[sp] = take(N * kSegMax * bs);
-      h.T1[sp] = take(N * kSegMax * bs);
       h.scan_ws[sp] = take((size_t)5 * kBlock * kSegMax * bs);
       h.stack[sp] = take((size_t)n_slots * nb * 8);
       h.slot_log[sp] = take((size_t)n_slots * 8);
@@ -563,6 +562,7 @@ gpqmc_status gpqmc_create(int32_t n_chains, const gpqmc_chain_desc* chains,
     }
     h.field_off = take((size_t)c->n_slices * N);
     h.st = take(sizeof(ChainState));
+    h.flist = take((size_t)kSegMax * 4);
     h.meas = take((size_t)c->meas_cap * 3 * 8);
     if (h.trace) {
       h.tr_ratio = take((size_t)c->n_slices * N * 2 * 8);
@@ -576,15 +576,15 @@ gpqmc_status gpqmc_create(int32_t n_chains, const gpqmc_chain_desc* chains,
   std::vector<std::pair<int, int>> sz[5];
   for (auto& h : c->ch) {
     c->n_max = std::max(c->n_max, h.N);
+    c->n_part = std::max(c->n_part, std::max(h.n[0], h.n[1]));
     for (int sp = 0; sp < 2; ++sp) {
       sz[T_NN].push_back({h.N, h.N});
       sz[T_Nn].push_back({h.N, h.n[sp]});
       sz[T_nn].push_back({h.n[sp], h.n[sp]});
       sz[T_nN].push_back({h.n[sp], h.N});
-      sz[T_sN].push_back({std::min(c->kseg, h.N), h.N});
     }
   }
-  for (int t = 0; t < 5; ++t) {
+  for (int t = 0; t < T_COUNT; ++t) {
     build_tiles(c->tiles[t], sz[t]);
     c->off_tiles[t] = take(sizeof(TileRef) * c->tiles[t].size());
   }
@@ -656,9 +656,7 @@ gpqmc_status gpqmc_bind_workspace(gpqmc_ctx* ctx, void* device_ptr, size_t bytes
       d.U[sp][0] = ctx->ws + h.U2[sp][0];
       d.U[sp][1] = ctx->ws + h.U2[sp][1];
       d.Z[sp] = ctx->ws + h.Z[sp];
-      d.Xg[sp] = ctx->ws + h.Xg[sp];
       d.Yg[sp] = ctx->ws + h.Yg[sp];
-      d.T1[sp] = ctx->ws + h.T1[sp];
       d.scan_ws[sp] = ctx->ws + h.scan_ws[sp];
       d.P[sp] = ctx->at<double>(ctx->trials[h.trial[sp]].off);
       d.stack[sp] = ctx->at<double>(h.stack[sp]);
@@ -677,6 +675,7 @@ gpqmc_status gpqmc_bind_workspace(gpqmc_ctx* ctx, void* device_ptr, size_t bytes
     d.Khop = ctx->at<double>(L.off_K);
     d.field = ctx->at<int8_t>(h.field_off);
     d.st = ctx->at<ChainState>(h.st);
+    d.flist = ctx->at<int>(h.flist);
     d.meas = ctx->at<double>(h.meas);
     d.meas_cap = ctx->meas_cap;
     if (h.trace) {
@@ -720,13 +719,6 @@ gpqmc_status gpqmc_bind_workspace(gpqmc_ctx* ctx, void* device_ptr, size_t bytes
       E[E_WRAP2_UP][ei] = nnE(d.Gtmp[sp], d.Kp, d.G[sp]);
       E[E_WRAP1_DN][ei] = nnE(d.Kp, d.G[sp], d.Gtmp[sp]);
       E[E_WRAP2_DN][ei] = nnE(d.Gtmp[sp], d.Km, d.G[sp]);
-      GemmEntry t1 = mk(d.Z[sp], d.Z[sp], d.Yg[sp], d.Yg[sp], d.T1[sp], d.T1[sp],
-                        std::min(ctx->kseg, N), N, 0, kSegMax, N, N);
-      t1.dynMK = &d.st->fcount;
-      E[E_T1][ei] = t1;
-      GemmEntry fl = mk(d.Xg[sp], d.Xg[sp], d.T1[sp], d.T1[sp], d.G[sp], d.G[sp], N, N, 0, kSegMax, N, N);
-      fl.dynMK = &d.st->fcount;
-      E[E_FLUSH][ei] = fl;
       const void* Kmb = ctx->ws + L.off_Kmb;
       E[E_PROP][ei] = mk(Kmb, Kmb, d.U[sp][0], d.U[sp][1], d.U[sp][0], d.U[sp][1], N, n, N, N, n, n);
       // checkpoint: Cholesky QR of U[parity] (or of its FP64 copy in Hw)
@@ -755,7 +747,7 @@ gpqmc_status gpqmc_bind_workspace(gpqmc_ctx* ctx, void* device_ptr, size_t bytes
   HIPCHK(up(ctx->off_chains, cd.data(), sizeof(ChainDev) * nc), "upload chains");
   for (int k = 0; k < E_COUNT; ++k)
     HIPCHK(up(ctx->off_ent[k], E[k].data(), sizeof(GemmEntry) * E[k].size()), "upload entries");
-  for (int t = 0; t < 5; ++t)
+  for (int t = 0; t < T_COUNT; ++t)
     HIPCHK(up(ctx->off_tiles[t], ctx->tiles[t].data(), sizeof(TileRef) * ctx->tiles[t].size()), "tiles");
   Ctl ctl = {0, 0, ctx->drift_tol, 0};
   HIPCHK(up(ctx->off_ctl, &ctl, sizeof ctl), "upload ctl");
@@ -1089,11 +1081,9 @@ gpqmc_status gpqmc_debug_step(gpqmc_ctx* ctx, int32_t stage, int32_t l, int32_t 
   Launcher L = make_launcher(ctx);
   HIPCHK(launch_set_ctl(ctx->at<Ctl>(ctx->off_ctl), 0, ctx->debug_flags & 1, ctx->drift_tol,
                         ctx->stream), "ctl");
-  GemmArgs a = L.args();
   hipError_t e = hipErrorInvalidValue;
   if (stage == 0) e = launch_scan(ctx->fp32, L.chains, L.nc, L.ctl, l, ctx->M, s0, s1, ctx->stream);
-  if (stage == 1) e = L.gemm(E_T1, GM_T1, T_sN, a);
-  if (stage == 2) e = L.gemm(E_FLUSH, GM_FLUSH, T_NN, a);
+  if (stage == 1) e = launch_flush(ctx->fp32, L.chains, L.nc, ctx->n_max, ctx->kseg, -1, 0, ctx->M, ctx->stream);
   HIPCHK(e, "debug step");
   HIPCHK(hipStreamSynchronize(ctx->stream), "debug step");
   return GPQMC_OK;
@@ -1104,29 +1094,30 @@ gpqmc_status gpqmc_debug_read(gpqmc_ctx* ctx, int32_t chain, int32_t what, int32
   if (!ctx || !out || chain < 0 || chain >= ctx->n_chains || spin < 0 || spin > 1 || count < 0)
     return GPQMC_EINVAL;
   const ChainHost& h = ctx->ch[chain];
-  size_t off = 0, elem = ctx->fp32 ? 4 : 8;
+  size_t off = 0, elem = ctx->fp32 ? 4 : 8, cap = 0;
+  bool is_int = false;
   switch (what) {
-    case 0: off = h.G[spin]; break;
-    case 1: off = h.Z[spin]; break;
-    case 2: off = h.Xg[spin]; break;
-    case 3: off = h.Yg[spin]; break;
-    case 4: off = h.T1[spin]; break;
-    case 5: off = h.st; elem = 0; break;
+    case 0: off = h.G[spin]; cap = (size_t)h.N * h.N; break;
+    case 1: off = h.Z[spin]; cap = (size_t)kSegMax * kSegMax; break;
+    case 2: off = h.flist; elem = 4; is_int = true; cap = kSegMax; break;
+    case 3: off = h.Yg[spin]; cap = (size_t)h.N * kSegMax; break;
+    case 5: off = h.st; elem = 0; cap = 3; break;
     default: return GPQMC_EINVAL;
   }
+  if ((size_t)count > cap) return fail(ctx, GPQMC_EINVAL, "debug_read: count exceeds the buffer");
   HIPCHK(hipStreamSynchronize(ctx->stream), "sync");
   if (elem == 0) {
     ChainState st;
     HIPCHK(hipMemcpy(&st, ctx->ws + off, sizeof st, hipMemcpyDeviceToHost), "state");
-    out[0] = st.fcount;
-    out[1] = st.sign;
-    out[2] = (double)st.accepted;
+    const double v[3] = {(double)st.fcount, (double)st.sign, (double)st.accepted};
+    for (int64_t i = 0; i < count; ++i) out[i] = v[i];
     return GPQMC_OK;
   }
   std::vector<char> buf((size_t)count * elem);
   HIPCHK(hipMemcpy(buf.data(), ctx->ws + off, buf.size(), hipMemcpyDeviceToHost), "read");
   for (int64_t i = 0; i < count; ++i)
-    out[i] = elem == 4 ? (double)((float*)buf.data())[i] : ((double*)buf.data())[i];
+    out[i] = is_int ? (double)((int*)buf.data())[i]
+             : elem == 4 ? (double)((float*)buf.data())[i] : ((double*)buf.data())[i];
   return GPQMC_OK;
 }
 

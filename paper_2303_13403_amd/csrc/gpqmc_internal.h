@@ -92,10 +92,9 @@ struct ChainDev {
   void* G[2];           // equal-time Green's function in the current frame
   void* Gtmp[2];        // wrap intermediate
   void* Z[2];           // delayed-update coefficients of a segment (f x f, ld kSegMax)
-  void* Xg[2];          // G0[:, F]  (N x f, ld kSegMax)
   void* Yg[2];          // (1 - G0)[F, :]  (f x N, ld N)
-  void* T1[2];          // Z Yg  (f x N, ld N)
   void* scan_ws[2];     // scan scratch, 5 * kBlock * kSegMax elements
+  int* flist;           // accepted sites F of the last segment (kSegMax)
   const void* Km;       // e^{-dtau K}
   const void* Kp;       // e^{+dtau K}
   // basis precision (float or double)
@@ -142,7 +141,6 @@ struct GemmEntry {
   int slot_stride;      // elements per stack slot
   int M, N, K;          // static sizes
   int lda, ldb, ldc, ldc2;
-  const int* dynMK;     // if set, K (and M in mode GM_T1) = *dynMK (accepted count)
   const int8_t* field;  // base of the chain's field
   int n_sites;
   int spin;
@@ -169,10 +167,8 @@ struct GemmArgs {
 enum GemmMode : int {
   GM_STORE = 0,   // C = A B
   GM_WRAP = 1,    // C = D (A B) D^{-1}  (or D^{-1}(A B)D, or unscaled)
-  GM_FLUSH = 2,   // C = D (C - A B) D^{-1}  (scaling optional)
   GM_PROPB = 3,   // C[p^1] = A (D B[p])
   GM_PROPR = 4,   // C[p^1] = D (A B[p])
-  GM_T1 = 5,      // C = A B with M = K = accepted count
   GM_GRAM = 6,    // C = A[p]^T A[p]  (FP64)
   GM_APPLY = 7,   // C = A[p] B       (FP64)
   GM_XMAT = 8,    // C = Lt^T R       (FP64)

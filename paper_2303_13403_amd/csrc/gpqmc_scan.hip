@@ -1,4 +1,5 @@
-// Metropolis scan of one segment of one imaginary-time slice (gfx950).
+// Metropolis scan of one segment of one imaginary-time slice and the delayed-
+// update flush that follows it (gfx950).
 //
 // One workgroup per chain handles both spins.  G0 is the chain's current
 // Green's function in the frame where D_l acts, so flipping s_{l,i} changes the
@@ -13,19 +14,68 @@
 // wave with rank-1 (Sherman-Morrison) updates of that block while it builds
 // the block's own coefficient matrix Zb, which is then merged into Z:
 //     Z <- [[Z + P Zb Q, P Zb], [Zb Q, Zb]],  P = Z G0[F,Fb], Q = G0[Fb,F] Z.
-// The kernel ends by writing the operands of (*), Xg = G0[:,F] and
-// Yg = (1 - G0)[F,:]; the T1 = Z Yg and FLUSH G -= Xg T1 GEMMs apply the
-// update to the whole Green's function (a delayed update of rank |F|).
+// The kernel ends by writing F and Yg = (1 - G0)[F,:]; k_flush then applies
+// (*) to the whole Green's function (a delayed update of rank |F|).
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
+
+#include <type_traits>
 
 #include "gpqmc_device.h"
 
 namespace gpqmc {
 
+// value of x held by lane src (src uniform across the wave)
+__device__ inline float lane_value(float x, int src) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), src));
+}
+__device__ inline double lane_value(double x, int src) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), src);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// one 128-bit LDS chunk (4 floats or 2 doubles) into registers
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_scan(const ChainDev* __restrict__ chains,
+__device__ inline void lds_chunk_load(T (&r)[16 / sizeof(T)], const T* p) {
+  using V4 = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+  const V4 v = *reinterpret_cast<const V4*>(p);
+  const T* e = reinterpret_cast<const T*>(&v);
+#pragma unroll
+  for (int t = 0; t < (int)(16 / sizeof(T)); ++t) r[t] = e[t];
+}
+
+// whole kBlock-long LDS row <-> registers with 128-bit accesses
+template <typename T>
+__device__ inline void lds_row_load(T (&r)[kBlock], const T* p) {
+  constexpr int V = 16 / sizeof(T);
+  using V4 = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+#pragma unroll
+  for (int q = 0; q < kBlock; q += V) {
+    const V4 v = *reinterpret_cast<const V4*>(p + q);
+    const T* e = reinterpret_cast<const T*>(&v);
+#pragma unroll
+    for (int t = 0; t < V; ++t) r[q + t] = e[t];
+  }
+}
+template <typename T>
+__device__ inline void lds_row_store(T* p, const T (&r)[kBlock]) {
+  constexpr int V = 16 / sizeof(T);
+  using V4 = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+#pragma unroll
+  for (int q = 0; q < kBlock; q += V) {
+    V4 v;
+    T* e = reinterpret_cast<T*>(&v);
+#pragma unroll
+    for (int t = 0; t < V; ++t) e[t] = r[q + t];
+    *reinterpret_cast<V4*>(p + q) = v;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_scan(const ChainDev* __restrict__ chains,
                                                    const Ctl* __restrict__ ctl, int l, int M,
                                                    int s0, int s1) {
   const ChainDev& C = chains[xcd_remap(blockIdx.x, gridDim.x)];
@@ -37,16 +87,19 @@ __global__ __launch_bounds__(kThreads) void k_scan(const ChainDev* __restrict__ 
     return;
   }
   const int send = min(s1, N), nseg = send - s0;
-  constexpr int KP = kBlock + 1;
+  constexpr int KL = kBlock + (16 / sizeof(T));
   constexpr int LDZ = kSegMax;
 
   __shared__ double u_s[kSegMax];
   __shared__ int8_t fs[kSegMax];
   __shared__ int Fs[kSegMax];
-  __shared__ T Hs[2][kBlock][KP];
-  __shared__ T Gt[2][kBlock][KP];
-  __shared__ T Zb[2][kBlock][KP];
-  __shared__ T rowb[2][kBlock], uvec[2][kBlock], vvec[2][kBlock];
+  // block matrices, row-major with a 16-byte aligned leading dimension so a
+  // lane can read a whole row with 128-bit loads; Hs = G[S,S] at block start,
+  // HsT its transpose, Zs the block's coefficient matrix indexed by block site
+  __shared__ __align__(16) T Hs[2][kBlock][KL];
+  __shared__ __align__(16) T HsT[2][kBlock][KL];
+  __shared__ __align__(16) T Zs[2][kBlock][KL];
+  __shared__ __align__(16) T rowbuf[2][kBlock], uvec[2][kBlock], vvec[2][kBlock];
   __shared__ T Rsf[kBlock * kSegMax];
   __shared__ int Fb[kBlock];
   __shared__ int sh_f, sh_fb, sh_sign, sh_acc;
@@ -117,69 +170,97 @@ __global__ __launch_bounds__(kThreads) void k_scan(const ChainDev* __restrict__ 
           T acc = G0[s][(size_t)(b0 + a) * N + b0 + c];
           for (int q = 0; q < f; ++q)
             acc += W1[s][(size_t)a * LDZ + q] * G0[s][(size_t)Fs[q] * N + b0 + c];
-          Gt[s][a][c] = acc;
           Hs[s][a][c] = acc;
+          HsT[s][c][a] = acc;
+        } else {
+          Hs[s][a][c] = T(0);
+          HsT[s][c][a] = T(0);
         }
       }
+      // rows kb..31 of a ragged last block are zero
+      if (kb < kBlock)
+        for (int row = 2 * wave + half; row < 2 * kBlock; row += 8) {
+          const int s = row >> 5, a = row & 31;
+          if (a >= kb) {
+            Hs[s][a][c] = T(0);
+            HsT[s][c][a] = T(0);
+          }
+        }
     }
     __syncthreads();
 
-    // ---- sequential proposals of the block: one wave, rank-1 updates ----
-    // lane = (spin s, row a): colb/rowb, u/v and the row-wise updates
+    // ---- sequential proposals of the block: one wave, registers ----
+    // lane = (spin s, block row a) holds row a of the current block of G (g),
+    // and row a / column a of the block coefficient matrix (zr / zc), which
+    // is indexed by block site and stays zero on sites not yet accepted.  For
+    // an accepted site j with ratio r and coefficient c = Delta / r:
+    //   u = e_j + Zs H[:,j],  v = e_j + Zs^T H[j,:]^T,  Zs += c u v^T
+    //   G[S,S] -= c G[S,j] (e_j - G[j,S])            (Sherman-Morrison)
     if (wave == 0) {
+      constexpr int VW = 16 / sizeof(T);
       const int s = lane >> 5, a = lane & 31;
+      T g[kBlock], zr[kBlock], zc[kBlock];
+      lds_row_load(g, &Hs[s][a][0]);
+#pragma unroll
+      for (int q = 0; q < kBlock; ++q) zr[q] = zc[q] = T(0);
       int fb = 0, sign = sh_sign, nacc = 0;
-      for (int j = 0; j < kb; ++j) {
-        const int li = b0 + j - s0;
-        const int si = fs[li] > 0 ? 0 : 1;
-        const double du = C.delta[bnd][0][si], dd = C.delta[bnd][1][si];
-        const double ru = 1.0 + du * (1.0 - (double)Gt[0][j][j]);
-        const double rd = 1.0 + dd * (1.0 - (double)Gt[1][j][j]);
-        const bool accept = !force_reject && (u_s[li] < fabs(ru * rd));
-        if (lane == 0 && C.trace_ratio) {
-          C.trace_ratio[((size_t)l * N + b0 + j) * 2 + 0] = ru;
-          C.trace_ratio[((size_t)l * N + b0 + j) * 2 + 1] = rd;
-        }
-        if (!accept) continue;
-        if (!zero_delta) {
-          T col = T(0);
-          if (a < kb) {
-            col = Gt[s][a][j];
-            rowb[s][a] = (a == j ? T(1) : T(0)) - Gt[s][j][a];
+#pragma unroll
+      for (int j = 0; j < kBlock; ++j) {
+        if (j < kb) {
+          const int li = b0 + j - s0;
+          const int si = fs[li] > 0 ? 0 : 1;
+          const double du = C.delta[bnd][0][si], dd = C.delta[bnd][1][si];
+          const double ru = 1.0 + du * (1.0 - (double)lane_value(g[j], j));
+          const double rd = 1.0 + dd * (1.0 - (double)lane_value(g[j], 32 + j));
+          const bool accept = !force_reject && (u_s[li] < fabs(ru * rd));
+          if (lane == 0 && C.trace_ratio) {
+            C.trace_ratio[((size_t)l * N + b0 + j) * 2 + 0] = ru;
+            C.trace_ratio[((size_t)l * N + b0 + j) * 2 + 1] = rd;
           }
-          T uu = (a == fb) ? T(1) : T(0), vv = uu;
-          if (a < fb) {   // row/column fb of Zb is the new (still zero) one
-            for (int c = 0; c < fb; ++c) {
-              uu += Zb[s][a][c] * Hs[s][Fb[c]][j];
-              vv += Zb[s][c][a] * Hs[s][j][Fb[c]];
+          if (accept) {
+            if (!zero_delta) {
+              if (a == j) lds_row_store(&rowbuf[s][0], g);
+              T uu = (a == j) ? T(1) : T(0), vv = uu;
+#pragma unroll
+              for (int c = 0; c < kBlock; c += VW) {
+                T hc[VW], hr[VW];
+                lds_chunk_load(hc, &HsT[s][j][c]);
+                lds_chunk_load(hr, &Hs[s][j][c]);
+#pragma unroll
+                for (int t = 0; t < VW; ++t) {
+                  uu += zr[c + t] * hc[t];
+                  vv += zc[c + t] * hr[t];
+                }
+              }
+              uvec[s][a] = uu;
+              vvec[s][a] = vv;
+              wave_sync();
+              const T coef = (T)((s == 0 ? du : dd) / (s == 0 ? ru : rd));
+              const T cc = coef * g[j], cu = coef * uu, cv = coef * vv;
+#pragma unroll
+              for (int q = 0; q < kBlock; q += VW) {
+                T rb[VW], ub[VW], vb[VW];
+                lds_chunk_load(rb, &rowbuf[s][q]);
+                lds_chunk_load(ub, &uvec[s][q]);
+                lds_chunk_load(vb, &vvec[s][q]);
+#pragma unroll
+                for (int t = 0; t < VW; ++t) {
+                  g[q + t] -= cc * ((q + t == j ? T(1) : T(0)) - rb[t]);
+                  zr[q + t] += cu * vb[t];
+                  zc[q + t] += cv * ub[t];
+                }
+              }
+              if (lane == 0) Fb[fb] = j;
+              fb += 1;
+              wave_sync();
             }
+            if (lane == 0) fs[li] = (int8_t)(-fs[li]);
+            if (ru * rd < 0) sign = -sign;
+            nacc += 1;
           }
-          if (a <= fb) {
-            uvec[s][a] = uu;
-            vvec[s][a] = vv;
-          }
-          wave_sync();
-          const T coef = (T)((s == 0 ? du : dd) / (s == 0 ? ru : rd));
-          if (a < kb) {
-            const T cc = coef * col;
-            for (int bb = 0; bb < kb; ++bb) Gt[s][a][bb] -= cc * rowb[s][bb];
-          }
-          const int fb1 = fb + 1;
-          if (a < fb1) {
-            const T cu = coef * uu;
-            for (int q = 0; q < fb1; ++q) {
-              const T base = (a < fb && q < fb) ? Zb[s][a][q] : T(0);
-              Zb[s][a][q] = base + cu * vvec[s][q];
-            }
-          }
-          if (lane == 0) Fb[fb] = j;
-          fb = fb1;
         }
-        if (lane == 0) fs[li] = (int8_t)(-fs[li]);
-        if (ru * rd < 0) sign = -sign;
-        nacc += 1;
-        wave_sync();
       }
+      lds_row_store(&Zs[s][a][0], zr);
       if (lane == 0) {
         sh_fb = fb;
         sh_sign = sign;
@@ -188,7 +269,7 @@ __global__ __launch_bounds__(kThreads) void k_scan(const ChainDev* __restrict__ 
     }
     __syncthreads();
 
-    // ---- merge the block's Zb into Z ----
+    // ---- merge the block's coefficients Zb = Zs[Fb,Fb] into Z ----
     //   Z <- [[Z + P Zb Q, P Zb], [Zb Q, Zb]],  P = Z G0[F,Fb], Q = G0[Fb,F] Z
     const int fb = sh_fb;
     if (fb > 0) {
@@ -216,13 +297,13 @@ __global__ __launch_bounds__(kThreads) void k_scan(const ChainDev* __restrict__ 
           for (int p = wave; p < f; p += 4)
             for (int c = lane; c < fb; c += 64) {
               T acc = 0;
-              for (int d = 0; d < fb; ++d) acc += Pm[s][p * kBlock + d] * Zb[s][d][c];
+              for (int d = 0; d < fb; ++d) acc += Pm[s][p * kBlock + d] * Zs[s][Fb[d]][Fb[c]];
               PZ[s][p * kBlock + c] = acc;
             }
           for (int c = wave; c < fb; c += 4)
             for (int q = lane; q < f; q += 64) {
               T acc = 0;
-              for (int d = 0; d < fb; ++d) acc += Zb[s][c][d] * Qm[s][d * LDZ + q];
+              for (int d = 0; d < fb; ++d) acc += Zs[s][Fb[c]][Fb[d]] * Qm[s][d * LDZ + q];
               ZQ[s][c * LDZ + q] = acc;
             }
         }
@@ -242,7 +323,7 @@ __global__ __launch_bounds__(kThreads) void k_scan(const ChainDev* __restrict__ 
       }
       for (int s = 0; s < 2; ++s)
         for (int c = wave; c < fb; c += 4)
-          for (int d = lane; d < fb; d += 64) Z[s][(size_t)(f + c) * LDZ + f + d] = Zb[s][c][d];
+          for (int d = lane; d < fb; d += 64) Z[s][(size_t)(f + c) * LDZ + f + d] = Zs[s][Fb[c]][Fb[d]];
       if (tid < fb) Fs[f + tid] = b0 + Fb[tid];
       __syncthreads();
       if (tid == 0) sh_f = f + fb;
@@ -250,17 +331,23 @@ __global__ __launch_bounds__(kThreads) void k_scan(const ChainDev* __restrict__ 
     }
   }
 
-  // operands of the flush: Xg = G0[:, F] (ld LDZ), Yg = (1 - G0)[F, :]
+  // operands of the flush: the accepted sites F and Yg = (1 - G0)[F, :]
+  // (rows of G0 gathered eight at a time so the loads are issued together)
   const int f = sh_f;
+  for (int p = tid; p < f; p += kThreads) C.flist[p] = Fs[p];
   for (int s = 0; s < 2; ++s) {
-    T* Xg = (T*)C.Xg[s];
-    T* Yg = (T*)C.Yg[s];
-    for (int i = wave; i < N; i += 4)
-      for (int p = lane; p < f; p += 64) Xg[(size_t)i * LDZ + p] = G0[s][(size_t)i * N + Fs[p]];
-    for (int p = wave; p < f; p += 4) {
-      const int site = Fs[p];
-      const T* src = G0[s] + (size_t)site * N;
-      for (int j = lane; j < N; j += 64) Yg[(size_t)p * N + j] = (site == j ? T(1) : T(0)) - src[j];
+    T* __restrict__ Yg = (T*)C.Yg[s];
+    for (int p0 = 8 * wave; p0 < f; p0 += 32) {
+      for (int j0 = 0; j0 < N; j0 += 64) {
+        const int j = j0 + lane;
+        T v[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+          v[r] = (p0 + r < f && j < N) ? G0[s][(size_t)Fs[p0 + r] * N + j] : T(0);
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+          if (p0 + r < f && j < N) Yg[(size_t)(p0 + r) * N + j] = (Fs[p0 + r] == j ? T(1) : T(0)) - v[r];
+      }
     }
   }
   for (int i = tid; i < nseg; i += kThreads) frow[s0 + i] = fs[i];
@@ -270,6 +357,252 @@ __global__ __launch_bounds__(kThreads) void k_scan(const ChainDev* __restrict__ 
     st->accepted += sh_acc;
     st->proposed += nseg;
   }
+}
+
+// Delayed-update flush of one segment, applied to whole rows:
+//   G[I,:] <- D (G0[I,:] - (G0[I,F] Z) Yg) D^{-1}      (scaling optional)
+// One workgroup owns kFlushRows rows of one chain and spin, so it can gather
+// X = G0[I,F] from its own rows before overwriting them; W = X Z is formed in
+// LDS and W Yg runs on MFMA.  Grid: chains x 2 spins x row blocks.  Loads that
+// do not depend on the accepted count (the site list, the first block of G)
+// are issued first; Z is staged in LDS (ZLDS) when it fits.
+constexpr int kFlushRows = 32;
+
+struct FlushLayout {
+  int lw;       // leading dimension of the LDS tiles (k-padded segment + 1)
+  size_t bytes; // dynamic LDS
+};
+template <typename T>
+__host__ __device__ inline FlushLayout flush_layout(int kseg, bool zlds) {
+  const int kp = (kseg + 3) / 4 * 4;
+  FlushLayout L;
+  L.lw = kp + 1;
+  L.bytes = ((size_t)2 * kFlushRows * L.lw + (zlds ? (size_t)kseg * L.lw : 0)) * sizeof(T) +
+            (size_t)kSegMax * sizeof(int);
+  return L;
+}
+
+template <typename T, bool ZLDS>
+__device__ __forceinline__ void flush_body(const ChainDev* __restrict__ chains, int nrb, int kseg,
+                                           int scale_slice, int scale_inverse, int M) {
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int cs = b / nrb, rb = b - cs * nrb;
+  const int spin = cs & 1;
+  const ChainDev& C = chains[cs >> 1];
+  const int N = C.N, i0 = rb * kFlushRows;
+  if (i0 >= N) return;
+  constexpr int KS = sizeof(T) == 4 ? 2 : 4;           // MFMA k-step
+  const FlushLayout lay = flush_layout<T>(kseg, ZLDS);
+  const int LW = lay.lw;
+  extern __shared__ __align__(16) unsigned char flush_smem[];
+  T* Xs = (T*)flush_smem;                // kFlushRows x LW
+  T* Ws = Xs + kFlushRows * LW;          // kFlushRows x LW
+  T* Zl = Ws + kFlushRows * LW;          // kseg x LW (ZLDS)
+  int* Fl = (int*)(Zl + (ZLDS ? kseg * LW : 0));
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  T* __restrict__ G = (T*)C.G[spin];
+  const T* __restrict__ Z = (const T*)C.Z[spin];
+  const T* __restrict__ Yg = (const T*)C.Yg[spin];
+
+  // issued together: accepted count, site list, first block of G
+  const int f = C.st->fcount;
+  const int fl_t = tid < kseg ? C.flist[tid] : 0;
+  constexpr int NG = 32;                                // G elements per lane and pass
+  T gpre[NG];
+  auto g_index = [&](int cb, int e, int& i, int& j) {
+    if constexpr (sizeof(T) == 4) {
+      // element (i, j) of a 32 x 32 block of v_mfma_f32_32x32x2f32 lives in
+      // lane j + 32 ((i / 4) % 2), register (i % 4) + 4 (i / 8); e = 16 block + register
+      const int r = e & 15;
+      i = i0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      j = cb + 32 * (e >> 4) + (lane & 31);
+    } else {
+      // element (i, j) of a 16 x 16 block of v_mfma_f64_16x16x4f64 lives in
+      // lane j + 16 (i % 4), register i / 4; e = 16 ra + 4 q + r
+      const int ra = e >> 4, q = (e >> 2) & 3, r = e & 3;
+      i = i0 + 16 * ra + 4 * r + (lane >> 4);
+      j = cb + 16 * q + (lane & 15);
+    }
+  };
+  auto g_load = [&](int cb) {
+#pragma unroll
+    for (int e = 0; e < NG; ++e) {
+      int i, j;
+      g_index(cb, e, i, j);
+      gpre[e] = (i < N && j < N) ? G[(size_t)i * N + j] : T(0);
+    }
+  };
+  if (64 * wave < N) g_load(64 * wave);
+  if (f == 0 && scale_slice < 0) return;
+  const int fp = (f + KS - 1) / KS * KS;
+
+  if (f > 0) {
+    if (tid < kseg) Fl[tid] = fl_t;
+    if (ZLDS)
+      for (int p = wave; p < f; p += 4)
+        for (int q = lane; q < f; q += 64) Zl[p * LW + q] = Z[(size_t)p * kSegMax + q];
+    __syncthreads();
+    // X = G0[I, F], zero beyond f
+    for (int r = wave; r < kFlushRows; r += 4) {
+      const int i = i0 + r;
+      for (int p = lane; p < fp; p += 64)
+        Xs[r * LW + p] = (i < N && p < f) ? G[(size_t)i * N + Fl[p]] : T(0);
+    }
+    __syncthreads();
+    // W = X Z  (rows over waves, columns over lanes), zero beyond f
+    {
+      const T* Zs = ZLDS ? Zl : Z;
+      const int ldz = ZLDS ? LW : kSegMax;
+      T acc[kFlushRows / 4][2];
+#pragma unroll
+      for (int m = 0; m < kFlushRows / 4; ++m) acc[m][0] = acc[m][1] = T(0);
+#pragma unroll 2
+      for (int p = 0; p < f; ++p) {
+        const T z0 = lane < f ? Zs[p * ldz + lane] : T(0);
+        const T z1 = lane + 64 < f ? Zs[p * ldz + lane + 64] : T(0);
+#pragma unroll
+        for (int m = 0; m < kFlushRows / 4; ++m) {
+          const T x = Xs[(wave + 4 * m) * LW + p];
+          acc[m][0] += x * z0;
+          acc[m][1] += x * z1;
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < kFlushRows / 4; ++m) {
+        if (lane < fp) Ws[(wave + 4 * m) * LW + lane] = acc[m][0];
+        if (lane + 64 < fp) Ws[(wave + 4 * m) * LW + lane + 64] = acc[m][1];
+      }
+    }
+    __syncthreads();
+  }
+
+  // scaling of the last flush of a slice: row i by d(i), column j by 1/d(j)
+  const int8_t* sf = scale_slice >= 0 ? C.field + (size_t)scale_slice * N : nullptr;
+  const int sb = (scale_slice == 0 || scale_slice == M + 1) ? 0 : 1;
+  const bool inv = scale_inverse != 0;
+  auto dfl = [&](int site, bool invert) -> double {
+    const int si = sf[site] > 0 ? 0 : 1;
+    return C.dval[sb][spin][invert ? 1 - si : si];
+  };
+
+  // G[I, :] -= W Yg: each wave takes 64 columns per pass; the old values of
+  // the pass's block are in gpre (the first pass's loaded before the W phase)
+  for (int cb = 64 * wave; cb < N; cb += 256) {
+    T accv[NG];
+    if constexpr (sizeof(T) == 4) {
+      const int kr = lane >> 5, cc = lane & 31;
+      const int j0 = cb + cc, j1 = cb + 32 + cc;
+      floatx16 a0, a1;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) a0[r] = a1[r] = 0.f;
+      for (int k0 = 0; k0 < fp; k0 += 8 * KS) {
+        float av[8], bv0[8], bv1[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const int k = k0 + t * KS + kr;
+          av[t] = k < fp ? Ws[cc * LW + k] : 0.f;
+          bv0[t] = (k < f && j0 < N) ? Yg[(size_t)k * N + j0] : 0.f;
+          bv1[t] = (k < f && j1 < N) ? Yg[(size_t)k * N + j1] : 0.f;
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          a0 = __builtin_amdgcn_mfma_f32_32x32x2f32(av[t], bv0[t], a0, 0, 0, 0);
+          a1 = __builtin_amdgcn_mfma_f32_32x32x2f32(av[t], bv1[t], a1, 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        accv[r] = a0[r];
+        accv[16 + r] = a1[r];
+      }
+    } else {
+      const int kr = lane >> 4, cc = lane & 15;
+      doublex4 acc[2][4];
+#pragma unroll
+      for (int ra = 0; ra < 2; ++ra)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[ra][q][r] = 0.0;
+      for (int k0 = 0; k0 < fp; k0 += 2 * KS) {
+        double av[2][2], bv[2][4];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          const int k = k0 + t * KS + kr;
+#pragma unroll
+          for (int ra = 0; ra < 2; ++ra) av[t][ra] = k < fp ? (double)Ws[(16 * ra + cc) * LW + k] : 0.0;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int j = cb + 16 * q + cc;
+            bv[t][q] = (k < f && j < N) ? (double)Yg[(size_t)k * N + j] : 0.0;
+          }
+        }
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+          for (int ra = 0; ra < 2; ++ra)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              acc[ra][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t][ra], bv[t][q], acc[ra][q], 0, 0, 0);
+      }
+#pragma unroll
+      for (int ra = 0; ra < 2; ++ra)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) accv[16 * ra + 4 * q + r] = (T)acc[ra][q][r];
+    }
+#pragma unroll
+    for (int e = 0; e < NG; ++e) {
+      int i, j;
+      g_index(cb, e, i, j);
+      T v = gpre[e] - accv[e];
+      if (sf && i < N && j < N) v *= (T)(dfl(i, inv) * dfl(j, !inv));
+      if (i < N && j < N) G[(size_t)i * N + j] = v;
+    }
+    if (cb + 256 < N) g_load(cb + 256);
+  }
+}
+
+// FP32: three waves per SIMD (168 registers); FP64 keeps its accumulators
+// unspilled at two
+template <bool ZLDS>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_flush32(
+    const ChainDev* __restrict__ chains, int nrb, int kseg, int scale_slice, int scale_inverse, int M) {
+  flush_body<float, ZLDS>(chains, nrb, kseg, scale_slice, scale_inverse, M);
+}
+template <bool ZLDS>
+__global__ __launch_bounds__(kThreads) void k_flush64(const ChainDev* __restrict__ chains, int nrb,
+                                                      int kseg, int scale_slice, int scale_inverse,
+                                                      int M) {
+  flush_body<double, ZLDS>(chains, nrb, kseg, scale_slice, scale_inverse, M);
+}
+
+hipError_t launch_flush(int fp32, const ChainDev* c, int nc, int n_max, int kseg, int scale_slice,
+                        int scale_inverse, int M, hipStream_t s) {
+  const int nrb = (n_max + kFlushRows - 1) / kFlushRows;
+  const dim3 grid(nc * 2 * nrb);
+  constexpr size_t kZldsMax = 64 * 1024;
+  if (fp32) {
+    const FlushLayout L = flush_layout<float>(kseg, true);
+    if (L.bytes <= kZldsMax)
+      hipLaunchKernelGGL((k_flush32<true>), grid, dim3(kThreads), L.bytes, s, c, nrb, kseg,
+                         scale_slice, scale_inverse, M);
+    else
+      hipLaunchKernelGGL((k_flush32<false>), grid, dim3(kThreads),
+                         flush_layout<float>(kseg, false).bytes, s, c, nrb, kseg, scale_slice,
+                         scale_inverse, M);
+  } else {
+    const FlushLayout L = flush_layout<double>(kseg, true);
+    if (L.bytes <= kZldsMax)
+      hipLaunchKernelGGL((k_flush64<true>), grid, dim3(kThreads), L.bytes, s, c, nrb, kseg,
+                         scale_slice, scale_inverse, M);
+    else
+      hipLaunchKernelGGL((k_flush64<false>), grid, dim3(kThreads),
+                         flush_layout<double>(kseg, false).bytes, s, c, nrb, kseg, scale_slice,
+                         scale_inverse, M);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_scan(int fp32, const ChainDev* c, int nc, const Ctl* ctl, int l, int M, int s0,

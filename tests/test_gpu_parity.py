@@ -81,9 +81,7 @@ FIXED = [
 ]
 
 
-@pytest.mark.parametrize("prec,kw", FIXED)
-def test_fixed_field_pass_matches_oracle(prec, kw):
-    w = small(prec, **kw)
+def check_fixed_field(w, prec):
     ctx = make_context([w], prec, trace=True).init_trial()
     ctx.set_debug(True)
     ch = oracle_chain(w, 0)
@@ -99,11 +97,27 @@ def test_fixed_field_pass_matches_oracle(prec, kw):
             assert rel_err(g_gpu[k, 0], gu) < TOL[prec], f"G_up at p={p}, sweep {sweep}"
             assert rel_err(g_gpu[k, 1], gd) < TOL[prec], f"G_dn at p={p}, sweep {sweep}"
         assert np.max(d_gpu) < (1e-8 if prec == "fp64" else 1e-3)
-        print(f"{prec} {kw}: sweep {sweep}: max ratio err {rel_err(r_gpu, r_ref):.2e}, "
+        print(f"{prec} {w.name}: sweep {sweep}: max ratio err {rel_err(r_gpu, r_ref):.2e}, "
               f"max G err {max(rel_err(g_gpu[k, s], g[2 + s]) for k, g in enumerate(ch.checkpoint_greens) for s in (0, 1)):.2e}, "
               f"max drift {np.max(d_gpu):.2e}")
     assert np.array_equal(ctx.get_field(0), ch.field)
     ctx.close()
+
+
+@pytest.mark.parametrize("prec,kw", FIXED)
+def test_fixed_field_pass_matches_oracle(prec, kw):
+    check_fixed_field(small(prec, **kw), prec)
+
+
+# the 16x16 benchmark workload (N = 256, 112 + 112 electrons, shell-closing
+# ramp) at a short projection time: every tile, segment and factorisation size
+# of the benchmark
+BENCH = WORKLOADS["16x16"].replace(stab_interval=5, delay_rank=32)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_fixed_field_pass_16x16(prec):
+    check_fixed_field(BENCH.replace(l_half=5, precision=prec), prec)
 
 
 # --------------------------------------------------------------------------- #
@@ -149,6 +163,36 @@ def test_trajectory_follows_oracle(prec, kw, n_sweeps):
     follow_and_compare(ctx, [ch], prec, n_sweeps, indep)
     if prec == "fp64":   # independent oracle run reaches the same field exactly
         assert np.array_equal(indep[0].field, ctx.get_field(0))
+    ctx.close()
+
+
+def test_trajectory_16x16_fp64():
+    w = BENCH.replace(l_half=5, precision="fp64")
+    ctx = make_context([w], "fp64").init_trial()
+    follow_and_compare(ctx, [oracle_chain(w, 0)], "fp64", 2)
+    ctx.close()
+
+
+def test_bench_configuration_sampled_chains_fp64():
+    """The benchmark's launch configuration (512 chains of the 16x16 workload
+    at l_half = 100, k = 32, n_s = 5), one FP64 sweep; two sampled chains are
+    followed through the whole pass by the oracle: fields (tie band aside) and
+    the measured (sign, E/N, D)."""
+    n_chains = 512
+    ctx = make_context([BENCH] * n_chains, "fp64", meas_capacity=4).init_trial()
+    ctx.sweep(1, measure=True)
+    for c in (0, 389):
+        ch = oracle_chain(BENCH, c)
+        f_gpu = ctx.get_field(c)
+        bad = ch.sweep_following(f_gpu, TIE["fp64"])
+        assert not bad, f"chain {c}: decisions differ beyond the tie band: {bad[:3]}"
+        assert np.array_equal(ch.field, f_gpu)
+        m_gpu, m_ref = ctx.measurements(c), np.array(ch.measurements)
+        assert m_gpu.shape == m_ref.shape
+        assert np.array_equal(m_gpu[:, 0], m_ref[:, 0])
+        assert np.max(np.abs(m_gpu[:, 1:] - m_ref[:, 1:])) < 1e-10
+        info = ctx.chain_info(c)
+        assert info["sign_mismatch"] == 0 and (info["flags"] & ~16) == 0, info
     ctx.close()
 
 
