@@ -29,8 +29,10 @@ METRIC = "HS-field updates/sec at 16×16, L=100; mixed vs FP64 GPU at 1e-5 rel G
 UNIT = "HS-field updates/s"
 PEAK_FP32_MFMA = 157.3e12   # MI355X dense FP32 matrix, FLOP/s
 PEAK_FP64_MFMA = 78.6e12
-KERNEL_SRC = os.path.join(ROOT, "paper_2303_13403_amd", "csrc", "gpqmc_gemm.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_wrap_gemm_16x16_b512.txt")
+PEAK_HBM = 8.0e12           # MI355X HBM3E, B/s
+# the dominant kernel (largest share of the sweep) is the delayed-update flush
+KERNEL_SRC = os.path.join(ROOT, "paper_2303_13403_amd", "csrc", "gpqmc_scan.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_flush_16x16_b512.txt")
 
 
 def log(*a):
@@ -42,9 +44,9 @@ def kernel_sha() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def read_traffic(chains: int):
-    """HBM bytes per launch of the wrap GEMM from the committed PMC summary, if
-    it was taken on the current kernel source and the same batch size."""
+def read_traffic(chains: int, precision: str):
+    """HBM bytes per launch of the flush from the committed PMC summary, if it
+    was taken on the current kernel source, batch size and precision."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     kv = {}
@@ -52,7 +54,8 @@ def read_traffic(chains: int):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("kernel_source_sha") != kernel_sha() or int(kv.get("chains", -1)) != chains:
+    if (kv.get("kernel_source_sha") != kernel_sha() or int(kv.get("chains", -1)) != chains
+            or kv.get("precision") != precision):
         return None
     return float(kv["hbm_bytes_per_launch"])
 
@@ -98,15 +101,17 @@ def run_gpu(args, precision_name, steps, warmup):
     assert prop == n_updates, (prop, n_updates)
     wrap_ms = ctx.time_kernel(0, reps=10)
     prop_ms = ctx.time_kernel(1, reps=10)
+    flush_ms = ctx.time_kernel(2, reps=20)
     res = dict(ms=ms, wall=wall, updates=n_updates, accept=acc / max(prop, 1),
                max_drift=max(i["max_drift"] for i in infos),
                flags=sorted({i["flags"] for i in infos}),
                sign_mismatch=sum(i["sign_mismatch"] for i in infos),
-               wrap_ms=wrap_ms, prop_ms=prop_ms,
+               wrap_ms=wrap_ms, prop_ms=prop_ms, flush_ms=flush_ms,
                sign=ctx.measure_sign(-1) if args.chains * (steps + warmup) >= 20 else None)
     log(f"[{precision_name}] {steps} sweeps: {ms:.1f} ms (wall {wall * 1e3:.1f} ms), "
         f"{n_updates / (ms / 1e3):.4g} updates/s, acceptance {res['accept']:.3f}, "
-        f"wrap GEMM {wrap_ms:.3f} ms/launch, max drift {res['max_drift']:.2e}, flags {res['flags']}")
+        f"flush {flush_ms:.3f} ms/launch, wrap GEMM {wrap_ms:.3f} ms/launch, "
+        f"max drift {res['max_drift']:.2e}, flags {res['flags']}")
     ctx.close()
     del ctx
     torch.cuda.empty_cache()
@@ -137,6 +142,21 @@ def cpu_baseline(args, budget_s=30.0):
                       f"serial FP64 NumPy, BLAS threads = 1, {dt:.1f} s"}
 
 
+def copy_calibration(mib: int, reps: int = 5):
+    """Device-to-device copies of a known size: the FETCH_SIZE / WRITE_SIZE
+    counters of these dispatches give the scale of the counters in bytes."""
+    import torch
+
+    n = mib * 2 ** 20 // 4
+    src = torch.rand(n, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": n * 4, "reps": reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -144,11 +164,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--chains", type=int, default=512)
     ap.add_argument("--ns", type=int, default=5)
-    ap.add_argument("--k", type=int, default=64)
+    ap.add_argument("--k", type=int, default=32)
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64", "mixed32b"])
     ap.add_argument("--fp64-steps", type=int, default=2,
                     help="sweeps of the plain FP64 GPU path timed for comparison (0 = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="choose --k and --ns with the autotuner on this batch first (table on stderr)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run device-to-device copies of MIB MiB (the reference kernel for "
+                         "scaling the HBM traffic counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): the chains of a "
@@ -161,6 +186,18 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
 
+    if args.copy_calibration > 0:
+        copy_calibration(args.copy_calibration)
+        return
+    if args.autotune:
+        from paper_2303_13403_amd import gpqmc
+        from paper_2303_13403_amd.autotune import autotune
+
+        prec = {"mixed": gpqmc.MIXED, "fp64": gpqmc.FP64, "mixed32b": gpqmc.MIXED_FP32_BASIS}[args.precision]
+        best, _ = autotune([workload(args)] * args.chains, prec, delay_ranks=(16, 32, 64),
+                           stab_intervals=(3, 5, 10), log=log)
+        args.k, args.ns = best.delay_rank, best.stab_interval
+        log(f"autotune: k={args.k} n_s={args.ns}")
     w = workload(args)
     N, M = w.n_sites, 2 * w.l_half
     main_res = run_gpu(args, args.precision, args.steps, args.warmup)
@@ -169,12 +206,16 @@ def main():
         fp64_res = run_gpu(args, "fp64", args.fp64_steps, 1)
 
     value = main_res["updates"] / (main_res["ms"] / 1e3)
-    # dominant kernel: the kinetic-wrap GEMM e^{-dtau K} G; one launch covers
-    # every chain and both spins: 2 * chains * 2 N^3 flops
-    flops = 2.0 * args.chains * 2.0 * N ** 3
-    peak = PEAK_FP32_MFMA if args.precision != "fp64" else PEAK_FP64_MFMA
-    achieved = flops / (main_res["wrap_ms"] / 1e3)
-    traffic = read_traffic(args.chains)
+    elem = 8 if args.precision == "fp64" else 4
+    # dominant kernel: the delayed-update flush, HBM-bound; algorithmic bytes
+    # per launch = every chain x 2 spins x (read + write of the N x N G)
+    flush_bytes = args.chains * 2 * 2 * N * N * elem
+    achieved = flush_bytes / (main_res["flush_ms"] / 1e3)
+    # the kinetic-wrap GEMM e^{-dtau K} G: 2 spins x 2 N^3 flops per chain
+    wrap_flops = 2.0 * args.chains * 2.0 * N ** 3
+    wrap_peak = PEAK_FP32_MFMA if args.precision != "fp64" else PEAK_FP64_MFMA
+    wrap_achieved = wrap_flops / (main_res["wrap_ms"] / 1e3)
+    traffic = read_traffic(args.chains, args.precision)
     out = {
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup,
@@ -190,10 +231,13 @@ def main():
             "delay_rank": args.k, "acceptance": round(main_res["accept"], 4),
             "max_drift": main_res["max_drift"], "flags": main_res["flags"],
         },
-        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
-                     "kernel": "k_gemm<float, GM_STORE> (e^{-dtau K} G, all chains x 2 spins)",
-                     "ms_per_launch": main_res["wrap_ms"]},
+        "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9,
+                     "unit": "GB/s", "frac": achieved / PEAK_HBM, "traffic": traffic,
+                     "kernel": "k_flush (delayed-update flush G -= (G0[:,F] Z) Yg, all chains x 2 spins)",
+                     "bytes_per_launch": flush_bytes, "ms_per_launch": main_res["flush_ms"]},
+        "mfma_wrap_gemm": {"achieved": wrap_achieved / 1e12, "peak": wrap_peak / 1e12,
+                           "unit": "TFLOP/s", "frac": wrap_achieved / wrap_peak,
+                           "ms_per_launch": main_res["wrap_ms"]},
     }
     if fp64_res is not None:
         out["fp64_gpu"] = {"value": fp64_res["updates"] / (fp64_res["ms"] / 1e3), "unit": UNIT,

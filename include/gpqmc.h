@@ -92,7 +92,7 @@ typedef struct {
   int32_t meas_capacity;      /* measurement records kept per chain (default 4096) */
   int32_t use_graph;          /* capture each pass in a HIP graph (default 1) */
   double drift_tol;           /* drift above this flags a chain (default 1e-3 mixed,
-                                 1e-6 fp64) */
+                                 1e-4 fp64) */
 } gpqmc_options;
 
 typedef struct {
@@ -190,7 +190,9 @@ gpqmc_status gpqmc_debug_gemm(int32_t precision, int32_t M, int32_t N, int32_t K
 /* Average duration (ms) of one launch of a hot-path kernel for all chains,
  * timed with HIP events on the context's stream over reps back-to-back
  * launches on the chains' current data: kernel 0 = the kinetic-wrap GEMM
- * e^{-dtau K} G (every chain and spin), 1 = the basis-propagation GEMM.
+ * e^{-dtau K} G (every chain and spin), 1 = the basis-propagation GEMM,
+ * 2 = the delayed-update flush of the last segment (its result goes to the
+ * wrap scratch, G is left unchanged; meaningful after a sweep).
  * Writes only scratch that every pass rebuilds.  Synchronises.
  * Errors: ESTATE before init_trial. */
 gpqmc_status gpqmc_time_kernel(gpqmc_ctx* ctx, int32_t kernel, int32_t reps, float* ms_per_launch);
@@ -201,7 +203,8 @@ gpqmc_status gpqmc_time_kernel(gpqmc_ctx* ctx, int32_t kernel, int32_t reps, flo
  * debug_read copies at most `count` elements of an internal buffer of one
  * chain and spin as doubles: 0 = G (N x N), 1 = Z (128 x 128), 2 = the
  * accepted sites of the last segment (128), 3 = Yg (rows of 1 - G, ld N),
- * 5 = (accepted count of the last segment, sign, accepted total).  A count
+ * 4 = Wg (G[:, F] Z, ld 128), 5 = (accepted count of the last segment, sign,
+ * accepted total).  A count
  * beyond the buffer is GPQMC_EINVAL. */
 gpqmc_status gpqmc_debug_step(gpqmc_ctx* ctx, int32_t stage, int32_t l, int32_t s0, int32_t s1);
 gpqmc_status gpqmc_debug_read(gpqmc_ctx* ctx, int32_t chain, int32_t what, int32_t spin, double* out,

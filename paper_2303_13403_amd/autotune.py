@@ -1,0 +1,99 @@
+"""Autotuner for the delay rank k and the stabilisation interval n_s of a batch.
+
+Both parameters trade speed against work or accuracy:
+
+* k (sites per delayed segment) sets how often the whole Green's function is
+  streamed by a flush (N / k times per slice) against the size of the
+  submatrix merge inside the scan (quadratic in the accepted count);
+* n_s (slices between re-stabilisations) sets how often the FP64 checkpoint
+  (Cholesky-QR, (L R)^{-1}, fresh G) runs, against the drift the wrapped
+  Green's function accumulates in between.
+
+For every candidate pair the tuner builds a context for the caller's batch,
+runs warm-up sweeps, times sweeps with HIP events on the context's stream and
+reads the largest checkpoint drift of the batch.  It returns the fastest pair
+whose drift stays below the precision's limit (FP64: 1e-4, mixed: 1e-3, the
+drift tolerances of the library), or the least-drifting pair if none does.
+Everything runs through the C ABI; nothing here computes any part of the
+method.
+"""
+from __future__ import annotations
+
+import dataclasses
+import time
+from typing import Iterable, List, Optional, Sequence
+
+from . import gpqmc
+from .workloads import Workload
+
+__all__ = ["Trial", "autotune"]
+
+DRIFT_LIMIT = {gpqmc.FP64: 1e-4, gpqmc.MIXED: 1e-3, gpqmc.MIXED_FP32_BASIS: 1e-3}
+
+
+@dataclasses.dataclass
+class Trial:
+    delay_rank: int
+    stab_interval: int
+    ms_per_sweep: float
+    updates_per_s: float
+    max_drift: float
+    flags: int
+
+
+def _run(ws: Sequence[Workload], precision: int, k: int, n_s: int, warmup: int, sweeps: int,
+         device: str) -> Trial:
+    import torch
+
+    descs = [gpqmc.chain_desc_arrays(w.replace(delay_rank=k, stab_interval=n_s), c, precision)
+             for c, w in enumerate(ws)]
+    ctx = gpqmc.Context(descs, device=device, meas_capacity=max(8, warmup + sweeps + 2))
+    try:
+        ctx.init_trial()
+        ctx.sweep(warmup, measure=False)
+        ctx.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(ctx.stream)
+        ctx.sweep(sweeps, measure=False)
+        ev1.record(ctx.stream)
+        ev1.synchronize()
+        ms = ev0.elapsed_time(ev1) / sweeps
+        infos = [ctx.chain_info(c) for c in range(len(ws))]
+    finally:
+        ctx.close()
+    updates = sum((2 * w.l_half + 2) * w.n_sites for w in ws)
+    flags = 0
+    for i in infos:
+        flags |= i["flags"]
+    return Trial(k, n_s, ms, updates / (ms / 1e3), max(i["max_drift"] for i in infos), flags)
+
+
+def autotune(workloads: Sequence[Workload], precision: int,
+             delay_ranks: Iterable[int] = (16, 32, 64),
+             stab_intervals: Iterable[int] = (3, 5, 10),
+             warmup: int = 1, sweeps: int = 2, device: str = "cuda:0",
+             drift_limit: Optional[float] = None, log=None):
+    """Time every (k, n_s) candidate on the batch ``workloads`` and return
+    ``(best, trials)``: the chosen :class:`Trial` and the table of all trials.
+
+    Candidates with k above the largest lattice are skipped (they equal
+    k = N).  ``drift_limit`` defaults to the library's drift tolerance of the
+    precision."""
+    limit = DRIFT_LIMIT[precision] if drift_limit is None else drift_limit
+    n_max = max(w.n_sites for w in workloads)
+    trials: List[Trial] = []
+    for k in delay_ranks:
+        if k > max(n_max, min(delay_ranks)):
+            continue
+        for n_s in stab_intervals:
+            t0 = time.time()
+            tr = _run(workloads, precision, int(k), int(n_s), warmup, sweeps, device)
+            trials.append(tr)
+            if log is not None:
+                log(f"autotune k={k:3d} n_s={n_s:2d}: {tr.ms_per_sweep:9.2f} ms/sweep "
+                    f"{tr.updates_per_s:.4g} upd/s  drift {tr.max_drift:.2e} "
+                    f"({time.time() - t0:.1f} s)")
+    ok = [t for t in trials if t.max_drift <= limit and (t.flags & ~16) == 0]
+    best = min(ok, key=lambda t: t.ms_per_sweep) if ok else min(trials, key=lambda t: t.max_drift)
+    return best, trials

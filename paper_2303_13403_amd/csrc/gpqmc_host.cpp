@@ -24,8 +24,9 @@ hipError_t launch_gemm_plain(int fp32, int transA, const GemmEntry* e, const Til
                              GemmArgs a, hipStream_t s);
 hipError_t launch_scan(int fp32, const ChainDev* c, int nc, const Ctl* ctl, int l, int M, int s0,
                        int s1, hipStream_t s);
+hipError_t launch_wmat(int fp32, const ChainDev* c, int nc, int n_max, int s0, int s1, hipStream_t s);
 hipError_t launch_flush(int fp32, const ChainDev* c, int nc, int n_max, int kseg, int scale_slice,
-                        int scale_inverse, int M, hipStream_t s);
+                        int scale_inverse, int M, int to_tmp, hipStream_t s);
 hipError_t launch_chol_inv(const ChainDev* c, int nc, int n_part, hipStream_t s);
 hipError_t launch_gj_inv(const ChainDev* c, int nc, int n_part, hipStream_t s);
 hipError_t launch_basis_to_fp64(int fp32b, const ChainDev* c, int nc, int parity, hipStream_t s);
@@ -123,7 +124,7 @@ struct ChainHost {
   bool field_set = false;
   std::vector<int8_t> field;
   // workspace offsets
-  size_t G[2], Gtmp[2], U2[2][2], Z[2], Yg[2], scan_ws[2], flist;
+  size_t G[2], Gtmp[2], U2[2][2], Z[2], Yg[2], Wg[2], scan_ws[2], flist;
   size_t stack[2], slot_log[2], slot_sgn[2], Hw[2], Qc[2], Wm[2], Rinv[2], Xm[2], Ym[2], G64[2];
   size_t field_off, st, meas, tr_ratio = 0, tr_green = 0, tr_drift = 0;
 };
@@ -258,8 +259,10 @@ struct Launcher {
       const bool last = s0 + ctx->kseg >= ctx->n_max;
       if ((e = launch_scan(ctx->fp32, chains, nc, ctl, l, ctx->M, s0, s0 + ctx->kseg, s)) != hipSuccess)
         return e;
+      if ((e = launch_wmat(ctx->fp32, chains, nc, ctx->n_max, s0, s0 + ctx->kseg, s)) != hipSuccess)
+        return e;
       if ((e = launch_flush(ctx->fp32, chains, nc, ctx->n_max, ctx->kseg, last ? scale_slice : -1, inverse,
-                            ctx->M, s)) != hipSuccess)
+                            ctx->M, 0, s)) != hipSuccess)
         return e;
     }
     return hipSuccess;
@@ -409,7 +412,7 @@ gpqmc_status gpqmc_create(int32_t n_chains, const gpqmc_chain_desc* chains,
     return bad(GPQMC_EINVAL, "need l_half >= 0, stab_interval >= 1, 1 <= delay_rank <= 128");
   c->M = 2 * c->l_half;
   c->n_slices = c->M + 2;
-  c->drift_tol = c->fp32 ? 1e-3f : 1e-6f;
+  c->drift_tol = c->fp32 ? 1e-3f : 1e-4f;
   if (opts) {
     if (opts->meas_capacity > 0) c->meas_cap = opts->meas_capacity;
     c->use_graph = opts->use_graph != 0;
@@ -548,6 +551,7 @@ gpqmc_status gpqmc_create(int32_t n_chains, const gpqmc_chain_desc* chains,
       h.U2[sp][1] = take(nb * ub);
       h.Z[sp] = take((size_t)kSegMax * kSegMax * bs);
       h.Yg[sp] = take(N * kSegMax * bs);
+      h.Wg[sp] = take(N * kSegMax * bs);
       h.scan_ws[sp] = take((size_t)5 * kBlock * kSegMax * bs);
       h.stack[sp] = take((size_t)n_slots * nb * 8);
       h.slot_log[sp] = take((size_t)n_slots * 8);
@@ -657,6 +661,7 @@ gpqmc_status gpqmc_bind_workspace(gpqmc_ctx* ctx, void* device_ptr, size_t bytes
       d.U[sp][1] = ctx->ws + h.U2[sp][1];
       d.Z[sp] = ctx->ws + h.Z[sp];
       d.Yg[sp] = ctx->ws + h.Yg[sp];
+      d.Wg[sp] = ctx->ws + h.Wg[sp];
       d.scan_ws[sp] = ctx->ws + h.scan_ws[sp];
       d.P[sp] = ctx->at<double>(ctx->trials[h.trial[sp]].off);
       d.stack[sp] = ctx->at<double>(h.stack[sp]);
@@ -1050,16 +1055,19 @@ gpqmc_status gpqmc_debug_gemm(int32_t precision, int32_t M, int32_t N, int32_t K
 }
 
 gpqmc_status gpqmc_time_kernel(gpqmc_ctx* ctx, int32_t kernel, int32_t reps, float* ms_per_launch) {
-  if (!ctx || !ms_per_launch || reps < 1 || kernel < 0 || kernel > 1) return GPQMC_EINVAL;
+  if (!ctx || !ms_per_launch || reps < 1 || kernel < 0 || kernel > 2) return GPQMC_EINVAL;
   if (!ctx->initialized) return fail(ctx, GPQMC_ESTATE, "time_kernel before init_trial");
   Launcher L = make_launcher(ctx);
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0), "event");
   HIPCHK(hipEventCreate(&e1), "event");
-  // both kernels write only scratch that every pass rebuilds before reading it
+  // every kernel writes only scratch that every pass rebuilds before reading it
   auto one = [&]() -> hipError_t {
     GemmArgs a = L.args();
     if (kernel == 0) return L.gemm(E_WRAP1_UP, GM_STORE, T_NN, a);  // Gtmp = e^{-dtau K} G
+    if (kernel == 2)   // the last segment's flush, result into Gtmp instead of G
+      return launch_flush(ctx->fp32, L.chains, L.nc, ctx->n_max, ctx->kseg, -1, 0, ctx->M, 1,
+                          ctx->stream);
     a.parity = 0;                                                  // U[1] = e^{-dtau K} U[0]
     return L.gemm(E_PROP, GM_PROPB, T_Nn, a);
   };
@@ -1083,7 +1091,11 @@ gpqmc_status gpqmc_debug_step(gpqmc_ctx* ctx, int32_t stage, int32_t l, int32_t 
                         ctx->stream), "ctl");
   hipError_t e = hipErrorInvalidValue;
   if (stage == 0) e = launch_scan(ctx->fp32, L.chains, L.nc, L.ctl, l, ctx->M, s0, s1, ctx->stream);
-  if (stage == 1) e = launch_flush(ctx->fp32, L.chains, L.nc, ctx->n_max, ctx->kseg, -1, 0, ctx->M, ctx->stream);
+  if (stage == 1) {
+    e = launch_wmat(ctx->fp32, L.chains, L.nc, ctx->n_max, s0, s1, ctx->stream);
+    if (e == hipSuccess)
+      e = launch_flush(ctx->fp32, L.chains, L.nc, ctx->n_max, ctx->kseg, -1, 0, ctx->M, 0, ctx->stream);
+  }
   HIPCHK(e, "debug step");
   HIPCHK(hipStreamSynchronize(ctx->stream), "debug step");
   return GPQMC_OK;
@@ -1101,6 +1113,7 @@ gpqmc_status gpqmc_debug_read(gpqmc_ctx* ctx, int32_t chain, int32_t what, int32
     case 1: off = h.Z[spin]; cap = (size_t)kSegMax * kSegMax; break;
     case 2: off = h.flist; elem = 4; is_int = true; cap = kSegMax; break;
     case 3: off = h.Yg[spin]; cap = (size_t)h.N * kSegMax; break;
+    case 4: off = h.Wg[spin]; cap = (size_t)h.N * kSegMax; break;
     case 5: off = h.st; elem = 0; cap = 3; break;
     default: return GPQMC_EINVAL;
   }

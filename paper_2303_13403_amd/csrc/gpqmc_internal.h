@@ -93,6 +93,7 @@ struct ChainDev {
   void* Gtmp[2];        // wrap intermediate
   void* Z[2];           // delayed-update coefficients of a segment (f x f, ld kSegMax)
   void* Yg[2];          // (1 - G0)[F, :]  (f x N, ld N)
+  void* Wg[2];          // G0[:, F] Z  (N x f, ld kSegMax)
   void* scan_ws[2];     // scan scratch, 5 * kBlock * kSegMax elements
   int* flist;           // accepted sites F of the last segment (kSegMax)
   const void* Km;       // e^{-dtau K}

@@ -14,8 +14,9 @@
 // wave with rank-1 (Sherman-Morrison) updates of that block while it builds
 // the block's own coefficient matrix Zb, which is then merged into Z:
 //     Z <- [[Z + P Zb Q, P Zb], [Zb Q, Zb]],  P = Z G0[F,Fb], Q = G0[Fb,F] Z.
-// The kernel ends by writing F and Yg = (1 - G0)[F,:]; k_flush then applies
-// (*) to the whole Green's function (a delayed update of rank |F|).
+// The kernel ends by writing F, Z and Yg = (1 - G0)[F,:]; k_wmat forms
+// Wg = G0[:,F] Z and k_flush applies (*) = G0 - Wg Yg to the whole Green's
+// function (a delayed update of rank |F|).
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -359,32 +360,18 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
   }
 }
 
-// Delayed-update flush of one segment, applied to whole rows:
-//   G[I,:] <- D (G0[I,:] - (G0[I,F] Z) Yg) D^{-1}      (scaling optional)
-// One workgroup owns kFlushRows rows of one chain and spin, so it can gather
-// X = G0[I,F] from its own rows before overwriting them; W = X Z is formed in
-// LDS and W Yg runs on MFMA.  Grid: chains x 2 spins x row blocks.  Loads that
-// do not depend on the accepted count (the site list, the first block of G)
-// are issued first; Z is staged in LDS (ZLDS) when it fits.
+// Delayed-update flush of one segment:
+//   G <- D (G0 - Wg Yg) D^{-1}      (scaling optional; Wg = G0[:,F] Z from k_wmat)
+// One workgroup updates kFlushRows rows of one chain and spin; each wave takes
+// 64 columns per pass (two 32-column halves on FP32 MFMA, 2 x 4 blocks of
+// 16 x 16 on FP64 MFMA).  The only dependent load is the accepted count: the
+// block of G, the rows of Wg and the rows of Yg are issued together.
+// Grid: chains x 2 spins x row blocks.
 constexpr int kFlushRows = 32;
 
-struct FlushLayout {
-  int lw;       // leading dimension of the LDS tiles (k-padded segment + 1)
-  size_t bytes; // dynamic LDS
-};
 template <typename T>
-__host__ __device__ inline FlushLayout flush_layout(int kseg, bool zlds) {
-  const int kp = (kseg + 3) / 4 * 4;
-  FlushLayout L;
-  L.lw = kp + 1;
-  L.bytes = ((size_t)2 * kFlushRows * L.lw + (zlds ? (size_t)kseg * L.lw : 0)) * sizeof(T) +
-            (size_t)kSegMax * sizeof(int);
-  return L;
-}
-
-template <typename T, bool ZLDS>
-__device__ __forceinline__ void flush_body(const ChainDev* __restrict__ chains, int nrb, int kseg,
-                                           int scale_slice, int scale_inverse, int M) {
+__device__ __forceinline__ void flush_body(const ChainDev* __restrict__ chains, int nrb,
+                                           int scale_slice, int scale_inverse, int M, int to_tmp) {
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int cs = b / nrb, rb = b - cs * nrb;
   const int spin = cs & 1;
@@ -392,27 +379,21 @@ __device__ __forceinline__ void flush_body(const ChainDev* __restrict__ chains, 
   const int N = C.N, i0 = rb * kFlushRows;
   if (i0 >= N) return;
   constexpr int KS = sizeof(T) == 4 ? 2 : 4;           // MFMA k-step
-  const FlushLayout lay = flush_layout<T>(kseg, ZLDS);
-  const int LW = lay.lw;
-  extern __shared__ __align__(16) unsigned char flush_smem[];
-  T* Xs = (T*)flush_smem;                // kFlushRows x LW
-  T* Ws = Xs + kFlushRows * LW;          // kFlushRows x LW
-  T* Zl = Ws + kFlushRows * LW;          // kseg x LW (ZLDS)
-  int* Fl = (int*)(Zl + (ZLDS ? kseg * LW : 0));
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  T* __restrict__ G = (T*)C.G[spin];
-  const T* __restrict__ Z = (const T*)C.Z[spin];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const T* __restrict__ G = (const T*)C.G[spin];
+  // the result goes back into G; to_tmp (kernel timing) sends it to Gtmp
+  T* __restrict__ Gout = to_tmp ? (T*)C.Gtmp[spin] : (T*)C.G[spin];
+  const T* __restrict__ W = (const T*)C.Wg[spin];
   const T* __restrict__ Yg = (const T*)C.Yg[spin];
-
-  // issued together: accepted count, site list, first block of G
   const int f = C.st->fcount;
-  const int fl_t = tid < kseg ? C.flist[tid] : 0;
+  if (f == 0 && scale_slice < 0) return;
+
   constexpr int NG = 32;                                // G elements per lane and pass
   T gpre[NG];
   auto g_index = [&](int cb, int e, int& i, int& j) {
     if constexpr (sizeof(T) == 4) {
       // element (i, j) of a 32 x 32 block of v_mfma_f32_32x32x2f32 lives in
-      // lane j + 32 ((i / 4) % 2), register (i % 4) + 4 (i / 8); e = 16 block + register
+      // lane j + 32 ((i / 4) % 2), register (i % 4) + 4 (i / 8); e = 16 half + register
       const int r = e & 15;
       i = i0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
       j = cb + 32 * (e >> 4) + (lane & 31);
@@ -424,57 +405,14 @@ __device__ __forceinline__ void flush_body(const ChainDev* __restrict__ chains, 
       j = cb + 16 * q + (lane & 15);
     }
   };
-  auto g_load = [&](int cb) {
+  auto g_load = [&](int cb, int e0, int ne) {
 #pragma unroll
-    for (int e = 0; e < NG; ++e) {
+    for (int e = e0; e < e0 + ne; ++e) {
       int i, j;
       g_index(cb, e, i, j);
       gpre[e] = (i < N && j < N) ? G[(size_t)i * N + j] : T(0);
     }
   };
-  if (64 * wave < N) g_load(64 * wave);
-  if (f == 0 && scale_slice < 0) return;
-  const int fp = (f + KS - 1) / KS * KS;
-
-  if (f > 0) {
-    if (tid < kseg) Fl[tid] = fl_t;
-    if (ZLDS)
-      for (int p = wave; p < f; p += 4)
-        for (int q = lane; q < f; q += 64) Zl[p * LW + q] = Z[(size_t)p * kSegMax + q];
-    __syncthreads();
-    // X = G0[I, F], zero beyond f
-    for (int r = wave; r < kFlushRows; r += 4) {
-      const int i = i0 + r;
-      for (int p = lane; p < fp; p += 64)
-        Xs[r * LW + p] = (i < N && p < f) ? G[(size_t)i * N + Fl[p]] : T(0);
-    }
-    __syncthreads();
-    // W = X Z  (rows over waves, columns over lanes), zero beyond f
-    {
-      const T* Zs = ZLDS ? Zl : Z;
-      const int ldz = ZLDS ? LW : kSegMax;
-      T acc[kFlushRows / 4][2];
-#pragma unroll
-      for (int m = 0; m < kFlushRows / 4; ++m) acc[m][0] = acc[m][1] = T(0);
-#pragma unroll 2
-      for (int p = 0; p < f; ++p) {
-        const T z0 = lane < f ? Zs[p * ldz + lane] : T(0);
-        const T z1 = lane + 64 < f ? Zs[p * ldz + lane + 64] : T(0);
-#pragma unroll
-        for (int m = 0; m < kFlushRows / 4; ++m) {
-          const T x = Xs[(wave + 4 * m) * LW + p];
-          acc[m][0] += x * z0;
-          acc[m][1] += x * z1;
-        }
-      }
-#pragma unroll
-      for (int m = 0; m < kFlushRows / 4; ++m) {
-        if (lane < fp) Ws[(wave + 4 * m) * LW + lane] = acc[m][0];
-        if (lane + 64 < fp) Ws[(wave + 4 * m) * LW + lane + 64] = acc[m][1];
-      }
-    }
-    __syncthreads();
-  }
 
   // scaling of the last flush of a slice: row i by d(i), column j by 1/d(j)
   const int8_t* sf = scale_slice >= 0 ? C.field + (size_t)scale_slice * N : nullptr;
@@ -484,38 +422,43 @@ __device__ __forceinline__ void flush_body(const ChainDev* __restrict__ chains, 
     const int si = sf[site] > 0 ? 0 : 1;
     return C.dval[sb][spin][invert ? 1 - si : si];
   };
+  // new value of element e of the pass from its old value and the product
+  auto put = [&](int cb, int e, T acc) {
+    int i, j;
+    g_index(cb, e, i, j);
+    T v = gpre[e] - acc;
+    if (sf && i < N && j < N) v *= (T)(dfl(i, inv) * dfl(j, !inv));
+    if (i < N && j < N) Gout[(size_t)i * N + j] = v;
+  };
 
-  // G[I, :] -= W Yg: each wave takes 64 columns per pass; the old values of
-  // the pass's block are in gpre (the first pass's loaded before the W phase)
   for (int cb = 64 * wave; cb < N; cb += 256) {
-    T accv[NG];
     if constexpr (sizeof(T) == 4) {
       const int kr = lane >> 5, cc = lane & 31;
-      const int j0 = cb + cc, j1 = cb + 32 + cc;
-      floatx16 a0, a1;
+      const int ia = i0 + cc;
+      const T* wrow = W + (size_t)ia * kSegMax;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) a0[r] = a1[r] = 0.f;
-      for (int k0 = 0; k0 < fp; k0 += 8 * KS) {
-        float av[8], bv0[8], bv1[8];
+      for (int h = 0; h < 2; ++h) {
+        const int jh = cb + 32 * h + cc;
+        g_load(cb, 16 * h, 16);
+        floatx16 a0;
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          const int k = k0 + t * KS + kr;
-          av[t] = k < fp ? Ws[cc * LW + k] : 0.f;
-          bv0[t] = (k < f && j0 < N) ? Yg[(size_t)k * N + j0] : 0.f;
-          bv1[t] = (k < f && j1 < N) ? Yg[(size_t)k * N + j1] : 0.f;
+        for (int r = 0; r < 16; ++r) a0[r] = 0.f;
+        for (int k0 = 0; k0 < f; k0 += 8 * KS) {
+          float av[8], bv[8];
+#pragma unroll
+          for (int t = 0; t < 8; ++t) {
+            const int k = k0 + t * KS + kr;
+            av[t] = (k < f && ia < N) ? wrow[k] : 0.f;
+            bv[t] = (k < f && jh < N) ? Yg[(size_t)k * N + jh] : 0.f;
+          }
+#pragma unroll
+          for (int t = 0; t < 8; ++t) a0 = __builtin_amdgcn_mfma_f32_32x32x2f32(av[t], bv[t], a0, 0, 0, 0);
         }
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          a0 = __builtin_amdgcn_mfma_f32_32x32x2f32(av[t], bv0[t], a0, 0, 0, 0);
-          a1 = __builtin_amdgcn_mfma_f32_32x32x2f32(av[t], bv1[t], a1, 0, 0, 0);
-        }
-      }
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        accv[r] = a0[r];
-        accv[16 + r] = a1[r];
+        for (int r = 0; r < 16; ++r) put(cb, 16 * h + r, a0[r]);
       }
     } else {
+      g_load(cb, 0, NG);
       const int kr = lane >> 4, cc = lane & 15;
       doublex4 acc[2][4];
 #pragma unroll
@@ -524,13 +467,16 @@ __device__ __forceinline__ void flush_body(const ChainDev* __restrict__ chains, 
         for (int q = 0; q < 4; ++q)
 #pragma unroll
           for (int r = 0; r < 4; ++r) acc[ra][q][r] = 0.0;
-      for (int k0 = 0; k0 < fp; k0 += 2 * KS) {
+      for (int k0 = 0; k0 < f; k0 += 2 * KS) {
         double av[2][2], bv[2][4];
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
           const int k = k0 + t * KS + kr;
 #pragma unroll
-          for (int ra = 0; ra < 2; ++ra) av[t][ra] = k < fp ? (double)Ws[(16 * ra + cc) * LW + k] : 0.0;
+          for (int ra = 0; ra < 2; ++ra) {
+            const int ia = i0 + 16 * ra + cc;
+            av[t][ra] = (k < f && ia < N) ? (double)W[(size_t)ia * kSegMax + k] : 0.0;
+          }
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const int j = cb + 16 * q + cc;
@@ -550,58 +496,103 @@ __device__ __forceinline__ void flush_body(const ChainDev* __restrict__ chains, 
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) accv[16 * ra + 4 * q + r] = (T)acc[ra][q][r];
+          for (int r = 0; r < 4; ++r) put(cb, 16 * ra + 4 * q + r, (T)acc[ra][q][r]);
     }
-#pragma unroll
-    for (int e = 0; e < NG; ++e) {
-      int i, j;
-      g_index(cb, e, i, j);
-      T v = gpre[e] - accv[e];
-      if (sf && i < N && j < N) v *= (T)(dfl(i, inv) * dfl(j, !inv));
-      if (i < N && j < N) G[(size_t)i * N + j] = v;
-    }
-    if (cb + 256 < N) g_load(cb + 256);
   }
 }
 
-// FP32: three waves per SIMD (168 registers); FP64 keeps its accumulators
-// unspilled at two
-template <bool ZLDS>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_flush32(
-    const ChainDev* __restrict__ chains, int nrb, int kseg, int scale_slice, int scale_inverse, int M) {
-  flush_body<float, ZLDS>(chains, nrb, kseg, scale_slice, scale_inverse, M);
+__global__ __launch_bounds__(kThreads) void k_flush32(const ChainDev* __restrict__ chains, int nrb,
+                                                      int scale_slice, int scale_inverse, int M,
+                                                      int to_tmp) {
+  flush_body<float>(chains, nrb, scale_slice, scale_inverse, M, to_tmp);
 }
-template <bool ZLDS>
 __global__ __launch_bounds__(kThreads) void k_flush64(const ChainDev* __restrict__ chains, int nrb,
-                                                      int kseg, int scale_slice, int scale_inverse,
-                                                      int M) {
-  flush_body<double, ZLDS>(chains, nrb, kseg, scale_slice, scale_inverse, M);
+                                                      int scale_slice, int scale_inverse, int M,
+                                                      int to_tmp) {
+  flush_body<double>(chains, nrb, scale_slice, scale_inverse, M, to_tmp);
 }
 
 hipError_t launch_flush(int fp32, const ChainDev* c, int nc, int n_max, int kseg, int scale_slice,
-                        int scale_inverse, int M, hipStream_t s) {
+                        int scale_inverse, int M, int to_tmp, hipStream_t s) {
+  (void)kseg;
   const int nrb = (n_max + kFlushRows - 1) / kFlushRows;
-  const dim3 grid(nc * 2 * nrb);
-  constexpr size_t kZldsMax = 64 * 1024;
-  if (fp32) {
-    const FlushLayout L = flush_layout<float>(kseg, true);
-    if (L.bytes <= kZldsMax)
-      hipLaunchKernelGGL((k_flush32<true>), grid, dim3(kThreads), L.bytes, s, c, nrb, kseg,
-                         scale_slice, scale_inverse, M);
-    else
-      hipLaunchKernelGGL((k_flush32<false>), grid, dim3(kThreads),
-                         flush_layout<float>(kseg, false).bytes, s, c, nrb, kseg, scale_slice,
-                         scale_inverse, M);
-  } else {
-    const FlushLayout L = flush_layout<double>(kseg, true);
-    if (L.bytes <= kZldsMax)
-      hipLaunchKernelGGL((k_flush64<true>), grid, dim3(kThreads), L.bytes, s, c, nrb, kseg,
-                         scale_slice, scale_inverse, M);
-    else
-      hipLaunchKernelGGL((k_flush64<false>), grid, dim3(kThreads),
-                         flush_layout<double>(kseg, false).bytes, s, c, nrb, kseg, scale_slice,
-                         scale_inverse, M);
+  const dim3 grid(nc * 2 * nrb);   // exactly one workgroup per (chain, spin, row block)
+  if (fp32)
+    hipLaunchKernelGGL(k_flush32, grid, dim3(kThreads), 0, s, c, nrb, scale_slice, scale_inverse, M,
+                       to_tmp);
+  else
+    hipLaunchKernelGGL(k_flush64, grid, dim3(kThreads), 0, s, c, nrb, scale_slice, scale_inverse, M,
+                       to_tmp);
+  return hipGetLastError();
+}
+
+// Wg = G0[:, F] Z (N x f, ld kSegMax) of the segment [s0, s1), computed as
+// G0[:, S] Zs with S the segment's consecutive sites and Zs = Z spread over
+// them (zero rows on rejected sites): each thread reads a contiguous slab of
+// 32 sites of its row; 32 columns of Wg at a time, the 32 x 32 slab of Zs in
+// LDS.  Grid: chains x 2 spins x ceil(N_max / 256) row blocks.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_wmat(const ChainDev* __restrict__ chains, int nrb,
+                                                   int s0, int s1) {
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int cs = b / nrb, rb = b - cs * nrb;
+  const int spin = cs & 1;
+  const ChainDev& C = chains[cs >> 1];
+  const int N = C.N;
+  if (s0 >= N || rb * kThreads >= N) return;
+  const int f = C.st->fcount;
+  if (f == 0) return;
+  const int nseg = min(s1, N) - s0, tid = threadIdx.x;
+  __shared__ __align__(16) T Zs[32][32];
+  __shared__ int pos[kSegMax];
+  for (int c = tid; c < nseg; c += kThreads) pos[c] = -1;
+  __syncthreads();
+  for (int p = tid; p < f; p += kThreads) pos[C.flist[p] - s0] = p;
+  const T* __restrict__ Z = (const T*)C.Z[spin];
+  const T* __restrict__ G = (const T*)C.G[spin];
+  T* __restrict__ W = (T*)C.Wg[spin];
+  const int i = rb * kThreads + tid;
+  for (int q0 = 0; q0 < f; q0 += 32) {
+    T acc[32];
+#pragma unroll
+    for (int t = 0; t < 32; ++t) acc[t] = T(0);
+    for (int sc = 0; sc < nseg; sc += 32) {
+      __syncthreads();
+      for (int e = tid; e < 32 * 32; e += kThreads) {
+        const int c = e >> 5, t = e & 31;
+        const int p = sc + c < nseg ? pos[sc + c] : -1;
+        Zs[c][t] = (p >= 0 && q0 + t < f) ? Z[(size_t)p * kSegMax + q0 + t] : T(0);
+      }
+      __syncthreads();
+      if (i < N) {
+        const int nc = min(32, nseg - sc);
+        const T* grow = G + (size_t)i * N + s0 + sc;
+        T x[32];
+#pragma unroll
+        for (int c = 0; c < 32; ++c) x[c] = c < nc ? grow[c] : T(0);
+#pragma unroll
+        for (int c = 0; c < 32; ++c) {
+#pragma unroll
+          for (int t = 0; t < 32; ++t) acc[t] += x[c] * Zs[c][t];
+        }
+      }
+    }
+    if (i < N) {
+      T* wrow = W + (size_t)i * kSegMax + q0;
+#pragma unroll
+      for (int t = 0; t < 32; ++t)
+        if (q0 + t < f) wrow[t] = acc[t];
+    }
   }
+}
+
+hipError_t launch_wmat(int fp32, const ChainDev* c, int nc, int n_max, int s0, int s1, hipStream_t s) {
+  const int nrb = (n_max + kThreads - 1) / kThreads;
+  const dim3 grid(nc * 2 * nrb);
+  if (fp32)
+    hipLaunchKernelGGL(k_wmat<float>, grid, dim3(kThreads), 0, s, c, nrb, s0, s1);
+  else
+    hipLaunchKernelGGL(k_wmat<double>, grid, dim3(kThreads), 0, s, c, nrb, s0, s1);
   return hipGetLastError();
 }
 

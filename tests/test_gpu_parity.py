@@ -231,3 +231,15 @@ def test_graph_and_direct_launch_agree():
         res.append((ctx.get_field(0), ctx.measurements(0)))
         ctx.close()
     assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])
+
+
+def test_autotune_times_every_candidate_and_picks_a_valid_one():
+    from paper_2303_13403_amd.autotune import autotune
+
+    ws = [w.replace(l_half=5) for w in batch_uneven(8, l_half=5)]
+    best, trials = autotune(ws, gpqmc.MIXED, delay_ranks=(8, 16), stab_intervals=(2, 4), sweeps=1)
+    assert sorted((t.delay_rank, t.stab_interval) for t in trials) == [(8, 2), (8, 4), (16, 2), (16, 4)]
+    assert all(t.ms_per_sweep > 0 and t.updates_per_s > 0 for t in trials)
+    assert best in trials and best.max_drift <= 1e-3 and (best.flags & ~16) == 0
+    assert best.ms_per_sweep == min(t.ms_per_sweep for t in trials
+                                    if t.max_drift <= 1e-3 and (t.flags & ~16) == 0)
