@@ -79,8 +79,9 @@ typedef struct {
   double m_neel;              /* Neel order parameter M_N of the trial */
   int32_t l_half;             /* slices per side, Theta / dtau (>= 0) */
   int32_t stab_interval;      /* n_s: slices between QR re-stabilisations (>= 1) */
-  int32_t delay_rank;         /* k: sites per segment of the delayed scan (1 .. 128); each
-                                 segment ends with one rank-(accepted) update of G */
+  int32_t delay_rank;         /* k: sites per segment of the flip scan (1 .. 64); the
+                                 accepted flips of all segments of a slice are
+                                 applied to G by one delayed update per slice */
   int32_t precision;          /* gpqmc_precision */
   uint64_t seed;              /* Philox key; words (lo32(seed), hi32(seed) ^ tag) */
   uint64_t chain_id;          /* counter word 0 of every draw of this chain */
@@ -180,18 +181,21 @@ gpqmc_status gpqmc_set_debug(gpqmc_ctx* ctx, int32_t flags);
 gpqmc_status gpqmc_get_trace(gpqmc_ctx* ctx, int32_t chain, double* ratios, double* greens,
                              double* drifts, int32_t* n_checkpoints);
 
-/* Batched-GEMM self test on caller device memory: C = op(A) B with the
- * library's MFMA tile kernel (precision GPQMC_FP64 or GPQMC_MIXED = FP32),
- * A M x K row-major (or K x M when trans_a), B K x N, C M x N.  Synchronises. */
-gpqmc_status gpqmc_debug_gemm(int32_t precision, int32_t M, int32_t N, int32_t K,
-                              int32_t trans_a, const void* A, int32_t lda, const void* B,
-                              int32_t ldb, void* C, int32_t ldc, void* hip_stream);
+/* GEMM self test on caller device memory: C = op(A) B with one of the
+ * library's MFMA tile kernels (precision GPQMC_FP64 or GPQMC_MIXED = FP32).
+ * flags bit 0: op(A) = A^T (A is K x M); bit 1: the large-tile FP32 kernel of
+ * the kinetic wrap (requires GPQMC_MIXED and no transpose).  A M x K
+ * row-major (or K x M), B K x N, C M x N.  Synchronises.
+ * Errors: EINVAL on bad sizes or an unsupported flag combination. */
+gpqmc_status gpqmc_debug_gemm(int32_t precision, int32_t M, int32_t N, int32_t K, int32_t flags,
+                              const void* A, int32_t lda, const void* B, int32_t ldb, void* C,
+                              int32_t ldc, void* hip_stream);
 
 /* Average duration (ms) of one launch of a hot-path kernel for all chains,
  * timed with HIP events on the context's stream over reps back-to-back
  * launches on the chains' current data: kernel 0 = the kinetic-wrap GEMM
  * e^{-dtau K} G (every chain and spin), 1 = the basis-propagation GEMM,
- * 2 = the delayed-update flush of the last segment (its result goes to the
+ * 2 = the delayed update of the last slice, G - Xa Ya (its result goes to the
  * wrap scratch, G is left unchanged; meaningful after a sweep).
  * Writes only scratch that every pass rebuilds.  Synchronises.
  * Errors: ESTATE before init_trial. */
@@ -199,12 +203,12 @@ gpqmc_status gpqmc_time_kernel(gpqmc_ctx* ctx, int32_t kernel, int32_t reps, flo
 
 /* Debugging hooks (off the hot path; synchronise).  debug_step runs one
  * stage of slice l on every chain: 0 = the flip scan of sites [s0, s1),
- * 1 = the delayed-update flush of that segment into G (no frame change).
+ * 1 = appending that segment's factors to the slice's delayed update
+ * G - Xa Ya, 2 = applying the delayed update to G (no frame change).
  * debug_read copies at most `count` elements of an internal buffer of one
- * chain and spin as doubles: 0 = G (N x N), 1 = Z (128 x 128), 2 = the
- * accepted sites of the last segment (128), 3 = Yg (rows of 1 - G, ld N),
- * 4 = Wg (G[:, F] Z, ld 128), 5 = (accepted count of the last segment, sign,
- * accepted total).  A count
+ * chain and spin as doubles: 0 = G (N x N), 1 = Z (64 x 64), 2 = the
+ * accepted sites of the last segment (64), 3 = Ya (N x N), 4 = Xa (N x N),
+ * 5 = (accepted count of the last segment, sign, accepted total).  A count
  * beyond the buffer is GPQMC_EINVAL. */
 gpqmc_status gpqmc_debug_step(gpqmc_ctx* ctx, int32_t stage, int32_t l, int32_t s0, int32_t s1);
 gpqmc_status gpqmc_debug_read(gpqmc_ctx* ctx, int32_t chain, int32_t what, int32_t spin, double* out,

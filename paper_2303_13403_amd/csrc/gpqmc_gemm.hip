@@ -1,6 +1,7 @@
 // Batched MFMA GEMM of the PQMC sweep (gfx950), one 64 x 64 output tile per
 // workgroup, with the epilogues that fuse the sweep's elementwise work:
 //   the kinetic wrap                    G <- D_{l+1} (Gtmp e^{dtau K}) D_{l+1}^{-1}
+//   the slice's delayed update          G <- D (G - Xa Ya) D^{-1}
 //   the basis propagation               U <- e^{-dtau K} (D_l U)   /  D_l (e^{-dtau K} U)
 //   the checkpoint products (FP64)      U^T U, U R^{-1}, L^T R, (L R)^{-1} L, 1 - R Y
 // The tile list maps every workgroup to (entry, tile); entries are one chain
@@ -21,7 +22,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm(const GemmEntry* __restrict__
   if (bid >= n_tiles) return;
   const TileRef tr = tiles[bid];
   const GemmEntry& e = ents[tr.entry];
-  const int M = e.M, N = e.N, K = e.K;
+  const int M = e.M, N = e.N, K = e.dynK ? *e.dynK : e.K;
   const int m0 = tr.tm * kTile, n0 = tr.tn * kTile;
   if (m0 >= M || n0 >= N) return;
 
@@ -163,11 +164,14 @@ __global__ __launch_bounds__(kThreads) void k_gemm(const GemmEntry* __restrict__
       T v = acc;
       if (sfield) v *= (T)dfac(e.dval, sbnd, sfield[i], false);
       C[o] = v;
-    } else if (MODE == GM_WRAP) {
-      T v = acc;
+    } else if (MODE == GM_WRAP || MODE == GM_FLUSH) {
+      T v = (MODE == GM_FLUSH) ? ((const T*)e.C[0])[o] - acc : acc;
       if (sfield)
         v *= (T)(dfac(e.dval, sbnd, sfield[i], inv) * dfac(e.dval, sbnd, sfield[j], !inv));
-      C[o] = v;
+      if (MODE == GM_FLUSH)
+        ((T*)e.C[1])[o] = v;
+      else
+        C[o] = v;
     } else if (MODE == GM_GFRESH) {
       const double g = (i == j ? 1.0 : 0.0) - (double)acc;
       C[o] = (T)g;
@@ -196,6 +200,201 @@ __global__ __launch_bounds__(kThreads) void k_gemm(const GemmEntry* __restrict__
   }
 }
 
+// ---------------------------------------------------------------------------
+// Large-tile FP32 GEMM for the N x N x N products of the kinetic wrap (modes
+// STORE and WRAP) and the slice's delayed update (FLUSH, K = accepted flips): 128 x 128 output tile per workgroup, 64 x 64 per wave as
+// 2 x 2 blocks of v_mfma_f32_32x32x2f32, k-tiles of 32 double-buffered in LDS
+// with the next k-tile prefetched into registers (one barrier per k-tile).
+// A is kept in LDS with each row's k values split by parity (k = 2 kk + h at
+// [row][h][kk]), so a lane fetches the A operand of four MFMA k-steps with one
+// 128-bit read; B stays row-major ([k][j]), read one float per k-step.
+// ---------------------------------------------------------------------------
+constexpr int kTileL = 128, BKL = 32;
+constexpr int LDAL = BKL + 4;        // A tile row: 16 even-k, 16 odd-k, 4 pad
+constexpr int LDBL = kTileL + 4;     // B tile row
+
+__device__ inline float4 load4(const float* __restrict__ p, int valid, bool aligned) {
+  if (aligned && valid >= 4) return *reinterpret_cast<const float4*>(p);
+  float4 v;
+  v.x = valid > 0 ? p[0] : 0.f;
+  v.y = valid > 1 ? p[1] : 0.f;
+  v.z = valid > 2 ? p[2] : 0.f;
+  v.w = valid > 3 ? p[3] : 0.f;
+  return v;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kThreads) void k_gemm_l(const GemmEntry* __restrict__ ents,
+                                                     const TileRef* __restrict__ tiles,
+                                                     int n_tiles, GemmArgs args) {
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  if (bid >= n_tiles) return;
+  const TileRef tr = tiles[bid];
+  const GemmEntry& e = ents[tr.entry];
+  const int M = e.M, N = e.N, K = e.dynK ? *e.dynK : e.K;
+  const int m0 = tr.tm * kTileL, n0 = tr.tn * kTileL;
+  if (m0 >= M || n0 >= N) return;
+  const float* __restrict__ A = (const float*)e.A[0];
+  const float* __restrict__ B = (const float*)e.B[0];
+  float* __restrict__ C = (float*)e.C[0];
+  const int lda = e.lda, ldb = e.ldb, ldc = e.ldc;
+  const bool a_al = (lda & 3) == 0, b_al = (ldb & 3) == 0;
+
+  __shared__ __align__(16) float As[2][kTileL * LDAL];
+  __shared__ __align__(16) float Bs[2][BKL * LDBL];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+
+  // global -> register mapping: A rows am, k from ak; B k-row bk, columns from bj
+  const int am = tid >> 1, ak = (tid & 1) * 16;
+  const int bk = tid >> 3, bj = (tid & 7) * 16;
+  float4 ra[4], rb[4];
+  auto gload = [&](int k0) {
+    const int i = m0 + am;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int k = k0 + ak + 4 * q;
+      ra[q] = load4(A + (size_t)i * lda + k, i < M ? K - k : 0, a_al);
+    }
+    const int kb = k0 + bk;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int j = n0 + bj + 4 * q;
+      rb[q] = load4(B + (size_t)kb * ldb + j, kb < K ? N - j : 0, b_al);
+    }
+  };
+  auto sstore = [&](int buf) {
+    float* a = &As[buf][am * LDAL + ak / 2];
+    *reinterpret_cast<float4*>(a) = make_float4(ra[0].x, ra[0].z, ra[1].x, ra[1].z);
+    *reinterpret_cast<float4*>(a + 4) = make_float4(ra[2].x, ra[2].z, ra[3].x, ra[3].z);
+    *reinterpret_cast<float4*>(a + 16) = make_float4(ra[0].y, ra[0].w, ra[1].y, ra[1].w);
+    *reinterpret_cast<float4*>(a + 20) = make_float4(ra[2].y, ra[2].w, ra[3].y, ra[3].w);
+    float* b = &Bs[buf][bk * LDBL + bj];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) *reinterpret_cast<float4*>(b + 4 * q) = rb[q];
+  };
+
+  floatx16 acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[x][y][r] = 0.f;
+
+  const int h = lane >> 5, l32 = lane & 31;
+  // FLUSH: the old values of the wave's 64 x 64 block of C, loaded before the
+  // k-loop so that their latency overlaps it
+  float cold[2][2][16];
+  if (MODE == GM_FLUSH) {
+    const float* __restrict__ C0 = (const float*)e.C[0];
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+      const int j = n0 + wn + 32 * y + l32;
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int i = m0 + wm + 32 * x + 8 * (r >> 2) + 4 * h + (r & 3);
+          cold[x][y][r] = (i < M && j < N) ? C0[(size_t)i * ldc + j] : 0.f;
+        }
+    }
+  }
+  const int nk = (K + BKL - 1) / BKL;
+  if (nk > 0) {
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+      const int buf = kt & 1;
+      if (kt + 1 < nk) gload((kt + 1) * BKL);
+      const float* as = As[buf];
+      const float* bs = Bs[buf];
+#pragma unroll
+      for (int c = 0; c < BKL / 8; ++c) {          // four k-steps (k = 8c .. 8c + 7)
+        float4 av[2];
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+          av[x] = *reinterpret_cast<const float4*>(&as[(wm + 32 * x + l32) * LDAL + 16 * h + 4 * c]);
+#pragma unroll
+        for (int pp = 0; pp < 4; ++pp) {
+          const int kr = 2 * (4 * c + pp) + h;
+          float bv[2];
+#pragma unroll
+          for (int y = 0; y < 2; ++y) bv[y] = bs[kr * LDBL + wn + 32 * y + l32];
+#pragma unroll
+          for (int x = 0; x < 2; ++x) {
+            const float a = pp == 0 ? av[x].x : pp == 1 ? av[x].y : pp == 2 ? av[x].z : av[x].w;
+#pragma unroll
+            for (int y = 0; y < 2; ++y)
+              acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bv[y], acc[x][y], 0, 0, 0);
+          }
+        }
+      }
+      if (kt + 1 < nk) sstore(buf ^ 1);
+      __syncthreads();
+    }
+  }
+
+  // epilogue: element (i, j) of a 32 x 32 block lives in lane j + 32 ((i / 4) % 2),
+  // register (i % 4) + 4 (i / 8)
+  const int8_t* sfield = nullptr;
+  int sbnd = 1;
+  if ((MODE == GM_WRAP || MODE == GM_FLUSH) && args.scale_slice >= 0) {
+    sfield = e.field + (size_t)args.scale_slice * e.n_sites;
+    sbnd = (args.scale_slice == 0 || args.scale_slice == args.n_bulk_last + 1) ? 0 : 1;
+  }
+  const bool inv = args.scale_inverse != 0;
+  // the tile's row factors d(i) and column factors 1/d(j), staged once in LDS
+  // (the A buffer is free after the last k-tile's barrier)
+  float* drow = As[0];
+  float* dcol = As[0] + kTileL;
+  if (sfield) {
+    if (tid < kTileL) {
+      const int i = m0 + tid;
+      drow[tid] = i < M ? (float)dfac(e.dval, sbnd, sfield[i], inv) : 0.f;
+    } else {
+      const int j = n0 + tid - kTileL;
+      dcol[tid - kTileL] = j < N ? (float)dfac(e.dval, sbnd, sfield[j], !inv) : 0.f;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int y = 0; y < 2; ++y) {
+    const int jl = wn + 32 * y + l32, j = n0 + jl;
+    const float dj = sfield ? dcol[jl] : 1.f;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int il = wm + 32 * x + 8 * (r >> 2) + 4 * h + (r & 3), i = m0 + il;
+        if (i < M && j < N) {
+          const size_t o = (size_t)i * ldc + j;
+          float v = MODE == GM_FLUSH ? cold[x][y][r] - acc[x][y][r] : acc[x][y][r];
+          if (sfield) v *= drow[il] * dj;
+          if (MODE == GM_FLUSH)
+            ((float*)e.C[1])[o] = v;
+          else
+            C[o] = v;
+        }
+      }
+  }
+}
+
+hipError_t launch_gemm_l(int mode, const GemmEntry* e, const TileRef* t, int n, GemmArgs a,
+                         hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (mode == GM_STORE)
+    hipLaunchKernelGGL(k_gemm_l<GM_STORE>, dim3(n), dim3(kThreads), 0, s, e, t, n, a);
+  else if (mode == GM_WRAP)
+    hipLaunchKernelGGL(k_gemm_l<GM_WRAP>, dim3(n), dim3(kThreads), 0, s, e, t, n, a);
+  else if (mode == GM_FLUSH)
+    hipLaunchKernelGGL(k_gemm_l<GM_FLUSH>, dim3(n), dim3(kThreads), 0, s, e, t, n, a);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
 template <typename T, int MODE, bool TA, bool TB, typename Tb>
 static hipError_t gemm_t(const GemmEntry* e, const TileRef* t, int n, GemmArgs a, hipStream_t s) {
   if (n <= 0) return hipSuccess;
@@ -222,6 +421,7 @@ hipError_t launch_gemm(int fp32, int g_fp32, int mode, const GemmEntry* e, const
     switch (mode) {
       case GM_STORE: return gemm_t<float, GM_STORE, false, false, float>(e, t, n, a, s);
       case GM_WRAP: return gemm_t<float, GM_WRAP, false, false, float>(e, t, n, a, s);
+      case GM_FLUSH: return gemm_t<float, GM_FLUSH, false, false, float>(e, t, n, a, s);
       case GM_PROPB: return gemm_t<float, GM_PROPB, false, false, float>(e, t, n, a, s);
       case GM_PROPR: return gemm_t<float, GM_PROPR, false, false, float>(e, t, n, a, s);
     }
@@ -229,6 +429,7 @@ hipError_t launch_gemm(int fp32, int g_fp32, int mode, const GemmEntry* e, const
     switch (mode) {
       case GM_STORE: return gemm_t<double, GM_STORE, false, false, double>(e, t, n, a, s);
       case GM_WRAP: return gemm_t<double, GM_WRAP, false, false, double>(e, t, n, a, s);
+      case GM_FLUSH: return gemm_t<double, GM_FLUSH, false, false, double>(e, t, n, a, s);
       case GM_PROPB: return gemm_t<double, GM_PROPB, false, false, double>(e, t, n, a, s);
       case GM_PROPR: return gemm_t<double, GM_PROPR, false, false, double>(e, t, n, a, s);
     }

@@ -20,13 +20,13 @@
 namespace gpqmc {
 hipError_t launch_gemm(int fp32, int g_fp32, int mode, const GemmEntry* e, const TileRef* t, int n,
                        GemmArgs a, hipStream_t s);
+hipError_t launch_gemm_l(int mode, const GemmEntry* e, const TileRef* t, int n, GemmArgs a,
+                         hipStream_t s);
 hipError_t launch_gemm_plain(int fp32, int transA, const GemmEntry* e, const TileRef* t, int n,
                              GemmArgs a, hipStream_t s);
 hipError_t launch_scan(int fp32, const ChainDev* c, int nc, const Ctl* ctl, int l, int M, int s0,
                        int s1, hipStream_t s);
-hipError_t launch_wmat(int fp32, const ChainDev* c, int nc, int n_max, int s0, int s1, hipStream_t s);
-hipError_t launch_flush(int fp32, const ChainDev* c, int nc, int n_max, int kseg, int scale_slice,
-                        int scale_inverse, int M, int to_tmp, hipStream_t s);
+hipError_t launch_xy(int fp32, const ChainDev* c, int nc, int n_max, int kseg, hipStream_t s);
 hipError_t launch_chol_inv(const ChainDev* c, int nc, int n_part, hipStream_t s);
 hipError_t launch_gj_inv(const ChainDev* c, int nc, int n_part, hipStream_t s);
 hipError_t launch_basis_to_fp64(int fp32b, const ChainDev* c, int nc, int parity, hipStream_t s);
@@ -124,7 +124,7 @@ struct ChainHost {
   bool field_set = false;
   std::vector<int8_t> field;
   // workspace offsets
-  size_t G[2], Gtmp[2], U2[2][2], Z[2], Yg[2], Wg[2], scan_ws[2], flist;
+  size_t G[2], Gtmp[2], U2[2][2], Z[2], Xa[2], Ya[2], scan_ws[2], flist;
   size_t stack[2], slot_log[2], slot_sgn[2], Hw[2], Qc[2], Wm[2], Rinv[2], Xm[2], Ym[2], G64[2];
   size_t field_off, st, meas, tr_ratio = 0, tr_green = 0, tr_drift = 0;
 };
@@ -156,8 +156,9 @@ struct gpqmc_ctx {
   size_t off_chains = 0, off_ctl = 0;
   size_t off_ent[16] = {0};
   // tile lists: N x N, N x n, n x n, n x N and (delay rank) x N outputs
-  std::vector<TileRef> tiles[5];
-  size_t off_tiles[5] = {0};
+  std::vector<TileRef> tiles[6];
+  size_t off_tiles[6] = {0};
+  int n_min = 1 << 30;             // smallest lattice of the batch
   char* ws = nullptr;
   bool bound = false, initialized = false;
   long long sweeps_done = 0;       // passes enqueued since init_trial (mirrors the device counter)
@@ -175,9 +176,9 @@ struct gpqmc_ctx {
 
 namespace {
 
-enum EntryKind { E_WRAP1_UP = 0, E_WRAP2_UP, E_WRAP1_DN, E_WRAP2_DN, E_PROP, E_GRAM_U, E_APPLY1,
-                 E_XMAT, E_YMAT, E_GFRESH, E_COUNT };
-enum TileKind { T_NN = 0, T_Nn, T_nn, T_nN, T_COUNT };
+enum EntryKind { E_WRAP1_UP = 0, E_WRAP2_UP, E_WRAP1_DN, E_WRAP2_DN, E_FLUSH, E_FLUSH_T, E_PROP,
+                 E_GRAM_U, E_APPLY1, E_XMAT, E_YMAT, E_GFRESH, E_COUNT };
+enum TileKind { T_NN = 0, T_Nn, T_nn, T_nN, T_NN_L, T_COUNT };   // T_NN_L: 128 x 128 tiles
 
 gpqmc_status fail(gpqmc_ctx* c, gpqmc_status s, const std::string& msg) {
   if (c) c->err = msg;
@@ -222,6 +223,11 @@ struct Launcher {
   }
   hipError_t gemm(int kind, int mode, int tk, GemmArgs a) {
     const int f32 = (mode == GM_PROPB || mode == GM_PROPR) ? ctx->fp32b : ctx->fp32;
+    // FP32 N x N x N products of lattices with N >= 128: large-tile kernel
+    if (f32 && tk == T_NN && (mode == GM_STORE || mode == GM_WRAP || mode == GM_FLUSH) &&
+        ctx->n_min >= 128)
+      return launch_gemm_l(mode, ents(ctx, kind), ctx->at<TileRef>(ctx->off_tiles[T_NN_L]),
+                           (int)ctx->tiles[T_NN_L].size(), a, s);
     return launch_gemm(f32, ctx->fp32, mode, ents(ctx, kind), ctx->at<TileRef>(ctx->off_tiles[tk]),
                        (int)ctx->tiles[tk].size(), a, s);
   }
@@ -256,16 +262,14 @@ struct Launcher {
   hipError_t scan_and_flush(int l, int scale_slice, int inverse) {
     hipError_t e;
     for (int s0 = 0; s0 < ctx->n_max; s0 += ctx->kseg) {
-      const bool last = s0 + ctx->kseg >= ctx->n_max;
       if ((e = launch_scan(ctx->fp32, chains, nc, ctl, l, ctx->M, s0, s0 + ctx->kseg, s)) != hipSuccess)
         return e;
-      if ((e = launch_wmat(ctx->fp32, chains, nc, ctx->n_max, s0, s0 + ctx->kseg, s)) != hipSuccess)
-        return e;
-      if ((e = launch_flush(ctx->fp32, chains, nc, ctx->n_max, ctx->kseg, last ? scale_slice : -1, inverse,
-                            ctx->M, 0, s)) != hipSuccess)
-        return e;
+      if ((e = launch_xy(ctx->fp32, chains, nc, ctx->n_max, ctx->kseg, s)) != hipSuccess) return e;
     }
-    return hipSuccess;
+    GemmArgs a = args();
+    a.scale_slice = scale_slice;
+    a.scale_inverse = inverse;
+    return gemm(E_FLUSH, GM_FLUSH, T_NN, a);
   }
 
   hipError_t up_pass() {
@@ -366,10 +370,10 @@ Launcher make_launcher(gpqmc_ctx* ctx) {
   return L;
 }
 
-void build_tiles(std::vector<TileRef>& out, const std::vector<std::pair<int, int>>& mn) {
+void build_tiles(std::vector<TileRef>& out, const std::vector<std::pair<int, int>>& mn, int tile) {
   out.clear();
   for (size_t e = 0; e < mn.size(); ++e) {
-    const int tm = (mn[e].first + kTile - 1) / kTile, tn = (mn[e].second + kTile - 1) / kTile;
+    const int tm = (mn[e].first + tile - 1) / tile, tn = (mn[e].second + tile - 1) / tile;
     for (int a = 0; a < tm; ++a)
       for (int b = 0; b < tn; ++b) out.push_back(TileRef{(int)e, a, b, 0});
   }
@@ -409,7 +413,7 @@ gpqmc_status gpqmc_create(int32_t n_chains, const gpqmc_chain_desc* chains,
       d0.precision != GPQMC_MIXED_FP32_BASIS)
     return bad(GPQMC_EINVAL, "precision must be GPQMC_FP64, GPQMC_MIXED or GPQMC_MIXED_FP32_BASIS");
   if (c->l_half < 0 || c->n_s < 1 || c->kseg < 1 || c->kseg > kSegMax)
-    return bad(GPQMC_EINVAL, "need l_half >= 0, stab_interval >= 1, 1 <= delay_rank <= 128");
+    return bad(GPQMC_EINVAL, "need l_half >= 0, stab_interval >= 1, 1 <= delay_rank <= 64");
   c->M = 2 * c->l_half;
   c->n_slices = c->M + 2;
   c->drift_tol = c->fp32 ? 1e-3f : 1e-4f;
@@ -550,8 +554,8 @@ gpqmc_status gpqmc_create(int32_t n_chains, const gpqmc_chain_desc* chains,
       h.U2[sp][0] = take(nb * ub);
       h.U2[sp][1] = take(nb * ub);
       h.Z[sp] = take((size_t)kSegMax * kSegMax * bs);
-      h.Yg[sp] = take(N * kSegMax * bs);
-      h.Wg[sp] = take(N * kSegMax * bs);
+      h.Xa[sp] = take(nn * bs);
+      h.Ya[sp] = take(nn * bs);
       h.scan_ws[sp] = take((size_t)5 * kBlock * kSegMax * bs);
       h.stack[sp] = take((size_t)n_slots * nb * 8);
       h.slot_log[sp] = take((size_t)n_slots * 8);
@@ -577,19 +581,21 @@ gpqmc_status gpqmc_create(int32_t n_chains, const gpqmc_chain_desc* chains,
   c->off_chains = take(sizeof(ChainDev) * n_chains);
   c->off_ctl = take(sizeof(Ctl));
   for (int k = 0; k < E_COUNT; ++k) c->off_ent[k] = take(sizeof(GemmEntry) * 2 * n_chains);
-  std::vector<std::pair<int, int>> sz[5];
+  std::vector<std::pair<int, int>> sz[T_COUNT];
   for (auto& h : c->ch) {
     c->n_max = std::max(c->n_max, h.N);
+    c->n_min = std::min(c->n_min, h.N);
     c->n_part = std::max(c->n_part, std::max(h.n[0], h.n[1]));
     for (int sp = 0; sp < 2; ++sp) {
       sz[T_NN].push_back({h.N, h.N});
       sz[T_Nn].push_back({h.N, h.n[sp]});
       sz[T_nn].push_back({h.n[sp], h.n[sp]});
       sz[T_nN].push_back({h.n[sp], h.N});
+      sz[T_NN_L].push_back({h.N, h.N});
     }
   }
   for (int t = 0; t < T_COUNT; ++t) {
-    build_tiles(c->tiles[t], sz[t]);
+    build_tiles(c->tiles[t], sz[t], t == T_NN_L ? 128 : kTile);
     c->off_tiles[t] = take(sizeof(TileRef) * c->tiles[t].size());
   }
   c->bytes = align256(off);
@@ -660,8 +666,8 @@ gpqmc_status gpqmc_bind_workspace(gpqmc_ctx* ctx, void* device_ptr, size_t bytes
       d.U[sp][0] = ctx->ws + h.U2[sp][0];
       d.U[sp][1] = ctx->ws + h.U2[sp][1];
       d.Z[sp] = ctx->ws + h.Z[sp];
-      d.Yg[sp] = ctx->ws + h.Yg[sp];
-      d.Wg[sp] = ctx->ws + h.Wg[sp];
+      d.Xa[sp] = ctx->ws + h.Xa[sp];
+      d.Ya[sp] = ctx->ws + h.Ya[sp];
       d.scan_ws[sp] = ctx->ws + h.scan_ws[sp];
       d.P[sp] = ctx->at<double>(ctx->trials[h.trial[sp]].off);
       d.stack[sp] = ctx->at<double>(h.stack[sp]);
@@ -724,6 +730,13 @@ gpqmc_status gpqmc_bind_workspace(gpqmc_ctx* ctx, void* device_ptr, size_t bytes
       E[E_WRAP2_UP][ei] = nnE(d.Gtmp[sp], d.Kp, d.G[sp]);
       E[E_WRAP1_DN][ei] = nnE(d.Kp, d.G[sp], d.Gtmp[sp]);
       E[E_WRAP2_DN][ei] = nnE(d.Gtmp[sp], d.Km, d.G[sp]);
+      // the slice's delayed update G <- G - Xa Ya (K = the slice's accepted flips);
+      // the timing copy writes the wrap scratch instead of G
+      GemmEntry fl = mk(d.Xa[sp], d.Xa[sp], d.Ya[sp], d.Ya[sp], d.G[sp], d.G[sp], N, N, N, N, N, N);
+      fl.dynK = &d.st->ftot;
+      E[E_FLUSH][ei] = fl;
+      fl.C[1] = d.Gtmp[sp];
+      E[E_FLUSH_T][ei] = fl;
       const void* Kmb = ctx->ws + L.off_Kmb;
       E[E_PROP][ei] = mk(Kmb, Kmb, d.U[sp][0], d.U[sp][1], d.U[sp][0], d.U[sp][1], N, n, N, N, n, n);
       // checkpoint: Cholesky QR of U[parity] (or of its FP64 copy in Hw)
@@ -1014,10 +1027,12 @@ gpqmc_status gpqmc_get_trace(gpqmc_ctx* ctx, int32_t chain, double* ratios, doub
   return GPQMC_OK;
 }
 
-gpqmc_status gpqmc_debug_gemm(int32_t precision, int32_t M, int32_t N, int32_t K, int32_t trans_a,
+gpqmc_status gpqmc_debug_gemm(int32_t precision, int32_t M, int32_t N, int32_t K, int32_t flags,
                               const void* A, int32_t lda, const void* B, int32_t ldb, void* C,
                               int32_t ldc, void* hip_stream) {
   if (M <= 0 || N <= 0 || K < 0 || !A || !B || !C) return GPQMC_EINVAL;
+  const int trans_a = flags & 1, large = (flags >> 1) & 1;
+  if (large && (trans_a || precision != GPQMC_MIXED)) return GPQMC_EINVAL;
   gpqmc_ctx* ctx = nullptr;
   GemmEntry e;
   memset(&e, 0, sizeof e);
@@ -1031,7 +1046,7 @@ gpqmc_status gpqmc_debug_gemm(int32_t precision, int32_t M, int32_t N, int32_t K
   e.ldb = ldb;
   e.ldc = ldc;
   std::vector<TileRef> tl;
-  build_tiles(tl, {{M, N}});
+  build_tiles(tl, {{M, N}}, large ? 128 : kTile);
   // test hook: a small descriptor buffer in device memory for this one call
   void* dbuf = nullptr;
   const size_t bytes = align256(sizeof e) + sizeof(TileRef) * tl.size();
@@ -1044,8 +1059,9 @@ gpqmc_status gpqmc_debug_gemm(int32_t precision, int32_t M, int32_t N, int32_t K
   memset(&a, 0, sizeof a);
   a.scale_slice = -1;
   a.bscale_slice = -1;
-  hipError_t err = launch_gemm_plain(precision == GPQMC_MIXED, trans_a, (const GemmEntry*)dbuf, dt,
-                                     (int)tl.size(), a, s);
+  hipError_t err = large ? launch_gemm_l(GM_STORE, (const GemmEntry*)dbuf, dt, (int)tl.size(), a, s)
+                         : launch_gemm_plain(precision == GPQMC_MIXED, trans_a,
+                                             (const GemmEntry*)dbuf, dt, (int)tl.size(), a, s);
   hipError_t err2 = hipStreamSynchronize(s);
   const hipError_t err3 = hipFree(dbuf);
   if (err3 != hipSuccess) return GPQMC_EHIP;
@@ -1065,9 +1081,8 @@ gpqmc_status gpqmc_time_kernel(gpqmc_ctx* ctx, int32_t kernel, int32_t reps, flo
   auto one = [&]() -> hipError_t {
     GemmArgs a = L.args();
     if (kernel == 0) return L.gemm(E_WRAP1_UP, GM_STORE, T_NN, a);  // Gtmp = e^{-dtau K} G
-    if (kernel == 2)   // the last segment's flush, result into Gtmp instead of G
-      return launch_flush(ctx->fp32, L.chains, L.nc, ctx->n_max, ctx->kseg, -1, 0, ctx->M, 1,
-                          ctx->stream);
+    if (kernel == 2)   // the last slice's delayed update, result into Gtmp instead of G
+      return L.gemm(E_FLUSH_T, GM_FLUSH, T_NN, a);
     a.parity = 0;                                                  // U[1] = e^{-dtau K} U[0]
     return L.gemm(E_PROP, GM_PROPB, T_Nn, a);
   };
@@ -1091,10 +1106,10 @@ gpqmc_status gpqmc_debug_step(gpqmc_ctx* ctx, int32_t stage, int32_t l, int32_t 
                         ctx->stream), "ctl");
   hipError_t e = hipErrorInvalidValue;
   if (stage == 0) e = launch_scan(ctx->fp32, L.chains, L.nc, L.ctl, l, ctx->M, s0, s1, ctx->stream);
-  if (stage == 1) {
-    e = launch_wmat(ctx->fp32, L.chains, L.nc, ctx->n_max, s0, s1, ctx->stream);
-    if (e == hipSuccess)
-      e = launch_flush(ctx->fp32, L.chains, L.nc, ctx->n_max, ctx->kseg, -1, 0, ctx->M, 0, ctx->stream);
+  if (stage == 1) e = launch_xy(ctx->fp32, L.chains, L.nc, ctx->n_max, ctx->kseg, ctx->stream);
+  if (stage == 2) {
+    GemmArgs a = L.args();
+    e = L.gemm(E_FLUSH, GM_FLUSH, T_NN, a);
   }
   HIPCHK(e, "debug step");
   HIPCHK(hipStreamSynchronize(ctx->stream), "debug step");
@@ -1112,8 +1127,8 @@ gpqmc_status gpqmc_debug_read(gpqmc_ctx* ctx, int32_t chain, int32_t what, int32
     case 0: off = h.G[spin]; cap = (size_t)h.N * h.N; break;
     case 1: off = h.Z[spin]; cap = (size_t)kSegMax * kSegMax; break;
     case 2: off = h.flist; elem = 4; is_int = true; cap = kSegMax; break;
-    case 3: off = h.Yg[spin]; cap = (size_t)h.N * kSegMax; break;
-    case 4: off = h.Wg[spin]; cap = (size_t)h.N * kSegMax; break;
+    case 3: off = h.Ya[spin]; cap = (size_t)h.N * h.N; break;
+    case 4: off = h.Xa[spin]; cap = (size_t)h.N * h.N; break;
     case 5: off = h.st; elem = 0; cap = 3; break;
     default: return GPQMC_EINVAL;
   }

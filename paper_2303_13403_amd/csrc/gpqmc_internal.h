@@ -9,7 +9,7 @@ namespace gpqmc {
 
 constexpr int kThreads = 256;   // every kernel runs 256-thread workgroups (4 waves)
 constexpr int kBlock = 32;      // submatrix block of the flip scan (sites)
-constexpr int kSegMax = 128;    // largest delay rank: sites per scan segment / flush
+constexpr int kSegMax = 64;     // largest delay rank: sites per scan segment
 constexpr int kMaxSites = 1024; // largest lattice
 constexpr int kTile = 64;       // GEMM output tile (kTile x kTile per workgroup)
 constexpr int kLdsDense = 128;  // small dense factorisations run in LDS up to this order
@@ -47,6 +47,9 @@ struct ChainState {
   int sign;             // tracked sign of W_up * W_dn
   int sweep;            // pass counter: word 1 of the Philox counter
   int fcount;           // flips with nonzero Delta accepted in the current scan segment
+  int foff;             // such flips accepted in the slice before the current segment
+  int ftot;             // such flips accepted in the slice so far (foff + fcount)
+  int pad1;
   int flags;            // sticky error bits (FLAG_*)
   int n_meas;           // stored measurement records
   int sign_mismatch;    // checkpoints where tracked and recomputed signs differ
@@ -92,8 +95,10 @@ struct ChainDev {
   void* G[2];           // equal-time Green's function in the current frame
   void* Gtmp[2];        // wrap intermediate
   void* Z[2];           // delayed-update coefficients of a segment (f x f, ld kSegMax)
-  void* Yg[2];          // (1 - G0)[F, :]  (f x N, ld N)
-  void* Wg[2];          // G0[:, F] Z  (N x f, ld kSegMax)
+  // slice-level delayed update G = G0 - Xa Ya over the ftot flips accepted in
+  // the slice so far (N x N each, ld N; columns / rows 0 .. ftot used)
+  void* Xa[2];
+  void* Ya[2];
   void* scan_ws[2];     // scan scratch, 5 * kBlock * kSegMax elements
   int* flist;           // accepted sites F of the last segment (kSegMax)
   const void* Km;       // e^{-dtau K}
@@ -146,6 +151,8 @@ struct GemmEntry {
   int n_sites;
   int spin;
   ChainState* st;
+  const int* dynK;      // if set, the chain's K is *dynK (the slice's accepted count)
+  int pad;
   double dval[2][2];    // [b][s] diagonal of D for this spin (see ChainDev)
 };
 
@@ -168,6 +175,7 @@ struct GemmArgs {
 enum GemmMode : int {
   GM_STORE = 0,   // C = A B
   GM_WRAP = 1,    // C = D (A B) D^{-1}  (or D^{-1}(A B)D, or unscaled)
+  GM_FLUSH = 2,   // C[1] = D (C[0] - A B) D^{-1}  (scaling optional, K = *dynK)
   GM_PROPB = 3,   // C[p^1] = A (D B[p])
   GM_PROPR = 4,   // C[p^1] = D (A B[p])
   GM_GRAM = 6,    // C = A[p]^T A[p]  (FP64)

@@ -14,9 +14,12 @@
 // wave with rank-1 (Sherman-Morrison) updates of that block while it builds
 // the block's own coefficient matrix Zb, which is then merged into Z:
 //     Z <- [[Z + P Zb Q, P Zb], [Zb Q, Zb]],  P = Z G0[F,Fb], Q = G0[Fb,F] Z.
-// The kernel ends by writing F, Z and Yg = (1 - G0)[F,:]; k_wmat forms
-// Wg = G0[:,F] Z and k_flush applies (*) = G0 - Wg Yg to the whole Green's
-// function (a delayed update of rank |F|).
+// G0 here is the Green's function of the segment's start, G_s = G - Xa Ya
+// with Xa Ya the not yet applied flips of earlier segments of the slice; the
+// kernel forms its block G_s[S,S] over the segment's sites S in LDS and works
+// on it alone.  It ends by writing F and Z; k_xy appends the segment to Xa Ya,
+// and one GEMM per slice applies G <- G - Xa Ya (a delayed update of rank =
+// the slice's accepted flips), fused with the frame change.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -84,7 +87,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
   const int N = C.N;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (s0 >= N) {   // uneven batch: this chain has no site in the segment
-    if (tid == 0) st->fcount = 0;
+    if (tid == 0) {
+      st->fcount = 0;
+      st->foff = st->ftot;
+    }
     return;
   }
   const int send = min(s1, N), nseg = send - s0;
@@ -101,7 +107,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
   __shared__ __align__(16) T HsT[2][kBlock][KL];
   __shared__ __align__(16) T Zs[2][kBlock][KL];
   __shared__ __align__(16) T rowbuf[2][kBlock], uvec[2][kBlock], vvec[2][kBlock];
-  __shared__ T Rsf[kBlock * kSegMax];
+  __shared__ __align__(16) T Rsf[kSegMax * 36];   // >= kBlock * kSegMax
+  // the segment's block of the current Green's function, G_s[S,S] (S = s0 .. s1)
+  constexpr int LGS = kSegMax + 1;
+  __shared__ T Gss[2][kSegMax * LGS];
   __shared__ int Fb[kBlock];
   __shared__ int sh_f, sh_fb, sh_sign, sh_acc;
 
@@ -121,7 +130,6 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     sh_acc = 0;
   }
   const bool zero_delta = C.delta[bnd][0][0] == 0.0 && C.delta[bnd][0][1] == 0.0;
-  const T* G0[2] = {(const T*)C.G[0], (const T*)C.G[1]};
   T* Z[2] = {(T*)C.Z[0], (T*)C.Z[1]};
   T *W1[2], *Pm[2], *Qm[2], *PZ[2], *ZQ[2];
   for (int s = 0; s < 2; ++s) {
@@ -133,16 +141,76 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     PZ[s] = w + 3 * blk;  // f x fb       (ld kBlock)
     ZQ[s] = w + 4 * blk;  // fb x f       (ld LDZ)
   }
+  // ---- G_s[S,S] = G0[S,S] - Xa[S, :fp] Ya[:fp, S]: the fp flips accepted in
+  // earlier segments of this slice are not yet applied to G ----
+  const int fprev = (s0 == 0) ? 0 : st->ftot;
+  {
+    // lane = column c of the segment, rows wave + 4 m; the rank-fprev
+    // correction runs in k-chunks of 32 staged in LDS: A = Xa[S, k] (in Rsf,
+    // nseg x 32), B = Ya[k, S] (in the Hs area, 32 x nseg)
+    T* As = Rsf;
+    T* Bs = &Hs[0][0][0];
+    constexpr int LA = 36, LB = kSegMax + 4;
+    static_assert(32 * LB <= 2 * kBlock * (kBlock + 2), "B tile fits in Hs");
+    const int c = lane;
+    for (int s = 0; s < 2; ++s) {
+      const T* __restrict__ g0 = (const T*)C.G[s];
+      const T* __restrict__ xa = (const T*)C.Xa[s];
+      const T* __restrict__ ya = (const T*)C.Ya[s];
+      T acc[kSegMax / 4];
+#pragma unroll
+      for (int m = 0; m < kSegMax / 4; ++m) {
+        const int row = wave + 4 * m;
+        acc[m] = (row < nseg && c < nseg) ? g0[(size_t)(s0 + row) * N + s0 + c] : T(0);
+      }
+      // k-chunks of 32, the next chunk's loads issued before this one's FMAs
+      constexpr int NL = kSegMax * 32 / kThreads;
+      T va[NL], vb[NL];
+      auto load_chunk = [&](int k0) {
+        const int kn = min(32, fprev - k0);
+#pragma unroll
+        for (int t = 0; t < NL; ++t) {
+          const int e = tid + t * kThreads, r = e >> 5, k = e & 31;
+          va[t] = (r < nseg && k < kn) ? xa[(size_t)(s0 + r) * N + k0 + k] : T(0);
+          const int kb = e / kSegMax, cc = e % kSegMax;
+          vb[t] = (kb < kn && cc < nseg) ? ya[(size_t)(k0 + kb) * N + s0 + cc] : T(0);
+        }
+      };
+      if (fprev > 0) load_chunk(0);
+      for (int k0 = 0; k0 < fprev; k0 += 32) {
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < NL; ++t) {
+          const int e = tid + t * kThreads;
+          As[(e >> 5) * LA + (e & 31)] = va[t];
+          Bs[(e / kSegMax) * LB + e % kSegMax] = vb[t];
+        }
+        __syncthreads();
+        if (k0 + 32 < fprev) load_chunk(k0 + 32);
+        for (int k = 0; k < 32; ++k) {
+          const T bv = Bs[k * LB + c];
+#pragma unroll
+          for (int m = 0; m < kSegMax / 4; ++m) acc[m] -= As[(wave + 4 * m) * LA + k] * bv;
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < kSegMax / 4; ++m) {
+        const int row = wave + 4 * m;
+        if (row < nseg && c < nseg) Gss[s][row * LGS + c] = acc[m];
+      }
+    }
+  }
   __syncthreads();
 
   for (int b0 = s0; b0 < send; b0 += kBlock) {
+    const int bl = b0 - s0;
     const int kb = min(kBlock, send - b0);
     const int f = sh_f;
-    // ---- W1 = G0[S, F] Z  (kb x f), one spin at a time through LDS ----
+    // ---- W1 = G_s[B, F] Z  (kb x f), one spin at a time through LDS ----
     if (f > 0) {
       for (int s = 0; s < 2; ++s) {
         for (int a = wave; a < kb; a += 4)
-          for (int p = lane; p < f; p += 64) Rsf[a * f + p] = G0[s][(size_t)(b0 + a) * N + Fs[p]];
+          for (int p = lane; p < f; p += 64) Rsf[a * f + p] = Gss[s][(bl + a) * LGS + Fs[p] - s0];
         __syncthreads();
         for (int q = tid; q < f; q += kThreads) {
           T acc[kBlock];
@@ -161,16 +229,16 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
         __syncthreads();
       }
     }
-    // ---- block of the current Green's function: G[S,S] = G0[S,S] + W1 G0[F,S] ----
+    // ---- block of the current Green's function: G[B,B] = G_s[B,B] + W1 G_s[F,B] ----
     // rows (spin, a) over waves and lane halves, columns over lanes 0..31
     {
       const int half = lane >> 5, c = lane & 31;
       for (int row = 2 * wave + half; row < 2 * kb; row += 8) {
         const int s = row >= kb ? 1 : 0, a = row - s * kb;
         if (c < kb) {
-          T acc = G0[s][(size_t)(b0 + a) * N + b0 + c];
+          T acc = Gss[s][(bl + a) * LGS + bl + c];
           for (int q = 0; q < f; ++q)
-            acc += W1[s][(size_t)a * LDZ + q] * G0[s][(size_t)Fs[q] * N + b0 + c];
+            acc += W1[s][(size_t)a * LDZ + q] * Gss[s][(Fs[q] - s0) * LGS + bl + c];
           Hs[s][a][c] = acc;
           HsT[s][c][a] = acc;
         } else {
@@ -271,7 +339,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     __syncthreads();
 
     // ---- merge the block's coefficients Zb = Zs[Fb,Fb] into Z ----
-    //   Z <- [[Z + P Zb Q, P Zb], [Zb Q, Zb]],  P = Z G0[F,Fb], Q = G0[Fb,F] Z
+    //   Z <- [[Z + P Zb Q, P Zb], [Zb Q, Zb]],  P = Z G_s[F,Fb], Q = G_s[Fb,F] Z
     const int fb = sh_fb;
     if (fb > 0) {
       if (f > 0) {
@@ -279,16 +347,16 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
           // P (f x fb): rows over waves, columns over lanes; Q (fb x f) likewise
           for (int p = wave; p < f; p += 4)
             for (int c = lane; c < fb; c += 64) {
-              const int col = b0 + Fb[c];
+              const int col = bl + Fb[c];
               T acc = 0;
-              for (int q = 0; q < f; ++q) acc += Z[s][(size_t)p * LDZ + q] * G0[s][(size_t)Fs[q] * N + col];
+              for (int q = 0; q < f; ++q) acc += Z[s][(size_t)p * LDZ + q] * Gss[s][(Fs[q] - s0) * LGS + col];
               Pm[s][p * kBlock + c] = acc;
             }
           for (int c = wave; c < fb; c += 4) {
-            const T* row = G0[s] + (size_t)(b0 + Fb[c]) * N;
+            const T* row = &Gss[s][(bl + Fb[c]) * LGS];
             for (int q = lane; q < f; q += 64) {
               T acc = 0;
-              for (int p = 0; p < f; ++p) acc += row[Fs[p]] * Z[s][(size_t)p * LDZ + q];
+              for (int p = 0; p < f; ++p) acc += row[Fs[p] - s0] * Z[s][(size_t)p * LDZ + q];
               Qm[s][c * LDZ + q] = acc;
             }
           }
@@ -332,267 +400,242 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     }
   }
 
-  // operands of the flush: the accepted sites F and Yg = (1 - G0)[F, :]
-  // (rows of G0 gathered eight at a time so the loads are issued together)
+  // the accepted sites F of the segment (their coefficients Z are in place)
   const int f = sh_f;
   for (int p = tid; p < f; p += kThreads) C.flist[p] = Fs[p];
-  for (int s = 0; s < 2; ++s) {
-    T* __restrict__ Yg = (T*)C.Yg[s];
-    for (int p0 = 8 * wave; p0 < f; p0 += 32) {
-      for (int j0 = 0; j0 < N; j0 += 64) {
-        const int j = j0 + lane;
-        T v[8];
-#pragma unroll
-        for (int r = 0; r < 8; ++r)
-          v[r] = (p0 + r < f && j < N) ? G0[s][(size_t)Fs[p0 + r] * N + j] : T(0);
-#pragma unroll
-        for (int r = 0; r < 8; ++r)
-          if (p0 + r < f && j < N) Yg[(size_t)(p0 + r) * N + j] = (Fs[p0 + r] == j ? T(1) : T(0)) - v[r];
-      }
-    }
-  }
   for (int i = tid; i < nseg; i += kThreads) frow[s0 + i] = fs[i];
   if (tid == 0) {
     st->fcount = f;
+    st->foff = fprev;
+    st->ftot = fprev + f;
     st->sign = sh_sign;
     st->accepted += sh_acc;
     st->proposed += nseg;
   }
 }
 
-// Delayed-update flush of one segment:
-//   G <- D (G0 - Wg Yg) D^{-1}      (scaling optional; Wg = G0[:,F] Z from k_wmat)
-// One workgroup updates kFlushRows rows of one chain and spin; each wave takes
-// 64 columns per pass (two 32-column halves on FP32 MFMA, 2 x 4 blocks of
-// 16 x 16 on FP64 MFMA).  The only dependent load is the accepted count: the
-// block of G, the rows of Wg and the rows of Yg are issued together.
-// Grid: chains x 2 spins x row blocks.
-constexpr int kFlushRows = 32;
+// Appends the factors of one segment to the slice-level update G = G0 - Xa Ya:
+//   Xa[:, fp : fp + f] = (G0[:, F] - Xa[:, :fp] Ya[:fp, F]) Z          (X part)
+//   Ya[fp : fp + f, :] = (1 - G0)[F, :] + Xa[F, :fp] Ya[:fp, :]        (Y part)
+// with fp the flips accepted in earlier segments of the slice, f <= FMAX the
+// flips of this segment, F their sites (inside the segment [s0, s0 + kseg))
+// and Z their coefficients (from the scan).  The X part reads Xa columns < fp
+// and Ya rows < fp only, the Y part writes Ya rows >= fp and reads Xa columns
+// < fp, so the two parts run concurrently.  A workgroup takes ROWS (256)
+// rows (X part) or columns (Y part) of one chain and spin; the inner dimension
+// fp runs in k-chunks of 16 whose operand tiles are loaded into LDS with
+// coalesced reads, and each thread accumulates an 8 x 4 (x FMAX / 32)
+// register block.  Grid: chains x 2 spins x 2 parts x ceil(N_max / ROWS).
+template <typename T, int FMAX>
+struct XyShape {
+  static constexpr int ROWS = (sizeof(T) == 8 && FMAX == 64) ? 128 : 256;   // LDS budget
+};
 
-template <typename T>
-__device__ __forceinline__ void flush_body(const ChainDev* __restrict__ chains, int nrb,
-                                           int scale_slice, int scale_inverse, int M, int to_tmp) {
+template <typename T, int FMAX>
+__global__ __launch_bounds__(kThreads) void k_xy(const ChainDev* __restrict__ chains, int nrb) {
+  constexpr int ROWS = XyShape<T, FMAX>::ROWS;       // rows (X) / columns (Y) per workgroup
+  constexpr int RPT = ROWS / 32;                      // per thread
+  constexpr int QB = FMAX / 32;                       // 32-wide q blocks
+  constexpr int BK = 16;                              // k-chunk
+  constexpr int V = 16 / sizeof(T);                   // elements per 128-bit LDS access
   const int b = xcd_remap(blockIdx.x, gridDim.x);
-  const int cs = b / nrb, rb = b - cs * nrb;
+  const int rb = b % nrb, part = (b / nrb) & 1, cs = b / (2 * nrb);
   const int spin = cs & 1;
   const ChainDev& C = chains[cs >> 1];
-  const int N = C.N, i0 = rb * kFlushRows;
-  if (i0 >= N) return;
-  constexpr int KS = sizeof(T) == 4 ? 2 : 4;           // MFMA k-step
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const T* __restrict__ G = (const T*)C.G[spin];
-  // the result goes back into G; to_tmp (kernel timing) sends it to Gtmp
-  T* __restrict__ Gout = to_tmp ? (T*)C.Gtmp[spin] : (T*)C.G[spin];
-  const T* __restrict__ W = (const T*)C.Wg[spin];
-  const T* __restrict__ Yg = (const T*)C.Yg[spin];
-  const int f = C.st->fcount;
-  if (f == 0 && scale_slice < 0) return;
-
-  constexpr int NG = 32;                                // G elements per lane and pass
-  T gpre[NG];
-  auto g_index = [&](int cb, int e, int& i, int& j) {
-    if constexpr (sizeof(T) == 4) {
-      // element (i, j) of a 32 x 32 block of v_mfma_f32_32x32x2f32 lives in
-      // lane j + 32 ((i / 4) % 2), register (i % 4) + 4 (i / 8); e = 16 half + register
-      const int r = e & 15;
-      i = i0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-      j = cb + 32 * (e >> 4) + (lane & 31);
-    } else {
-      // element (i, j) of a 16 x 16 block of v_mfma_f64_16x16x4f64 lives in
-      // lane j + 16 (i % 4), register i / 4; e = 16 ra + 4 q + r
-      const int ra = e >> 4, q = (e >> 2) & 3, r = e & 3;
-      i = i0 + 16 * ra + 4 * r + (lane >> 4);
-      j = cb + 16 * q + (lane & 15);
-    }
-  };
-  auto g_load = [&](int cb, int e0, int ne) {
-#pragma unroll
-    for (int e = e0; e < e0 + ne; ++e) {
-      int i, j;
-      g_index(cb, e, i, j);
-      gpre[e] = (i < N && j < N) ? G[(size_t)i * N + j] : T(0);
-    }
-  };
-
-  // scaling of the last flush of a slice: row i by d(i), column j by 1/d(j)
-  const int8_t* sf = scale_slice >= 0 ? C.field + (size_t)scale_slice * N : nullptr;
-  const int sb = (scale_slice == 0 || scale_slice == M + 1) ? 0 : 1;
-  const bool inv = scale_inverse != 0;
-  auto dfl = [&](int site, bool invert) -> double {
-    const int si = sf[site] > 0 ? 0 : 1;
-    return C.dval[sb][spin][invert ? 1 - si : si];
-  };
-  // new value of element e of the pass from its old value and the product
-  auto put = [&](int cb, int e, T acc) {
-    int i, j;
-    g_index(cb, e, i, j);
-    T v = gpre[e] - acc;
-    if (sf && i < N && j < N) v *= (T)(dfl(i, inv) * dfl(j, !inv));
-    if (i < N && j < N) Gout[(size_t)i * N + j] = v;
-  };
-
-  for (int cb = 64 * wave; cb < N; cb += 256) {
-    if constexpr (sizeof(T) == 4) {
-      const int kr = lane >> 5, cc = lane & 31;
-      const int ia = i0 + cc;
-      const T* wrow = W + (size_t)ia * kSegMax;
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int jh = cb + 32 * h + cc;
-        g_load(cb, 16 * h, 16);
-        floatx16 a0;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) a0[r] = 0.f;
-        for (int k0 = 0; k0 < f; k0 += 8 * KS) {
-          float av[8], bv[8];
-#pragma unroll
-          for (int t = 0; t < 8; ++t) {
-            const int k = k0 + t * KS + kr;
-            av[t] = (k < f && ia < N) ? wrow[k] : 0.f;
-            bv[t] = (k < f && jh < N) ? Yg[(size_t)k * N + jh] : 0.f;
-          }
-#pragma unroll
-          for (int t = 0; t < 8; ++t) a0 = __builtin_amdgcn_mfma_f32_32x32x2f32(av[t], bv[t], a0, 0, 0, 0);
-        }
-#pragma unroll
-        for (int r = 0; r < 16; ++r) put(cb, 16 * h + r, a0[r]);
-      }
-    } else {
-      g_load(cb, 0, NG);
-      const int kr = lane >> 4, cc = lane & 15;
-      doublex4 acc[2][4];
-#pragma unroll
-      for (int ra = 0; ra < 2; ++ra)
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) acc[ra][q][r] = 0.0;
-      for (int k0 = 0; k0 < f; k0 += 2 * KS) {
-        double av[2][2], bv[2][4];
-#pragma unroll
-        for (int t = 0; t < 2; ++t) {
-          const int k = k0 + t * KS + kr;
-#pragma unroll
-          for (int ra = 0; ra < 2; ++ra) {
-            const int ia = i0 + 16 * ra + cc;
-            av[t][ra] = (k < f && ia < N) ? (double)W[(size_t)ia * kSegMax + k] : 0.0;
-          }
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int j = cb + 16 * q + cc;
-            bv[t][q] = (k < f && j < N) ? (double)Yg[(size_t)k * N + j] : 0.0;
-          }
-        }
-#pragma unroll
-        for (int t = 0; t < 2; ++t)
-#pragma unroll
-          for (int ra = 0; ra < 2; ++ra)
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-              acc[ra][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t][ra], bv[t][q], acc[ra][q], 0, 0, 0);
-      }
-#pragma unroll
-      for (int ra = 0; ra < 2; ++ra)
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) put(cb, 16 * ra + 4 * q + r, (T)acc[ra][q][r]);
-    }
-  }
-}
-
-__global__ __launch_bounds__(kThreads) void k_flush32(const ChainDev* __restrict__ chains, int nrb,
-                                                      int scale_slice, int scale_inverse, int M,
-                                                      int to_tmp) {
-  flush_body<float>(chains, nrb, scale_slice, scale_inverse, M, to_tmp);
-}
-__global__ __launch_bounds__(kThreads) void k_flush64(const ChainDev* __restrict__ chains, int nrb,
-                                                      int scale_slice, int scale_inverse, int M,
-                                                      int to_tmp) {
-  flush_body<double>(chains, nrb, scale_slice, scale_inverse, M, to_tmp);
-}
-
-hipError_t launch_flush(int fp32, const ChainDev* c, int nc, int n_max, int kseg, int scale_slice,
-                        int scale_inverse, int M, int to_tmp, hipStream_t s) {
-  (void)kseg;
-  const int nrb = (n_max + kFlushRows - 1) / kFlushRows;
-  const dim3 grid(nc * 2 * nrb);   // exactly one workgroup per (chain, spin, row block)
-  if (fp32)
-    hipLaunchKernelGGL(k_flush32, grid, dim3(kThreads), 0, s, c, nrb, scale_slice, scale_inverse, M,
-                       to_tmp);
-  else
-    hipLaunchKernelGGL(k_flush64, grid, dim3(kThreads), 0, s, c, nrb, scale_slice, scale_inverse, M,
-                       to_tmp);
-  return hipGetLastError();
-}
-
-// Wg = G0[:, F] Z (N x f, ld kSegMax) of the segment [s0, s1), computed as
-// G0[:, S] Zs with S the segment's consecutive sites and Zs = Z spread over
-// them (zero rows on rejected sites): each thread reads a contiguous slab of
-// 32 sites of its row; 32 columns of Wg at a time, the 32 x 32 slab of Zs in
-// LDS.  Grid: chains x 2 spins x ceil(N_max / 256) row blocks.
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_wmat(const ChainDev* __restrict__ chains, int nrb,
-                                                   int s0, int s1) {
-  const int b = xcd_remap(blockIdx.x, gridDim.x);
-  const int cs = b / nrb, rb = b - cs * nrb;
-  const int spin = cs & 1;
-  const ChainDev& C = chains[cs >> 1];
-  const int N = C.N;
-  if (s0 >= N || rb * kThreads >= N) return;
-  const int f = C.st->fcount;
+  const int N = C.N, tid = threadIdx.x;
+  const int r0 = rb * ROWS;                           // first row (X) / column (Y)
+  if (r0 >= N) return;
+  const int f = C.st->fcount, fp = C.st->foff;
   if (f == 0) return;
-  const int nseg = min(s1, N) - s0, tid = threadIdx.x;
-  __shared__ __align__(16) T Zs[32][32];
-  __shared__ int pos[kSegMax];
-  for (int c = tid; c < nseg; c += kThreads) pos[c] = -1;
-  __syncthreads();
-  for (int p = tid; p < f; p += kThreads) pos[C.flist[p] - s0] = p;
-  const T* __restrict__ Z = (const T*)C.Z[spin];
   const T* __restrict__ G = (const T*)C.G[spin];
-  T* __restrict__ W = (T*)C.Wg[spin];
-  const int i = rb * kThreads + tid;
-  for (int q0 = 0; q0 < f; q0 += 32) {
-    T acc[32];
+  T* __restrict__ Xa = (T*)C.Xa[spin];
+  T* __restrict__ Ya = (T*)C.Ya[spin];
+  __shared__ int Fl[FMAX];
+  // X part: At[k][r] = Xa[r0 + r, k0 + k],  Bt[k][q] = Ya[k0 + k, F[q]]
+  // Y part: At[k][j] = Ya[k0 + k, r0 + j],  Bt[k][q] = Xa[F[q], k0 + k]
+  constexpr int LA = ROWS + 8, LB = FMAX + 4;
+  constexpr int LP = FMAX + 1;                         // P rows (X part), aliasing At
+  constexpr int AS = BK * LA > ROWS * LP ? BK * LA : ROWS * LP;
+  __shared__ __align__(16) T At[AS];
+  __shared__ __align__(16) T Bt[BK * LB];
+  __shared__ T Zl[FMAX][FMAX + 1];
+  for (int q = tid; q < FMAX; q += kThreads) Fl[q] = q < f ? C.flist[q] : 0;
+  __syncthreads();
+
+  // register block: rows / columns u0 .. u0 + RPT - 1, q = 4 g + 32 qb + v
+  const int u0 = RPT * (tid >> 3), g = tid & 7;
+  T acc[RPT][QB][4];
 #pragma unroll
-    for (int t = 0; t < 32; ++t) acc[t] = T(0);
-    for (int sc = 0; sc < nseg; sc += 32) {
-      __syncthreads();
-      for (int e = tid; e < 32 * 32; e += kThreads) {
-        const int c = e >> 5, t = e & 31;
-        const int p = sc + c < nseg ? pos[sc + c] : -1;
-        Zs[c][t] = (p >= 0 && q0 + t < f) ? Z[(size_t)p * kSegMax + q0 + t] : T(0);
+  for (int a = 0; a < RPT; ++a)
+#pragma unroll
+    for (int qb = 0; qb < QB; ++qb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[a][qb][v] = T(0);
+
+  constexpr int NA = ROWS * BK / kThreads, NB = BK * FMAX / kThreads;
+  for (int k0 = 0; k0 < fp; k0 += BK) {
+    const int kn = min(BK, fp - k0);
+    // all loads of the chunk are issued before the first LDS store
+    T va[NA], vb[NB];
+    if (part == 0) {
+#pragma unroll
+      for (int t = 0; t < NA; ++t) {                          // Xa rows, BK along k
+        const int e = tid + t * kThreads, r = e / BK, k = e % BK;
+        va[t] = (k < kn && r0 + r < N) ? Xa[(size_t)(r0 + r) * N + k0 + k] : T(0);
       }
-      __syncthreads();
-      if (i < N) {
-        const int nc = min(32, nseg - sc);
-        const T* grow = G + (size_t)i * N + s0 + sc;
-        T x[32];
 #pragma unroll
-        for (int c = 0; c < 32; ++c) x[c] = c < nc ? grow[c] : T(0);
+      for (int t = 0; t < NB; ++t) {                          // Ya rows gathered at F
+        const int e = tid + t * kThreads, k = e / FMAX, q = e % FMAX;
+        vb[t] = (k < kn && q < f) ? Ya[(size_t)(k0 + k) * N + Fl[q]] : T(0);
+      }
+    } else {
 #pragma unroll
-        for (int c = 0; c < 32; ++c) {
+      for (int t = 0; t < NA; ++t) {                          // Ya rows, ROWS columns
+        const int e = tid + t * kThreads, k = e / ROWS, j = e % ROWS;
+        va[t] = (k < kn && r0 + j < N) ? Ya[(size_t)(k0 + k) * N + r0 + j] : T(0);
+      }
 #pragma unroll
-          for (int t = 0; t < 32; ++t) acc[t] += x[c] * Zs[c][t];
-        }
+      for (int t = 0; t < NB; ++t) {                          // Xa rows F, BK along k
+        const int e = tid + t * kThreads, q = e / BK, k = e % BK;
+        vb[t] = (k < kn && q < f) ? Xa[(size_t)Fl[q] * N + k0 + k] : T(0);
       }
     }
-    if (i < N) {
-      T* wrow = W + (size_t)i * kSegMax + q0;
+    __syncthreads();
 #pragma unroll
-      for (int t = 0; t < 32; ++t)
-        if (q0 + t < f) wrow[t] = acc[t];
+    for (int t = 0; t < NA; ++t) {
+      const int e = tid + t * kThreads;
+      if (part == 0)
+        At[(e % BK) * LA + e / BK] = va[t];
+      else
+        At[(e / ROWS) * LA + e % ROWS] = va[t];
+    }
+#pragma unroll
+    for (int t = 0; t < NB; ++t) {
+      const int e = tid + t * kThreads;
+      if (part == 0)
+        Bt[(e / FMAX) * LB + e % FMAX] = vb[t];
+      else
+        Bt[(e % BK) * LB + e / BK] = vb[t];
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int k = 0; k < BK; ++k) {
+      T a[RPT];
+#pragma unroll
+      for (int h = 0; h < RPT; h += V) {
+        using VT = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+        const VT x = *reinterpret_cast<const VT*>(&At[k * LA + u0 + h]);
+        const T* xe = reinterpret_cast<const T*>(&x);
+#pragma unroll
+        for (int t = 0; t < V; ++t) a[h + t] = xe[t];
+      }
+#pragma unroll
+      for (int qb = 0; qb < QB; ++qb) {
+        T bq[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) bq[v] = Bt[k * LB + 32 * qb + 4 * g + v];
+#pragma unroll
+        for (int aa = 0; aa < RPT; ++aa)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[aa][qb][v] += a[aa] * bq[v];
+      }
+    }
+  }
+
+  if (part == 0) {
+    // P = G0[i, F] - acc (in the A tile), then Xa[i, fp + c] = sum_q P[i][q] Z[q][c]
+    const T* __restrict__ Z = (const T*)C.Z[spin];
+    __syncthreads();
+    T* Pl = At;
+    for (int e = tid; e < FMAX * FMAX; e += kThreads) {
+      const int q = e / FMAX, c = e % FMAX;
+      Zl[q][c] = (q < f && c < f) ? Z[(size_t)q * kSegMax + c] : T(0);
+    }
+#pragma unroll
+    for (int aa = 0; aa < RPT; ++aa) {
+      const int i = r0 + u0 + aa;
+#pragma unroll
+      for (int qb = 0; qb < QB; ++qb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int q = 32 * qb + 4 * g + v;
+          Pl[(u0 + aa) * LP + q] = (i < N && q < f) ? G[(size_t)i * N + Fl[q]] - acc[aa][qb][v] : T(0);
+        }
+    }
+    __syncthreads();
+    // the thread's rows u0 .. u0 + RPT - 1 and columns c = 32 cb + 4 g + v
+    T xo[RPT][QB][4];
+#pragma unroll
+    for (int aa = 0; aa < RPT; ++aa)
+#pragma unroll
+      for (int cb = 0; cb < QB; ++cb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) xo[aa][cb][v] = T(0);
+    for (int q = 0; q < f; ++q) {
+      T pq[RPT];
+#pragma unroll
+      for (int aa = 0; aa < RPT; ++aa) pq[aa] = Pl[(u0 + aa) * LP + q];
+#pragma unroll
+      for (int cb = 0; cb < QB; ++cb) {
+        T zq[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) zq[v] = Zl[q][32 * cb + 4 * g + v];
+#pragma unroll
+        for (int aa = 0; aa < RPT; ++aa)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) xo[aa][cb][v] += pq[aa] * zq[v];
+      }
+    }
+#pragma unroll
+    for (int aa = 0; aa < RPT; ++aa) {
+      const int i = r0 + u0 + aa;
+      if (i >= N) continue;
+#pragma unroll
+      for (int cb = 0; cb < QB; ++cb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int c = 32 * cb + 4 * g + v;
+          if (c < f) Xa[(size_t)i * N + fp + c] = xo[aa][cb][v];
+        }
+    }
+  } else {
+    // Ya[fp + q, j] = (F[q] == j) - G0[F[q], j] + acc
+#pragma unroll
+    for (int aa = 0; aa < RPT; ++aa) {
+      const int j = r0 + u0 + aa;
+      if (j >= N) continue;
+#pragma unroll
+      for (int qb = 0; qb < QB; ++qb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int q = 32 * qb + 4 * g + v;
+          if (q < f)
+            Ya[(size_t)(fp + q) * N + j] =
+                (Fl[q] == j ? T(1) : T(0)) - G[(size_t)Fl[q] * N + j] + acc[aa][qb][v];
+        }
     }
   }
 }
 
-hipError_t launch_wmat(int fp32, const ChainDev* c, int nc, int n_max, int s0, int s1, hipStream_t s) {
-  const int nrb = (n_max + kThreads - 1) / kThreads;
-  const dim3 grid(nc * 2 * nrb);
-  if (fp32)
-    hipLaunchKernelGGL(k_wmat<float>, grid, dim3(kThreads), 0, s, c, nrb, s0, s1);
-  else
-    hipLaunchKernelGGL(k_wmat<double>, grid, dim3(kThreads), 0, s, c, nrb, s0, s1);
+template <typename T, int FMAX>
+static void launch_xy_t(const ChainDev* c, int nc, int n_max, hipStream_t s) {
+  constexpr int ROWS = XyShape<T, FMAX>::ROWS;
+  const int nrb = (n_max + ROWS - 1) / ROWS;
+  hipLaunchKernelGGL((k_xy<T, FMAX>), dim3(nc * 2 * 2 * nrb), dim3(kThreads), 0, s, c, nrb);
+}
+
+hipError_t launch_xy(int fp32, const ChainDev* c, int nc, int n_max, int kseg, hipStream_t s) {
+  if (kseg <= 32) {
+    if (fp32)
+      launch_xy_t<float, 32>(c, nc, n_max, s);
+    else
+      launch_xy_t<double, 32>(c, nc, n_max, s);
+  } else {
+    if (fp32)
+      launch_xy_t<float, 64>(c, nc, n_max, s);
+    else
+      launch_xy_t<double, 64>(c, nc, n_max, s);
+  }
   return hipGetLastError();
 }
 

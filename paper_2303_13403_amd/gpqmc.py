@@ -296,8 +296,10 @@ class Context:
             pass
 
 
-def debug_gemm(A, B, trans_a: bool = False, precision: int = FP64, stream=None):
-    """C = op(A) B with the library's MFMA tile kernel (torch device tensors)."""
+def debug_gemm(A, B, trans_a: bool = False, precision: int = FP64, stream=None,
+               large_tile: bool = False):
+    """C = op(A) B with one of the library's MFMA tile kernels (torch device
+    tensors); large_tile selects the FP32 large-tile kernel of the wrap."""
     import torch
 
     lib = load()
@@ -309,7 +311,7 @@ def debug_gemm(A, B, trans_a: bool = False, precision: int = FP64, stream=None):
     N = B.shape[1]
     C = torch.empty((M, N), dtype=dt, device=A.device)
     s = stream if stream is not None else torch.cuda.current_stream(A.device)
-    st = lib.gpqmc_debug_gemm(precision, M, N, K, 1 if trans_a else 0,
+    st = lib.gpqmc_debug_gemm(precision, M, N, K, (1 if trans_a else 0) | (2 if large_tile else 0),
                               ctypes.c_void_p(A.data_ptr()), A.shape[1],
                               ctypes.c_void_p(B.data_ptr()), B.shape[1],
                               ctypes.c_void_p(C.data_ptr()), N, ctypes.c_void_p(s.cuda_stream))

@@ -48,6 +48,19 @@ def test_mfma_gemm_matches_cpu(prec, shape, trans):
     assert rel_err(C.numpy(), ref.numpy()) < tol
 
 
+@pytest.mark.parametrize("shape", [(256, 256, 256), (128, 128, 1), (144, 72, 144),
+                                   (300, 130, 37), (257, 255, 33), (36, 36, 36)])
+def test_large_tile_fp32_gemm_matches_cpu(shape):
+    """The kinetic wrap's 128 x 128 FP32 kernel: whole, ragged and thin tiles,
+    k not a multiple of its k-tile."""
+    M, N, K = shape
+    g = torch.Generator().manual_seed(M * 5 + N * 11 + K)
+    A = torch.randn((M, K), generator=g, dtype=torch.float64).to(torch.float32).to(torch.float64)
+    B = torch.randn((K, N), generator=g, dtype=torch.float64).to(torch.float32).to(torch.float64)
+    C = gpqmc.debug_gemm(A.cuda(), B.cuda(), precision=gpqmc.MIXED, large_tile=True).cpu()
+    assert rel_err(C.to(torch.float64).numpy(), (A @ B).numpy()) < 2e-6
+
+
 # --------------------------------------------------------------------------- #
 # initialisation
 # --------------------------------------------------------------------------- #

@@ -94,7 +94,7 @@ def test_create_rejects_a_degenerate_trial():
 
 @pytest.mark.parametrize("bad", [
     dict(n_up=0), dict(n_up=17), dict(dtau=0.0), dict(U=-1.0), dict(g=-0.5),
-    dict(k=0), dict(k=129), dict(n_s=0), dict(l_half=-1), dict(precision=7),
+    dict(k=0), dict(k=65), dict(n_s=0), dict(l_half=-1), dict(precision=7),
 ])
 def test_create_rejects_invalid_arguments(bad):
     st, msg, _ = _create([_desc(WORKLOADS["4x4"], **bad)])
