@@ -26,7 +26,8 @@ hipError_t launch_gemm_plain(int fp32, int transA, const GemmEntry* e, const Til
                              GemmArgs a, hipStream_t s);
 hipError_t launch_scan(int fp32, const ChainDev* c, int nc, const Ctl* ctl, int l, int M, int s0,
                        int s1, hipStream_t s);
-hipError_t launch_xy(int fp32, const ChainDev* c, int nc, int n_max, int kseg, hipStream_t s);
+hipError_t launch_xy(int fp32, const ChainDev* c, int nc, int n_max, int s0, int kseg,
+                     hipStream_t s);
 hipError_t launch_chol_inv(const ChainDev* c, int nc, int n_part, hipStream_t s);
 hipError_t launch_gj_inv(const ChainDev* c, int nc, int n_part, hipStream_t s);
 hipError_t launch_basis_to_fp64(int fp32b, const ChainDev* c, int nc, int parity, hipStream_t s);
@@ -264,7 +265,7 @@ struct Launcher {
     for (int s0 = 0; s0 < ctx->n_max; s0 += ctx->kseg) {
       if ((e = launch_scan(ctx->fp32, chains, nc, ctl, l, ctx->M, s0, s0 + ctx->kseg, s)) != hipSuccess)
         return e;
-      if ((e = launch_xy(ctx->fp32, chains, nc, ctx->n_max, ctx->kseg, s)) != hipSuccess) return e;
+      if ((e = launch_xy(ctx->fp32, chains, nc, ctx->n_max, s0, ctx->kseg, s)) != hipSuccess) return e;
     }
     GemmArgs a = args();
     a.scale_slice = scale_slice;
@@ -1106,7 +1107,7 @@ gpqmc_status gpqmc_debug_step(gpqmc_ctx* ctx, int32_t stage, int32_t l, int32_t 
                         ctx->stream), "ctl");
   hipError_t e = hipErrorInvalidValue;
   if (stage == 0) e = launch_scan(ctx->fp32, L.chains, L.nc, L.ctl, l, ctx->M, s0, s1, ctx->stream);
-  if (stage == 1) e = launch_xy(ctx->fp32, L.chains, L.nc, ctx->n_max, ctx->kseg, ctx->stream);
+  if (stage == 1) e = launch_xy(ctx->fp32, L.chains, L.nc, ctx->n_max, s0, ctx->kseg, ctx->stream);
   if (stage == 2) {
     GemmArgs a = L.args();
     e = L.gemm(E_FLUSH, GM_FLUSH, T_NN, a);

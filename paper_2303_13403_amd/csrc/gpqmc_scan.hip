@@ -432,7 +432,8 @@ struct XyShape {
 };
 
 template <typename T, int FMAX>
-__global__ __launch_bounds__(kThreads) void k_xy(const ChainDev* __restrict__ chains, int nrb) {
+__global__ __launch_bounds__(kThreads) void k_xy(const ChainDev* __restrict__ chains, int nrb,
+                                                 int s0, int kseg) {
   constexpr int ROWS = XyShape<T, FMAX>::ROWS;       // rows (X) / columns (Y) per workgroup
   constexpr int RPT = ROWS / 32;                      // per thread
   constexpr int QB = FMAX / 32;                       // 32-wide q blocks
@@ -542,28 +543,52 @@ __global__ __launch_bounds__(kThreads) void k_xy(const ChainDev* __restrict__ ch
     }
   }
 
+  // epilogues: every global access below is a contiguous row segment; the
+  // register blocks go through LDS (the A tile) for the gathers and stores
+  constexpr int LR = ROWS + 1;
+  static_assert(ROWS * LP <= AS && FMAX * LR <= AS, "epilogue tiles fit in the A tile");
+  __syncthreads();
   if (part == 0) {
-    // P = G0[i, F] - acc (in the A tile), then Xa[i, fp + c] = sum_q P[i][q] Z[q][c]
+    // the segment's slab G0[rows, s0 .. s0 + kseg) and Z
+    T* S1 = At;
+    constexpr int NE = ROWS * FMAX / kThreads;
+    T vs[NE];
+#pragma unroll
+    for (int t = 0; t < NE; ++t) {
+      const int e = tid + t * kThreads, r = e / FMAX, cc = e % FMAX;
+      vs[t] = (r0 + r < N && cc < kseg && s0 + cc < N) ? G[(size_t)(r0 + r) * N + s0 + cc] : T(0);
+    }
     const T* __restrict__ Z = (const T*)C.Z[spin];
-    __syncthreads();
-    T* Pl = At;
     for (int e = tid; e < FMAX * FMAX; e += kThreads) {
       const int q = e / FMAX, c = e % FMAX;
       Zl[q][c] = (q < f && c < f) ? Z[(size_t)q * kSegMax + c] : T(0);
     }
 #pragma unroll
-    for (int aa = 0; aa < RPT; ++aa) {
-      const int i = r0 + u0 + aa;
+    for (int t = 0; t < NE; ++t) {
+      const int e = tid + t * kThreads;
+      S1[(e / FMAX) * LP + e % FMAX] = vs[t];
+    }
+    __syncthreads();
+    // P = G0[i, F] - acc, kept in acc
+#pragma unroll
+    for (int aa = 0; aa < RPT; ++aa)
 #pragma unroll
       for (int qb = 0; qb < QB; ++qb)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int q = 32 * qb + 4 * g + v;
-          Pl[(u0 + aa) * LP + q] = (i < N && q < f) ? G[(size_t)i * N + Fl[q]] - acc[aa][qb][v] : T(0);
+          acc[aa][qb][v] = q < f ? S1[(u0 + aa) * LP + Fl[q] - s0] - acc[aa][qb][v] : T(0);
         }
-    }
     __syncthreads();
-    // the thread's rows u0 .. u0 + RPT - 1 and columns c = 32 cb + 4 g + v
+    T* Pl = At;
+#pragma unroll
+    for (int aa = 0; aa < RPT; ++aa)
+#pragma unroll
+      for (int qb = 0; qb < QB; ++qb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Pl[(u0 + aa) * LP + 32 * qb + 4 * g + v] = acc[aa][qb][v];
+    __syncthreads();
+    // Xa[i, fp + c] = sum_q P[i][q] Z[q][c]: rows u0 .., columns c = 32 cb + 4 g + v
     T xo[RPT][QB][4];
 #pragma unroll
     for (int aa = 0; aa < RPT; ++aa)
@@ -586,55 +611,81 @@ __global__ __launch_bounds__(kThreads) void k_xy(const ChainDev* __restrict__ ch
           for (int v = 0; v < 4; ++v) xo[aa][cb][v] += pq[aa] * zq[v];
       }
     }
+    __syncthreads();
 #pragma unroll
-    for (int aa = 0; aa < RPT; ++aa) {
-      const int i = r0 + u0 + aa;
-      if (i >= N) continue;
+    for (int aa = 0; aa < RPT; ++aa)
 #pragma unroll
       for (int cb = 0; cb < QB; ++cb)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int c = 32 * cb + 4 * g + v;
-          if (c < f) Xa[(size_t)i * N + fp + c] = xo[aa][cb][v];
-        }
+        for (int v = 0; v < 4; ++v) Pl[(u0 + aa) * LP + 32 * cb + 4 * g + v] = xo[aa][cb][v];
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < NE; ++t) {
+      const int e = tid + t * kThreads, r = e / FMAX, c = e % FMAX;
+      if (r0 + r < N && c < f) Xa[(size_t)(r0 + r) * N + fp + c] = Pl[r * LP + c];
     }
   } else {
-    // Ya[fp + q, j] = (F[q] == j) - G0[F[q], j] + acc
+    // rows F of G0 over the workgroup's columns
+    T* Gr = At;
+    constexpr int NE = FMAX * ROWS / kThreads;
+    T vs[NE];
 #pragma unroll
-    for (int aa = 0; aa < RPT; ++aa) {
-      const int j = r0 + u0 + aa;
-      if (j >= N) continue;
+    for (int t = 0; t < NE; ++t) {
+      const int e = tid + t * kThreads, q = e / ROWS, j = e % ROWS;
+      vs[t] = (q < f && r0 + j < N) ? G[(size_t)Fl[q] * N + r0 + j] : T(0);
+    }
+#pragma unroll
+    for (int t = 0; t < NE; ++t) {
+      const int e = tid + t * kThreads;
+      Gr[(e / ROWS) * LR + e % ROWS] = vs[t];
+    }
+    __syncthreads();
+    // Ya[fp + q, j] = (F[q] == j) - G0[F[q], j] + acc, kept in acc
+#pragma unroll
+    for (int aa = 0; aa < RPT; ++aa)
 #pragma unroll
       for (int qb = 0; qb < QB; ++qb)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int q = 32 * qb + 4 * g + v;
-          if (q < f)
-            Ya[(size_t)(fp + q) * N + j] =
-                (Fl[q] == j ? T(1) : T(0)) - G[(size_t)Fl[q] * N + j] + acc[aa][qb][v];
+          const int q = 32 * qb + 4 * g + v, j = u0 + aa;
+          acc[aa][qb][v] += (Fl[q] == r0 + j ? T(1) : T(0)) - Gr[q * LR + j];
         }
+    __syncthreads();
+#pragma unroll
+    for (int aa = 0; aa < RPT; ++aa)
+#pragma unroll
+      for (int qb = 0; qb < QB; ++qb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Gr[(32 * qb + 4 * g + v) * LR + u0 + aa] = acc[aa][qb][v];
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < NE; ++t) {
+      const int e = tid + t * kThreads, q = e / ROWS, j = e % ROWS;
+      if (q < f && r0 + j < N) Ya[(size_t)(fp + q) * N + r0 + j] = Gr[q * LR + j];
     }
   }
 }
 
 template <typename T, int FMAX>
-static void launch_xy_t(const ChainDev* c, int nc, int n_max, hipStream_t s) {
+static void launch_xy_t(const ChainDev* c, int nc, int n_max, int s0, int kseg, hipStream_t s) {
   constexpr int ROWS = XyShape<T, FMAX>::ROWS;
   const int nrb = (n_max + ROWS - 1) / ROWS;
-  hipLaunchKernelGGL((k_xy<T, FMAX>), dim3(nc * 2 * 2 * nrb), dim3(kThreads), 0, s, c, nrb);
+  hipLaunchKernelGGL((k_xy<T, FMAX>), dim3(nc * 2 * 2 * nrb), dim3(kThreads), 0, s, c, nrb, s0,
+                     kseg);
 }
 
-hipError_t launch_xy(int fp32, const ChainDev* c, int nc, int n_max, int kseg, hipStream_t s) {
+hipError_t launch_xy(int fp32, const ChainDev* c, int nc, int n_max, int s0, int kseg,
+                     hipStream_t s) {
   if (kseg <= 32) {
     if (fp32)
-      launch_xy_t<float, 32>(c, nc, n_max, s);
+      launch_xy_t<float, 32>(c, nc, n_max, s0, kseg, s);
     else
-      launch_xy_t<double, 32>(c, nc, n_max, s);
+      launch_xy_t<double, 32>(c, nc, n_max, s0, kseg, s);
   } else {
     if (fp32)
-      launch_xy_t<float, 64>(c, nc, n_max, s);
+      launch_xy_t<float, 64>(c, nc, n_max, s0, kseg, s);
     else
-      launch_xy_t<double, 64>(c, nc, n_max, s);
+      launch_xy_t<double, 64>(c, nc, n_max, s0, kseg, s);
   }
   return hipGetLastError();
 }
