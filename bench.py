@@ -30,9 +30,10 @@ UNIT = "HS-field updates/s"
 PEAK_FP32_MFMA = 157.3e12   # MI355X dense FP32 matrix, FLOP/s
 PEAK_FP64_MFMA = 78.6e12
 PEAK_HBM = 8.0e12           # MI355X HBM3E, B/s
-# the dominant kernel (largest share of the sweep) is the delayed-update flush
-KERNEL_SRC = os.path.join(ROOT, "paper_2303_13403_amd", "csrc", "gpqmc_scan.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_flush_16x16_b512.txt")
+# the dominant kernel (largest share of the sweep): the large-tile MFMA GEMM of
+# the kinetic wrap and the slice update; the roofline is taken on its wrap launch
+KERNEL_SRC = os.path.join(ROOT, "paper_2303_13403_amd", "csrc", "gpqmc_gemm.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_wrap_gemm_16x16_b512.txt")
 
 
 def log(*a):
@@ -45,8 +46,8 @@ def kernel_sha() -> str:
 
 
 def read_traffic(chains: int, precision: str):
-    """HBM bytes per launch of the flush from the committed PMC summary, if it
-    was taken on the current kernel source, batch size and precision."""
+    """HBM bytes per launch of the wrap GEMM from the committed PMC summary, if
+    it was taken on the current kernel source, batch size and precision."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     kv = {}
@@ -101,7 +102,7 @@ def run_gpu(args, precision_name, steps, warmup):
     assert prop == n_updates, (prop, n_updates)
     wrap_ms = ctx.time_kernel(0, reps=10)
     prop_ms = ctx.time_kernel(1, reps=10)
-    flush_ms = ctx.time_kernel(2, reps=20)
+    flush_ms = ctx.time_kernel(2, reps=10)
     res = dict(ms=ms, wall=wall, updates=n_updates, accept=acc / max(prop, 1),
                max_drift=max(i["max_drift"] for i in infos),
                flags=sorted({i["flags"] for i in infos}),
@@ -110,7 +111,7 @@ def run_gpu(args, precision_name, steps, warmup):
                sign=ctx.measure_sign(-1) if args.chains * (steps + warmup) >= 20 else None)
     log(f"[{precision_name}] {steps} sweeps: {ms:.1f} ms (wall {wall * 1e3:.1f} ms), "
         f"{n_updates / (ms / 1e3):.4g} updates/s, acceptance {res['accept']:.3f}, "
-        f"flush {flush_ms:.3f} ms/launch, wrap GEMM {wrap_ms:.3f} ms/launch, "
+        f"slice update {flush_ms:.3f} ms/launch, wrap GEMM {wrap_ms:.3f} ms/launch, "
         f"max drift {res['max_drift']:.2e}, flags {res['flags']}")
     ctx.close()
     del ctx
@@ -206,15 +207,11 @@ def main():
         fp64_res = run_gpu(args, "fp64", args.fp64_steps, 1)
 
     value = main_res["updates"] / (main_res["ms"] / 1e3)
-    elem = 8 if args.precision == "fp64" else 4
-    # dominant kernel: the delayed-update flush, HBM-bound; algorithmic bytes
-    # per launch = every chain x 2 spins x (read + write of the N x N G)
-    flush_bytes = args.chains * 2 * 2 * N * N * elem
-    achieved = flush_bytes / (main_res["flush_ms"] / 1e3)
-    # the kinetic-wrap GEMM e^{-dtau K} G: 2 spins x 2 N^3 flops per chain
+    # dominant kernel: the kinetic-wrap GEMM Gtmp = e^{-dtau K} G, MFMA-bound;
+    # algorithmic flops per launch = every chain x 2 spins x 2 N^3
     wrap_flops = 2.0 * args.chains * 2.0 * N ** 3
-    wrap_peak = PEAK_FP32_MFMA if args.precision != "fp64" else PEAK_FP64_MFMA
-    wrap_achieved = wrap_flops / (main_res["wrap_ms"] / 1e3)
+    peak = PEAK_FP32_MFMA if args.precision != "fp64" else PEAK_FP64_MFMA
+    achieved = wrap_flops / (main_res["wrap_ms"] / 1e3)
     traffic = read_traffic(args.chains, args.precision)
     out = {
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1,
@@ -231,13 +228,13 @@ def main():
             "delay_rank": args.k, "acceptance": round(main_res["accept"], 4),
             "max_drift": main_res["max_drift"], "flags": main_res["flags"],
         },
-        "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9,
-                     "unit": "GB/s", "frac": achieved / PEAK_HBM, "traffic": traffic,
-                     "kernel": "k_flush (delayed-update flush G -= (G0[:,F] Z) Yg, all chains x 2 spins)",
-                     "bytes_per_launch": flush_bytes, "ms_per_launch": main_res["flush_ms"]},
-        "mfma_wrap_gemm": {"achieved": wrap_achieved / 1e12, "peak": wrap_peak / 1e12,
-                           "unit": "TFLOP/s", "frac": wrap_achieved / wrap_peak,
-                           "ms_per_launch": main_res["wrap_ms"]},
+        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
+                     "kernel": "k_gemm_l STORE (e^{-dtau K} G, every chain x 2 spins; 128x128 "
+                               "MFMA tiles)" if args.precision != "fp64" else
+                               "k_gemm<double> STORE (e^{-dtau K} G, every chain x 2 spins)",
+                     "flops_per_launch": wrap_flops, "ms_per_launch": main_res["wrap_ms"]},
+        "slice_update_gemm_ms": main_res["flush_ms"],
     }
     if fp64_res is not None:
         out["fp64_gpu"] = {"value": fp64_res["updates"] / (fp64_res["ms"] / 1e3), "unit": UNIT,

@@ -119,7 +119,7 @@ WORKLOADS = {
     "12x12": Workload("12x12 U=4 half filling Theta=5", 12, 12, 4.0, 72, 72, 0.1, 50,
                       0.21, 0.6, 10, 64, "mixed", 500),
     "16x16": Workload("16x16 U=3.5 n=0.875 Theta=10", 16, 16, 3.5, 112, 112, 0.1, 100,
-                      0.07, 0.55, 5, 64, "mixed", 1000, ramp=0.1),
+                      0.07, 0.55, 5, 32, "mixed", 1000, ramp=0.1),
     "24x24": Workload("24x24 U=4 half filling Theta=10 dtau=0.05", 24, 24, 4.0, 288, 288,
                       0.05, 200, 0.21, 0.6, 10, 64, "mixed", 100),
 }
