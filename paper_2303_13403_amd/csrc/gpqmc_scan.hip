@@ -429,10 +429,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
 template <typename T, int FMAX>
 struct XyShape {
   static constexpr int ROWS = (sizeof(T) == 8 && FMAX == 64) ? 128 : 256;   // LDS budget
+  static constexpr int WAVES = (sizeof(T) == 4 && FMAX == 32) ? 3 : 1;       // per SIMD
 };
 
 template <typename T, int FMAX>
-__global__ __launch_bounds__(kThreads) void k_xy(const ChainDev* __restrict__ chains, int nrb,
+__global__ __launch_bounds__(kThreads)
+__attribute__((amdgpu_waves_per_eu(XyShape<T, FMAX>::WAVES))) void k_xy(const ChainDev* __restrict__ chains, int nrb,
                                                  int s0, int kseg) {
   constexpr int ROWS = XyShape<T, FMAX>::ROWS;       // rows (X) / columns (Y) per workgroup
   constexpr int RPT = ROWS / 32;                      // per thread
@@ -552,21 +554,23 @@ __global__ __launch_bounds__(kThreads) void k_xy(const ChainDev* __restrict__ ch
     // the segment's slab G0[rows, s0 .. s0 + kseg) and Z
     T* S1 = At;
     constexpr int NE = ROWS * FMAX / kThreads;
-    T vs[NE];
-#pragma unroll
-    for (int t = 0; t < NE; ++t) {
-      const int e = tid + t * kThreads, r = e / FMAX, cc = e % FMAX;
-      vs[t] = (r0 + r < N && cc < kseg && s0 + cc < N) ? G[(size_t)(r0 + r) * N + s0 + cc] : T(0);
-    }
     const T* __restrict__ Z = (const T*)C.Z[spin];
     for (int e = tid; e < FMAX * FMAX; e += kThreads) {
       const int q = e / FMAX, c = e % FMAX;
       Zl[q][c] = (q < f && c < f) ? Z[(size_t)q * kSegMax + c] : T(0);
     }
+    for (int t0 = 0; t0 < NE; t0 += 8) {       // eight loads in flight, then their stores
+      T vs[8];
 #pragma unroll
-    for (int t = 0; t < NE; ++t) {
-      const int e = tid + t * kThreads;
-      S1[(e / FMAX) * LP + e % FMAX] = vs[t];
+      for (int t = 0; t < 8; ++t) {
+        const int e = tid + (t0 + t) * kThreads, r = e / FMAX, cc = e % FMAX;
+        vs[t] = (r0 + r < N && cc < kseg && s0 + cc < N) ? G[(size_t)(r0 + r) * N + s0 + cc] : T(0);
+      }
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int e = tid + (t0 + t) * kThreads;
+        S1[(e / FMAX) * LP + e % FMAX] = vs[t];
+      }
     }
     __syncthreads();
     // P = G0[i, F] - acc, kept in acc
@@ -628,16 +632,18 @@ __global__ __launch_bounds__(kThreads) void k_xy(const ChainDev* __restrict__ ch
     // rows F of G0 over the workgroup's columns
     T* Gr = At;
     constexpr int NE = FMAX * ROWS / kThreads;
-    T vs[NE];
+    for (int t0 = 0; t0 < NE; t0 += 8) {       // eight loads in flight, then their stores
+      T vs[8];
 #pragma unroll
-    for (int t = 0; t < NE; ++t) {
-      const int e = tid + t * kThreads, q = e / ROWS, j = e % ROWS;
-      vs[t] = (q < f && r0 + j < N) ? G[(size_t)Fl[q] * N + r0 + j] : T(0);
-    }
+      for (int t = 0; t < 8; ++t) {
+        const int e = tid + (t0 + t) * kThreads, q = e / ROWS, j = e % ROWS;
+        vs[t] = (q < f && r0 + j < N) ? G[(size_t)Fl[q] * N + r0 + j] : T(0);
+      }
 #pragma unroll
-    for (int t = 0; t < NE; ++t) {
-      const int e = tid + t * kThreads;
-      Gr[(e / ROWS) * LR + e % ROWS] = vs[t];
+      for (int t = 0; t < 8; ++t) {
+        const int e = tid + (t0 + t) * kThreads;
+        Gr[(e / ROWS) * LR + e % ROWS] = vs[t];
+      }
     }
     __syncthreads();
     // Ya[fp + q, j] = (F[q] == j) - G0[F[q], j] + acc, kept in acc

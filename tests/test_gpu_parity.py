@@ -179,6 +179,42 @@ def test_trajectory_follows_oracle(prec, kw, n_sweeps):
     ctx.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_fixed_field_pass_24x24(prec):
+    """The large workload (N = 576, 288 + 288 electrons, dtau = 0.05, k = 64):
+    factorisations beyond the register-tile size (n = 288) and 64-site
+    segments, at a short projection time."""
+    check_fixed_field(WORKLOADS["24x24"].replace(l_half=3, stab_interval=3, precision=prec), prec)
+
+
+def test_uneven_batch_configuration_sampled_chains():
+    """The uneven-batch configuration at its full size (256 chains, lattices
+    6x6 .. 12x12, U in [2, 6], l_half = 50, k = 32, mixed), one sweep; a 12x12
+    and a 6x6 chain are followed through the whole pass by the oracle."""
+    ws = [w.replace(delay_rank=32) for w in batch_uneven(256)]
+    ctx = make_context(ws, "mixed", meas_capacity=4).init_trial()
+    ctx.sweep(1, measure=True)
+    picks = [next(c for c, w in enumerate(ws) if w.lx == 12), next(c for c, w in enumerate(ws) if w.lx == 6)]
+    for c in picks:
+        ch = oracle_chain(ws[c], c)
+        f_gpu = ctx.get_field(c)
+        bad = ch.sweep_following(f_gpu, TIE["mixed"])
+        assert not bad, f"chain {c}: decisions differ beyond the tie band: {bad[:3]}"
+        assert np.array_equal(ch.field, f_gpu)
+        m_gpu, m_ref = ctx.measurements(c), np.array(ch.measurements)
+        assert m_gpu.shape == m_ref.shape
+        assert np.array_equal(m_gpu[:, 0], m_ref[:, 0])
+        assert np.max(np.abs(m_gpu[:, 1:] - m_ref[:, 1:])) < 1e-4
+        info = ctx.chain_info(c)
+        # the FP32 Green's function may drift past the mixed flag threshold
+        # (1e-3) between checkpoints at U up to 6; decisions and measurements
+        # above still agree with the FP64 oracle
+        print(f"chain {c} ({ws[c].lx}x{ws[c].lx}, U={ws[c].U:.2f}): max drift {info['max_drift']:.2e}")
+        assert info["max_drift"] < 0.1, info
+        assert info["sign_mismatch"] == 0 and (info["flags"] & ~(16 | 1)) == 0, info
+    ctx.close()
+
+
 def test_trajectory_16x16_fp64():
     w = BENCH.replace(l_half=5, precision="fp64")
     ctx = make_context([w], "fp64").init_trial()
