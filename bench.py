@@ -61,19 +61,20 @@ def read_traffic(chains: int, precision: str):
     return float(kv["hbm_bytes_per_launch"])
 
 
-def workload(args):
+def workload(args, ns=None):
     from paper_2303_13403_amd.workloads import WORKLOADS
 
-    return WORKLOADS["16x16"].replace(stab_interval=args.ns, delay_rank=args.k)
+    return WORKLOADS["16x16"].replace(stab_interval=args.ns if ns is None else ns,
+                                      delay_rank=args.k)
 
 
-def run_gpu(args, precision_name, steps, warmup):
+def run_gpu(args, precision_name, steps, warmup, ns=None):
     import torch
 
     from paper_2303_13403_amd import gpqmc
 
     prec = {"mixed": gpqmc.MIXED, "fp64": gpqmc.FP64, "mixed32b": gpqmc.MIXED_FP32_BASIS}[precision_name]
-    w = workload(args)
+    w = workload(args, ns)
     t0 = time.time()
     chains = [gpqmc.chain_desc_arrays(w, c, prec) for c in range(args.chains)]
     ctx = gpqmc.Context(chains, device="cuda:0", meas_capacity=max(64, steps + warmup + 4))
@@ -87,6 +88,9 @@ def run_gpu(args, precision_name, steps, warmup):
     prop0 = sum(ctx.chain_info(c)["proposed"] for c in range(args.chains))
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
+    # HIP events around every launch of the wrap, propagation and slice-update
+    # GEMMs inside the timed sweeps (on the context's stream)
+    ctx.set_kernel_timing(7)
     torch.cuda.synchronize()
     ev0.record(ctx.stream)
     w0 = time.time()
@@ -95,24 +99,40 @@ def run_gpu(args, precision_name, steps, warmup):
     torch.cuda.synchronize()
     wall = time.time() - w0
     ms = ev0.elapsed_time(ev1)
+    kt = [ctx.kernel_timing(k) for k in range(3)]
+    ctx.set_kernel_timing(0)
     infos = [ctx.chain_info(c) for c in range(args.chains)]
+    graph_ms = None
+    if args.graph_check:
+        torch.cuda.synchronize()
+        ev0.record(ctx.stream)
+        ctx.sweep(steps, measure=True)
+        ev1.record(ctx.stream)
+        torch.cuda.synchronize()
+        graph_ms = ev0.elapsed_time(ev1)
     acc = sum(i["accepted"] for i in infos) - acc0
     prop = sum(i["proposed"] for i in infos) - prop0
     n_updates = (2 * w.l_half + 2) * w.n_sites * args.chains * steps
     assert prop == n_updates, (prop, n_updates)
-    wrap_ms = ctx.time_kernel(0, reps=10)
-    prop_ms = ctx.time_kernel(1, reps=10)
-    flush_ms = ctx.time_kernel(2, reps=10)
+    wrap_ms, prop_ms, flush_ms = (t / max(n, 1) for t, n in kt)
+    launches = {"wrap": kt[0][1], "prop": kt[1][1], "slice_update": kt[2][1]}
+    rel = sorted(i["max_rel_drift"] for i in infos)
     res = dict(ms=ms, wall=wall, updates=n_updates, accept=acc / max(prop, 1),
                max_drift=max(i["max_drift"] for i in infos),
+               rel_drift={"max": rel[-1], "median": rel[len(rel) // 2],
+                          "p90": rel[min(len(rel) - 1, (9 * len(rel)) // 10)],
+                          "frac_above_1e-5": sum(r > 1e-5 for r in rel) / len(rel)},
                flags=sorted({i["flags"] for i in infos}),
                sign_mismatch=sum(i["sign_mismatch"] for i in infos),
-               wrap_ms=wrap_ms, prop_ms=prop_ms, flush_ms=flush_ms,
-               sign=ctx.measure_sign(-1) if args.chains * (steps + warmup) >= 20 else None)
+               wrap_ms=wrap_ms, prop_ms=prop_ms, flush_ms=flush_ms, launches=launches,
+               graph_ms=graph_ms,
+               sign=ctx.measure_sign(-1) if args.chains * (steps + warmup) >= 20 else None,
+               energy=ctx.measure_energy(-1) if args.chains * (steps + warmup) >= 20 else None)
     log(f"[{precision_name}] {steps} sweeps: {ms:.1f} ms (wall {wall * 1e3:.1f} ms), "
         f"{n_updates / (ms / 1e3):.4g} updates/s, acceptance {res['accept']:.3f}, "
         f"slice update {flush_ms:.3f} ms/launch, wrap GEMM {wrap_ms:.3f} ms/launch, "
-        f"max drift {res['max_drift']:.2e}, flags {res['flags']}")
+        f"max drift {res['max_drift']:.2e}, relative drift over chains {res['rel_drift']}, "
+        f"flags {res['flags']}")
     ctx.close()
     del ctx
     torch.cuda.empty_cache()
@@ -169,7 +189,12 @@ def main():
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64", "mixed32b"])
     ap.add_argument("--fp64-steps", type=int, default=2,
                     help="sweeps of the plain FP64 GPU path timed for comparison (0 = skip)")
+    ap.add_argument("--fp64-ns", type=int, default=10,
+                    help="stabilisation interval of the FP64 comparison (its relative drift "
+                         "stays below 1e-6 at 10 on this workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--graph-check", action="store_true",
+                    help="also time the same number of sweeps launched as HIP graphs")
     ap.add_argument("--autotune", action="store_true",
                     help="choose --k and --ns with the autotuner on this batch first (table on stderr)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -204,7 +229,7 @@ def main():
     main_res = run_gpu(args, args.precision, args.steps, args.warmup)
     fp64_res = None
     if args.fp64_steps > 0 and args.precision != "fp64":
-        fp64_res = run_gpu(args, "fp64", args.fp64_steps, 1)
+        fp64_res = run_gpu(args, "fp64", args.fp64_steps, 1, ns=args.fp64_ns)
 
     value = main_res["updates"] / (main_res["ms"] / 1e3)
     # dominant kernel: the kinetic-wrap GEMM Gtmp = e^{-dtau K} G, MFMA-bound;
@@ -226,20 +251,29 @@ def main():
                         f"g=0.55, batch of {args.chains} chains",
             "chains": args.chains, "precision": args.precision, "stab_interval": args.ns,
             "delay_rank": args.k, "acceptance": round(main_res["accept"], 4),
-            "max_drift": main_res["max_drift"], "flags": main_res["flags"],
+            "max_drift": main_res["max_drift"], "rel_drift": main_res["rel_drift"],
+            "flags": main_res["flags"], "energy_per_site": main_res["energy"],
+            "sign": main_res["sign"],
         },
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
                      "kernel": "k_gemm_l STORE (e^{-dtau K} G, every chain x 2 spins; 128x128 "
                                "MFMA tiles)" if args.precision != "fp64" else
                                "k_gemm<double> STORE (e^{-dtau K} G, every chain x 2 spins)",
-                     "flops_per_launch": wrap_flops, "ms_per_launch": main_res["wrap_ms"]},
+                     "flops_per_launch": wrap_flops, "ms_per_launch": main_res["wrap_ms"],
+                     "timing": f"HIP events on the context's stream around each of the "
+                               f"{main_res['launches']['wrap']} launches in the timed sweeps"},
         "slice_update_gemm_ms": main_res["flush_ms"],
+        "propagation_gemm_ms": main_res["prop_ms"],
+        "launch": "direct (kernel events in the timed sweeps)",
     }
+    if main_res["graph_ms"] is not None:
+        out["graph_ms_per_step"] = main_res["graph_ms"] / args.steps
     if fp64_res is not None:
         out["fp64_gpu"] = {"value": fp64_res["updates"] / (fp64_res["ms"] / 1e3), "unit": UNIT,
-                           "steps": args.fp64_steps,
-                           "wrap_gemm_ms_per_launch": fp64_res["wrap_ms"]}
+                           "steps": args.fp64_steps, "stab_interval": args.fp64_ns,
+                           "wrap_gemm_ms_per_launch": fp64_res["wrap_ms"],
+                           "rel_drift": fp64_res["rel_drift"], "energy_per_site": fp64_res["energy"]}
         out["mixed_over_fp64"] = value / out["fp64_gpu"]["value"]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args)

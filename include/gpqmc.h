@@ -92,8 +92,10 @@ typedef struct {
 typedef struct {
   int32_t meas_capacity;      /* measurement records kept per chain (default 4096) */
   int32_t use_graph;          /* capture each pass in a HIP graph (default 1) */
-  double drift_tol;           /* drift above this flags a chain (default 1e-3 mixed,
-                                 1e-4 fp64) */
+  double drift_tol;           /* relative checkpoint drift (max |G_wrapped - G_fresh|
+                                 over max |G_fresh|) above which a chain is flagged
+                                 (default 1e-1 with an FP32 Green's function,
+                                 1e-6 fp64) */
 } gpqmc_options;
 
 typedef struct {
@@ -106,6 +108,9 @@ typedef struct {
   float max_drift;            /* max |G_wrapped - G_fresh| over checkpoints */
   float last_drift;
   int64_t accepted, proposed; /* Metropolis counters */
+  float max_rel_drift;        /* max over checkpoints of the drift divided by
+                                 max |G_fresh| (largest over both spins) */
+  float last_rel_drift;
 } gpqmc_chain_info;
 
 typedef struct gpqmc_ctx gpqmc_ctx;
@@ -183,8 +188,9 @@ gpqmc_status gpqmc_get_trace(gpqmc_ctx* ctx, int32_t chain, double* ratios, doub
 
 /* GEMM self test on caller device memory: C = op(A) B with one of the
  * library's MFMA tile kernels (precision GPQMC_FP64 or GPQMC_MIXED = FP32).
- * flags bit 0: op(A) = A^T (A is K x M); bit 1: the large-tile FP32 kernel of
- * the kinetic wrap (requires GPQMC_MIXED and no transpose).  A M x K
+ * flags bit 0: op(A) = A^T (A is K x M); bit 1: the 128 x 128 large-tile
+ * kernel of the wrap, slice update and (FP64) basis propagation, in FP32 for
+ * GPQMC_MIXED or FP64 for GPQMC_FP64 (requires no transpose).  A M x K
  * row-major (or K x M), B K x N, C M x N.  Synchronises.
  * Errors: EINVAL on bad sizes or an unsupported flag combination. */
 gpqmc_status gpqmc_debug_gemm(int32_t precision, int32_t M, int32_t N, int32_t K, int32_t flags,
@@ -200,6 +206,21 @@ gpqmc_status gpqmc_debug_gemm(int32_t precision, int32_t M, int32_t N, int32_t K
  * Writes only scratch that every pass rebuilds.  Synchronises.
  * Errors: ESTATE before init_trial. */
 gpqmc_status gpqmc_time_kernel(gpqmc_ctx* ctx, int32_t kernel, int32_t reps, float* ms_per_launch);
+
+/* In-sweep kernel timing.  Bit t of mask (0..7) records a HIP event pair on
+ * the context's stream around every launch, inside later sweeps, of timed
+ * kernel t: 0 = the kinetic-wrap GEMM e^{-dtau K} G of every slice, 1 = the
+ * B-scaled basis-propagation GEMM, 2 = the slice's delayed update
+ * G <- D (G - Xa Ya) D^{-1}.  While mask is nonzero the passes are launched
+ * directly rather than as HIP graphs.  Setting a mask (0 included) clears the
+ * recorded launches.  Synchronises.  Errors: EINVAL for a mask outside 0..7. */
+gpqmc_status gpqmc_set_kernel_timing(gpqmc_ctx* ctx, int32_t mask);
+
+/* Sum of the durations (ms) and the number of the launches of timed kernel
+ * kernel (0..2) recorded since the last gpqmc_set_kernel_timing.
+ * Synchronises.  Errors: EINVAL. */
+gpqmc_status gpqmc_get_kernel_timing(gpqmc_ctx* ctx, int32_t kernel, float* total_ms,
+                                     int32_t* launches);
 
 /* Debugging hooks (off the hot path; synchronise).  debug_step runs one
  * stage of slice l on every chain: 0 = the flip scan of sites [s0, s1),

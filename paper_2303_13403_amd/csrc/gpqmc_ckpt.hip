@@ -562,12 +562,18 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const ChainDev* __restric
         st->flags |= FLAG_SIGN;
         st->sign = wsign;
       }
+      // drift relative to the largest element of the fresh G (both spins)
       const float d = __uint_as_float(st->drift_bits);
+      const float gm = __uint_as_float(st->gmax_bits);
+      const float rd = d / fmaxf(gm, 1e-30f);
       st->last_drift = d;
+      st->last_rel_drift = rd;
       if (!(d <= st->max_drift)) st->max_drift = d;
-      if (!(d <= ctl->drift_tol)) st->flags |= (d != d || isinf(d)) ? FLAG_NAN : FLAG_DRIFT;
+      if (!(rd <= st->max_rel_drift)) st->max_rel_drift = rd;
+      if (!(rd <= ctl->drift_tol)) st->flags |= (d != d || isinf(d)) ? FLAG_NAN : FLAG_DRIFT;
     }
     st->drift_bits = 0u;
+    st->gmax_bits = 0u;
   }
   if (mode != 2 && measure_here && ctl->measure) {
     double ek = 0.0, dsum = 0.0;

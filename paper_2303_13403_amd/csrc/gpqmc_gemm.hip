@@ -142,7 +142,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm(const GemmEntry* __restrict__
     sbnd = (args.scale_slice == 0 || args.scale_slice == args.n_bulk_last + 1) ? 0 : 1;
   }
   const bool inv = args.scale_inverse != 0;
-  float dmax = 0.f;
+  float dmax = 0.f, gmx = 0.f;
   // the drift check reads the wrapped Green's function it replaces: all of
   // those loads are issued before the first store of the tile
   Tb prev[16];
@@ -180,6 +180,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm(const GemmEntry* __restrict__
       if (args.check_drift) {
         const float d = (float)fabs((double)prev[k] - g);
         dmax = (d != d) ? __builtin_inff() : fmaxf(dmax, d);
+        gmx = fmaxf(gmx, (float)fabs(g));
       }
       double v = g;
       if (sfield) v *= dfac(e.dval, sbnd, sfield[i], inv) * dfac(e.dval, sbnd, sfield[j], !inv);
@@ -189,13 +190,20 @@ __global__ __launch_bounds__(kThreads) void k_gemm(const GemmEntry* __restrict__
     }
   });
   if (MODE == GM_GFRESH && args.check_drift) {
-    __shared__ float red[4];
+    __shared__ float red[2][4];
     dmax = wave_max(dmax);
-    if (lane == 0) red[wave] = dmax;
+    gmx = wave_max(gmx);
+    if (lane == 0) {
+      red[0][wave] = dmax;
+      red[1][wave] = gmx;
+    }
     __syncthreads();
     if (tid == 0) {
-      const float m = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+      // non-negative floats order as their bit patterns
+      const float m = fmaxf(fmaxf(red[0][0], red[0][1]), fmaxf(red[0][2], red[0][3]));
+      const float gm = fmaxf(fmaxf(red[1][0], red[1][1]), fmaxf(red[1][2], red[1][3]));
       atomicMax(&e.st->drift_bits, __float_as_uint(m));
+      atomicMax(&e.st->gmax_bits, __float_as_uint(gm));
     }
   }
 }
@@ -203,14 +211,14 @@ __global__ __launch_bounds__(kThreads) void k_gemm(const GemmEntry* __restrict__
 // ---------------------------------------------------------------------------
 // Large-tile FP32 GEMM for the N x N x N products of the kinetic wrap (modes
 // STORE and WRAP) and the slice's delayed update (FLUSH, K = accepted flips): 128 x 128 output tile per workgroup, 64 x 64 per wave as
-// 2 x 2 blocks of v_mfma_f32_32x32x2f32, k-tiles of 32 double-buffered in LDS
+// 2 x 2 blocks of v_mfma_f32_32x32x2f32, k-tiles of 16 double-buffered in LDS
 // with the next k-tile prefetched into registers (one barrier per k-tile).
 // A is kept in LDS with each row's k values split by parity (k = 2 kk + h at
 // [row][h][kk]), so a lane fetches the A operand of four MFMA k-steps with one
 // 128-bit read; B stays row-major ([k][j]), read one float per k-step.
 // ---------------------------------------------------------------------------
-constexpr int kTileL = 128, BKL = 32;
-constexpr int LDAL = BKL + 4;        // A tile row: 16 even-k, 16 odd-k, 4 pad
+constexpr int kTileL = 128, BKL = 16;
+constexpr int LDAL = BKL + 4;        // A tile row: BKL / 2 even-k, BKL / 2 odd-k, 4 pad
 constexpr int LDBL = kTileL + 4;     // B tile row
 
 __device__ inline float4 load4(const float* __restrict__ p, int valid, bool aligned) {
@@ -245,33 +253,40 @@ __global__ __launch_bounds__(kThreads) void k_gemm_l(const GemmEntry* __restrict
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
 
-  // global -> register mapping: A rows am, k from ak; B k-row bk, columns from bj
-  const int am = tid >> 1, ak = (tid & 1) * 16;
-  const int bk = tid >> 3, bj = (tid & 7) * 16;
-  float4 ra[4], rb[4];
+  // global -> register mapping: A row am, BKL / 2 k values from ak; B k-row
+  // bk, BKL / 2 columns from bj (NQ float4 loads of each per thread)
+  constexpr int NQ = BKL / 8, TPR = kThreads / BKL;
+  static_assert(NQ % 2 == 0, "A rows are stored as pairs of float4");
+  const int am = tid >> 1, ak = (tid & 1) * (BKL / 2);
+  const int bk = tid / TPR, bj = (tid % TPR) * (BKL / 2);
+  float4 ra[NQ], rb[NQ];
   auto gload = [&](int k0) {
     const int i = m0 + am;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < NQ; ++q) {
       const int k = k0 + ak + 4 * q;
       ra[q] = load4(A + (size_t)i * lda + k, i < M ? K - k : 0, a_al);
     }
     const int kb = k0 + bk;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < NQ; ++q) {
       const int j = n0 + bj + 4 * q;
       rb[q] = load4(B + (size_t)kb * ldb + j, kb < K ? N - j : 0, b_al);
     }
   };
   auto sstore = [&](int buf) {
+    // k = ak + 4 q + {0, 1, 2, 3}: even k to [row][0][kk], odd k to [row][1][kk]
     float* a = &As[buf][am * LDAL + ak / 2];
-    *reinterpret_cast<float4*>(a) = make_float4(ra[0].x, ra[0].z, ra[1].x, ra[1].z);
-    *reinterpret_cast<float4*>(a + 4) = make_float4(ra[2].x, ra[2].z, ra[3].x, ra[3].z);
-    *reinterpret_cast<float4*>(a + 16) = make_float4(ra[0].y, ra[0].w, ra[1].y, ra[1].w);
-    *reinterpret_cast<float4*>(a + 20) = make_float4(ra[2].y, ra[2].w, ra[3].y, ra[3].w);
+#pragma unroll
+    for (int q = 0; q < NQ; q += 2) {
+      *reinterpret_cast<float4*>(a + 2 * q) =
+          make_float4(ra[q].x, ra[q].z, ra[q + 1].x, ra[q + 1].z);
+      *reinterpret_cast<float4*>(a + BKL / 2 + 2 * q) =
+          make_float4(ra[q].y, ra[q].w, ra[q + 1].y, ra[q + 1].w);
+    }
     float* b = &Bs[buf][bk * LDBL + bj];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) *reinterpret_cast<float4*>(b + 4 * q) = rb[q];
+    for (int q = 0; q < NQ; ++q) *reinterpret_cast<float4*>(b + 4 * q) = rb[q];
   };
 
   floatx16 acc[2][2];
@@ -315,7 +330,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_l(const GemmEntry* __restrict
         float4 av[2];
 #pragma unroll
         for (int x = 0; x < 2; ++x)
-          av[x] = *reinterpret_cast<const float4*>(&as[(wm + 32 * x + l32) * LDAL + 16 * h + 4 * c]);
+          av[x] = *reinterpret_cast<const float4*>(&as[(wm + 32 * x + l32) * LDAL + (BKL / 2) * h + 4 * c]);
 #pragma unroll
         for (int pp = 0; pp < 4; ++pp) {
           const int kr = 2 * (4 * c + pp) + h;
@@ -392,6 +407,203 @@ hipError_t launch_gemm_l(int mode, const GemmEntry* e, const TileRef* t, int n, 
     hipLaunchKernelGGL(k_gemm_l<GM_FLUSH>, dim3(n), dim3(kThreads), 0, s, e, t, n, a);
   else
     return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Large-tile FP64 GEMM (modes STORE, WRAP, FLUSH, PROPB, PROPR): 128 x 128
+// output tile per workgroup, 64 x 64 per wave as 4 x 4 blocks of
+// v_mfma_f64_16x16x4f64, k-tiles of 16 double-buffered in LDS with the next
+// k-tile prefetched into registers.  A is kept in LDS with each row's k values
+// split by k mod 4 (k = 4 s + kq at [row][kq][s]), so a lane fetches the A
+// operand of two MFMA k-steps with one 128-bit read; B stays row-major.
+// ---------------------------------------------------------------------------
+constexpr int BKD = 16;
+// the factor staging is ordered by the k-loop's first barrier; with no k-loop
+// (K = 0) an explicit barrier is needed
+__device__ inline bool nk_zero_guard(int K) { return K <= 0; }
+constexpr int LDAD = BKD + 2;        // A tile row: 4 groups of 4 (k mod 4), 2 pad
+constexpr int LDBD = kTileL + 2;     // B tile row
+
+__device__ inline double2 load2(const double* __restrict__ p, int valid, bool aligned) {
+  if (aligned && valid >= 2) return *reinterpret_cast<const double2*>(p);
+  double2 v;
+  v.x = valid > 0 ? p[0] : 0.0;
+  v.y = valid > 1 ? p[1] : 0.0;
+  return v;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_gemm_l64(const GemmEntry* __restrict__ ents,
+                                                       const TileRef* __restrict__ tiles,
+                                                       int n_tiles, GemmArgs args) {
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  if (bid >= n_tiles) return;
+  const TileRef tr = tiles[bid];
+  const GemmEntry& e = ents[tr.entry];
+  const int M = e.M, N = e.N, K = e.dynK ? *e.dynK : e.K;
+  const int m0 = tr.tm * kTileL, n0 = tr.tn * kTileL;
+  if (m0 >= M || n0 >= N) return;
+  const int p = args.parity;
+  const double* __restrict__ A = (const double*)e.A[0];
+  const double* __restrict__ B = (const double*)e.B[0];
+  double* __restrict__ C = (double*)e.C[0];
+  if (MODE == GM_PROPB || MODE == GM_PROPR) {
+    B = (const double*)e.B[p];
+    C = (double*)e.C[p ^ 1];
+  }
+  const int lda = e.lda, ldb = e.ldb, ldc = e.ldc;
+  const bool a_al = (lda & 1) == 0, b_al = (ldb & 1) == 0;
+
+  __shared__ __align__(16) double As[2][kTileL * LDAD];
+  __shared__ __align__(16) double Bs[2][BKD * LDBD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+
+  // B-row scaling by the diagonal of D_l (basis propagation A (D B))
+  const int8_t* bfield = nullptr;
+  int bbnd = 1;
+  if (MODE == GM_PROPB && args.bscale_slice >= 0) {
+    bfield = e.field + (size_t)args.bscale_slice * e.n_sites;
+    bbnd = (args.bscale_slice == 0 || args.bscale_slice == args.n_bulk_last + 1) ? 0 : 1;
+  }
+
+  // output scaling (frame change, or the D_l rows of a propagation): the
+  // tile's row and column factors, staged once (ordered by the first barrier)
+  const int8_t* sfield = nullptr;
+  int sbnd = 1;
+  if ((MODE == GM_WRAP || MODE == GM_FLUSH || MODE == GM_PROPR) && args.scale_slice >= 0) {
+    sfield = e.field + (size_t)args.scale_slice * e.n_sites;
+    sbnd = (args.scale_slice == 0 || args.scale_slice == args.n_bulk_last + 1) ? 0 : 1;
+  }
+  const bool inv = args.scale_inverse != 0;
+  __shared__ double drow[kTileL], dcol[kTileL];
+  if (sfield) {
+    if (tid < kTileL) {
+      const int i = m0 + tid;
+      drow[tid] = i < M ? dfac(e.dval, sbnd, sfield[i], MODE == GM_PROPR ? false : inv) : 0.0;
+    } else {
+      const int j = n0 + tid - kTileL;
+      dcol[tid - kTileL] = (MODE != GM_PROPR && j < N) ? dfac(e.dval, sbnd, sfield[j], !inv) : 1.0;
+    }
+  }
+  if (nk_zero_guard(K)) __syncthreads();
+
+  // global -> register mapping: A row am, k from ak (8 values); B k-row bk, columns from bj
+  const int am = tid >> 1, ak = (tid & 1) * 8;
+  const int bk = tid >> 4, bj = (tid & 15) * 8;
+  double2 ra[4], rb[4];
+  auto gload = [&](int k0) {
+    const int i = m0 + am;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int k = k0 + ak + 2 * q;
+      ra[q] = load2(A + (size_t)i * lda + k, i < M ? K - k : 0, a_al);
+    }
+    const int kb = k0 + bk;
+    double sc = 1.0;
+    if (bfield && kb < K) sc = dfac(e.dval, bbnd, bfield[kb], false);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int j = n0 + bj + 2 * q;
+      rb[q] = load2(B + (size_t)kb * ldb + j, kb < K ? N - j : 0, b_al);
+      rb[q].x *= sc;
+      rb[q].y *= sc;
+    }
+  };
+  auto sstore = [&](int buf) {
+    // k = ak + e, e = 0..7: kq = k & 3, s = k >> 2 (ak is 0 or 8)
+    double* a = &As[buf][am * LDAD + ak / 4];
+    const double v[8] = {ra[0].x, ra[0].y, ra[1].x, ra[1].y, ra[2].x, ra[2].y, ra[3].x, ra[3].y};
+#pragma unroll
+    for (int kq = 0; kq < 4; ++kq)
+      *reinterpret_cast<double2*>(a + 4 * kq) = make_double2(v[kq], v[4 + kq]);
+    double* b = &Bs[buf][bk * LDBD + bj];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) *reinterpret_cast<double2*>(b + 2 * q) = rb[q];
+  };
+
+  doublex4 acc[4][4];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[x][y][r] = 0.0;
+
+  const int kq = lane >> 4, l16 = lane & 15;
+  const int nk = (K + BKD - 1) / BKD;
+  if (nk > 0) {
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+      const int buf = kt & 1;
+      if (kt + 1 < nk) gload((kt + 1) * BKD);
+      const double* as = As[buf];
+      const double* bs = Bs[buf];
+#pragma unroll
+      for (int s = 0; s < BKD / 4; s += 2) {          // two k-steps (k = 4 s + kq, 4 s + 4 + kq)
+        double2 av[4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+          av[x] = *reinterpret_cast<const double2*>(&as[(wm + 16 * x + l16) * LDAD + 4 * kq + s]);
+#pragma unroll
+        for (int ss = 0; ss < 2; ++ss) {
+          const int kr = 4 * (s + ss) + kq;
+          double bv[4];
+#pragma unroll
+          for (int y = 0; y < 4; ++y) bv[y] = bs[kr * LDBD + wn + 16 * y + l16];
+#pragma unroll
+          for (int x = 0; x < 4; ++x) {
+            const double a = ss == 0 ? av[x].x : av[x].y;
+#pragma unroll
+            for (int y = 0; y < 4; ++y)
+              acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv[y], acc[x][y], 0, 0, 0);
+          }
+        }
+      }
+      if (kt + 1 < nk) sstore(buf ^ 1);
+      __syncthreads();
+    }
+  }
+
+  // epilogue: element (i, j) of a 16 x 16 block lives in lane j + 16 (i % 4),
+  // register i / 4
+#pragma unroll
+  for (int y = 0; y < 4; ++y) {
+    const int jl = wn + 16 * y + l16, j = n0 + jl;
+    const double dj = sfield ? dcol[jl] : 1.0;
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int il = wm + 16 * x + 4 * r + kq, i = m0 + il;
+        if (i < M && j < N) {
+          const size_t o = (size_t)i * ldc + j;
+          double v = MODE == GM_FLUSH ? ((const double*)e.C[0])[o] - acc[x][y][r] : acc[x][y][r];
+          if (sfield) v *= drow[il] * dj;
+          if (MODE == GM_FLUSH)
+            ((double*)e.C[1])[o] = v;
+          else
+            C[o] = v;
+        }
+        if (r == 3) __builtin_amdgcn_sched_barrier(0);   // one 16 x 16 block at a time
+      }
+  }
+}
+
+hipError_t launch_gemm_l64(int mode, const GemmEntry* e, const TileRef* t, int n, GemmArgs a,
+                           hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  switch (mode) {
+    case GM_STORE: hipLaunchKernelGGL(k_gemm_l64<GM_STORE>, dim3(n), dim3(kThreads), 0, s, e, t, n, a); break;
+    case GM_WRAP: hipLaunchKernelGGL(k_gemm_l64<GM_WRAP>, dim3(n), dim3(kThreads), 0, s, e, t, n, a); break;
+    case GM_FLUSH: hipLaunchKernelGGL(k_gemm_l64<GM_FLUSH>, dim3(n), dim3(kThreads), 0, s, e, t, n, a); break;
+    case GM_PROPB: hipLaunchKernelGGL(k_gemm_l64<GM_PROPB>, dim3(n), dim3(kThreads), 0, s, e, t, n, a); break;
+    case GM_PROPR: hipLaunchKernelGGL(k_gemm_l64<GM_PROPR>, dim3(n), dim3(kThreads), 0, s, e, t, n, a); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -62,7 +62,9 @@ struct ChainState {
   unsigned int drift_bits;  // max |G_wrapped - G_fresh| of the current checkpoint (float bits)
   float max_drift;      // since initialisation
   float last_drift;
-  int pad0;
+  unsigned int gmax_bits;   // max |G_fresh| of the current checkpoint (float bits)
+  float max_rel_drift;  // max over checkpoints of drift / max |G_fresh|
+  float last_rel_drift;
   long long accepted;   // accepted proposals
   long long proposed;   // proposals
 };
@@ -132,7 +134,7 @@ struct ChainDev {
 struct Ctl {
   int measure;          // record measurements at tau = Theta
   int force_reject;     // debug: reject every proposal (fixed-field parity)
-  float drift_tol;      // drift above this sets FLAG_DRIFT
+  float drift_tol;      // relative drift above this sets FLAG_DRIFT
   int pad;
 };
 

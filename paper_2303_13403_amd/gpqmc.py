@@ -43,7 +43,8 @@ class ChainInfo(ctypes.Structure):
     _fields_ = [("sign", ctypes.c_int32), ("flags", ctypes.c_int32), ("n_meas", ctypes.c_int32),
                 ("sign_mismatch", ctypes.c_int32), ("sweep", ctypes.c_int32),
                 ("max_drift", ctypes.c_float), ("last_drift", ctypes.c_float),
-                ("accepted", ctypes.c_int64), ("proposed", ctypes.c_int64)]
+                ("accepted", ctypes.c_int64), ("proposed", ctypes.c_int64),
+                ("max_rel_drift", ctypes.c_float), ("last_rel_drift", ctypes.c_float)]
 
 
 class GpqmcError(RuntimeError):
@@ -59,8 +60,8 @@ EXPORTS = [
     "gpqmc_measure_sign", "gpqmc_get_measurements", "gpqmc_reset_measurements",
     "gpqmc_set_field", "gpqmc_get_field", "gpqmc_get_green", "gpqmc_get_chain_info",
     "gpqmc_set_debug", "gpqmc_get_trace", "gpqmc_debug_gemm", "gpqmc_chain_status",
-    "gpqmc_time_kernel", "gpqmc_debug_step", "gpqmc_debug_read", "gpqmc_last_error",
-    "gpqmc_destroy",
+    "gpqmc_time_kernel", "gpqmc_set_kernel_timing", "gpqmc_get_kernel_timing",
+    "gpqmc_debug_step", "gpqmc_debug_read", "gpqmc_last_error", "gpqmc_destroy",
 ]
 
 
@@ -94,6 +95,8 @@ def load():
         "gpqmc_debug_gemm": [I32, I32, I32, I32, I32, VP, I32, VP, I32, VP, I32, VP],
         "gpqmc_chain_status": [VP, I32],
         "gpqmc_time_kernel": [VP, I32, I32, P(ctypes.c_float)],
+        "gpqmc_set_kernel_timing": [VP, I32],
+        "gpqmc_get_kernel_timing": [VP, I32, P(ctypes.c_float), P(ctypes.c_int32)],
         "gpqmc_debug_step": [VP, I32, I32, I32, I32],
         "gpqmc_debug_read": [VP, I32, I32, I32, P(D), I64],
         "gpqmc_last_error": [VP],
@@ -274,6 +277,20 @@ class Context:
         self._call("gpqmc_time_kernel", kernel, reps, ctypes.byref(ms))
         return ms.value
 
+    def set_kernel_timing(self, mask: int):
+        """Record HIP events around every launch, in later sweeps, of the timed
+        kernels in ``mask``: bit 0 the wrap GEMM, bit 1 the B-scaled
+        propagation GEMM, bit 2 the slice's delayed update (passes then launch
+        directly); clears what was recorded."""
+        self._call("gpqmc_set_kernel_timing", mask)
+
+    def kernel_timing(self, kernel: int):
+        """(total ms, launches) of timed kernel ``kernel`` since the last
+        :meth:`set_kernel_timing`."""
+        ms, n = ctypes.c_float(), ctypes.c_int32()
+        self._call("gpqmc_get_kernel_timing", kernel, ctypes.byref(ms), ctypes.byref(n))
+        return ms.value, n.value
+
     def debug_step(self, stage: int, l: int, s0: int = 0, s1: int = 0):
         self._call("gpqmc_debug_step", stage, l, s0, s1)
 
@@ -299,7 +316,8 @@ class Context:
 def debug_gemm(A, B, trans_a: bool = False, precision: int = FP64, stream=None,
                large_tile: bool = False):
     """C = op(A) B with one of the library's MFMA tile kernels (torch device
-    tensors); large_tile selects the FP32 large-tile kernel of the wrap."""
+    tensors); large_tile selects the 128 x 128 kernel of the wrap, the slice
+    update and the FP64 basis propagation (FP32 or FP64 by ``precision``)."""
     import torch
 
     lib = load()
