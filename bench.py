@@ -221,7 +221,7 @@ def main():
 
         prec = {"mixed": gpqmc.MIXED, "fp64": gpqmc.FP64, "mixed32b": gpqmc.MIXED_FP32_BASIS}[args.precision]
         best, _ = autotune([workload(args)] * args.chains, prec, delay_ranks=(16, 32, 64),
-                           stab_intervals=(3, 5, 10), log=log)
+                           stab_intervals=(5, 10, 20), log=log)
         args.k, args.ns = best.delay_rank, best.stab_interval
         log(f"autotune: k={args.k} n_s={args.ns}")
     w = workload(args)

@@ -381,13 +381,12 @@ def test_in_sweep_kernel_timing_counts_every_launch():
 
 
 def test_autotune_times_every_candidate_and_picks_a_valid_one():
-    from paper_2303_13403_amd.autotune import DRIFT_LIMIT, autotune
+    from paper_2303_13403_amd.autotune import DRIFT_LIMIT, autotune, qualifies
 
     ws = [w.replace(l_half=5) for w in batch_uneven(8, l_half=5)]
     best, trials = autotune(ws, gpqmc.MIXED, delay_ranks=(8, 16), stab_intervals=(2, 4), sweeps=1)
     assert sorted((t.delay_rank, t.stab_interval) for t in trials) == [(8, 2), (8, 4), (16, 2), (16, 4)]
     assert all(t.ms_per_sweep > 0 and t.updates_per_s > 0 for t in trials)
     lim = DRIFT_LIMIT[gpqmc.MIXED]
-    assert best in trials and best.max_rel_drift <= lim and (best.flags & ~16) == 0
-    assert best.ms_per_sweep == min(t.ms_per_sweep for t in trials
-                                    if t.max_rel_drift <= lim and (t.flags & ~16) == 0)
+    assert best in trials and qualifies(best, lim)
+    assert best.ms_per_sweep == min(t.ms_per_sweep for t in trials if qualifies(t, lim))
