@@ -426,6 +426,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
 // fp runs in k-chunks of 16 whose operand tiles are loaded into LDS with
 // coalesced reads, and each thread accumulates an 8 x 4 (x FMAX / 32)
 // register block.  Grid: chains x 2 spins x 2 parts x ceil(N_max / ROWS).
+// (Launched for FP64; the FP32 append runs on MFMA in k_xy_mfma below.)
 template <typename T, int FMAX>
 struct XyShape {
   static constexpr int ROWS = (sizeof(T) == 8 && FMAX == 64) ? 128 : 256;   // LDS budget
@@ -672,6 +673,282 @@ __attribute__((amdgpu_waves_per_eu(XyShape<T, FMAX>::WAVES))) void k_xy(const Ch
   }
 }
 
+// FP32 form of the same append on MFMA (v_mfma_f32_32x32x2f32).  Both parts
+// are products of a wide operand (ROWS rows of Xa, or ROWS columns of Ya) and
+// a narrow one (Ya gathered at the columns F, or the rows F of Xa) over the
+// inner dimension fp, staged k-major in LDS in k-chunks of 16 (the next chunk
+// is loaded into registers while the current one is multiplied).  Workgroups
+// of 128 rows keep five of them per CU in flight: the kernel is bound by the
+// latency of its loads rather than by the products.
+//   X part: C[r][q] = sum_k Xa[r0 + r, k] Ya[k, F[q]]   (wave: rows 64 w ..)
+//   Y part: C[q][j] = sum_k Xa[F[q], k] Ya[k, r0 + j]   (wave: columns 64 w ..)
+// so that the Y part comes out with lanes along j and its stores to the rows of
+// Ya are contiguous.  The X part then forms P = G0[:, F] - C in LDS and its
+// product with Z on MFMA as well; its lanes run along the columns fp + c of Xa.
+template <int FMAX>
+struct XyMfmaShape {
+  static constexpr int ROWS = 128;   // rows (X) / columns (Y) per workgroup
+  static constexpr int XB = ROWS / 128;                  // 32-wide row blocks per wave
+  static constexpr int QB = FMAX / 32;                   // 32-wide q blocks
+  static constexpr int BK = 16;                          // k-chunk
+  static constexpr int LA = ROWS + 4;                    // wide tile row (k-major)
+  static constexpr int LS = FMAX + 4;                    // narrow tile row (k-major)
+  static constexpr int LP = FMAX + 1;                    // G0 slab / P rows
+  static constexpr int UNION = BK * LA > ROWS * LP ? BK * LA : ROWS * LP;
+  static constexpr int WAVES = FMAX == 32 ? 4 : 2;       // per SIMD
+};
+
+__device__ inline float4 xy_load4(const float* __restrict__ p, int valid, bool aligned) {
+  if (aligned && valid >= 4) return *reinterpret_cast<const float4*>(p);
+  float4 v;
+  v.x = valid > 0 ? p[0] : 0.f;
+  v.y = valid > 1 ? p[1] : 0.f;
+  v.z = valid > 2 ? p[2] : 0.f;
+  v.w = valid > 3 ? p[3] : 0.f;
+  return v;
+}
+
+template <int FMAX>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(XyMfmaShape<FMAX>::WAVES)))
+void k_xy_mfma(const ChainDev* __restrict__ chains, int nrb, int s0, int kseg) {
+  using S = XyMfmaShape<FMAX>;
+  constexpr int ROWS = S::ROWS, XB = S::XB, QB = S::QB, BK = S::BK;
+  constexpr int LA = S::LA, LS = S::LS, LP = S::LP;
+  constexpr int NQ4 = BK * ROWS / (4 * kThreads);        // float4 loads of the wide tile per thread
+  constexpr int NS = BK * FMAX / kThreads;               // loads of the narrow tile per thread
+  static_assert(NQ4 >= 1 && NS >= 1 && ROWS % 128 == 0, "tile shape");
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int rb = b % nrb, part = (b / nrb) & 1, cs = b / (2 * nrb);
+  const int spin = cs & 1;
+  const ChainDev& C = chains[cs >> 1];
+  const int N = C.N, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r0 = rb * ROWS;
+  if (r0 >= N) return;
+  const int f = C.st->fcount, fp = C.st->foff;
+  if (f == 0) return;
+  const float* __restrict__ G = (const float*)C.G[spin];
+  float* __restrict__ Xa = (float*)C.Xa[spin];
+  float* __restrict__ Ya = (float*)C.Ya[spin];
+  const bool al = (N & 3) == 0;
+
+  __shared__ int Fl[FMAX];
+  __shared__ __align__(16) float U[S::UNION];            // wide tile, then G0 slab / P
+  __shared__ __align__(16) float Sm[BK * LS];            // narrow tile
+  __shared__ float Zl[FMAX * LP];
+  for (int q = tid; q < FMAX; q += kThreads) Fl[q] = q < f ? C.flist[q] : 0;
+  __syncthreads();
+
+  const int h = lane >> 5, l32 = lane & 31, w0 = wave * (ROWS / 4);
+  floatx16 acc[XB * QB];
+#pragma unroll
+  for (int t = 0; t < XB * QB; ++t)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[t][r] = 0.f;
+
+  // global -> register mapping of a k-chunk
+  float4 va[NQ4];
+  float vs[NS];
+  // wide X tile: BK / 4 lanes per row, each a float4 along k, so a wave reads
+  // eight whole 128-byte row segments per instruction
+  constexpr int K4 = BK / 4, RS = kThreads / K4;
+  auto gload = [&](int k0) {
+    if (part == 0) {
+      const int k = k0 + 4 * (tid % K4), rr = tid / K4;
+#pragma unroll
+      for (int t = 0; t < NQ4; ++t) {
+        const int r = rr + RS * t;
+        va[t] = xy_load4(Xa + (size_t)(r0 + r) * N + k, r0 + r < N ? fp - k : 0, al);
+      }
+      // narrow: Ya[k0 + k, F[q]]
+#pragma unroll
+      for (int t = 0; t < NS; ++t) {
+        const int e = tid + t * kThreads, k = e / FMAX, q = e % FMAX;
+        vs[t] = (k0 + k < fp && q < f) ? Ya[(size_t)(k0 + k) * N + Fl[q]] : 0.f;
+      }
+    } else {
+      // wide: Ya[k0 + k, r0 + 4 j4 ..]
+      constexpr int J4 = ROWS / 4, KS = kThreads / J4;
+      const int j = 4 * (tid % J4), kr = tid / J4;
+#pragma unroll
+      for (int t = 0; t < NQ4; ++t) {
+        const int k = k0 + kr + KS * t;
+        va[t] = xy_load4(Ya + (size_t)k * N + r0 + j, k < fp ? N - (r0 + j) : 0, al);
+      }
+      // narrow: Xa[F[q], k0 + k]
+#pragma unroll
+      for (int t = 0; t < NS; ++t) {
+        const int e = tid + t * kThreads, k = e % BK, q = e / BK;
+        vs[t] = (k0 + k < fp && q < f) ? Xa[(size_t)Fl[q] * N + k0 + k] : 0.f;
+      }
+    }
+  };
+  auto sstore = [&]() {
+    float* A = U;
+    if (part == 0) {
+      const int k = 4 * (tid % K4), rr = tid / K4;
+#pragma unroll
+      for (int t = 0; t < NQ4; ++t) {
+        const int r = rr + RS * t;
+        A[(k + 0) * LA + r] = va[t].x;
+        A[(k + 1) * LA + r] = va[t].y;
+        A[(k + 2) * LA + r] = va[t].z;
+        A[(k + 3) * LA + r] = va[t].w;
+      }
+#pragma unroll
+      for (int t = 0; t < NS; ++t) {
+        const int e = tid + t * kThreads;
+        Sm[(e / FMAX) * LS + e % FMAX] = vs[t];
+      }
+    } else {
+      constexpr int J4 = ROWS / 4, KS = kThreads / J4;
+      const int j = 4 * (tid % J4), kr = tid / J4;
+#pragma unroll
+      for (int t = 0; t < NQ4; ++t) *reinterpret_cast<float4*>(&A[(kr + KS * t) * LA + j]) = va[t];
+#pragma unroll
+      for (int t = 0; t < NS; ++t) {
+        const int e = tid + t * kThreads;
+        Sm[(e % BK) * LS + e / BK] = vs[t];
+      }
+    }
+  };
+
+  const int nk = (fp + BK - 1) / BK;
+  if (nk > 0) gload(0);
+  for (int kt = 0; kt < nk; ++kt) {
+    if (kt > 0) __syncthreads();                          // the previous chunk is consumed
+    sstore();
+    __syncthreads();
+    if (kt + 1 < nk) gload((kt + 1) * BK);                // in flight during the products
+    {
+      const float* A = U;
+      const float* Bn = Sm;
+#pragma unroll
+      for (int s2 = 0; s2 < BK / 2; ++s2) {
+        const int kk = 2 * s2 + h;                        // lane's k of this MFMA k-step
+        float wv[XB], nv[QB];
+#pragma unroll
+        for (int x = 0; x < XB; ++x) wv[x] = A[kk * LA + w0 + 32 * x + l32];
+#pragma unroll
+        for (int qb = 0; qb < QB; ++qb) nv[qb] = Bn[kk * LS + 32 * qb + l32];
+#pragma unroll
+        for (int x = 0; x < XB; ++x)
+#pragma unroll
+          for (int qb = 0; qb < QB; ++qb) {
+            floatx16& a = acc[x * QB + qb];
+            a = part == 0 ? __builtin_amdgcn_mfma_f32_32x32x2f32(wv[x], nv[qb], a, 0, 0, 0)
+                          : __builtin_amdgcn_mfma_f32_32x32x2f32(nv[qb], wv[x], a, 0, 0, 0);
+          }
+      }
+    }
+  }
+  __syncthreads();                                        // U is reused below
+
+  // accumulator element r of block (x, qb): C row 8 (r / 4) + 4 h + (r % 4),
+  // column l32 of the block (X part: row r0 + w0 + 32 x + .., q = 32 qb + l32;
+  // Y part: q = 32 qb + .., column r0 + w0 + 32 x + l32)
+  if (part == 1) {
+    // one 32 x 32 block at a time: its 16 loads of G0 in flight, then its stores
+#pragma unroll
+    for (int x = 0; x < XB; ++x)
+#pragma unroll
+      for (int qb = 0; qb < QB; ++qb) {
+        const int j = r0 + w0 + 32 * x + l32;
+        float gv[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int q = 32 * qb + 8 * (r >> 2) + 4 * h + (r & 3);
+          gv[r] = (q < f && j < N) ? G[(size_t)Fl[q] * N + j] : 0.f;
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int q = 32 * qb + 8 * (r >> 2) + 4 * h + (r & 3);
+          if (q < f && j < N)
+            Ya[(size_t)(fp + q) * N + j] = (Fl[q] == j ? 1.f : 0.f) - gv[r] + acc[x * QB + qb][r];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    return;
+  }
+
+  // X part: the segment's slab S1[r][c] = G0[r0 + r, s0 + c] and Z, then
+  // P = G0[:, F] - C, then Xa[:, fp + c] = P Z
+  float* S1 = U;
+  const float* __restrict__ Z = (const float*)C.Z[spin];
+  for (int e = tid; e < FMAX * FMAX; e += kThreads) {
+    const int q = e / FMAX, c = e % FMAX;
+    Zl[q * LP + c] = (q < f && c < f) ? Z[(size_t)q * kSegMax + c] : 0.f;
+  }
+  constexpr int NE = ROWS * FMAX / kThreads;
+  for (int t0 = 0; t0 < NE; t0 += 8) {       // eight loads in flight, then their stores
+    float v8[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int e = tid + (t0 + t) * kThreads, r = e / FMAX, c = e % FMAX;
+      v8[t] = (r0 + r < N && c < kseg && s0 + c < N) ? G[(size_t)(r0 + r) * N + s0 + c] : 0.f;
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int e = tid + (t0 + t) * kThreads;
+      S1[(e / FMAX) * LP + e % FMAX] = v8[t];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int x = 0; x < XB; ++x)
+#pragma unroll
+    for (int qb = 0; qb < QB; ++qb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int i = w0 + 32 * x + 8 * (r >> 2) + 4 * h + (r & 3), q = 32 * qb + l32;
+        const float a = acc[x * QB + qb][r];
+        acc[x * QB + qb][r] = q < f ? S1[i * LP + Fl[q] - s0] - a : 0.f;
+      }
+  __syncthreads();
+  float* Pl = U;
+#pragma unroll
+  for (int x = 0; x < XB; ++x)
+#pragma unroll
+    for (int qb = 0; qb < QB; ++qb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int i = w0 + 32 * x + 8 * (r >> 2) + 4 * h + (r & 3), q = 32 * qb + l32;
+        Pl[i * LP + q] = acc[x * QB + qb][r];
+        acc[x * QB + qb][r] = 0.f;
+      }
+  __syncthreads();
+  const int nsz = (f + 1) / 2;                            // MFMA k-steps over q < f
+  for (int s2 = 0; s2 < nsz; ++s2) {
+    const int q = 2 * s2 + h;
+    float pv[XB], zv[QB];
+#pragma unroll
+    for (int x = 0; x < XB; ++x) pv[x] = Pl[(w0 + 32 * x + l32) * LP + q];
+#pragma unroll
+    for (int cb = 0; cb < QB; ++cb) zv[cb] = Zl[q * LP + 32 * cb + l32];
+#pragma unroll
+    for (int x = 0; x < XB; ++x)
+#pragma unroll
+      for (int cb = 0; cb < QB; ++cb)
+        acc[x * QB + cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(pv[x], zv[cb], acc[x * QB + cb], 0, 0, 0);
+  }
+#pragma unroll
+  for (int x = 0; x < XB; ++x)
+#pragma unroll
+    for (int cb = 0; cb < QB; ++cb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int i = r0 + w0 + 32 * x + 8 * (r >> 2) + 4 * h + (r & 3), c = 32 * cb + l32;
+        if (i < N && c < f) Xa[(size_t)i * N + fp + c] = acc[x * QB + cb][r];
+      }
+}
+
+template <int FMAX>
+static void launch_xy_mfma(const ChainDev* c, int nc, int n_max, int s0, int kseg, hipStream_t s) {
+  constexpr int ROWS = XyMfmaShape<FMAX>::ROWS;
+  const int nrb = (n_max + ROWS - 1) / ROWS;
+  hipLaunchKernelGGL((k_xy_mfma<FMAX>), dim3(nc * 2 * 2 * nrb), dim3(kThreads), 0, s, c, nrb, s0,
+                     kseg);
+}
+
 template <typename T, int FMAX>
 static void launch_xy_t(const ChainDev* c, int nc, int n_max, int s0, int kseg, hipStream_t s) {
   constexpr int ROWS = XyShape<T, FMAX>::ROWS;
@@ -684,12 +961,12 @@ hipError_t launch_xy(int fp32, const ChainDev* c, int nc, int n_max, int s0, int
                      hipStream_t s) {
   if (kseg <= 32) {
     if (fp32)
-      launch_xy_t<float, 32>(c, nc, n_max, s0, kseg, s);
+      launch_xy_mfma<32>(c, nc, n_max, s0, kseg, s);
     else
       launch_xy_t<double, 32>(c, nc, n_max, s0, kseg, s);
   } else {
     if (fp32)
-      launch_xy_t<float, 64>(c, nc, n_max, s0, kseg, s);
+      launch_xy_mfma<64>(c, nc, n_max, s0, kseg, s);
     else
       launch_xy_t<double, 64>(c, nc, n_max, s0, kseg, s);
   }
