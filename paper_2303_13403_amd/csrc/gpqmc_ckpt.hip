@@ -218,97 +218,122 @@ __global__ __launch_bounds__(kDenseThreads) void k_gj_inv(const ChainDev* __rest
 }
 
 // ---------------------------------------------------------------------------
-// Register-tiled variants for n <= 16 NB (the usual case).  One 256-thread
-// workgroup per matrix; thread t owns the elements (ti + 16 a, tj + 16 b),
-// ti = t / 16, tj = t % 16, in m[a][b], so a row segment is 16 consecutive
+// Register-tiled variants for n <= TG NB (the usual case).  One workgroup of
+// TG x TG threads per matrix; thread t owns the elements (ti + TG a, tj + TG b),
+// ti = t / TG, tj = t % TG, in m[a][b], so a row segment is TG consecutive
 // lanes (coalesced loads).  Every elimination step publishes the rows and the
 // column it needs in double-buffered LDS vectors and updates the registers.
+// The step index is uniform across the workgroup, so the register row and
+// column that hold a given matrix row or column are chosen by uniform
+// branches: an elimination step is one FMA per element plus O(NB) fixes for
+// the pivot row, row k and column k, with no per-element selects.
 // ---------------------------------------------------------------------------
 constexpr int kRtMax = 128;
 
-template <int NB>
+template <int NB, int TG>
 struct RegTile {
   double m[NB][NB];
   int ti, tj, n;
   __device__ void load(const double* __restrict__ g, int n_) {
     n = n_;
-    ti = threadIdx.x >> 4;
-    tj = threadIdx.x & 15;
+    ti = threadIdx.x / TG;
+    tj = threadIdx.x % TG;
 #pragma unroll
     for (int a = 0; a < NB; ++a)
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
-        const int r = ti + 16 * a, c = tj + 16 * b;
+        const int r = ti + TG * a, c = tj + TG * b;
         m[a][b] = (r < n && c < n) ? g[(size_t)r * n + c] : 0.0;
       }
   }
-  // row r (owned by ti == r % 16) into v[c]; column c (tj == c % 16) into v[r]
+  // row r (owned by ti == r % TG) into v[c]; column c (tj == c % TG) into
+  // v[r].  r and c are uniform, so is the register row / column.
   __device__ void put_row(int r, double* v) const {
-    if (ti != (r & 15)) return;
-    const int ar = r >> 4;
+    const int ar = r / TG;
+    if (ti != r % TG) return;
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      double x = 0.0;
+    for (int a = 0; a < NB; ++a)
+      if (a == ar) {
 #pragma unroll
-      for (int a = 0; a < NB; ++a) x = (a == ar) ? m[a][b] : x;
-      const int c = tj + 16 * b;
-      if (c < n) v[c] = x;
-    }
+        for (int b = 0; b < NB; ++b) {
+          const int c = tj + TG * b;
+          if (c < n) v[c] = m[a][b];
+        }
+      }
   }
   __device__ void put_col(int c, double* v) const {
-    if (tj != (c & 15)) return;
-    const int bc = c >> 4;
+    const int bc = c / TG;
+    if (tj != c % TG) return;
 #pragma unroll
-    for (int a = 0; a < NB; ++a) {
-      double x = 0.0;
+    for (int b = 0; b < NB; ++b)
+      if (b == bc) {
 #pragma unroll
-      for (int b = 0; b < NB; ++b) x = (b == bc) ? m[a][b] : x;
-      const int r = ti + 16 * a;
-      if (r < n) v[r] = x;
-    }
+        for (int a = 0; a < NB; ++a) {
+          const int r = ti + TG * a;
+          if (r < n) v[r] = m[a][b];
+        }
+      }
   }
-  // one Gauss-Jordan step at pivot k with the pivot row taken from row p:
-  // rk = old row k, rp = old row p, ck = old column k (all in LDS).  The
-  // vector entries are loaded first, the update is branch-free.
+  // one Gauss-Jordan step at pivot k (uniform) with the pivot row taken from
+  // row p (uniform): rk = old row k, rp = old row p, ck = old column k (all in
+  // LDS).  Every element is first updated as an ordinary row,
+  // m -= ck[r] rp[c] / pivot; then the row that receives the old row k, column
+  // k (-f_r / pivot) and row k (the normalised pivot row) are rewritten.
   __device__ void gj_step(int k, int p, double inv, const double* rk, const double* rp,
                           const double* ck) {
-    double prc[NB], rkc[NB], ckr[NB];
+    double prc[NB], ckr[NB];
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      prc[b] = rp[tj + 16 * b];
-      rkc[b] = rk[tj + 16 * b];
-    }
+    for (int b = 0; b < NB; ++b) prc[b] = rp[tj + TG * b] * inv;
 #pragma unroll
-    for (int a = 0; a < NB; ++a) ckr[a] = ck[ti + 16 * a];
+    for (int a = 0; a < NB; ++a) ckr[a] = ck[ti + TG * a];
     const double fpk = rk[k];   // column-k entry of the row that moves to p
+    const int ak = k / TG, bk = k / TG, ap = p / TG;
+    const bool lk_r = ti == k % TG, lk_c = tj == k % TG, lp_r = (ti == p % TG) & (p != k);
 #pragma unroll
-    for (int b = 0; b < NB; ++b) prc[b] = (tj + 16 * b == k) ? inv : prc[b] * inv;
+    for (int a = 0; a < NB; ++a)
 #pragma unroll
-    for (int a = 0; a < NB; ++a) {
-      const int r = ti + 16 * a;
-      const bool isk = r == k, isp = (r == p) & (p != k);
-      const double fr = isp ? fpk : ckr[a];
-      const double nfi = -fr * inv;
+      for (int b = 0; b < NB; ++b) m[a][b] = fma(-ckr[a], prc[b], m[a][b]);
+    if (p != k) {
 #pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        const bool colk = tj + 16 * b == k;
-        const double src = isp ? rkc[b] : m[a][b];
-        const double upd = colk ? nfi : fma(-fr, prc[b], src);
-        m[a][b] = isk ? prc[b] : upd;
-      }
+      for (int a = 0; a < NB; ++a)
+        if (a == ap) {
+#pragma unroll
+          for (int b = 0; b < NB; ++b) {
+            const double v = fma(-fpk, prc[b], rk[tj + TG * b]);
+            m[a][b] = lp_r ? v : m[a][b];
+          }
+        }
     }
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+      if (b == bk) {
+#pragma unroll
+        for (int a = 0; a < NB; ++a) {
+          const double fr = (lp_r & (a == ap)) ? fpk : ckr[a];
+          m[a][b] = lk_c ? -fr * inv : m[a][b];
+        }
+      }
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+      if (a == ak) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          const double v = (lk_c & (b == bk)) ? inv : prc[b];
+          m[a][b] = lk_r ? v : m[a][b];
+        }
+      }
   }
 };
 
 // In-place inverse.  triangular: upper triangular input, no pivoting.  Returns
-// log|det| (to thread 0) and the sign (0: singular, the tile is then
-// unusable; to every thread);
+// log|det| (to thread 0, over the nonzero pivots) and the sign (0: singular,
+// the tile is then unusable; to every thread);
 // colmap receives, for every column of the eliminated matrix, its column in
 // the inverse.
-template <int NB>
-__device__ void rt_invert(RegTile<NB>& T, bool triangular, double (*rk)[kRtMax],
-                          double (*rp)[kRtMax], double (*ck)[kRtMax], double (*cv)[16],
-                          int (*ci)[16], int* piv, int* colmap, double& logabs, int& sgn) {
+template <int NB, int TG>
+__device__ void rt_invert(RegTile<NB, TG>& T, bool triangular, double (*rk)[kRtMax],
+                          double (*rp)[kRtMax], double (*ck)[kRtMax], double (*cv)[32],
+                          int (*ci)[32], int* piv, int* colmap, double& logabs, int& sgn) {
   const int n = T.n, tid = threadIdx.x;
   logabs = 0.0;
   sgn = 1;
@@ -321,54 +346,56 @@ __device__ void rt_invert(RegTile<NB>& T, bool triangular, double (*rk)[kRtMax],
     int p = k;
     if (!triangular) {
       // candidates of the owners of column k, one per row residue
-      if (T.tj == (k & 15)) {
+      const int bc = k / TG;
+      if (T.tj == k % TG) {
         double best = -1.0;
         int bi = k;
-        const int bc = k >> 4;
 #pragma unroll
-        for (int a = 0; a < NB; ++a) {
-          double x = 0.0;
+        for (int b = 0; b < NB; ++b)
+          if (b == bc) {
 #pragma unroll
-          for (int b = 0; b < NB; ++b) x = (b == bc) ? T.m[a][b] : x;
-          const int r = T.ti + 16 * a;
-          const bool take = (r >= k) & (r < n) & (fabs(x) > best);
-          best = take ? fabs(x) : best;
-          bi = take ? r : bi;
-        }
+            for (int a = 0; a < NB; ++a) {
+              const double x = T.m[a][b];
+              const int r = T.ti + TG * a;
+              const bool take = (r >= k) & (r < n) & (fabs(x) > best);
+              best = take ? fabs(x) : best;
+              bi = take ? r : bi;
+            }
+          }
         cv[kb][T.ti] = best;
         ci[kb][T.ti] = bi;
       }
       __syncthreads();
-      double vq[16];
-      int iq[16];
+      // largest candidate, ties to the smallest row: a shuffle reduction over
+      // each group of TG lanes, which holds all TG candidates
+      double best = cv[kb][tid % TG];
+      int bi = ci[kb][tid % TG];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        vq[q] = cv[kb][q];
-        iq[q] = ci[kb][q];
+      for (int off = TG / 2; off > 0; off >>= 1) {
+        const double ob = __shfl_xor(best, off, TG);
+        const int oi = __shfl_xor(bi, off, TG);
+        const bool take = (ob > best) | ((ob == best) & (oi < bi));
+        best = take ? ob : best;
+        bi = take ? oi : bi;
       }
-      double best = -1.0;
-#pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const bool take = (vq[q] > best) | ((vq[q] == best) & (iq[q] < p));
-        best = take ? vq[q] : best;
-        p = take ? iq[q] : p;
-      }
+      p = __builtin_amdgcn_readfirstlane(bi);   // the same on every lane
       if (p != k) T.put_row(p, rp[kb]);
     }
     __syncthreads();
     const double* prow = (p == k) ? rk[kb] : rp[kb];
     const double pv = prow[k];
-    if (pv == 0.0 || pv != pv) {
-      sgn = 0;
-      return;
-    }
+    // a zero or NaN pivot makes the matrix singular: the remaining steps run
+    // with a zero inverse pivot (finite, discarded) rather than leaving the
+    // loop, which kept a second copy of the tile live in registers
+    const bool bad = (pv == 0.0) | (pv != pv);
+    if (bad) sgn = 0;
     if (tid == 0) {
-      logabs += log(fabs(pv));
+      if (!bad) logabs += log(fabs(pv));
       piv[k] = p;
     }
     if (pv < 0) sgn = -sgn;
     if (p != k) sgn = -sgn;
-    T.gj_step(k, p, 1.0 / pv, rk[kb], prow, ck[kb]);
+    T.gj_step(k, p, bad ? 0.0 : 1.0 / pv, rk[kb], prow, ck[kb]);
   }
   __syncthreads();
   if (tid == 0) {
@@ -388,24 +415,28 @@ __device__ void rt_invert(RegTile<NB>& T, bool triangular, double (*rk)[kRtMax],
   __syncthreads();
 }
 
-template <int NB>
-__device__ void rt_store(const RegTile<NB>& T, double* __restrict__ g, const int* colmap,
+template <int NB, int TG>
+__device__ void rt_store(const RegTile<NB, TG>& T, double* __restrict__ g, const int* colmap,
                          bool upper_only) {
+  // destination columns, read once per register column
+  int cd[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int c = T.tj + TG * b;
+    cd[b] = c < T.n ? colmap[c] : 0;
+  }
 #pragma unroll
   for (int a = 0; a < NB; ++a)
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-      const int r = T.ti + 16 * a, c = T.tj + 16 * b;
-      if (r < T.n && c < T.n) {
-        const int cd = colmap[c];
-        g[(size_t)r * T.n + cd] = (upper_only && cd < r) ? 0.0 : T.m[a][b];
-      }
+      const int r = T.ti + TG * a, c = T.tj + TG * b;
+      if (r < T.n && c < T.n) g[(size_t)r * T.n + cd[b]] = (upper_only && cd[b] < r) ? 0.0 : T.m[a][b];
     }
 }
 
 // the step vectors are read at every residue, including entries beyond n
 __device__ inline void rt_clear(double (*rk)[kRtMax], double (*rp)[kRtMax], double (*ck)[kRtMax]) {
-  for (int i = threadIdx.x; i < 2 * kRtMax; i += kThreads) {
+  for (int i = threadIdx.x; i < 2 * kRtMax; i += blockDim.x) {
     rk[i / kRtMax][i % kRtMax] = 0.0;
     rp[i / kRtMax][i % kRtMax] = 0.0;
     ck[i / kRtMax][i % kRtMax] = 0.0;
@@ -414,19 +445,19 @@ __device__ inline void rt_clear(double (*rk)[kRtMax], double (*rp)[kRtMax], doub
 
 #define GPQMC_RT_SHARED                                 \
   __shared__ double rk[2][kRtMax], rp[2][kRtMax], ck[2][kRtMax]; \
-  __shared__ double cv[2][16];                          \
-  __shared__ int ci[2][16];                             \
+  __shared__ double cv[2][32];                          \
+  __shared__ int ci[2][32];                             \
   __shared__ int piv[kRtMax], colmap[kRtMax];
 
 // Cholesky W = R^T R (R upper) of the Gram matrix, then R^{-1}, in registers.
-template <int NB>
-__global__ __launch_bounds__(kThreads) void k_chol_inv_rt(const ChainDev* __restrict__ chains) {
+template <int NB, int TG>
+__global__ __launch_bounds__(TG * TG) void k_chol_inv_rt(const ChainDev* __restrict__ chains) {
   const int lg = xcd_remap(blockIdx.x, gridDim.x);
   const ChainDev& C = chains[lg >> 1];
   const int sp = lg & 1, n = C.n[sp], tid = threadIdx.x;
   GPQMC_RT_SHARED
   rt_clear(rk, rp, ck);
-  RegTile<NB> T;
+  RegTile<NB, TG> T;
   T.load(C.Wm[sp], n);
   double lsum = 0.0;
   bool bad = false;
@@ -441,35 +472,49 @@ __global__ __launch_bounds__(kThreads) void k_chol_inv_rt(const ChainDev* __rest
       for (int a = 0; a < NB; ++a)
 #pragma unroll
         for (int b = 0; b < NB; ++b)
-          if (T.ti + 16 * a == j && T.tj + 16 * b == j) T.m[a][b] = 1.0;
+          if (T.ti + TG * a == j && T.tj + TG * b == j) T.m[a][b] = 1.0;
       continue;
     }
     const double d = sqrt(d2), id = 1.0 / d;
     if (tid == 0) lsum += log(d);
-    double rc[NB], rr[NB];   // normalised row j at the thread's columns and rows
+    // normalised row j at the thread's columns (zero left of j) and rows
+    // (zero at and above j): one FMA per element updates the trailing matrix
+    // (its lower triangle too, which is cleared at the end) and leaves the
+    // finished rows unchanged; row j itself is then rewritten
+    double rc[NB], rr[NB];
 #pragma unroll
-    for (int b = 0; b < NB; ++b) rc[b] = rk[jb][T.tj + 16 * b] * id;
-#pragma unroll
-    for (int a = 0; a < NB; ++a) rr[a] = rk[jb][T.ti + 16 * a] * id;
+    for (int b = 0; b < NB; ++b) {
+      const int c = T.tj + TG * b;
+      rc[b] = c >= j ? rk[jb][c] * id : 0.0;
+    }
 #pragma unroll
     for (int a = 0; a < NB; ++a) {
-      const int r = T.ti + 16 * a;
-#pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        const int c = T.tj + 16 * b;
-        const double x = T.m[a][b];
-        const double rowj = (c == j) ? d : rc[b];
-        const double trail = fma(-rr[a], rc[b], x);
-        T.m[a][b] = (r == j) ? ((c >= j) ? rowj : x) : (((r > j) & (c >= r)) ? trail : x);
-      }
+      const int r = T.ti + TG * a;
+      rr[a] = r > j ? rk[jb][r] * id : 0.0;
     }
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) T.m[a][b] = fma(-rr[a], rc[b], T.m[a][b]);
+    const int aj = j / TG;
+    const bool lj = T.ti == j % TG;
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+      if (a == aj) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          const int c = T.tj + TG * b;
+          const double rowj = (c == j) ? d : rc[b];
+          T.m[a][b] = (lj & (c >= j)) ? rowj : T.m[a][b];
+        }
+      }
   }
   // clear the lower triangle
 #pragma unroll
   for (int a = 0; a < NB; ++a)
 #pragma unroll
     for (int b = 0; b < NB; ++b)
-      if (T.tj + 16 * b < T.ti + 16 * a) T.m[a][b] = 0.0;
+      if (T.tj + TG * b < T.ti + TG * a) T.m[a][b] = 0.0;
   if (tid == 0) {
     C.st->chk_log[sp] = lsum;
     C.st->chk_sgn[sp] = 1;
@@ -477,28 +522,28 @@ __global__ __launch_bounds__(kThreads) void k_chol_inv_rt(const ChainDev* __rest
   }
   double la;
   int sg;
-  rt_invert<NB>(T, true, rk, rp, ck, cv, ci, piv, colmap, la, sg);
+  rt_invert<NB, TG>(T, true, rk, rp, ck, cv, ci, piv, colmap, la, sg);
   if (sg != 0)
-    rt_store<NB>(T, C.Rinv[sp], colmap, true);
+    rt_store<NB, TG>(T, C.Rinv[sp], colmap, true);
   else if (tid == 0)
     atomicOr(&C.st->flags, (int)FLAG_SINGULAR);
 }
 
 // Inverse of X = L R (n x n) in place, partial pivoting; log|det X| and its
 // sign go to the chain state.
-template <int NB>
-__global__ __launch_bounds__(kThreads) void k_gj_inv_rt(const ChainDev* __restrict__ chains) {
+template <int NB, int TG>
+__global__ __launch_bounds__(TG * TG) void k_gj_inv_rt(const ChainDev* __restrict__ chains) {
   const int lg = xcd_remap(blockIdx.x, gridDim.x);
   const ChainDev& C = chains[lg >> 1];
   const int sp = lg & 1, n = C.n[sp], tid = threadIdx.x;
   GPQMC_RT_SHARED
   rt_clear(rk, rp, ck);
-  RegTile<NB> T;
+  RegTile<NB, TG> T;
   T.load(C.Xm[sp], n);
   double logabs;
   int sgn;
-  rt_invert<NB>(T, false, rk, rp, ck, cv, ci, piv, colmap, logabs, sgn);
-  if (sgn != 0) rt_store<NB>(T, C.Xm[sp], colmap, false);
+  rt_invert<NB, TG>(T, false, rk, rp, ck, cv, ci, piv, colmap, logabs, sgn);
+  if (sgn != 0) rt_store<NB, TG>(T, C.Xm[sp], colmap, false);
   if (tid == 0) {
     C.st->x_log[sp] = logabs;
     C.st->x_sgn[sp] = sgn;
@@ -671,26 +716,28 @@ __global__ void k_set_ctl(Ctl* ctl, int measure, int force_reject, float drift_t
 // ---------------------------------------------------------------------------
 // n_part: the largest particle number of the batch; register tiles up to
 // kRtMax, the LDS / global kernels beyond
-template <int NB>
+template <int NB, int TG>
 static hipError_t launch_rt(bool chol, const ChainDev* c, int nc, hipStream_t s) {
   if (chol)
-    hipLaunchKernelGGL(k_chol_inv_rt<NB>, dim3(2 * nc), dim3(kThreads), 0, s, c);
+    hipLaunchKernelGGL((k_chol_inv_rt<NB, TG>), dim3(2 * nc), dim3(TG * TG), 0, s, c);
   else
-    hipLaunchKernelGGL(k_gj_inv_rt<NB>, dim3(2 * nc), dim3(kThreads), 0, s, c);
+    hipLaunchKernelGGL((k_gj_inv_rt<NB, TG>), dim3(2 * nc), dim3(TG * TG), 0, s, c);
   return hipGetLastError();
 }
 
+// n_part <= 128: 16 x 16 threads with NB = ceil(n_part / 16) (measured faster
+// than 32 x 32 threads); beyond: the LDS / global kernels
 static hipError_t launch_dense(bool chol, const ChainDev* c, int nc, int n_part, hipStream_t s) {
   switch ((n_part + 15) / 16) {
     case 0:
-    case 1: return launch_rt<1>(chol, c, nc, s);
-    case 2: return launch_rt<2>(chol, c, nc, s);
-    case 3: return launch_rt<3>(chol, c, nc, s);
-    case 4: return launch_rt<4>(chol, c, nc, s);
-    case 5: return launch_rt<5>(chol, c, nc, s);
-    case 6: return launch_rt<6>(chol, c, nc, s);
-    case 7: return launch_rt<7>(chol, c, nc, s);
-    case 8: return launch_rt<8>(chol, c, nc, s);
+    case 1: return launch_rt<1, 16>(chol, c, nc, s);
+    case 2: return launch_rt<2, 16>(chol, c, nc, s);
+    case 3: return launch_rt<3, 16>(chol, c, nc, s);
+    case 4: return launch_rt<4, 16>(chol, c, nc, s);
+    case 5: return launch_rt<5, 16>(chol, c, nc, s);
+    case 6: return launch_rt<6, 16>(chol, c, nc, s);
+    case 7: return launch_rt<7, 16>(chol, c, nc, s);
+    case 8: return launch_rt<8, 16>(chol, c, nc, s);
     default: break;
   }
   if (chol)
