@@ -522,6 +522,9 @@ __global__ __launch_bounds__(TG * TG) void k_chol_inv_rt(const ChainDev* __restr
   }
   double la;
   int sg;
+  // the inverse's first step rewrites rk[0], which the last Cholesky step
+  // (j = n - 1 even) may still be reading
+  __syncthreads();
   rt_invert<NB, TG>(T, true, rk, rp, ck, cv, ci, piv, colmap, la, sg);
   if (sg != 0)
     rt_store<NB, TG>(T, C.Rinv[sp], colmap, true);

@@ -130,6 +130,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     sh_acc = 0;
   }
   const bool zero_delta = C.delta[bnd][0][0] == 0.0 && C.delta[bnd][0][1] == 0.0;
+  // the slice's flip factors, read once: the sequential loop below selects
+  // them in registers instead of loading them per site
+  const double dl_u0 = C.delta[bnd][0][0], dl_u1 = C.delta[bnd][0][1];
+  const double dl_d0 = C.delta[bnd][1][0], dl_d1 = C.delta[bnd][1][1];
+  double* const trace_ratio = C.trace_ratio;
   T* Z[2] = {(T*)C.Z[0], (T*)C.Z[1]};
   T *W1[2], *Pm[2], *Qm[2], *PZ[2], *ZQ[2];
   for (int s = 0; s < 2; ++s) {
@@ -278,13 +283,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
         if (j < kb) {
           const int li = b0 + j - s0;
           const int si = fs[li] > 0 ? 0 : 1;
-          const double du = C.delta[bnd][0][si], dd = C.delta[bnd][1][si];
+          const double du = si ? dl_u1 : dl_u0, dd = si ? dl_d1 : dl_d0;
           const double ru = 1.0 + du * (1.0 - (double)lane_value(g[j], j));
           const double rd = 1.0 + dd * (1.0 - (double)lane_value(g[j], 32 + j));
           const bool accept = !force_reject && (u_s[li] < fabs(ru * rd));
-          if (lane == 0 && C.trace_ratio) {
-            C.trace_ratio[((size_t)l * N + b0 + j) * 2 + 0] = ru;
-            C.trace_ratio[((size_t)l * N + b0 + j) * 2 + 1] = rd;
+          if (lane == 0 && trace_ratio) {
+            trace_ratio[((size_t)l * N + b0 + j) * 2 + 0] = ru;
+            trace_ratio[((size_t)l * N + b0 + j) * 2 + 1] = rd;
           }
           if (accept) {
             if (!zero_delta) {
