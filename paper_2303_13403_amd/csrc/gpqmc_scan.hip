@@ -946,6 +946,239 @@ void k_xy_mfma(const ChainDev* __restrict__ chains, int nrb, int s0, int kseg) {
       }
 }
 
+// FP64 form of k_xy_mfma for segments of up to 32 sites, on v_mfma_f64_16x16x4f64:
+// the same two products and the same staging, with 16 x 16 blocks (a wave owns
+// kXy64Rows / 4 rows or columns as XB blocks, and the 32 flips as two blocks)
+// and MFMA k-steps of 4.  Block element r of a lane: row 4 r + lane / 16,
+// column lane % 16.
+constexpr int kXy64Rows = 64, kXy64Bk = 16, kXy64La = kXy64Rows + 2, kXy64Ls = 32 + 2,
+              kXy64Lp = 32 + 1;
+constexpr int kXy64Union = kXy64Bk * kXy64La > kXy64Rows * kXy64Lp ? kXy64Bk * kXy64La
+                                                                   : kXy64Rows * kXy64Lp;
+
+__device__ inline double2 xy_load2(const double* __restrict__ p, int valid, bool aligned) {
+  if (aligned && valid >= 2) return *reinterpret_cast<const double2*>(p);
+  double2 v;
+  v.x = valid > 0 ? p[0] : 0.0;
+  v.y = valid > 1 ? p[1] : 0.0;
+  return v;
+}
+
+__global__ __launch_bounds__(kThreads) void k_xy_mfma64(const ChainDev* __restrict__ chains,
+                                                        int nrb, int s0, int kseg) {
+  constexpr int FMAX = 32, ROWS = kXy64Rows, BK = kXy64Bk, LA = kXy64La, LS = kXy64Ls,
+                LP = kXy64Lp;
+  constexpr int NQ2 = BK * ROWS / (2 * kThreads);        // double2 loads of the wide tile
+  constexpr int NS = BK * FMAX / kThreads;               // loads of the narrow tile
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int rb = b % nrb, part = (b / nrb) & 1, cs = b / (2 * nrb);
+  const int spin = cs & 1;
+  const ChainDev& C = chains[cs >> 1];
+  const int N = C.N, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r0 = rb * ROWS;
+  if (r0 >= N) return;
+  const int f = C.st->fcount, fp = C.st->foff;
+  if (f == 0) return;
+  const double* __restrict__ G = (const double*)C.G[spin];
+  double* __restrict__ Xa = (double*)C.Xa[spin];
+  double* __restrict__ Ya = (double*)C.Ya[spin];
+  const bool al = (N & 1) == 0;
+
+  __shared__ int Fl[FMAX];
+  __shared__ __align__(16) double U[kXy64Union];         // wide tile, then G0 slab / P
+  __shared__ __align__(16) double Sm[BK * LS];           // narrow tile
+  __shared__ double Zl[FMAX * LP];
+  for (int q = tid; q < FMAX; q += kThreads) Fl[q] = q < f ? C.flist[q] : 0;
+  __syncthreads();
+
+  constexpr int XB = ROWS / 64;                          // 16-row blocks per wave
+  const int kq = lane >> 4, l16 = lane & 15, w0 = wave * (ROWS / 4);
+  doublex4 acc[XB][2];                                    // [row or column block][flip block]
+#pragma unroll
+  for (int x = 0; x < XB; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[x][y][r] = 0.0;
+
+  double2 va[NQ2];
+  double vs[NS];
+  // wide X tile: BK / 2 lanes per row, each a double2 along k (128-byte row
+  // segments); wide Y tile: ROWS / 2 lanes along a row of Ya
+  constexpr int K2 = BK / 2, RS = kThreads / K2;
+  constexpr int J2 = ROWS / 2, KS = kThreads / J2;
+  auto gload = [&](int k0) {
+    if (part == 0) {
+      const int k = k0 + 2 * (tid % K2), rr = tid / K2;
+#pragma unroll
+      for (int t = 0; t < NQ2; ++t) {
+        const int r = rr + RS * t;
+        va[t] = xy_load2(Xa + (size_t)(r0 + r) * N + k, r0 + r < N ? fp - k : 0, al);
+      }
+#pragma unroll
+      for (int t = 0; t < NS; ++t) {
+        const int e = tid + t * kThreads, k = e / FMAX, q = e % FMAX;
+        vs[t] = (k0 + k < fp && q < f) ? Ya[(size_t)(k0 + k) * N + Fl[q]] : 0.0;
+      }
+    } else {
+      const int j = 2 * (tid % J2), kr = tid / J2;
+#pragma unroll
+      for (int t = 0; t < NQ2; ++t) {
+        const int k = k0 + kr + KS * t;
+        va[t] = xy_load2(Ya + (size_t)k * N + r0 + j, k < fp ? N - (r0 + j) : 0, al);
+      }
+#pragma unroll
+      for (int t = 0; t < NS; ++t) {
+        const int e = tid + t * kThreads, k = e % BK, q = e / BK;
+        vs[t] = (k0 + k < fp && q < f) ? Xa[(size_t)Fl[q] * N + k0 + k] : 0.0;
+      }
+    }
+  };
+  auto sstore = [&]() {
+    if (part == 0) {
+      const int k = 2 * (tid % K2), rr = tid / K2;
+#pragma unroll
+      for (int t = 0; t < NQ2; ++t) {
+        const int r = rr + RS * t;
+        U[k * LA + r] = va[t].x;
+        U[(k + 1) * LA + r] = va[t].y;
+      }
+#pragma unroll
+      for (int t = 0; t < NS; ++t) {
+        const int e = tid + t * kThreads;
+        Sm[(e / FMAX) * LS + e % FMAX] = vs[t];
+      }
+    } else {
+      const int j = 2 * (tid % J2), kr = tid / J2;
+#pragma unroll
+      for (int t = 0; t < NQ2; ++t) *reinterpret_cast<double2*>(&U[(kr + KS * t) * LA + j]) = va[t];
+#pragma unroll
+      for (int t = 0; t < NS; ++t) {
+        const int e = tid + t * kThreads;
+        Sm[(e % BK) * LS + e / BK] = vs[t];
+      }
+    }
+  };
+
+  const int nk = (fp + BK - 1) / BK;
+  if (nk > 0) gload(0);
+  for (int kt = 0; kt < nk; ++kt) {
+    if (kt > 0) __syncthreads();                          // the previous chunk is consumed
+    sstore();
+    __syncthreads();
+    if (kt + 1 < nk) gload((kt + 1) * BK);                // in flight during the products
+#pragma unroll
+    for (int s4 = 0; s4 < BK / 4; ++s4) {
+      const int kk = 4 * s4 + kq;                         // lane's k of this MFMA k-step
+      double wv[XB], nv[2];
+#pragma unroll
+      for (int x = 0; x < XB; ++x) wv[x] = U[kk * LA + w0 + 16 * x + l16];
+#pragma unroll
+      for (int y = 0; y < 2; ++y) nv[y] = Sm[kk * LS + 16 * y + l16];
+#pragma unroll
+      for (int x = 0; x < XB; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+          acc[x][y] = part == 0 ? __builtin_amdgcn_mfma_f64_16x16x4f64(wv[x], nv[y], acc[x][y], 0, 0, 0)
+                                : __builtin_amdgcn_mfma_f64_16x16x4f64(nv[y], wv[x], acc[x][y], 0, 0, 0);
+    }
+  }
+  __syncthreads();                                        // U is reused below
+
+  if (part == 1) {
+    // C[q][j]: q = 16 y + 4 r + kq, j = r0 + w0 + 16 x + l16
+#pragma unroll
+    for (int x = 0; x < XB; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+        const int j = r0 + w0 + 16 * x + l16;
+        double gv[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int q = 16 * y + 4 * r + kq;
+          gv[r] = (q < f && j < N) ? G[(size_t)Fl[q] * N + j] : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int q = 16 * y + 4 * r + kq;
+          if (q < f && j < N)
+            Ya[(size_t)(fp + q) * N + j] = (Fl[q] == j ? 1.0 : 0.0) - gv[r] + acc[x][y][r];
+        }
+      }
+    return;
+  }
+
+  // X part: slab S1[r][c] = G0[r0 + r, s0 + c], P = G0[:, F] - C, Xa[:, fp + c] = P Z
+  double* S1 = U;
+  const double* __restrict__ Z = (const double*)C.Z[spin];
+  for (int e = tid; e < FMAX * FMAX; e += kThreads) {
+    const int q = e / FMAX, c = e % FMAX;
+    Zl[q * LP + c] = (q < f && c < f) ? Z[(size_t)q * kSegMax + c] : 0.0;
+  }
+  constexpr int NE = ROWS * FMAX / kThreads;
+  {
+    double v[NE];
+#pragma unroll
+    for (int t = 0; t < NE; ++t) {
+      const int e = tid + t * kThreads, r = e / FMAX, c = e % FMAX;
+      v[t] = (r0 + r < N && c < kseg && s0 + c < N) ? G[(size_t)(r0 + r) * N + s0 + c] : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < NE; ++t) {
+      const int e = tid + t * kThreads;
+      S1[(e / FMAX) * LP + e % FMAX] = v[t];
+    }
+  }
+  __syncthreads();
+  // C[i][q]: i = w0 + 16 x + 4 r + kq, q = 16 y + l16
+#pragma unroll
+  for (int x = 0; x < XB; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = w0 + 16 * x + 4 * r + kq, q = 16 * y + l16;
+        const double a = acc[x][y][r];
+        acc[x][y][r] = q < f ? S1[i * LP + Fl[q] - s0] - a : 0.0;
+      }
+  __syncthreads();
+  double* Pl = U;
+#pragma unroll
+  for (int x = 0; x < XB; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = w0 + 16 * x + 4 * r + kq, q = 16 * y + l16;
+        Pl[i * LP + q] = acc[x][y][r];
+        acc[x][y][r] = 0.0;
+      }
+  __syncthreads();
+  const int nsz = (f + 3) / 4;                            // MFMA k-steps over q < f
+  for (int s4 = 0; s4 < nsz; ++s4) {
+    const int q = 4 * s4 + kq;
+    double pv[XB], zv[2];
+#pragma unroll
+    for (int x = 0; x < XB; ++x) pv[x] = Pl[(w0 + 16 * x + l16) * LP + q];
+#pragma unroll
+    for (int y = 0; y < 2; ++y) zv[y] = Zl[q * LP + 16 * y + l16];
+#pragma unroll
+    for (int x = 0; x < XB; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+        acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(pv[x], zv[y], acc[x][y], 0, 0, 0);
+  }
+#pragma unroll
+  for (int x = 0; x < XB; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = r0 + w0 + 16 * x + 4 * r + kq, c = 16 * y + l16;
+        if (i < N && c < f) Xa[(size_t)i * N + fp + c] = acc[x][y][r];
+      }
+}
+
 template <int FMAX>
 static void launch_xy_mfma(const ChainDev* c, int nc, int n_max, int s0, int kseg, hipStream_t s) {
   constexpr int ROWS = XyMfmaShape<FMAX>::ROWS;
@@ -965,10 +1198,12 @@ static void launch_xy_t(const ChainDev* c, int nc, int n_max, int s0, int kseg, 
 hipError_t launch_xy(int fp32, const ChainDev* c, int nc, int n_max, int s0, int kseg,
                      hipStream_t s) {
   if (kseg <= 32) {
-    if (fp32)
+    if (fp32) {
       launch_xy_mfma<32>(c, nc, n_max, s0, kseg, s);
-    else
-      launch_xy_t<double, 32>(c, nc, n_max, s0, kseg, s);
+    } else {
+      const int nrb = (n_max + kXy64Rows - 1) / kXy64Rows;
+      hipLaunchKernelGGL(k_xy_mfma64, dim3(nc * 2 * 2 * nrb), dim3(kThreads), 0, s, c, nrb, s0, kseg);
+    }
   } else {
     if (fp32)
       launch_xy_mfma<64>(c, nc, n_max, s0, kseg, s);
