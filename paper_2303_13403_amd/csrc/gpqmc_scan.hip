@@ -149,7 +149,60 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
   // ---- G_s[S,S] = G0[S,S] - Xa[S, :fp] Ya[:fp, S]: the fp flips accepted in
   // earlier segments of this slice are not yet applied to G ----
   const int fprev = (s0 == 0) ? 0 : st->ftot;
-  {
+  if (nseg <= kBlock) {
+    // segments of up to 32 sites: both spins in one pass, 128 threads per
+    // spin, thread t of a spin owns column t % 32 and rows t / 32 + 4 m; the
+    // rank-fprev correction runs in k-chunks of 32 with every operand row
+    // read as one contiguous 128-byte segment: A = Xa[S, k] (in Rsf) and
+    // B = Ya[k, S] (in the Hs area), both [spin][32][KL]
+    const int s = tid >> 7, t = tid & 127, c = t & 31, rb = t >> 5;
+    const T* __restrict__ g0 = (const T*)C.G[s];
+    const T* __restrict__ xa = (const T*)C.Xa[s];
+    const T* __restrict__ ya = (const T*)C.Ya[s];
+    T* As = Rsf + s * kBlock * KL;
+    T* Bs = &Hs[s][0][0];
+    static_assert(2 * kBlock * KL <= kSegMax * 36, "A tiles fit in Rsf");
+    T acc[kBlock / 4];
+#pragma unroll
+    for (int m = 0; m < kBlock / 4; ++m) {
+      const int row = rb + 4 * m;
+      acc[m] = (row < nseg && c < nseg) ? g0[(size_t)(s0 + row) * N + s0 + c] : T(0);
+    }
+    // thread t loads 8 consecutive entries of row (t / 4) of each tile
+    constexpr int E8 = 8;
+    const int lr = t >> 2, le = (t & 3) * E8;
+    T va[E8], vb[E8];
+    auto load_chunk = [&](int k0) {
+#pragma unroll
+      for (int e = 0; e < E8; ++e) {
+        const int k = k0 + le + e;
+        va[e] = (lr < nseg && k < fprev) ? xa[(size_t)(s0 + lr) * N + k] : T(0);
+        vb[e] = (k0 + lr < fprev && le + e < nseg) ? ya[(size_t)(k0 + lr) * N + s0 + le + e] : T(0);
+      }
+    };
+    if (fprev > 0) load_chunk(0);
+    for (int k0 = 0; k0 < fprev; k0 += 32) {
+      __syncthreads();
+#pragma unroll
+      for (int e = 0; e < E8; ++e) {
+        As[lr * KL + le + e] = va[e];
+        Bs[lr * KL + le + e] = vb[e];
+      }
+      __syncthreads();
+      if (k0 + 32 < fprev) load_chunk(k0 + 32);
+#pragma unroll 4
+      for (int k = 0; k < 32; ++k) {
+        const T bv = Bs[k * KL + c];
+#pragma unroll
+        for (int m = 0; m < kBlock / 4; ++m) acc[m] -= As[(rb + 4 * m) * KL + k] * bv;
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < kBlock / 4; ++m) {
+      const int row = rb + 4 * m;
+      if (row < nseg && c < nseg) Gss[s][row * LGS + c] = acc[m];
+    }
+  } else {
     // lane = column c of the segment, rows wave + 4 m; the rank-fprev
     // correction runs in k-chunks of 32 staged in LDS: A = Xa[S, k] (in Rsf,
     // nseg x 32), B = Ya[k, S] (in the Hs area, 32 x nseg)
