@@ -68,6 +68,11 @@ __global__ __launch_bounds__(kThreads) void k_gemm(const GemmEntry* __restrict__
     bbnd = (args.bscale_slice == 0 || args.bscale_slice == args.n_bulk_last + 1) ? 0 : 1;
   }
 
+  // the two possible B-row factors, read once; a prefetched row carries only
+  // its field value, the factor is applied when it is stored to LDS
+  const T bsc_p = bfield ? (T)dfac(e.dval, bbnd, 1, false) : T(1);
+  const T bsc_m = bfield ? (T)dfac(e.dval, bbnd, -1, false) : T(1);
+  int8_t bf = 1;
   T ra[4], rb[4];
   auto load_regs = [&](int kbase) {
     if (!TRANSA) {
@@ -83,11 +88,10 @@ __global__ __launch_bounds__(kThreads) void k_gemm(const GemmEntry* __restrict__
     }
     if (!TRANSB) {
       const int k = kbase + (tid >> 4), j = n0 + (tid & 15) * 4;
-      T sc = T(1);
-      if (bfield && k < K) sc = (T)dfac(e.dval, bbnd, bfield[k], false);
+      bf = (bfield && k < K) ? bfield[k] : (int8_t)1;
 #pragma unroll
       for (int q = 0; q < 4; ++q)
-        rb[q] = (k < K && j + q < N) ? B[(size_t)k * ldb + j + q] * sc : T(0);
+        rb[q] = (k < K && j + q < N) ? B[(size_t)k * ldb + j + q] : T(0);
     } else {
       const int j = n0 + (tid >> 2), k = kbase + (tid & 3) * 4;
 #pragma unroll
@@ -107,8 +111,9 @@ __global__ __launch_bounds__(kThreads) void k_gemm(const GemmEntry* __restrict__
     }
     if (!TRANSB) {
       const int k = tid >> 4, j = (tid & 15) * 4;
+      const T sc = bf > 0 ? bsc_p : bsc_m;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) Bs[k * LDS_LD + j + q] = rb[q];
+      for (int q = 0; q < 4; ++q) Bs[k * LDS_LD + j + q] = rb[q] * sc;
     } else {
       const int j = tid >> 2, k = (tid & 3) * 4;
 #pragma unroll
@@ -467,6 +472,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     bfield = e.field + (size_t)args.bscale_slice * e.n_sites;
     bbnd = (args.bscale_slice == 0 || args.bscale_slice == args.n_bulk_last + 1) ? 0 : 1;
   }
+  // the two possible factors, read once; a prefetched B row carries only its
+  // field value, and the factor is applied when the row is stored to LDS
+  // (after the current tile's products), so the prefetch never waits
+  const double bsc_p = bfield ? dfac(e.dval, bbnd, 1, false) : 1.0;
+  const double bsc_m = bfield ? dfac(e.dval, bbnd, -1, false) : 1.0;
+  int8_t bf = 1;
 
   // output scaling (frame change, or the D_l rows of a propagation): the
   // tile's row and column factors, staged once (ordered by the first barrier)
@@ -501,14 +512,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
       ra[q] = load2(A + (size_t)i * lda + k, i < M ? K - k : 0, a_al);
     }
     const int kb = k0 + bk;
-    double sc = 1.0;
-    if (bfield && kb < K) sc = dfac(e.dval, bbnd, bfield[kb], false);
+    bf = (bfield && kb < K) ? bfield[kb] : (int8_t)1;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int j = n0 + bj + 2 * q;
       rb[q] = load2(B + (size_t)kb * ldb + j, kb < K ? N - j : 0, b_al);
-      rb[q].x *= sc;
-      rb[q].y *= sc;
     }
   };
   auto sstore = [&](int buf) {
@@ -519,8 +527,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     for (int kq = 0; kq < 4; ++kq)
       *reinterpret_cast<double2*>(a + 4 * kq) = make_double2(v[kq], v[4 + kq]);
     double* b = &Bs[buf][bk * LDBD + bj];
+    const double sc = bf > 0 ? bsc_p : bsc_m;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) *reinterpret_cast<double2*>(b + 2 * q) = rb[q];
+    for (int q = 0; q < 4; ++q)
+      *reinterpret_cast<double2*>(b + 2 * q) = make_double2(rb[q].x * sc, rb[q].y * sc);
   };
 
   doublex4 acc[4][4];
