@@ -259,15 +259,14 @@ struct Launcher {
   hipError_t gemm_launch(int kind, int mode, int tk, GemmArgs a) {
     const int f32 = (mode == GM_PROPB || mode == GM_PROPR) ? ctx->fp32b : ctx->fp32;
     // lattices with N >= 128: the FP32 N x N x N products (wrap, slice
-    // update) on the large-tile kernel; in FP64 the modes where the large tile
-    // measured faster than the 64 x 64 kernel (the scaled wrap and the
-    // B-scaled propagation)
+    // update) on the large-tile kernel; in FP64 the mode where the large tile
+    // measured faster than the 64 x 64 kernel (the scaled wrap)
     if (ctx->n_min >= 128) {
       const bool nnn = tk == T_NN && (mode == GM_STORE || mode == GM_WRAP || mode == GM_FLUSH);
       if (f32 && nnn)
         return launch_gemm_l(mode, ents(ctx, kind), ctx->at<TileRef>(ctx->off_tiles[T_NN_L]),
                              (int)ctx->tiles[T_NN_L].size(), a, s);
-      const bool l64 = (tk == T_NN && mode == GM_WRAP) || (tk == T_Nn && mode == GM_PROPB);
+      const bool l64 = tk == T_NN && mode == GM_WRAP;
       if (!f32 && l64) {
         const int lt = tk == T_NN ? T_NN_L : T_Nn_L;
         return launch_gemm_l64(mode, ents(ctx, kind), ctx->at<TileRef>(ctx->off_tiles[lt]),
