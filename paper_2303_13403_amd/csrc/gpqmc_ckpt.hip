@@ -585,10 +585,24 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const ChainDev* __restric
     const size_t sz = (size_t)N * C.n[sp];
     double* dst = C.stack[sp] + (size_t)slot * sz;
     Tu* u = (Tu*)C.U[sp][parity];
-    for (size_t idx = tid; idx < sz; idx += kThreads) {
-      const double q = C.Qc[sp][idx];
-      dst[idx] = q;
-      u[idx] = (Tu)q;
+    const double* __restrict__ qc = C.Qc[sp];
+    // eight coalesced loads in flight per thread, then their stores
+    constexpr int D = 8;
+    for (size_t b0 = 0; b0 < sz; b0 += (size_t)D * kThreads) {
+      double v[D];
+#pragma unroll
+      for (int e = 0; e < D; ++e) {
+        const size_t idx = b0 + (size_t)e * kThreads + tid;
+        v[e] = idx < sz ? qc[idx] : 0.0;
+      }
+#pragma unroll
+      for (int e = 0; e < D; ++e) {
+        const size_t idx = b0 + (size_t)e * kThreads + tid;
+        if (idx < sz) {
+          dst[idx] = v[e];
+          u[idx] = (Tu)v[e];
+        }
+      }
     }
   }
   if (tid == 0) {
