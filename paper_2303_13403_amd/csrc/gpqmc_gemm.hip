@@ -416,8 +416,9 @@ hipError_t launch_gemm_l(int mode, const GemmEntry* e, const TileRef* t, int n, 
 }
 
 // ---------------------------------------------------------------------------
-// Large-tile FP64 GEMM (modes STORE, WRAP, FLUSH, PROPB, PROPR): 128 x 128
-// output tile per workgroup, 64 x 64 per wave as 4 x 4 blocks of
+// Large-tile FP64 GEMM (modes STORE and WRAP; it serves the FP64 scaled wrap,
+// where it measured faster than the 64 x 64 kernel): 128 x 128 output tile per
+// workgroup, 64 x 64 per wave as 4 x 4 blocks of
 // v_mfma_f64_16x16x4f64, k-tiles of 16 double-buffered in LDS with the next
 // k-tile prefetched into registers.  A is kept in LDS with each row's k values
 // split by k mod 4 (k = 4 s + kq at [row][kq][s]), so a lane fetches the A
@@ -449,14 +450,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
   const int M = e.M, N = e.N, K = e.dynK ? *e.dynK : e.K;
   const int m0 = tr.tm * kTileL, n0 = tr.tn * kTileL;
   if (m0 >= M || n0 >= N) return;
-  const int p = args.parity;
   const double* __restrict__ A = (const double*)e.A[0];
   const double* __restrict__ B = (const double*)e.B[0];
   double* __restrict__ C = (double*)e.C[0];
-  if (MODE == GM_PROPB || MODE == GM_PROPR) {
-    B = (const double*)e.B[p];
-    C = (double*)e.C[p ^ 1];
-  }
   const int lda = e.lda, ldb = e.ldb, ldc = e.ldc;
   const bool a_al = (lda & 1) == 0, b_al = (ldb & 1) == 0;
 
@@ -465,25 +461,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
 
-  // B-row scaling by the diagonal of D_l (basis propagation A (D B))
-  const int8_t* bfield = nullptr;
-  int bbnd = 1;
-  if (MODE == GM_PROPB && args.bscale_slice >= 0) {
-    bfield = e.field + (size_t)args.bscale_slice * e.n_sites;
-    bbnd = (args.bscale_slice == 0 || args.bscale_slice == args.n_bulk_last + 1) ? 0 : 1;
-  }
-  // the two possible factors, read once; a prefetched B row carries only its
-  // field value, and the factor is applied when the row is stored to LDS
-  // (after the current tile's products), so the prefetch never waits
-  const double bsc_p = bfield ? dfac(e.dval, bbnd, 1, false) : 1.0;
-  const double bsc_m = bfield ? dfac(e.dval, bbnd, -1, false) : 1.0;
-  int8_t bf = 1;
-
-  // output scaling (frame change, or the D_l rows of a propagation): the
-  // tile's row and column factors, staged once (ordered by the first barrier)
+  // output scaling (frame change): the tile's row and column factors, staged
+  // once (ordered by the first barrier)
   const int8_t* sfield = nullptr;
   int sbnd = 1;
-  if ((MODE == GM_WRAP || MODE == GM_FLUSH || MODE == GM_PROPR) && args.scale_slice >= 0) {
+  if (MODE == GM_WRAP && args.scale_slice >= 0) {
     sfield = e.field + (size_t)args.scale_slice * e.n_sites;
     sbnd = (args.scale_slice == 0 || args.scale_slice == args.n_bulk_last + 1) ? 0 : 1;
   }
@@ -492,10 +474,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
   if (sfield) {
     if (tid < kTileL) {
       const int i = m0 + tid;
-      drow[tid] = i < M ? dfac(e.dval, sbnd, sfield[i], MODE == GM_PROPR ? false : inv) : 0.0;
+      drow[tid] = i < M ? dfac(e.dval, sbnd, sfield[i], inv) : 0.0;
     } else {
       const int j = n0 + tid - kTileL;
-      dcol[tid - kTileL] = (MODE != GM_PROPR && j < N) ? dfac(e.dval, sbnd, sfield[j], !inv) : 1.0;
+      dcol[tid - kTileL] = j < N ? dfac(e.dval, sbnd, sfield[j], !inv) : 1.0;
     }
   }
   if (nk_zero_guard(K)) __syncthreads();
@@ -512,7 +494,6 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
       ra[q] = load2(A + (size_t)i * lda + k, i < M ? K - k : 0, a_al);
     }
     const int kb = k0 + bk;
-    bf = (bfield && kb < K) ? bfield[kb] : (int8_t)1;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int j = n0 + bj + 2 * q;
@@ -527,10 +508,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     for (int kq = 0; kq < 4; ++kq)
       *reinterpret_cast<double2*>(a + 4 * kq) = make_double2(v[kq], v[4 + kq]);
     double* b = &Bs[buf][bk * LDBD + bj];
-    const double sc = bf > 0 ? bsc_p : bsc_m;
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-      *reinterpret_cast<double2*>(b + 2 * q) = make_double2(rb[q].x * sc, rb[q].y * sc);
+    for (int q = 0; q < 4; ++q) *reinterpret_cast<double2*>(b + 2 * q) = rb[q];
   };
 
   doublex4 acc[4][4];
@@ -591,12 +570,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
         const int il = wm + 16 * x + 4 * r + kq, i = m0 + il;
         if (i < M && j < N) {
           const size_t o = (size_t)i * ldc + j;
-          double v = MODE == GM_FLUSH ? ((const double*)e.C[0])[o] - acc[x][y][r] : acc[x][y][r];
+          double v = acc[x][y][r];
           if (sfield) v *= drow[il] * dj;
-          if (MODE == GM_FLUSH)
-            ((double*)e.C[1])[o] = v;
-          else
-            C[o] = v;
+          C[o] = v;
         }
         if (r == 3) __builtin_amdgcn_sched_barrier(0);   // one 16 x 16 block at a time
       }
@@ -609,9 +585,6 @@ hipError_t launch_gemm_l64(int mode, const GemmEntry* e, const TileRef* t, int n
   switch (mode) {
     case GM_STORE: hipLaunchKernelGGL(k_gemm_l64<GM_STORE>, dim3(n), dim3(kThreads), 0, s, e, t, n, a); break;
     case GM_WRAP: hipLaunchKernelGGL(k_gemm_l64<GM_WRAP>, dim3(n), dim3(kThreads), 0, s, e, t, n, a); break;
-    case GM_FLUSH: hipLaunchKernelGGL(k_gemm_l64<GM_FLUSH>, dim3(n), dim3(kThreads), 0, s, e, t, n, a); break;
-    case GM_PROPB: hipLaunchKernelGGL(k_gemm_l64<GM_PROPB>, dim3(n), dim3(kThreads), 0, s, e, t, n, a); break;
-    case GM_PROPR: hipLaunchKernelGGL(k_gemm_l64<GM_PROPR>, dim3(n), dim3(kThreads), 0, s, e, t, n, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

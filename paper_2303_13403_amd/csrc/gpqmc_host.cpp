@@ -186,8 +186,8 @@ namespace {
 
 enum EntryKind { E_WRAP1_UP = 0, E_WRAP2_UP, E_WRAP1_DN, E_WRAP2_DN, E_FLUSH, E_FLUSH_T, E_PROP,
                  E_GRAM_U, E_APPLY1, E_XMAT, E_YMAT, E_GFRESH, E_COUNT };
-// T_NN_L, T_Nn_L: 128 x 128 tiles of the large-tile kernels
-enum TileKind { T_NN = 0, T_Nn, T_nn, T_nN, T_NN_L, T_Nn_L, T_COUNT };
+// T_NN_L: 128 x 128 tiles of the large-tile kernels
+enum TileKind { T_NN = 0, T_Nn, T_nn, T_nN, T_NN_L, T_COUNT };
 static_assert(T_COUNT <= (int)(sizeof(gpqmc_ctx::off_tiles) / sizeof(size_t)), "tile kinds");
 
 gpqmc_status fail(gpqmc_ctx* c, gpqmc_status s, const std::string& msg) {
@@ -266,12 +266,9 @@ struct Launcher {
       if (f32 && nnn)
         return launch_gemm_l(mode, ents(ctx, kind), ctx->at<TileRef>(ctx->off_tiles[T_NN_L]),
                              (int)ctx->tiles[T_NN_L].size(), a, s);
-      const bool l64 = tk == T_NN && mode == GM_WRAP;
-      if (!f32 && l64) {
-        const int lt = tk == T_NN ? T_NN_L : T_Nn_L;
-        return launch_gemm_l64(mode, ents(ctx, kind), ctx->at<TileRef>(ctx->off_tiles[lt]),
-                               (int)ctx->tiles[lt].size(), a, s);
-      }
+      if (!f32 && tk == T_NN && mode == GM_WRAP)
+        return launch_gemm_l64(mode, ents(ctx, kind), ctx->at<TileRef>(ctx->off_tiles[T_NN_L]),
+                               (int)ctx->tiles[T_NN_L].size(), a, s);
     }
     return launch_gemm(f32, ctx->fp32, mode, ents(ctx, kind), ctx->at<TileRef>(ctx->off_tiles[tk]),
                        (int)ctx->tiles[tk].size(), a, s);
@@ -641,11 +638,10 @@ gpqmc_status gpqmc_create(int32_t n_chains, const gpqmc_chain_desc* chains,
       sz[T_nn].push_back({h.n[sp], h.n[sp]});
       sz[T_nN].push_back({h.n[sp], h.N});
       sz[T_NN_L].push_back({h.N, h.N});
-      sz[T_Nn_L].push_back({h.N, h.n[sp]});
     }
   }
   for (int t = 0; t < T_COUNT; ++t) {
-    build_tiles(c->tiles[t], sz[t], (t == T_NN_L || t == T_Nn_L) ? 128 : kTile);
+    build_tiles(c->tiles[t], sz[t], t == T_NN_L ? 128 : kTile);
     c->off_tiles[t] = take(sizeof(TileRef) * c->tiles[t].size());
   }
   c->bytes = align256(off);

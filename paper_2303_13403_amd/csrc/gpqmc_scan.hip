@@ -79,7 +79,7 @@ __device__ inline void lds_row_store(T* p, const T (&r)[kBlock]) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_scan(const ChainDev* __restrict__ chains,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 2 : 1))) void k_scan(const ChainDev* __restrict__ chains,
                                                    const Ctl* __restrict__ ctl, int l, int M,
                                                    int s0, int s1) {
   const ChainDev& C = chains[xcd_remap(blockIdx.x, gridDim.x)];
