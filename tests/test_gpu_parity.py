@@ -255,6 +255,44 @@ def test_trajectory_follows_oracle(prec, kw, n_sweeps):
     ctx.close()
 
 
+def rect(prec, lx, ly, n, l_half, n_s, k, U=4.0):
+    return Workload(f"{lx}x{ly} test", lx, ly, U, n, n, 0.1, l_half, 0.21, 0.6, n_s, k, prec, 10)
+
+
+# odd site counts: every row of G, X_a, Y_a and the bases is misaligned for
+# vector loads, so the append, scan and GEMM kernels take their partial paths
+ODD = [
+    ("fp64", dict(lx=3, ly=5, n=7, l_half=5, n_s=3, k=8)),
+    ("mixed", dict(lx=3, ly=5, n=7, l_half=5, n_s=3, k=8)),
+    ("fp64", dict(lx=5, ly=5, n=12, l_half=4, n_s=3, k=16)),
+    ("mixed", dict(lx=5, ly=5, n=12, l_half=4, n_s=3, k=16)),
+]
+
+
+@pytest.mark.parametrize("prec,kw", ODD)
+def test_fixed_field_pass_odd_lattice(prec, kw):
+    check_fixed_field(rect(prec, **kw), prec)
+
+
+def test_trajectory_odd_lattice_fp64():
+    w = rect("fp64", 3, 7, 10, l_half=4, n_s=3, k=8)
+    ctx = make_context([w], "fp64").init_trial()
+    indep = [oracle_chain(w, 0)]
+    follow_and_compare(ctx, [oracle_chain(w, 0)], "fp64", 4, indep)
+    assert np.array_equal(indep[0].field, ctx.get_field(0))
+    ctx.close()
+
+
+def test_mixed_batch_of_odd_and_even_lattices_follows_oracle():
+    """One context over 3x5, 4x4 and 5x5 chains (15, 16 and 25 sites)."""
+    ws = [rect("mixed", 3, 5, 7, l_half=4, n_s=3, k=8), small("mixed", L=4, l_half=4, n_s=3, k=8),
+          rect("mixed", 5, 5, 12, l_half=4, n_s=3, k=8)]
+    ctx = make_context(ws, "mixed").init_trial()
+    chains = [oracle_chain(w, c) for c, w in enumerate(ws)]
+    follow_and_compare(ctx, chains, "mixed", 3)
+    ctx.close()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_fixed_field_pass_24x24(prec):
     """The large workload (N = 576, 288 + 288 electrons, dtau = 0.05, k = 64):
