@@ -33,7 +33,7 @@ PEAK_HBM = 8.0e12           # MI355X HBM3E, B/s
 # the dominant kernel (largest share of the sweep): the large-tile MFMA GEMM of
 # the kinetic wrap and the slice update; the roofline is taken on its wrap launch
 KERNEL_SRC = os.path.join(ROOT, "paper_2303_13403_amd", "csrc", "gpqmc_gemm.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_wrap_gemm_16x16_b512.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_wrap_gemm_16x16_b2048.txt")
 
 
 def log(*a):
@@ -183,7 +183,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=6)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--chains", type=int, default=512)
+    ap.add_argument("--chains", type=int, default=2048)
     ap.add_argument("--ns", type=int, default=5)
     ap.add_argument("--k", type=int, default=32)
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64", "mixed32b"])

@@ -337,14 +337,14 @@ def test_trajectory_16x16_fp64():
 
 
 def test_bench_configuration_sampled_chains_fp64():
-    """The benchmark's launch configuration (512 chains of the 16x16 workload
+    """The benchmark's launch configuration (2048 chains of the 16x16 workload
     at l_half = 100, k = 32, n_s = 5), one FP64 sweep; two sampled chains are
     followed through the whole pass by the oracle: fields (tie band aside) and
     the measured (sign, E/N, D)."""
-    n_chains = 512
+    n_chains = 2048
     ctx = make_context([BENCH] * n_chains, "fp64", meas_capacity=4).init_trial()
     ctx.sweep(1, measure=True)
-    for c in (0, 389):
+    for c in (0, 1733):
         ch = oracle_chain(BENCH, c)
         f_gpu = ctx.get_field(c)
         bad = ch.sweep_following(f_gpu, TIE["fp64"])
