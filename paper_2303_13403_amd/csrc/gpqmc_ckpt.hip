@@ -234,7 +234,7 @@ template <int NB, int TG>
 struct RegTile {
   double m[NB][NB];
   int ti, tj, n;
-  __device__ void load(const double* __restrict__ g, int n_) {
+  __device__ void load(const GLOBAL double* __restrict__ g, int n_) {
     n = n_;
     ti = threadIdx.x / TG;
     tj = threadIdx.x % TG;
@@ -416,7 +416,7 @@ __device__ void rt_invert(RegTile<NB, TG>& T, bool triangular, double (*rk)[kRtM
 }
 
 template <int NB, int TG>
-__device__ void rt_store(const RegTile<NB, TG>& T, double* __restrict__ g, const int* colmap,
+__device__ void rt_store(const RegTile<NB, TG>& T, GLOBAL double* __restrict__ g, const int* colmap,
                          bool upper_only) {
   // destination columns, read once per register column
   int cd[NB];
@@ -458,7 +458,7 @@ __global__ __launch_bounds__(TG * TG) void k_chol_inv_rt(const ChainDev* __restr
   GPQMC_RT_SHARED
   rt_clear(rk, rp, ck);
   RegTile<NB, TG> T;
-  T.load(C.Wm[sp], n);
+  T.load(gp(C.Wm[sp]), n);
   double lsum = 0.0;
   bool bad = false;
   for (int j = 0; j < n; ++j) {
@@ -527,7 +527,7 @@ __global__ __launch_bounds__(TG * TG) void k_chol_inv_rt(const ChainDev* __restr
   __syncthreads();
   rt_invert<NB, TG>(T, true, rk, rp, ck, cv, ci, piv, colmap, la, sg);
   if (sg != 0)
-    rt_store<NB, TG>(T, C.Rinv[sp], colmap, true);
+    rt_store<NB, TG>(T, gp(C.Rinv[sp]), colmap, true);
   else if (tid == 0)
     atomicOr(&C.st->flags, (int)FLAG_SINGULAR);
 }
@@ -542,11 +542,11 @@ __global__ __launch_bounds__(TG * TG) void k_gj_inv_rt(const ChainDev* __restric
   GPQMC_RT_SHARED
   rt_clear(rk, rp, ck);
   RegTile<NB, TG> T;
-  T.load(C.Xm[sp], n);
+  T.load(gp(C.Xm[sp]), n);
   double logabs;
   int sgn;
   rt_invert<NB, TG>(T, false, rk, rp, ck, cv, ci, piv, colmap, logabs, sgn);
-  if (sgn != 0) rt_store<NB, TG>(T, C.Xm[sp], colmap, false);
+  if (sgn != 0) rt_store<NB, TG>(T, gp(C.Xm[sp]), colmap, false);
   if (tid == 0) {
     C.st->x_log[sp] = logabs;
     C.st->x_sgn[sp] = sgn;
@@ -583,9 +583,9 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const ChainDev* __restric
   __shared__ double red[4];
   for (int sp = 0; sp < 2; ++sp) {
     const size_t sz = (size_t)N * C.n[sp];
-    double* dst = C.stack[sp] + (size_t)slot * sz;
-    Tu* u = (Tu*)C.U[sp][parity];
-    const double* __restrict__ qc = C.Qc[sp];
+    GLOBAL double* dst = gp(C.stack[sp] + (size_t)slot * sz);
+    GLOBAL Tu* u = gp((Tu*)C.U[sp][parity]);
+    const GLOBAL double* __restrict__ qc = gp((const double*)C.Qc[sp]);
     // eight coalesced loads in flight per thread, then their stores
     constexpr int D = 8;
     for (size_t b0 = 0; b0 < sz; b0 += (size_t)D * kThreads) {

@@ -11,6 +11,31 @@ namespace gpqmc {
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
+// Pointers into device memory typed in the global address space.  The buffers
+// reach the kernels through descriptor structs, so the compiler cannot tell
+// that they are not LDS and would emit flat loads; those count on the LDS
+// counter too, and every wait for an LDS read would then also wait for the
+// global loads in flight (the prefetch of the next k-tile).  Reads and writes
+// through a GLOBAL pointer are global_load / global_store.
+#define GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ GLOBAL T* gp(T* p) {
+  return (GLOBAL T*)p;
+}
+
+// 16-byte vector loads through a GLOBAL pointer (as builtin vector types: the
+// float4 / double2 classes have no constructor from a global-space lvalue)
+__device__ __forceinline__ float4 gload4(const GLOBAL float* p) {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  const v4 v = *(const GLOBAL v4*)p;
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ double2 gload2(const GLOBAL double* p) {
+  typedef double v2 __attribute__((ext_vector_type(2)));
+  const v2 v = *(const GLOBAL v2*)p;
+  return make_double2(v.x, v.y);
+}
+
 constexpr int BK = 16;        // GEMM k-tile
 constexpr int LDS_PAD = 4;    // LDS row padding of the GEMM tiles (elements)
 

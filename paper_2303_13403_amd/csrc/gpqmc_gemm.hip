@@ -27,28 +27,28 @@ __global__ __launch_bounds__(kThreads) void k_gemm(const GemmEntry* __restrict__
   if (m0 >= M || n0 >= N) return;
 
   const int p = args.parity;
-  const T* A = (const T*)e.A[0];
-  const T* B = (const T*)e.B[0];
-  T* C = (T*)e.C[0];
+  const GLOBAL T* A = gp((const T*)e.A[0]);
+  const GLOBAL T* B = gp((const T*)e.B[0]);
+  GLOBAL T* C = gp((T*)e.C[0]);
   if (MODE == GM_PROPB || MODE == GM_PROPR) {
-    B = (const T*)e.B[p];
-    C = (T*)e.C[p ^ 1];
+    B = gp((const T*)e.B[p]);
+    C = gp((T*)e.C[p ^ 1]);
   } else if (MODE == GM_GRAM) {
-    A = (const T*)e.A[p];
+    A = gp((const T*)e.A[p]);
     B = A;
   } else if (MODE == GM_APPLY) {
-    A = (const T*)e.A[p];
+    A = gp((const T*)e.A[p]);
   } else if (MODE == GM_XMAT || MODE == GM_YMAT || MODE == GM_GFRESH) {
     const double* slotp = e.stack + (size_t)args.slot * e.slot_stride;
     const double* R = args.dir == 0 ? e.Qc : slotp;
     const double* Lt = args.dir == 0 ? slotp : e.Qc;
     if (MODE == GM_XMAT) {
-      A = (const T*)Lt;
-      B = (const T*)R;
+      A = gp((const T*)Lt);
+      B = gp((const T*)R);
     } else if (MODE == GM_YMAT) {
-      B = (const T*)Lt;
+      B = gp((const T*)Lt);
     } else {
-      A = (const T*)R;
+      A = gp((const T*)R);
     }
   }
   const int lda = e.lda, ldb = e.ldb, ldc = e.ldc;
@@ -61,10 +61,10 @@ __global__ __launch_bounds__(kThreads) void k_gemm(const GemmEntry* __restrict__
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
 
   // B-row scaling by the diagonal of D_l (basis propagation A (D B))
-  const int8_t* bfield = nullptr;
+  const GLOBAL int8_t* bfield = nullptr;
   int bbnd = 1;
   if (MODE == GM_PROPB && args.bscale_slice >= 0) {
-    bfield = e.field + (size_t)args.bscale_slice * e.n_sites;
+    bfield = gp(e.field + (size_t)args.bscale_slice * e.n_sites);
     bbnd = (args.bscale_slice == 0 || args.bscale_slice == args.n_bulk_last + 1) ? 0 : 1;
   }
 
@@ -140,10 +140,10 @@ __global__ __launch_bounds__(kThreads) void k_gemm(const GemmEntry* __restrict__
   }
 
   // ---- epilogue ----
-  const int8_t* sfield = nullptr;
+  const GLOBAL int8_t* sfield = nullptr;
   int sbnd = 1;
   if (args.scale_slice >= 0) {
-    sfield = e.field + (size_t)args.scale_slice * e.n_sites;
+    sfield = gp(e.field + (size_t)args.scale_slice * e.n_sites);
     sbnd = (args.scale_slice == 0 || args.scale_slice == args.n_bulk_last + 1) ? 0 : 1;
   }
   const bool inv = args.scale_inverse != 0;
@@ -153,7 +153,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm(const GemmEntry* __restrict__
   Tb prev[16];
   int ix = 0;
   if (MODE == GM_GFRESH && args.check_drift) {
-    const Tb* Cb = (const Tb*)e.C[1];
+    const GLOBAL Tb* Cb = gp((const Tb*)e.C[1]);
     wt.each(wm, wn, lane, [&](int li, int lj, T) {
       const int i = m0 + li, j = n0 + lj;
       prev[ix++] = (i < M && j < N) ? Cb[(size_t)i * e.ldc2 + j] : Tb(0);
@@ -170,17 +170,17 @@ __global__ __launch_bounds__(kThreads) void k_gemm(const GemmEntry* __restrict__
       if (sfield) v *= (T)dfac(e.dval, sbnd, sfield[i], false);
       C[o] = v;
     } else if (MODE == GM_WRAP || MODE == GM_FLUSH) {
-      T v = (MODE == GM_FLUSH) ? ((const T*)e.C[0])[o] - acc : acc;
+      T v = (MODE == GM_FLUSH) ? gp((const T*)e.C[0])[o] - acc : acc;
       if (sfield)
         v *= (T)(dfac(e.dval, sbnd, sfield[i], inv) * dfac(e.dval, sbnd, sfield[j], !inv));
       if (MODE == GM_FLUSH)
-        ((T*)e.C[1])[o] = v;
+        gp((T*)e.C[1])[o] = v;
       else
         C[o] = v;
     } else if (MODE == GM_GFRESH) {
       const double g = (i == j ? 1.0 : 0.0) - (double)acc;
       C[o] = (T)g;
-      Tb* Cb = (Tb*)e.C[1];
+      GLOBAL Tb* Cb = gp((Tb*)e.C[1]);
       const size_t o2 = (size_t)i * e.ldc2 + j;
       if (args.check_drift) {
         const float d = (float)fabs((double)prev[k] - g);
@@ -226,8 +226,8 @@ constexpr int kTileL = 128, BKL = 16;
 constexpr int LDAL = BKL + 4;        // A tile row: BKL / 2 even-k, BKL / 2 odd-k, 4 pad
 constexpr int LDBL = kTileL + 4;     // B tile row
 
-__device__ inline float4 load4(const float* __restrict__ p, int valid, bool aligned) {
-  if (aligned && valid >= 4) return *reinterpret_cast<const float4*>(p);
+__device__ inline float4 load4(const GLOBAL float* __restrict__ p, int valid, bool aligned) {
+  if (aligned && valid >= 4) return gload4(p);
   float4 v;
   v.x = valid > 0 ? p[0] : 0.f;
   v.y = valid > 1 ? p[1] : 0.f;
@@ -247,11 +247,14 @@ __global__ __launch_bounds__(kThreads) void k_gemm_l(const GemmEntry* __restrict
   const int M = e.M, N = e.N, K = e.dynK ? *e.dynK : e.K;
   const int m0 = tr.tm * kTileL, n0 = tr.tn * kTileL;
   if (m0 >= M || n0 >= N) return;
-  const float* __restrict__ A = (const float*)e.A[0];
-  const float* __restrict__ B = (const float*)e.B[0];
-  float* __restrict__ C = (float*)e.C[0];
+  const GLOBAL float* __restrict__ A = gp((const float*)e.A[0]);
+  const GLOBAL float* __restrict__ B = gp((const float*)e.B[0]);
+  GLOBAL float* __restrict__ C = gp((float*)e.C[0]);
   const int lda = e.lda, ldb = e.ldb, ldc = e.ldc;
   const bool a_al = (lda & 3) == 0, b_al = (ldb & 3) == 0;
+  // a tile inside the matrices with aligned rows loads its whole k-tiles
+  // without bounds checks
+  const bool interior = a_al && b_al && m0 + kTileL <= M && n0 + kTileL <= N;
 
   __shared__ __align__(16) float As[2][kTileL * LDAL];
   __shared__ __align__(16) float Bs[2][BKL * LDBL];
@@ -266,13 +269,20 @@ __global__ __launch_bounds__(kThreads) void k_gemm_l(const GemmEntry* __restrict
   const int bk = tid / TPR, bj = (tid % TPR) * (BKL / 2);
   float4 ra[NQ], rb[NQ];
   auto gload = [&](int k0) {
-    const int i = m0 + am;
+    const int i = m0 + am, kb = k0 + bk;
+    if (interior && k0 + BKL <= K) {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        ra[q] = gload4(A + (size_t)i * lda + k0 + ak + 4 * q);
+        rb[q] = gload4(B + (size_t)kb * ldb + n0 + bj + 4 * q);
+      }
+      return;
+    }
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const int k = k0 + ak + 4 * q;
       ra[q] = load4(A + (size_t)i * lda + k, i < M ? K - k : 0, a_al);
     }
-    const int kb = k0 + bk;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const int j = n0 + bj + 4 * q;
@@ -307,7 +317,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_l(const GemmEntry* __restrict
   // k-loop so that their latency overlaps it
   float cold[2][2][16];
   if (MODE == GM_FLUSH) {
-    const float* __restrict__ C0 = (const float*)e.C[0];
+    const GLOBAL float* __restrict__ C0 = gp((const float*)e.C[0]);
 #pragma unroll
     for (int y = 0; y < 2; ++y) {
       const int j = n0 + wn + 32 * y + l32;
@@ -358,10 +368,10 @@ __global__ __launch_bounds__(kThreads) void k_gemm_l(const GemmEntry* __restrict
 
   // epilogue: element (i, j) of a 32 x 32 block lives in lane j + 32 ((i / 4) % 2),
   // register (i % 4) + 4 (i / 8)
-  const int8_t* sfield = nullptr;
+  const GLOBAL int8_t* sfield = nullptr;
   int sbnd = 1;
   if ((MODE == GM_WRAP || MODE == GM_FLUSH) && args.scale_slice >= 0) {
-    sfield = e.field + (size_t)args.scale_slice * e.n_sites;
+    sfield = gp(e.field + (size_t)args.scale_slice * e.n_sites);
     sbnd = (args.scale_slice == 0 || args.scale_slice == args.n_bulk_last + 1) ? 0 : 1;
   }
   const bool inv = args.scale_inverse != 0;
@@ -393,7 +403,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_l(const GemmEntry* __restrict
           float v = MODE == GM_FLUSH ? cold[x][y][r] - acc[x][y][r] : acc[x][y][r];
           if (sfield) v *= drow[il] * dj;
           if (MODE == GM_FLUSH)
-            ((float*)e.C[1])[o] = v;
+            gp((float*)e.C[1])[o] = v;
           else
             C[o] = v;
         }
@@ -431,8 +441,8 @@ __device__ inline bool nk_zero_guard(int K) { return K <= 0; }
 constexpr int LDAD = BKD + 2;        // A tile row: 4 groups of 4 (k mod 4), 2 pad
 constexpr int LDBD = kTileL + 2;     // B tile row
 
-__device__ inline double2 load2(const double* __restrict__ p, int valid, bool aligned) {
-  if (aligned && valid >= 2) return *reinterpret_cast<const double2*>(p);
+__device__ inline double2 load2(const GLOBAL double* __restrict__ p, int valid, bool aligned) {
+  if (aligned && valid >= 2) return gload2(p);
   double2 v;
   v.x = valid > 0 ? p[0] : 0.0;
   v.y = valid > 1 ? p[1] : 0.0;
@@ -450,11 +460,14 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
   const int M = e.M, N = e.N, K = e.dynK ? *e.dynK : e.K;
   const int m0 = tr.tm * kTileL, n0 = tr.tn * kTileL;
   if (m0 >= M || n0 >= N) return;
-  const double* __restrict__ A = (const double*)e.A[0];
-  const double* __restrict__ B = (const double*)e.B[0];
-  double* __restrict__ C = (double*)e.C[0];
+  const GLOBAL double* __restrict__ A = gp((const double*)e.A[0]);
+  const GLOBAL double* __restrict__ B = gp((const double*)e.B[0]);
+  GLOBAL double* __restrict__ C = gp((double*)e.C[0]);
   const int lda = e.lda, ldb = e.ldb, ldc = e.ldc;
   const bool a_al = (lda & 1) == 0, b_al = (ldb & 1) == 0;
+  // a tile inside the matrices with aligned rows loads its whole k-tiles
+  // without bounds checks
+  const bool interior = a_al && b_al && m0 + kTileL <= M && n0 + kTileL <= N;
 
   __shared__ __align__(16) double As[2][kTileL * LDAD];
   __shared__ __align__(16) double Bs[2][BKD * LDBD];
@@ -463,10 +476,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
 
   // output scaling (frame change): the tile's row and column factors, staged
   // once (ordered by the first barrier)
-  const int8_t* sfield = nullptr;
+  const GLOBAL int8_t* sfield = nullptr;
   int sbnd = 1;
   if (MODE == GM_WRAP && args.scale_slice >= 0) {
-    sfield = e.field + (size_t)args.scale_slice * e.n_sites;
+    sfield = gp(e.field + (size_t)args.scale_slice * e.n_sites);
     sbnd = (args.scale_slice == 0 || args.scale_slice == args.n_bulk_last + 1) ? 0 : 1;
   }
   const bool inv = args.scale_inverse != 0;
@@ -488,12 +501,20 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
   double2 ra[4], rb[4];
   auto gload = [&](int k0) {
     const int i = m0 + am;
+    const int kb = k0 + bk;
+    if (interior && k0 + BKD <= K) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        ra[q] = gload2(A + (size_t)i * lda + k0 + ak + 2 * q);
+        rb[q] = gload2(B + (size_t)kb * ldb + n0 + bj + 2 * q);
+      }
+      return;
+    }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int k = k0 + ak + 2 * q;
       ra[q] = load2(A + (size_t)i * lda + k, i < M ? K - k : 0, a_al);
     }
-    const int kb = k0 + bk;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int j = n0 + bj + 2 * q;

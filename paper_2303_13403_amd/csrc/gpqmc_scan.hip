@@ -135,10 +135,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof
   const double dl_u0 = C.delta[bnd][0][0], dl_u1 = C.delta[bnd][0][1];
   const double dl_d0 = C.delta[bnd][1][0], dl_d1 = C.delta[bnd][1][1];
   double* const trace_ratio = C.trace_ratio;
-  T* Z[2] = {(T*)C.Z[0], (T*)C.Z[1]};
-  T *W1[2], *Pm[2], *Qm[2], *PZ[2], *ZQ[2];
+  GLOBAL T* Z[2] = {gp((T*)C.Z[0]), gp((T*)C.Z[1])};
+  GLOBAL T *W1[2], *Pm[2], *Qm[2], *PZ[2], *ZQ[2];
   for (int s = 0; s < 2; ++s) {
-    T* w = (T*)C.scan_ws[s];
+    GLOBAL T* w = gp((T*)C.scan_ws[s]);
     const size_t blk = (size_t)kBlock * kSegMax;
     W1[s] = w;            // kb x f       (ld LDZ)
     Pm[s] = w + blk;      // f x fb       (ld kBlock)
@@ -156,9 +156,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof
     // read as one contiguous 128-byte segment: A = Xa[S, k] (in Rsf) and
     // B = Ya[k, S] (in the Hs area), both [spin][32][KL]
     const int s = tid >> 7, t = tid & 127, c = t & 31, rb = t >> 5;
-    const T* __restrict__ g0 = (const T*)C.G[s];
-    const T* __restrict__ xa = (const T*)C.Xa[s];
-    const T* __restrict__ ya = (const T*)C.Ya[s];
+    const GLOBAL T* __restrict__ g0 = gp((const T*)C.G[s]);
+    const GLOBAL T* __restrict__ xa = gp((const T*)C.Xa[s]);
+    const GLOBAL T* __restrict__ ya = gp((const T*)C.Ya[s]);
     T* As = Rsf + s * kBlock * KL;
     T* Bs = &Hs[s][0][0];
     static_assert(2 * kBlock * KL <= kSegMax * 36, "A tiles fit in Rsf");
@@ -212,9 +212,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof
     static_assert(32 * LB <= 2 * kBlock * (kBlock + 2), "B tile fits in Hs");
     const int c = lane;
     for (int s = 0; s < 2; ++s) {
-      const T* __restrict__ g0 = (const T*)C.G[s];
-      const T* __restrict__ xa = (const T*)C.Xa[s];
-      const T* __restrict__ ya = (const T*)C.Ya[s];
+      const GLOBAL T* __restrict__ g0 = gp((const T*)C.G[s]);
+      const GLOBAL T* __restrict__ xa = gp((const T*)C.Xa[s]);
+      const GLOBAL T* __restrict__ ya = gp((const T*)C.Ya[s]);
       T acc[kSegMax / 4];
 #pragma unroll
       for (int m = 0; m < kSegMax / 4; ++m) {
@@ -521,7 +521,7 @@ __attribute__((amdgpu_waves_per_eu(XyShape<T, FMAX>::WAVES))) void k_xy(const Ch
   __shared__ __align__(16) T At[AS];
   __shared__ __align__(16) T Bt[BK * LB];
   __shared__ T Zl[FMAX][FMAX + 1];
-  for (int q = tid; q < FMAX; q += kThreads) Fl[q] = q < f ? C.flist[q] : 0;
+  for (int q = tid; q < FMAX; q += kThreads) Fl[q] = q < f ? gp(C.flist)[q] : 0;
   __syncthreads();
 
   // register block: rows / columns u0 .. u0 + RPT - 1, q = 4 g + 32 qb + v
@@ -756,8 +756,8 @@ struct XyMfmaShape {
   static constexpr int WAVES = FMAX == 32 ? 6 : 2;       // per SIMD (a 16-byte spill at 6 measured faster than 5)
 };
 
-__device__ inline float4 xy_load4(const float* __restrict__ p, int valid, bool aligned) {
-  if (aligned && valid >= 4) return *reinterpret_cast<const float4*>(p);
+__device__ inline float4 xy_load4(const GLOBAL float* __restrict__ p, int valid, bool aligned) {
+  if (aligned && valid >= 4) return gload4(p);
   float4 v;
   v.x = valid > 0 ? p[0] : 0.f;
   v.y = valid > 1 ? p[1] : 0.f;
@@ -784,16 +784,16 @@ void k_xy_mfma(const ChainDev* __restrict__ chains, int nrb, int s0, int kseg) {
   if (r0 >= N) return;
   const int f = C.st->fcount, fp = C.st->foff;
   if (f == 0) return;
-  const float* __restrict__ G = (const float*)C.G[spin];
-  float* __restrict__ Xa = (float*)C.Xa[spin];
-  float* __restrict__ Ya = (float*)C.Ya[spin];
+  const GLOBAL float* __restrict__ G = gp((const float*)C.G[spin]);
+  GLOBAL float* __restrict__ Xa = gp((float*)C.Xa[spin]);
+  GLOBAL float* __restrict__ Ya = gp((float*)C.Ya[spin]);
   const bool al = (N & 3) == 0;
 
   __shared__ int Fl[FMAX];
   __shared__ __align__(16) float U[S::UNION];            // wide tile, then G0 slab / P
   __shared__ __align__(16) float Sm[BK * LS];            // narrow tile
   __shared__ float Zl[FMAX * LP];
-  for (int q = tid; q < FMAX; q += kThreads) Fl[q] = q < f ? C.flist[q] : 0;
+  for (int q = tid; q < FMAX; q += kThreads) Fl[q] = q < f ? gp(C.flist)[q] : 0;
   __syncthreads();
 
   const int h = lane >> 5, l32 = lane & 31, w0 = wave * (ROWS / 4);
@@ -931,7 +931,7 @@ void k_xy_mfma(const ChainDev* __restrict__ chains, int nrb, int s0, int kseg) {
   // X part: the segment's slab S1[r][c] = G0[r0 + r, s0 + c] and Z, then
   // P = G0[:, F] - C, then Xa[:, fp + c] = P Z
   float* S1 = U;
-  const float* __restrict__ Z = (const float*)C.Z[spin];
+  const GLOBAL float* __restrict__ Z = gp((const float*)C.Z[spin]);
   for (int e = tid; e < FMAX * FMAX; e += kThreads) {
     const int q = e / FMAX, c = e % FMAX;
     Zl[q * LP + c] = (q < f && c < f) ? Z[(size_t)q * kSegMax + c] : 0.f;
@@ -1009,8 +1009,8 @@ constexpr int kXy64Rows = 64, kXy64Bk = 16, kXy64La = kXy64Rows + 2, kXy64Ls = 3
 constexpr int kXy64Union = kXy64Bk * kXy64La > kXy64Rows * kXy64Lp ? kXy64Bk * kXy64La
                                                                    : kXy64Rows * kXy64Lp;
 
-__device__ inline double2 xy_load2(const double* __restrict__ p, int valid, bool aligned) {
-  if (aligned && valid >= 2) return *reinterpret_cast<const double2*>(p);
+__device__ inline double2 xy_load2(const GLOBAL double* __restrict__ p, int valid, bool aligned) {
+  if (aligned && valid >= 2) return gload2(p);
   double2 v;
   v.x = valid > 0 ? p[0] : 0.0;
   v.y = valid > 1 ? p[1] : 0.0;
@@ -1032,16 +1032,16 @@ __global__ __launch_bounds__(kThreads) void k_xy_mfma64(const ChainDev* __restri
   if (r0 >= N) return;
   const int f = C.st->fcount, fp = C.st->foff;
   if (f == 0) return;
-  const double* __restrict__ G = (const double*)C.G[spin];
-  double* __restrict__ Xa = (double*)C.Xa[spin];
-  double* __restrict__ Ya = (double*)C.Ya[spin];
+  const GLOBAL double* __restrict__ G = gp((const double*)C.G[spin]);
+  GLOBAL double* __restrict__ Xa = gp((double*)C.Xa[spin]);
+  GLOBAL double* __restrict__ Ya = gp((double*)C.Ya[spin]);
   const bool al = (N & 1) == 0;
 
   __shared__ int Fl[FMAX];
   __shared__ __align__(16) double U[kXy64Union];         // wide tile, then G0 slab / P
   __shared__ __align__(16) double Sm[BK * LS];           // narrow tile
   __shared__ double Zl[FMAX * LP];
-  for (int q = tid; q < FMAX; q += kThreads) Fl[q] = q < f ? C.flist[q] : 0;
+  for (int q = tid; q < FMAX; q += kThreads) Fl[q] = q < f ? gp(C.flist)[q] : 0;
   __syncthreads();
 
   constexpr int XB = ROWS / 64;                          // 16-row blocks per wave
@@ -1163,7 +1163,7 @@ __global__ __launch_bounds__(kThreads) void k_xy_mfma64(const ChainDev* __restri
 
   // X part: slab S1[r][c] = G0[r0 + r, s0 + c], P = G0[:, F] - C, Xa[:, fp + c] = P Z
   double* S1 = U;
-  const double* __restrict__ Z = (const double*)C.Z[spin];
+  const GLOBAL double* __restrict__ Z = gp((const double*)C.Z[spin]);
   for (int e = tid; e < FMAX * FMAX; e += kThreads) {
     const int q = e / FMAX, c = e % FMAX;
     Zl[q * LP + c] = (q < f && c < f) ? Z[(size_t)q * kSegMax + c] : 0.0;
