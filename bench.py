@@ -45,9 +45,9 @@ def kernel_sha() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def read_traffic(chains: int, precision: str):
+def read_traffic(chains_per_launch: int, precision: str):
     """HBM bytes per launch of the wrap GEMM from the committed PMC summary, if
-    it was taken on the current kernel source, batch size and precision."""
+    it was taken on the current kernel source, launch size and precision."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     kv = {}
@@ -55,7 +55,8 @@ def read_traffic(chains: int, precision: str):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    if (kv.get("kernel_source_sha") != kernel_sha() or int(kv.get("chains", -1)) != chains
+    if (kv.get("kernel_source_sha") != kernel_sha()
+            or int(kv.get("chains_per_launch", -1)) != chains_per_launch
             or kv.get("precision") != precision):
         return None
     return float(kv["hbm_bytes_per_launch"])
@@ -68,48 +69,92 @@ def workload(args, ns=None):
                                       delay_rank=args.k)
 
 
+def weighted_mean(rec, which):
+    """<s O>/<s> over measurement records (rows: sign, E/N, D/N) with a
+    delete-one-bin jackknife over bins of 10 records (which = 0: the sign
+    itself, binned mean); the estimator the library applies to one context."""
+    import numpy as np
+
+    nb = len(rec) // 10
+    if nb < 2:
+        return None
+    r = rec[: nb * 10].reshape(nb, 10, 3)
+    s = r[:, :, 0].mean(axis=1)
+    if which == 0:
+        return float(s.mean()), float(s.std(ddof=1) / np.sqrt(nb))
+    so = (r[:, :, 0] * r[:, :, which]).mean(axis=1)
+    S, SO = s.sum(), so.sum()
+    jk = (SO - so) / (S - s)
+    return float(SO / S), float(np.sqrt((nb - 1) / nb * ((jk - jk.mean()) ** 2).sum()))
+
+
 def run_gpu(args, precision_name, steps, warmup, ns=None):
+    """Time `steps` sweeps of every chain.  The chains are split into
+    args.groups contiguous groups, one context (and HIP stream) each, swept
+    concurrently: the latency-bound scan and append launches of one group
+    overlap the MFMA GEMMs of another."""
+    import numpy as np
     import torch
 
     from paper_2303_13403_amd import gpqmc
 
     prec = {"mixed": gpqmc.MIXED, "fp64": gpqmc.FP64, "mixed32b": gpqmc.MIXED_FP32_BASIS}[precision_name]
     w = workload(args, ns)
+    G = args.groups
+    if G < 1 or args.chains % G:
+        raise SystemExit(f"--groups {G} must divide --chains {args.chains}")
+    per = args.chains // G
     t0 = time.time()
-    chains = [gpqmc.chain_desc_arrays(w, c, prec) for c in range(args.chains)]
-    ctx = gpqmc.Context(chains, device="cuda:0", meas_capacity=max(64, steps + warmup + 4))
-    ctx.init_trial()
-    log(f"[{precision_name}] context + init_trial: {time.time() - t0:.1f} s, "
-        f"workspace {ctx.workspace_bytes / 2**30:.2f} GiB")
-    ctx.sweep(warmup, measure=True)
-    ctx.synchronize()
+    ctxs = []
+    for g in range(G):
+        chains = [gpqmc.chain_desc_arrays(w, g * per + c, prec) for c in range(per)]
+        ctxs.append(gpqmc.Context(chains, device="cuda:0", meas_capacity=max(64, steps + warmup + 4)))
+    for ctx in ctxs:
+        ctx.init_trial()
+    log(f"[{precision_name}] {G} contexts + init_trial: {time.time() - t0:.1f} s, "
+        f"workspace {sum(c.workspace_bytes for c in ctxs) / 2**30:.2f} GiB")
+    for ctx in ctxs:
+        ctx.sweep(warmup, measure=True)
+    torch.cuda.synchronize()
     log(f"[{precision_name}] warmup {warmup} sweeps done")
-    acc0 = sum(ctx.chain_info(c)["accepted"] for c in range(args.chains))
-    prop0 = sum(ctx.chain_info(c)["proposed"] for c in range(args.chains))
+
+    def all_infos():
+        return [ctx.chain_info(c) for ctx in ctxs for c in range(per)]
+
+    infos0 = all_infos()
+    acc0 = sum(i["accepted"] for i in infos0)
+    prop0 = sum(i["proposed"] for i in infos0)
     ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
+    ev1 = [torch.cuda.Event(enable_timing=True) for _ in ctxs]
     # HIP events around every launch of the wrap, propagation and slice-update
-    # GEMMs inside the timed sweeps (on the context's stream)
-    ctx.set_kernel_timing(7)
+    # GEMMs inside the timed sweeps (on each context's stream)
+    for ctx in ctxs:
+        ctx.set_kernel_timing(7)
     torch.cuda.synchronize()
-    ev0.record(ctx.stream)
-    w0 = time.time()
-    ctx.sweep(steps, measure=True)
-    ev1.record(ctx.stream)
-    torch.cuda.synchronize()
-    wall = time.time() - w0
-    ms = ev0.elapsed_time(ev1)
-    kt = [ctx.kernel_timing(k) for k in range(3)]
-    ctx.set_kernel_timing(0)
-    infos = [ctx.chain_info(c) for c in range(args.chains)]
-    graph_ms = None
-    if args.graph_check:
+
+    def timed(n):
         torch.cuda.synchronize()
-        ev0.record(ctx.stream)
-        ctx.sweep(steps, measure=True)
-        ev1.record(ctx.stream)
+        ev0.record(ctxs[0].stream)
+        for ctx in ctxs[1:]:
+            ctx.stream.wait_event(ev0)
+        w0 = time.time()
+        for _ in range(n):                 # one sweep of every group at a time
+            for ctx in ctxs:
+                ctx.sweep(1, measure=True)
+        for ctx, e in zip(ctxs, ev1):
+            e.record(ctx.stream)
         torch.cuda.synchronize()
-        graph_ms = ev0.elapsed_time(ev1)
+        return max(ev0.elapsed_time(e) for e in ev1), time.time() - w0
+
+    ms, wall = timed(steps)
+    kt = []
+    for k in range(3):
+        parts = [ctx.kernel_timing(k) for ctx in ctxs]
+        kt.append((sum(t for t, _ in parts), sum(n for _, n in parts)))
+    for ctx in ctxs:
+        ctx.set_kernel_timing(0)
+    infos = all_infos()
+    graph_ms = timed(steps)[0] if args.graph_check else None
     acc = sum(i["accepted"] for i in infos) - acc0
     prop = sum(i["proposed"] for i in infos) - prop0
     n_updates = (2 * w.l_half + 2) * w.n_sites * args.chains * steps
@@ -117,6 +162,10 @@ def run_gpu(args, precision_name, steps, warmup, ns=None):
     wrap_ms, prop_ms, flush_ms = (t / max(n, 1) for t, n in kt)
     launches = {"wrap": kt[0][1], "prop": kt[1][1], "slice_update": kt[2][1]}
     rel = sorted(i["max_rel_drift"] for i in infos)
+    energy = sign = None
+    if args.chains * (steps + warmup) >= 20:
+        rec = np.concatenate([ctx.measurements(c) for ctx in ctxs for c in range(per)])
+        energy, sign = weighted_mean(rec, 1), weighted_mean(rec, 0)
     res = dict(ms=ms, wall=wall, updates=n_updates, accept=acc / max(prop, 1),
                max_drift=max(i["max_drift"] for i in infos),
                rel_drift={"max": rel[-1], "median": rel[len(rel) // 2],
@@ -125,16 +174,15 @@ def run_gpu(args, precision_name, steps, warmup, ns=None):
                flags=sorted({i["flags"] for i in infos}),
                sign_mismatch=sum(i["sign_mismatch"] for i in infos),
                wrap_ms=wrap_ms, prop_ms=prop_ms, flush_ms=flush_ms, launches=launches,
-               graph_ms=graph_ms,
-               sign=ctx.measure_sign(-1) if args.chains * (steps + warmup) >= 20 else None,
-               energy=ctx.measure_energy(-1) if args.chains * (steps + warmup) >= 20 else None)
+               graph_ms=graph_ms, sign=sign, energy=energy)
     log(f"[{precision_name}] {steps} sweeps: {ms:.1f} ms (wall {wall * 1e3:.1f} ms), "
         f"{n_updates / (ms / 1e3):.4g} updates/s, acceptance {res['accept']:.3f}, "
         f"slice update {flush_ms:.3f} ms/launch, wrap GEMM {wrap_ms:.3f} ms/launch, "
         f"max drift {res['max_drift']:.2e}, relative drift over chains {res['rel_drift']}, "
         f"flags {res['flags']}")
-    ctx.close()
-    del ctx
+    for ctx in ctxs:
+        ctx.close()
+    del ctxs
     torch.cuda.empty_cache()
     return res
 
@@ -184,6 +232,9 @@ def main():
     ap.add_argument("--steps", type=int, default=6)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--chains", type=int, default=2048)
+    ap.add_argument("--groups", type=int, default=1,
+                    help="chain groups, one context and HIP stream each, swept concurrently "
+                         "(the roofline kernel's launches then overlap other groups' work)")
     ap.add_argument("--ns", type=int, default=5)
     ap.add_argument("--k", type=int, default=32)
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64", "mixed32b"])
@@ -233,11 +284,12 @@ def main():
 
     value = main_res["updates"] / (main_res["ms"] / 1e3)
     # dominant kernel: the kinetic-wrap GEMM Gtmp = e^{-dtau K} G, MFMA-bound;
-    # algorithmic flops per launch = every chain x 2 spins x 2 N^3
-    wrap_flops = 2.0 * args.chains * 2.0 * N ** 3
+    # algorithmic flops per launch = every chain of the group x 2 spins x 2 N^3
+    per_launch = args.chains // args.groups
+    wrap_flops = 2.0 * per_launch * 2.0 * N ** 3
     peak = PEAK_FP32_MFMA if args.precision != "fp64" else PEAK_FP64_MFMA
     achieved = wrap_flops / (main_res["wrap_ms"] / 1e3)
-    traffic = read_traffic(args.chains, args.precision)
+    traffic = read_traffic(per_launch, args.precision)
     out = {
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup,
@@ -249,7 +301,8 @@ def main():
             "workload": f"16x16 periodic Hubbard, U=3.5, 112+112 electrons, dtau=0.1, "
                         f"Theta=10 (l_half=100, {M + 2} slices), Neel M_N=0.07 + Gutzwiller "
                         f"g=0.55, batch of {args.chains} chains",
-            "chains": args.chains, "precision": args.precision, "stab_interval": args.ns,
+            "chains": args.chains, "chain_groups": args.groups,
+            "precision": args.precision, "stab_interval": args.ns,
             "delay_rank": args.k, "acceptance": round(main_res["accept"], 4),
             "max_drift": main_res["max_drift"], "rel_drift": main_res["rel_drift"],
             "flags": main_res["flags"], "energy_per_site": main_res["energy"],
@@ -257,15 +310,19 @@ def main():
         },
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
-                     "kernel": "k_gemm_l STORE (e^{-dtau K} G, every chain x 2 spins; 128x128 "
-                               "MFMA tiles)" if args.precision != "fp64" else
-                               "k_gemm<double> STORE (e^{-dtau K} G, every chain x 2 spins)",
+                     "kernel": "k_gemm_l STORE (e^{-dtau K} G, every chain of a group x 2 "
+                               "spins; 128x128 MFMA tiles)" if args.precision != "fp64" else
+                               "k_gemm<double> STORE (e^{-dtau K} G, every chain of a group x 2 "
+                               "spins)",
                      "flops_per_launch": wrap_flops, "ms_per_launch": main_res["wrap_ms"],
-                     "timing": f"HIP events on the context's stream around each of the "
-                               f"{main_res['launches']['wrap']} launches in the timed sweeps"},
+                     "timing": f"HIP events on each context's stream around each of the "
+                               f"{main_res['launches']['wrap']} launches in the timed sweeps "
+                               f"({args.groups} chain groups running concurrently)"},
         "slice_update_gemm_ms": main_res["flush_ms"],
         "propagation_gemm_ms": main_res["prop_ms"],
-        "launch": "direct (kernel events in the timed sweeps)",
+        "launch": (f"{args.groups} chain groups of {args.chains // args.groups}, one context and "
+                   f"HIP stream each, swept concurrently; " if args.groups > 1 else
+                   "one context; ") + "direct launches (kernel events in the timed sweeps)",
     }
     if main_res["graph_ms"] is not None:
         out["graph_ms_per_step"] = main_res["graph_ms"] / args.steps

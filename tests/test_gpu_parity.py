@@ -336,27 +336,37 @@ def test_trajectory_16x16_fp64():
     ctx.close()
 
 
-def test_bench_configuration_sampled_chains_fp64():
+@pytest.mark.parametrize("groups", [1, 4])
+def test_bench_configuration_sampled_chains_fp64(groups):
     """The benchmark's launch configuration (2048 chains of the 16x16 workload
-    at l_half = 100, k = 32, n_s = 5), one FP64 sweep; two sampled chains are
-    followed through the whole pass by the oracle: fields (tie band aside) and
-    the measured (sign, E/N, D)."""
+    at l_half = 100, k = 32, n_s = 5: one context, or 4 groups of 512 chains,
+    one context and stream each, swept concurrently), one FP64 sweep; two
+    sampled chains are followed through the whole pass by the oracle: fields
+    (tie band aside) and the measured (sign, E/N, D)."""
     n_chains = 2048
-    ctx = make_context([BENCH] * n_chains, "fp64", meas_capacity=4).init_trial()
-    ctx.sweep(1, measure=True)
+    per = n_chains // groups
+    ctxs = [make_context([BENCH] * per, "fp64", meas_capacity=4,
+                         chain_ids=list(range(g * per, (g + 1) * per))).init_trial()
+            for g in range(groups)]
+    for ctx in ctxs:
+        ctx.sweep(1, measure=True)
+    for ctx in ctxs:
+        ctx.synchronize()
     for c in (0, 1733):
+        ctx, lc = ctxs[c // per], c % per
         ch = oracle_chain(BENCH, c)
-        f_gpu = ctx.get_field(c)
+        f_gpu = ctx.get_field(lc)
         bad = ch.sweep_following(f_gpu, TIE["fp64"])
         assert not bad, f"chain {c}: decisions differ beyond the tie band: {bad[:3]}"
         assert np.array_equal(ch.field, f_gpu)
-        m_gpu, m_ref = ctx.measurements(c), np.array(ch.measurements)
+        m_gpu, m_ref = ctx.measurements(lc), np.array(ch.measurements)
         assert m_gpu.shape == m_ref.shape
         assert np.array_equal(m_gpu[:, 0], m_ref[:, 0])
         assert np.max(np.abs(m_gpu[:, 1:] - m_ref[:, 1:])) < 1e-10
-        info = ctx.chain_info(c)
+        info = ctx.chain_info(lc)
         assert info["sign_mismatch"] == 0 and (info["flags"] & ~16) == 0, info
-    ctx.close()
+    for ctx in ctxs:
+        ctx.close()
 
 
 def test_config_4x4_trajectory_fp64():
