@@ -236,8 +236,10 @@ __device__ inline float4 load4(const GLOBAL float* __restrict__ p, int valid, bo
   return v;
 }
 
+// FLUSH keeps four workgroups per CU like STORE: the old values of C are
+// loaded in the epilogue rather than held through the k-loop
 template <int MODE>
-__global__ __launch_bounds__(kThreads) void k_gemm_l(const GemmEntry* __restrict__ ents,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(MODE == GM_FLUSH ? 4 : 1))) void k_gemm_l(const GemmEntry* __restrict__ ents,
                                                      const TileRef* __restrict__ tiles,
                                                      int n_tiles, GemmArgs args) {
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
@@ -313,23 +315,6 @@ __global__ __launch_bounds__(kThreads) void k_gemm_l(const GemmEntry* __restrict
       for (int r = 0; r < 16; ++r) acc[x][y][r] = 0.f;
 
   const int h = lane >> 5, l32 = lane & 31;
-  // FLUSH: the old values of the wave's 64 x 64 block of C, loaded before the
-  // k-loop so that their latency overlaps it
-  float cold[2][2][16];
-  if (MODE == GM_FLUSH) {
-    const GLOBAL float* __restrict__ C0 = gp((const float*)e.C[0]);
-#pragma unroll
-    for (int y = 0; y < 2; ++y) {
-      const int j = n0 + wn + 32 * y + l32;
-#pragma unroll
-      for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int i = m0 + wm + 32 * x + 8 * (r >> 2) + 4 * h + (r & 3);
-          cold[x][y][r] = (i < M && j < N) ? C0[(size_t)i * ldc + j] : 0.f;
-        }
-    }
-  }
   const int nk = (K + BKL - 1) / BKL;
   if (nk > 0) {
     gload(0);
@@ -394,13 +379,23 @@ __global__ __launch_bounds__(kThreads) void k_gemm_l(const GemmEntry* __restrict
     const int jl = wn + 32 * y + l32, j = n0 + jl;
     const float dj = sfield ? dcol[jl] : 1.f;
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+    for (int x = 0; x < 2; ++x) {
+      // FLUSH: the block's old values of C, all sixteen loads in flight
+      float cold[16];
+      if (MODE == GM_FLUSH) {
+        const GLOBAL float* __restrict__ C0 = gp((const float*)e.C[0]);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int i = m0 + wm + 32 * x + 8 * (r >> 2) + 4 * h + (r & 3);
+          cold[r] = (i < M && j < N) ? C0[(size_t)i * ldc + j] : 0.f;
+        }
+      }
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int il = wm + 32 * x + 8 * (r >> 2) + 4 * h + (r & 3), i = m0 + il;
         if (i < M && j < N) {
           const size_t o = (size_t)i * ldc + j;
-          float v = MODE == GM_FLUSH ? cold[x][y][r] - acc[x][y][r] : acc[x][y][r];
+          float v = MODE == GM_FLUSH ? cold[r] - acc[x][y][r] : acc[x][y][r];
           if (sfield) v *= drow[il] * dj;
           if (MODE == GM_FLUSH)
             gp((float*)e.C[1])[o] = v;
@@ -408,6 +403,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_l(const GemmEntry* __restrict
             C[o] = v;
         }
       }
+    }
   }
 }
 
