@@ -14,6 +14,28 @@
 
 namespace gpqmc {
 
+// Four consecutive elements from global memory: one 16-byte (FP32) or two
+// 16-byte (FP64) loads when all four are in range and aligned, else element
+// by element with zeros past the end.
+__device__ inline void ld4(const GLOBAL float* __restrict__ p, int valid, bool aligned, float (&r)[4]) {
+  if (aligned && valid >= 4) {
+    const float4 v = gload4(p);
+    r[0] = v.x, r[1] = v.y, r[2] = v.z, r[3] = v.w;
+    return;
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) r[q] = q < valid ? p[q] : 0.f;
+}
+__device__ inline void ld4(const GLOBAL double* __restrict__ p, int valid, bool aligned, double (&r)[4]) {
+  if (aligned && valid >= 4) {
+    const double2 a = gload2(p), b = gload2(p + 2);
+    r[0] = a.x, r[1] = a.y, r[2] = b.x, r[3] = b.y;
+    return;
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) r[q] = q < valid ? p[q] : 0.0;
+}
+
 template <typename T, int MODE, bool TRANSA, bool TRANSB, typename Tb>
 __global__ __launch_bounds__(kThreads) void k_gemm(const GemmEntry* __restrict__ ents,
                                                    const TileRef* __restrict__ tiles,
@@ -52,6 +74,11 @@ __global__ __launch_bounds__(kThreads) void k_gemm(const GemmEntry* __restrict__
     }
   }
   const int lda = e.lda, ldb = e.ldb, ldc = e.ldc;
+  // 16-byte alignment of every row start (the four-element groups start at
+  // multiples of four)
+  constexpr int VA = 16 / sizeof(T) - 1;
+  const bool a_al = (lda & VA) == 0 && (reinterpret_cast<uintptr_t>(A) & 15) == 0;
+  const bool b_al = (ldb & VA) == 0 && (reinterpret_cast<uintptr_t>(B) & 15) == 0;
 
   constexpr int LDS_LD = kTile + LDS_PAD;
   __shared__ T As[BK * LDS_LD];
@@ -77,47 +104,41 @@ __global__ __launch_bounds__(kThreads) void k_gemm(const GemmEntry* __restrict__
   auto load_regs = [&](int kbase) {
     if (!TRANSA) {
       const int i = m0 + (tid >> 2), k = kbase + (tid & 3) * 4;
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        ra[q] = (i < M && k + q < K) ? A[(size_t)i * lda + k + q] : T(0);
+      ld4(A + (size_t)i * lda + k, i < M ? K - k : 0, a_al, ra);
     } else {
       const int k = kbase + (tid >> 4), i = m0 + (tid & 15) * 4;
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        ra[q] = (k < K && i + q < M) ? A[(size_t)k * lda + i + q] : T(0);
+      ld4(A + (size_t)k * lda + i, k < K ? M - i : 0, a_al, ra);
     }
     if (!TRANSB) {
       const int k = kbase + (tid >> 4), j = n0 + (tid & 15) * 4;
       bf = (bfield && k < K) ? bfield[k] : (int8_t)1;
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        rb[q] = (k < K && j + q < N) ? B[(size_t)k * ldb + j + q] : T(0);
+      ld4(B + (size_t)k * ldb + j, k < K ? N - j : 0, b_al, rb);
     } else {
       const int j = n0 + (tid >> 2), k = kbase + (tid & 3) * 4;
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        rb[q] = (j < N && k + q < K) ? B[(size_t)j * ldb + k + q] : T(0);
+      ld4(B + (size_t)j * ldb + k, j < N ? K - k : 0, b_al, rb);
     }
   };
   auto store_lds = [&]() {
+    T* as = As;
+    T* bs = Bs;
     if (!TRANSA) {
       const int i = tid >> 2, k = (tid & 3) * 4;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) As[(k + q) * LDS_LD + i] = ra[q];
+      for (int q = 0; q < 4; ++q) as[(k + q) * LDS_LD + i] = ra[q];
     } else {
       const int k = tid >> 4, i = (tid & 15) * 4;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) As[k * LDS_LD + i + q] = ra[q];
+      for (int q = 0; q < 4; ++q) as[k * LDS_LD + i + q] = ra[q];
     }
     if (!TRANSB) {
       const int k = tid >> 4, j = (tid & 15) * 4;
       const T sc = bf > 0 ? bsc_p : bsc_m;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) Bs[k * LDS_LD + j + q] = rb[q] * sc;
+      for (int q = 0; q < 4; ++q) bs[k * LDS_LD + j + q] = rb[q] * sc;
     } else {
       const int j = tid >> 2, k = (tid & 3) * 4;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) Bs[(k + q) * LDS_LD + j] = rb[q];
+      for (int q = 0; q < 4; ++q) bs[(k + q) * LDS_LD + j] = rb[q];
     }
   };
 
