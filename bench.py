@@ -111,7 +111,7 @@ def run_gpu(args, precision_name, steps, warmup, ns=None):
         ctxs.append(gpqmc.Context(chains, device="cuda:0", meas_capacity=max(64, steps + warmup + 4)))
     for ctx in ctxs:
         ctx.init_trial()
-    log(f"[{precision_name}] {G} contexts + init_trial: {time.time() - t0:.1f} s, "
+    log(f"[{precision_name}] {G} context(s) + init_trial: {time.time() - t0:.1f} s, "
         f"workspace {sum(c.workspace_bytes for c in ctxs) / 2**30:.2f} GiB")
     for ctx in ctxs:
         ctx.sweep(warmup, measure=True)
@@ -310,14 +310,16 @@ def main():
         },
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
-                     "kernel": "k_gemm_l STORE (e^{-dtau K} G, every chain of a group x 2 "
-                               "spins; 128x128 MFMA tiles)" if args.precision != "fp64" else
-                               "k_gemm<double> STORE (e^{-dtau K} G, every chain of a group x 2 "
-                               "spins)",
+                     "kernel": ("k_gemm_l STORE (e^{-dtau K} G, " if args.precision != "fp64" else
+                                "k_gemm<double> STORE (e^{-dtau K} G, ") +
+                               ("every chain x 2 spins" if args.groups == 1 else
+                                "every chain of a group x 2 spins") +
+                               ("; 128x128 MFMA tiles)" if args.precision != "fp64" else ")"),
                      "flops_per_launch": wrap_flops, "ms_per_launch": main_res["wrap_ms"],
-                     "timing": f"HIP events on each context's stream around each of the "
-                               f"{main_res['launches']['wrap']} launches in the timed sweeps "
-                               f"({args.groups} chain groups running concurrently)"},
+                     "timing": f"HIP events on the context's stream around each of the "
+                               f"{main_res['launches']['wrap']} launches in the timed sweeps" +
+                               (f" ({args.groups} chain groups running concurrently)"
+                                if args.groups > 1 else "")},
         "slice_update_gemm_ms": main_res["flush_ms"],
         "propagation_gemm_ms": main_res["prop_ms"],
         "launch": (f"{args.groups} chain groups of {args.chains // args.groups}, one context and "
