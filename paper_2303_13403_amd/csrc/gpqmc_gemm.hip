@@ -168,6 +168,19 @@ __global__ __launch_bounds__(kThreads) void k_gemm(const GemmEntry* __restrict__
     sbnd = (args.scale_slice == 0 || args.scale_slice == args.n_bulk_last + 1) ? 0 : 1;
   }
   const bool inv = args.scale_inverse != 0;
+  // the tile's row factors d(i) and column factors 1/d(j) of the frame
+  // change, staged once (PROPR scales rows only, by d(i))
+  __shared__ double drow[kTile], dcol[kTile];
+  if (sfield) {
+    if (tid < kTile) {
+      const int i = m0 + tid;
+      drow[tid] = i < M ? dfac(e.dval, sbnd, sfield[i], MODE == GM_PROPR ? false : inv) : 0.0;
+    } else if (tid < 2 * kTile) {
+      const int j = n0 + tid - kTile;
+      dcol[tid - kTile] = j < N ? dfac(e.dval, sbnd, sfield[j], !inv) : 0.0;
+    }
+    __syncthreads();
+  }
   float dmax = 0.f, gmx = 0.f;
   // the drift check reads the wrapped Green's function it replaces: all of
   // those loads are issued before the first store of the tile
@@ -188,12 +201,11 @@ __global__ __launch_bounds__(kThreads) void k_gemm(const GemmEntry* __restrict__
     const size_t o = (size_t)i * ldc + j;
     if (MODE == GM_PROPR) {
       T v = acc;
-      if (sfield) v *= (T)dfac(e.dval, sbnd, sfield[i], false);
+      if (sfield) v *= (T)drow[li];
       C[o] = v;
     } else if (MODE == GM_WRAP || MODE == GM_FLUSH) {
       T v = (MODE == GM_FLUSH) ? gp((const T*)e.C[0])[o] - acc : acc;
-      if (sfield)
-        v *= (T)(dfac(e.dval, sbnd, sfield[i], inv) * dfac(e.dval, sbnd, sfield[j], !inv));
+      if (sfield) v *= (T)(drow[li] * dcol[lj]);
       if (MODE == GM_FLUSH)
         gp((T*)e.C[1])[o] = v;
       else
@@ -209,7 +221,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm(const GemmEntry* __restrict__
         gmx = fmaxf(gmx, (float)fabs(g));
       }
       double v = g;
-      if (sfield) v *= dfac(e.dval, sbnd, sfield[i], inv) * dfac(e.dval, sbnd, sfield[j], !inv);
+      if (sfield) v *= drow[li] * dcol[lj];
       Cb[o2] = (Tb)v;
     } else {
       C[o] = acc;
