@@ -928,40 +928,32 @@ void k_xy_mfma(const ChainDev* __restrict__ chains, int nrb, int s0, int kseg) {
     return;
   }
 
-  // X part: the segment's slab S1[r][c] = G0[r0 + r, s0 + c] and Z, then
-  // P = G0[:, F] - C, then Xa[:, fp + c] = P Z
-  float* S1 = U;
+  // X part: Z to LDS, then P = G0[:, F] - C with G0 gathered at the
+  // accepted sites straight from memory (a lane's sixteen loads in flight at
+  // once), then Xa[:, fp + c] = P Z
   const GLOBAL float* __restrict__ Z = gp((const float*)C.Z[spin]);
   for (int e = tid; e < FMAX * FMAX; e += kThreads) {
     const int q = e / FMAX, c = e % FMAX;
     Zl[q * LP + c] = (q < f && c < f) ? Z[(size_t)q * kSegMax + c] : 0.f;
   }
-  constexpr int NE = ROWS * FMAX / kThreads;
-  for (int t0 = 0; t0 < NE; t0 += 8) {       // eight loads in flight, then their stores
-    float v8[8];
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int e = tid + (t0 + t) * kThreads, r = e / FMAX, c = e % FMAX;
-      v8[t] = (r0 + r < N && c < kseg && s0 + c < N) ? G[(size_t)(r0 + r) * N + s0 + c] : 0.f;
-    }
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int e = tid + (t0 + t) * kThreads;
-      S1[(e / FMAX) * LP + e % FMAX] = v8[t];
-    }
-  }
   __syncthreads();
 #pragma unroll
   for (int x = 0; x < XB; ++x)
 #pragma unroll
-    for (int qb = 0; qb < QB; ++qb)
+    for (int qb = 0; qb < QB; ++qb) {
+      const int q = 32 * qb + l32, col = q < f ? Fl[q] : 0;
+      float gv[16];
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int i = w0 + 32 * x + 8 * (r >> 2) + 4 * h + (r & 3), q = 32 * qb + l32;
-        const float a = acc[x * QB + qb][r];
-        acc[x * QB + qb][r] = q < f ? S1[i * LP + Fl[q] - s0] - a : 0.f;
+        const int i = r0 + w0 + 32 * x + 8 * (r >> 2) + 4 * h + (r & 3);
+        gv[r] = (q < f && i < N) ? G[(size_t)i * N + col] : 0.f;
       }
-  __syncthreads();
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float a = acc[x * QB + qb][r];
+        acc[x * QB + qb][r] = q < f ? gv[r] - a : 0.f;
+      }
+    }
   float* Pl = U;
 #pragma unroll
   for (int x = 0; x < XB; ++x)
