@@ -1153,40 +1153,32 @@ __global__ __launch_bounds__(kThreads) void k_xy_mfma64(const ChainDev* __restri
     return;
   }
 
-  // X part: slab S1[r][c] = G0[r0 + r, s0 + c], P = G0[:, F] - C, Xa[:, fp + c] = P Z
-  double* S1 = U;
+  // X part: Z to LDS, then P = G0[:, F] - C with G0 gathered at the
+  // accepted sites straight from memory, then Xa[:, fp + c] = P Z
   const GLOBAL double* __restrict__ Z = gp((const double*)C.Z[spin]);
   for (int e = tid; e < FMAX * FMAX; e += kThreads) {
     const int q = e / FMAX, c = e % FMAX;
     Zl[q * LP + c] = (q < f && c < f) ? Z[(size_t)q * kSegMax + c] : 0.0;
-  }
-  constexpr int NE = ROWS * FMAX / kThreads;
-  {
-    double v[NE];
-#pragma unroll
-    for (int t = 0; t < NE; ++t) {
-      const int e = tid + t * kThreads, r = e / FMAX, c = e % FMAX;
-      v[t] = (r0 + r < N && c < kseg && s0 + c < N) ? G[(size_t)(r0 + r) * N + s0 + c] : 0.0;
-    }
-#pragma unroll
-    for (int t = 0; t < NE; ++t) {
-      const int e = tid + t * kThreads;
-      S1[(e / FMAX) * LP + e % FMAX] = v[t];
-    }
   }
   __syncthreads();
   // C[i][q]: i = w0 + 16 x + 4 r + kq, q = 16 y + l16
 #pragma unroll
   for (int x = 0; x < XB; ++x)
 #pragma unroll
-    for (int y = 0; y < 2; ++y)
+    for (int y = 0; y < 2; ++y) {
+      const int q = 16 * y + l16, col = q < f ? Fl[q] : 0;
+      double gv[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = w0 + 16 * x + 4 * r + kq, q = 16 * y + l16;
-        const double a = acc[x][y][r];
-        acc[x][y][r] = q < f ? S1[i * LP + Fl[q] - s0] - a : 0.0;
+        const int i = r0 + w0 + 16 * x + 4 * r + kq;
+        gv[r] = (q < f && i < N) ? G[(size_t)i * N + col] : 0.0;
       }
-  __syncthreads();
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double a = acc[x][y][r];
+        acc[x][y][r] = q < f ? gv[r] - a : 0.0;
+      }
+    }
   double* Pl = U;
 #pragma unroll
   for (int x = 0; x < XB; ++x)
