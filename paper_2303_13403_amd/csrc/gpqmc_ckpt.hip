@@ -333,7 +333,8 @@ struct RegTile {
 template <int NB, int TG>
 __device__ void rt_invert(RegTile<NB, TG>& T, bool triangular, double (*rk)[kRtMax],
                           double (*rp)[kRtMax], double (*ck)[kRtMax], double (*cv)[32],
-                          int (*ci)[32], int* piv, int* colmap, double& logabs, int& sgn) {
+                          int (*ci)[32], int* piv, int* colmap, double* pabs, bool want_log,
+                          double& logabs, int& sgn) {
   const int n = T.n, tid = threadIdx.x;
   logabs = 0.0;
   sgn = 1;
@@ -390,7 +391,9 @@ __device__ void rt_invert(RegTile<NB, TG>& T, bool triangular, double (*rk)[kRtM
     const bool bad = (pv == 0.0) | (pv != pv);
     if (bad) sgn = 0;
     if (tid == 0) {
-      if (!bad) logabs += log(fabs(pv));
+      // |pivot| (1 for a bad one); the logs are taken after the loop, off
+      // the critical path of the elimination steps
+      if (want_log) pabs[k] = bad ? 1.0 : fabs(pv);
       piv[k] = p;
     }
     if (pv < 0) sgn = -sgn;
@@ -411,6 +414,13 @@ __device__ void rt_invert(RegTile<NB, TG>& T, bool triangular, double (*rk)[kRtM
     // colmap now holds the source column of each destination; invert it
     for (int c = 0; c < n; ++c) piv[colmap[c]] = c;
     for (int c = 0; c < n; ++c) colmap[c] = piv[c];
+  }
+  if (want_log) {
+    // log|pivot| on n threads at once, summed in pivot order by thread 0
+    for (int c = tid; c < n; c += blockDim.x) pabs[c] = log(pabs[c]);
+    __syncthreads();
+    if (tid == 0)
+      for (int c = 0; c < n; ++c) logabs += pabs[c];
   }
   __syncthreads();
 }
@@ -447,7 +457,8 @@ __device__ inline void rt_clear(double (*rk)[kRtMax], double (*rp)[kRtMax], doub
   __shared__ double rk[2][kRtMax], rp[2][kRtMax], ck[2][kRtMax]; \
   __shared__ double cv[2][32];                          \
   __shared__ int ci[2][32];                             \
-  __shared__ int piv[kRtMax], colmap[kRtMax];
+  __shared__ int piv[kRtMax], colmap[kRtMax];           \
+  __shared__ double pabs[kRtMax];
 
 // Cholesky W = R^T R (R upper) of the Gram matrix, then R^{-1}, in registers.
 template <int NB, int TG>
@@ -468,6 +479,7 @@ __global__ __launch_bounds__(TG * TG) void k_chol_inv_rt(const ChainDev* __restr
     const double d2 = rk[jb][j];
     if (!(d2 > 0.0)) {   // not positive definite (or NaN): flag, keep going finitely
       bad = true;
+      if (tid == 0) pabs[j] = 1.0;   // no contribution to log|det R|
 #pragma unroll
       for (int a = 0; a < NB; ++a)
 #pragma unroll
@@ -476,7 +488,7 @@ __global__ __launch_bounds__(TG * TG) void k_chol_inv_rt(const ChainDev* __restr
       continue;
     }
     const double d = sqrt(d2), id = 1.0 / d;
-    if (tid == 0) lsum += log(d);
+    if (tid == 0) pabs[j] = d;   // logged after the loop
     // normalised row j at the thread's columns (zero left of j) and rows
     // (zero at and above j): one FMA per element updates the trailing matrix
     // (its lower triangle too, which is cleared at the end) and leaves the
@@ -515,6 +527,13 @@ __global__ __launch_bounds__(TG * TG) void k_chol_inv_rt(const ChainDev* __restr
 #pragma unroll
     for (int b = 0; b < NB; ++b)
       if (T.tj + TG * b < T.ti + TG * a) T.m[a][b] = 0.0;
+  // log|det R| = sum of log R_jj: the logs on n threads at once, summed in
+  // order by thread 0
+  __syncthreads();
+  for (int c = tid; c < n; c += blockDim.x) pabs[c] = log(pabs[c]);
+  __syncthreads();
+  if (tid == 0)
+    for (int c = 0; c < n; ++c) lsum += pabs[c];
   if (tid == 0) {
     C.st->chk_log[sp] = lsum;
     C.st->chk_sgn[sp] = 1;
@@ -525,7 +544,7 @@ __global__ __launch_bounds__(TG * TG) void k_chol_inv_rt(const ChainDev* __restr
   // the inverse's first step rewrites rk[0], which the last Cholesky step
   // (j = n - 1 even) may still be reading
   __syncthreads();
-  rt_invert<NB, TG>(T, true, rk, rp, ck, cv, ci, piv, colmap, la, sg);
+  rt_invert<NB, TG>(T, true, rk, rp, ck, cv, ci, piv, colmap, pabs, false, la, sg);
   if (sg != 0)
     rt_store<NB, TG>(T, gp(C.Rinv[sp]), colmap, true);
   else if (tid == 0)
@@ -545,7 +564,7 @@ __global__ __launch_bounds__(TG * TG) void k_gj_inv_rt(const ChainDev* __restric
   T.load(gp(C.Xm[sp]), n);
   double logabs;
   int sgn;
-  rt_invert<NB, TG>(T, false, rk, rp, ck, cv, ci, piv, colmap, logabs, sgn);
+  rt_invert<NB, TG>(T, false, rk, rp, ck, cv, ci, piv, colmap, pabs, true, logabs, sgn);
   if (sgn != 0) rt_store<NB, TG>(T, gp(C.Xm[sp]), colmap, false);
   if (tid == 0) {
     C.st->x_log[sp] = logabs;
