@@ -768,7 +768,7 @@ __device__ inline float4 xy_load4(const GLOBAL float* __restrict__ p, int valid,
 
 template <int FMAX>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(XyMfmaShape<FMAX>::WAVES)))
-void k_xy_mfma(const ChainDev* __restrict__ chains, int nrb, int s0, int kseg) {
+void k_xy_mfma(const ChainDev* __restrict__ chains, int nrb) {
   using S = XyMfmaShape<FMAX>;
   constexpr int ROWS = S::ROWS, XB = S::XB, QB = S::QB, BK = S::BK;
   constexpr int LA = S::LA, LS = S::LS, LP = S::LP;
@@ -1010,7 +1010,7 @@ __device__ inline double2 xy_load2(const GLOBAL double* __restrict__ p, int vali
 }
 
 __global__ __launch_bounds__(kThreads) void k_xy_mfma64(const ChainDev* __restrict__ chains,
-                                                        int nrb, int s0, int kseg) {
+                                                        int nrb) {
   constexpr int FMAX = 32, ROWS = kXy64Rows, BK = kXy64Bk, LA = kXy64La, LS = kXy64Ls,
                 LP = kXy64Lp;
   constexpr int NQ2 = BK * ROWS / (2 * kThreads);        // double2 loads of the wide tile
@@ -1216,12 +1216,13 @@ __global__ __launch_bounds__(kThreads) void k_xy_mfma64(const ChainDev* __restri
       }
 }
 
+// (the MFMA forms read the segment's accepted sites and offsets from the
+// chain state, so they take no segment bounds)
 template <int FMAX>
-static void launch_xy_mfma(const ChainDev* c, int nc, int n_max, int s0, int kseg, hipStream_t s) {
+static void launch_xy_mfma(const ChainDev* c, int nc, int n_max, hipStream_t s) {
   constexpr int ROWS = XyMfmaShape<FMAX>::ROWS;
   const int nrb = (n_max + ROWS - 1) / ROWS;
-  hipLaunchKernelGGL((k_xy_mfma<FMAX>), dim3(nc * 2 * 2 * nrb), dim3(kThreads), 0, s, c, nrb, s0,
-                     kseg);
+  hipLaunchKernelGGL((k_xy_mfma<FMAX>), dim3(nc * 2 * 2 * nrb), dim3(kThreads), 0, s, c, nrb);
 }
 
 template <typename T, int FMAX>
@@ -1236,14 +1237,14 @@ hipError_t launch_xy(int fp32, const ChainDev* c, int nc, int n_max, int s0, int
                      hipStream_t s) {
   if (kseg <= 32) {
     if (fp32) {
-      launch_xy_mfma<32>(c, nc, n_max, s0, kseg, s);
+      launch_xy_mfma<32>(c, nc, n_max, s);
     } else {
       const int nrb = (n_max + kXy64Rows - 1) / kXy64Rows;
-      hipLaunchKernelGGL(k_xy_mfma64, dim3(nc * 2 * 2 * nrb), dim3(kThreads), 0, s, c, nrb, s0, kseg);
+      hipLaunchKernelGGL(k_xy_mfma64, dim3(nc * 2 * 2 * nrb), dim3(kThreads), 0, s, c, nrb);
     }
   } else {
     if (fp32)
-      launch_xy_mfma<64>(c, nc, n_max, s0, kseg, s);
+      launch_xy_mfma<64>(c, nc, n_max, s);
     else
       launch_xy_t<double, 64>(c, nc, n_max, s0, kseg, s);
   }
