@@ -25,6 +25,8 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+from paper_2303_13403_amd.estimators import weighted_mean  # noqa: E402
+
 METRIC = "HS-field updates/sec at 16×16, L=100; mixed vs FP64 GPU at 1e-5 rel G error"
 UNIT = "HS-field updates/s"
 PEAK_FP32_MFMA = 157.3e12   # MI355X dense FP32 matrix, FLOP/s
@@ -67,25 +69,6 @@ def workload(args, ns=None):
 
     return WORKLOADS["16x16"].replace(stab_interval=args.ns if ns is None else ns,
                                       delay_rank=args.k)
-
-
-def weighted_mean(rec, which):
-    """<s O>/<s> over measurement records (rows: sign, E/N, D/N) with a
-    delete-one-bin jackknife over bins of 10 records (which = 0: the sign
-    itself, binned mean); the estimator the library applies to one context."""
-    import numpy as np
-
-    nb = len(rec) // 10
-    if nb < 2:
-        return None
-    r = rec[: nb * 10].reshape(nb, 10, 3)
-    s = r[:, :, 0].mean(axis=1)
-    if which == 0:
-        return float(s.mean()), float(s.std(ddof=1) / np.sqrt(nb))
-    so = (r[:, :, 0] * r[:, :, which]).mean(axis=1)
-    S, SO = s.sum(), so.sum()
-    jk = (SO - so) / (S - s)
-    return float(SO / S), float(np.sqrt((nb - 1) / nb * ((jk - jk.mean()) ** 2).sum()))
 
 
 def run_gpu(args, precision_name, steps, warmup, ns=None):

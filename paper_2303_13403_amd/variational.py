@@ -1,0 +1,97 @@
+"""Variational energy scan at Theta = 0 over the trial parameters (g, M_N).
+
+At zero projection time (l_half = 0, M = 0) only the two boundary slices of
+the Gutzwiller projector remain, so the sampled estimate is the variational
+energy <psi_G|H|psi_G> / <psi_G|psi_G> of the Gutzwiller-projected Neel state
+(the paper's first stage, Method section and Fig. 1, which locates the optimal
+g and M_N before the projection runs).  Every grid point gets its own chains,
+and the whole grid runs as one batch: one launch per step for all points.
+
+    python -m paper_2303_13403_amd.variational --lattice 16x16 \
+        --g 0.3 0.45 0.55 0.65 --m 0.0 0.07 0.14 --chains 64 --sweeps 200
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import time
+from typing import List, Sequence
+
+import numpy as np
+
+from . import gpqmc
+from .estimators import weighted_mean
+from .workloads import WORKLOADS, Workload
+
+
+def variational_scan(workload: Workload, gs: Sequence[float], m_neels: Sequence[float],
+                     chains_per_point: int = 64, sweeps: int = 200, warmup: int = 20,
+                     precision: int = gpqmc.FP64, device: str = "cuda:0", log=None):
+    """Sample E/N at Theta = 0 on the grid gs x m_neels.
+
+    Returns ``(points, stats)``: one dict per grid point (g, m_neel, energy,
+    double_occupancy and sign as (mean, error), the records used) and a dict
+    with the batch size, the timed sweeps and the HS-field updates per second.
+    Chain ids are point * chains_per_point + c, so every chain draws its own
+    Philox stream."""
+    w0 = workload.replace(l_half=0, stab_interval=1)
+    grid = [(float(g), float(m)) for g in gs for m in m_neels]
+    descs = []
+    for p, (g, m) in enumerate(grid):
+        w = w0.replace(g=g, m_neel=m)
+        descs += [gpqmc.chain_desc_arrays(w, p * chains_per_point + c, precision)
+                  for c in range(chains_per_point)]
+    # one measurement at tau = Theta = 0 per sweep
+    ctx = gpqmc.Context(descs, device=device, meas_capacity=max(sweeps, warmup) + 4)
+    try:
+        ctx.init_trial()
+        ctx.sweep(warmup, measure=True)
+        ctx.synchronize()
+        ctx.reset_measurements()
+        t0 = time.time()
+        ctx.sweep(sweeps, measure=True)
+        ctx.synchronize()
+        dt = time.time() - t0
+        points: List[dict] = []
+        for p, (g, m) in enumerate(grid):
+            rec = np.concatenate([ctx.measurements(p * chains_per_point + c)
+                                  for c in range(chains_per_point)])
+            points.append(dict(g=g, m_neel=m, records=len(rec),
+                               energy=weighted_mean(rec, 1),
+                               double_occupancy=weighted_mean(rec, 2),
+                               sign=weighted_mean(rec, 0)))
+            if log is not None:
+                e = points[-1]["energy"]
+                log(f"g={g:.3f} M_N={m:.3f}: E/N = {e[0]:.5f} +- {e[1]:.5f}")
+    finally:
+        ctx.close()
+    n_updates = 2 * workload.n_sites * len(descs) * sweeps
+    stats = dict(chains=len(descs), sweeps=sweeps, seconds=dt, updates_per_s=n_updates / dt)
+    return points, stats
+
+
+def optimum(points: Sequence[dict]) -> dict:
+    """The grid point of lowest sampled energy."""
+    return min(points, key=lambda q: q["energy"][0])
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--lattice", default="16x16", choices=sorted(WORKLOADS))
+    ap.add_argument("--g", type=float, nargs="+", default=[0.35, 0.45, 0.55, 0.65, 0.75])
+    ap.add_argument("--m", type=float, nargs="+", default=[0.0, 0.035, 0.07, 0.14, 0.21])
+    ap.add_argument("--chains", type=int, default=64, help="chains per grid point")
+    ap.add_argument("--sweeps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    args = ap.parse_args()
+    prec = gpqmc.FP64 if args.precision == "fp64" else gpqmc.MIXED
+    pts, st = variational_scan(WORKLOADS[args.lattice], args.g, args.m, args.chains, args.sweeps,
+                               args.warmup, prec, log=print)
+    best = optimum(pts)
+    print(json.dumps(dict(lattice=args.lattice, optimum=dict(g=best["g"], m_neel=best["m_neel"],
+                                                             energy=best["energy"]), **st)))
+
+
+if __name__ == "__main__":
+    main()
