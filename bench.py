@@ -67,7 +67,7 @@ def read_traffic(chains_per_launch: int, precision: str):
 def workload(args, ns=None):
     from paper_2303_13403_amd.workloads import WORKLOADS
 
-    return WORKLOADS["16x16"].replace(stab_interval=args.ns if ns is None else ns,
+    return WORKLOADS[args.workload].replace(stab_interval=args.ns if ns is None else ns,
                                       delay_rank=args.k)
 
 
@@ -190,8 +190,8 @@ def cpu_baseline(args, budget_s=30.0):
         dt = time.time() - t0
     upd = (2 * w.l_half + 2) * w.n_sites * n
     return {"value": upd / dt, "unit": UNIT, "cores": 1, "kind": "oracle",
-            "sample": f"{n} sweep(s) of one 16x16 chain (202 slices x 256 sites), "
-                      f"serial FP64 NumPy, BLAS threads = 1, {dt:.1f} s"}
+            "sample": f"{n} sweep(s) of one {w.name} chain ({2 * w.l_half + 2} slices x "
+                      f"{w.n_sites} sites), serial FP64 NumPy, BLAS threads = 1, {dt:.1f} s"}
 
 
 def copy_calibration(mib: int, reps: int = 5):
@@ -215,6 +215,9 @@ def main():
     ap.add_argument("--steps", type=int, default=6)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--chains", type=int, default=2048)
+    ap.add_argument("--workload", default="16x16", choices=["16x16", "honeycomb12x12"],
+                    help="16x16: the headline configuration; honeycomb12x12: the paper's "
+                         "lattice at 288 sites")
     ap.add_argument("--groups", type=int, default=1,
                     help="chain groups, one context and HIP stream each, swept concurrently "
                          "(the roofline kernel's launches then overlap other groups' work)")
@@ -274,16 +277,20 @@ def main():
     achieved = wrap_flops / (main_res["wrap_ms"] / 1e3)
     traffic = read_traffic(per_launch, args.precision)
     out = {
-        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1,
+        "metric": METRIC if args.workload == "16x16" else f"HS-field updates/sec, {w.name}",
+        "value": value, "unit": UNIT, "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": main_res["ms"] / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {
-            "workload": f"16x16 periodic Hubbard, U=3.5, 112+112 electrons, dtau=0.1, "
-                        f"Theta=10 (l_half=100, {M + 2} slices), Neel M_N=0.07 + Gutzwiller "
-                        f"g=0.55, batch of {args.chains} chains",
+            "workload": (f"16x16 periodic Hubbard, U=3.5, 112+112 electrons, dtau=0.1, "
+                         f"Theta=10 (l_half=100, {M + 2} slices), Neel M_N=0.07 + Gutzwiller "
+                         f"g=0.55, batch of {args.chains} chains" if args.workload == "16x16" else
+                         f"{w.name}, {w.n_up}+{w.n_dn} electrons, dtau={w.dtau}, "
+                         f"{M + 2} slices, Neel M_N={w.m_neel} + Gutzwiller g={w.g}, "
+                         f"batch of {args.chains} chains"),
             "chains": args.chains, "chain_groups": args.groups,
             "precision": args.precision, "stab_interval": args.ns,
             "delay_rank": args.k, "acceptance": round(main_res["accept"], 4),

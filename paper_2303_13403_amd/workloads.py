@@ -7,10 +7,11 @@ define a batch of uneven chains.  It contains none of the method's arithmetic
 (no propagation, no Green's function, no Monte Carlo) and is imported both by
 the tests that drive the oracle and by the code that drives the HIP library.
 
-The paper works on the honeycomb lattice; the workloads here are the square
-lattice with periodic boundaries, nearest-neighbour hopping -t, which has the
-same two-sublattice (Neel) structure used by the trial state (Method section,
-Neel mean-field Hamiltonian after Eq. 2).
+The headline workloads are the square lattice with periodic boundaries and
+nearest-neighbour hopping -t, which has the same two-sublattice (Neel)
+structure used by the trial state (Method section, Neel mean-field Hamiltonian
+after Eq. 2).  The paper's own Hubbard lattice, the honeycomb lattice (Eq. 2),
+is available as ``Workload(..., lattice_kind="honeycomb")``.
 """
 from __future__ import annotations
 
@@ -21,6 +22,7 @@ import numpy as np
 
 __all__ = [
     "square_lattice",
+    "honeycomb_lattice",
     "shell_ramp",
     "Workload",
     "WORKLOADS",
@@ -52,6 +54,31 @@ def square_lattice(lx: int, ly: int, t: float = 1.0):
                 K[j, i] -= t
     eps = np.where((xy[:, 0] + xy[:, 1]) % 2 == 0, 1, -1).astype(np.int8)
     return K, eps, xy
+
+
+def honeycomb_lattice(l1: int, l2: int, t: float = 1.0):
+    """Hopping matrix of an l1 x l2 periodic honeycomb lattice (Eq. 2).
+
+    Unit cell (x, y) holds site A = 2 (x + l1 y) and site B = A + 1.  With
+    primitive vectors a1, a2, every A site is bonded to the B site of its own
+    cell and to the B sites of cells (x - 1, y) and (x, y - 1); each bond
+    carries -t (bonds that wrap onto the same pair twice accumulate).  Returns
+    ``(K, eps, cells)``: ``eps`` is +1 on A and -1 on B, ``cells`` the unit
+    cell of every site.
+    """
+    n = 2 * l1 * l2
+    K = np.zeros((n, n), dtype=np.float64)
+    cells = np.zeros((n, 2), dtype=np.int64)
+    for y in range(l2):
+        for x in range(l1):
+            a = 2 * (x + l1 * y)
+            cells[a] = cells[a + 1] = (x, y)
+            for dx, dy in ((0, 0), (-1, 0), (0, -1)):
+                b = 2 * ((x + dx) % l1 + l1 * ((y + dy) % l2)) + 1
+                K[a, b] -= t
+                K[b, a] -= t
+    eps = np.where(np.arange(n) % 2 == 0, 1, -1).astype(np.int8)
+    return K, eps, cells
 
 
 def shell_ramp(lx: int, ly: int, delta: float = 0.1, tilt: float = 0.37):
@@ -87,30 +114,38 @@ class Workload:
     t: float = 1.0
     ramp: float = 0.0      # trial-only shell-closing ramp amplitude (0 = none)
     seed: int = 13403
+    lattice_kind: str = "square"   # "square" (lx x ly sites) or "honeycomb" (lx x ly cells of 2)
 
     @property
     def n_sites(self) -> int:
-        return self.lx * self.ly
+        return self.lx * self.ly * (2 if self.lattice_kind == "honeycomb" else 1)
 
     @property
     def theta(self) -> float:
         return self.l_half * self.dtau
 
     def lattice(self):
+        if self.lattice_kind == "honeycomb":
+            return honeycomb_lattice(self.lx, self.ly, self.t)
+        if self.lattice_kind != "square":
+            raise ValueError(f"unknown lattice kind {self.lattice_kind!r}")
         return square_lattice(self.lx, self.ly, self.t)
 
     def trial_potential(self) -> Optional[np.ndarray]:
         if self.ramp == 0.0:
             return None
+        if self.lattice_kind != "square":
+            raise ValueError("the shell-closing ramp is defined on the square lattice")
         return shell_ramp(self.lx, self.ly, self.ramp)
 
     def replace(self, **kw) -> "Workload":
         return dataclasses.replace(self, **kw)
 
 
-# The five synthetic workloads: a small 4x4 case, a 12x12 half-filled case, the
+# The synthetic workloads: a small 4x4 case, a 12x12 half-filled case, the
 # 16x16 doped case whose throughput is the headline figure, a batch of uneven
-# lattices and a 24x24 large case.  Model parameters follow the Gutzwiller
+# lattices, a 24x24 large case and the half-filled honeycomb lattice of the
+# paper's Hubbard study at 288 sites.  Model parameters follow the Gutzwiller
 # optima the paper prints for the Hubbard model (Fig. 1 caption: g=0.55,
 # M_N=0.07 at U=3.5; g=0.6, M_N=0.21 at U=4).
 WORKLOADS = {
@@ -122,6 +157,9 @@ WORKLOADS = {
                       0.07, 0.55, 5, 32, "mixed", 1000, ramp=0.1),
     "24x24": Workload("24x24 U=4 half filling Theta=10 dtau=0.05", 24, 24, 4.0, 288, 288,
                       0.05, 200, 0.21, 0.6, 10, 64, "mixed", 100),
+    "honeycomb12x12": Workload("honeycomb 12x12 cells (288 sites) U=4 half filling Theta=5",
+                               12, 12, 4.0, 144, 144, 0.1, 50, 0.21, 0.6, 5, 32, "mixed", 100,
+                               lattice_kind="honeycomb"),
 }
 
 

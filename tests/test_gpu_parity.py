@@ -274,6 +274,37 @@ def test_fixed_field_pass_odd_lattice(prec, kw):
     check_fixed_field(rect(prec, **kw), prec)
 
 
+def honey(prec, l1, l2, U=4.0, l_half=5, n_s=3, k=8):
+    """Half-filled l1 x l2 honeycomb lattice (2 l1 l2 sites), the paper's
+    Hubbard lattice (Eq. 2)."""
+    n = l1 * l2
+    return Workload(f"honeycomb {l1}x{l2}", l1, l2, U, n, n, 0.1, l_half, 0.21, 0.6, n_s, k, prec,
+                    10, lattice_kind="honeycomb")
+
+
+@pytest.mark.parametrize("prec,l1,l2", [("fp64", 3, 3), ("mixed", 3, 3), ("fp64", 8, 8),
+                                        ("mixed", 8, 8)])
+def test_fixed_field_pass_honeycomb(prec, l1, l2):
+    """18 sites, and 128 sites (the large-tile GEMM path)."""
+    check_fixed_field(honey(prec, l1, l2), prec)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_trajectory_honeycomb(prec):
+    w = honey(prec, 3, 4, l_half=4, n_s=3, k=8)
+    ctx = make_context([w], prec).init_trial()
+    follow_and_compare(ctx, [oracle_chain(w, 0)], prec, 4)
+    ctx.close()
+
+
+def test_mixed_batch_of_honeycomb_and_square_follows_oracle():
+    ws = [honey("mixed", 3, 3, l_half=4, n_s=2, k=8), small("mixed", L=4, l_half=4, n_s=2, k=8),
+          honey("mixed", 4, 3, l_half=4, n_s=2, k=8)]
+    ctx = make_context(ws, "mixed").init_trial()
+    follow_and_compare(ctx, [oracle_chain(w, c) for c, w in enumerate(ws)], "mixed", 3)
+    ctx.close()
+
+
 def test_trajectory_odd_lattice_fp64():
     w = rect("fp64", 3, 7, 10, l_half=4, n_s=3, k=8)
     ctx = make_context([w], "fp64").init_trial()

@@ -74,7 +74,7 @@ def _create(chains):
 
 
 def test_create_accepts_the_workloads_and_sizes_workspace():
-    for name in ("4x4", "12x12"):
+    for name in ("4x4", "12x12", "honeycomb12x12"):
         st, msg, nbytes = _create([_desc(WORKLOADS[name])])
         assert st == 0, msg
         assert nbytes > 0
