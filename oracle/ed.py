@@ -76,6 +76,59 @@ def fock_operators(K, n_up, n_dn):
     return kin, dbl, su, sd
 
 
+def fock_spin_afm(eps, su, sd, n):
+    """sum_ij eps_i eps_j S_i . S_j as a dense matrix on the (n_up, n_dn)
+    sector (basis index = i_up * dim_dn + i_dn), from the spin operators:
+
+      S^z_i = (n_i,up - n_i,dn) / 2, diagonal;
+      S^+_i S^-_j = c_i,up^dag c_j,up  c_i,dn c_j,dn^dag
+                  = T^up_ij (x) (delta_ij - T^dn_ji),
+      S^-_i S^+_j = (delta_ij - T^up_ji) (x) T^dn_ij,
+
+    with T^s_ij the matrix of c_i,s^dag c_j,s on the species' occupation
+    basis (every up operator is ordered before every down operator, and the
+    pairs moved past each other are even, so no sign arises between species).
+    """
+    du, dd = len(su), len(sd)
+    e = np.asarray(eps, dtype=np.float64)
+    nu = np.array([[(b >> i) & 1 for i in range(n)] for b in su], dtype=np.float64)
+    nd = np.array([[(b >> i) & 1 for i in range(n)] for b in sd], dtype=np.float64)
+    mz = 0.5 * ((nu @ e)[:, None] - (nd @ e)[None, :]).ravel()     # sum_i eps_i S^z_i
+    out = np.diag(mz * mz)
+    Iu, Id = np.eye(du), np.eye(dd)
+    for i in range(n):
+        for j in range(n):
+            Eij = np.zeros((n, n))
+            Eij[i, j] = 1.0
+            Eji = Eij.T.copy()
+            Tu_ij, Tu_ji = _one_body(Eij, su), _one_body(Eji, su)
+            Td_ij, Td_ji = _one_body(Eij, sd), _one_body(Eji, sd)
+            dij = 1.0 if i == j else 0.0
+            pm = np.kron(Tu_ij, dij * Id - Td_ji)
+            mp = np.kron(dij * Iu - Tu_ji, Td_ij)
+            out += e[i] * e[j] * 0.5 * (pm + mp)
+    return out
+
+
+def trotter_saf_ed(model: "pqmc.Model"):
+    """S_AFM = <sum_ij eps_i eps_j S_i . S_j> / N^2 of the Trotterised projector
+    estimate, by Fock-space linear algebra (the bra and ket of
+    ``trotter_energy_ed``; l_half = 0 gives the Gutzwiller state's value)."""
+    m = model
+    kin, dbl, su, sd = fock_operators(m.K, m.n[1], m.n[-1])
+    psi = np.kron(_slater(m.P[1], su), _slater(m.P[-1], sd))
+    pg = np.exp(-m.g * dbl)
+    eK = scipy.linalg.expm(-m.dtau * kin)
+    eV = np.exp(-m.dtau * m.U * dbl)
+    ket = pg * psi
+    bra = pg * psi
+    for _ in range(m.l_half):
+        ket = eK @ (eV * ket)
+        bra = eV * (eK.T @ bra)
+    S = fock_spin_afm(m.eps, su, sd, m.N)
+    return float(bra @ S @ ket / (bra @ ket)) / (m.N * m.N)
+
+
 def trotter_energy_ed(model: "pqmc.Model"):
     """(E_Trot / N, D_Trot) by Fock-space linear algebra (no auxiliary field)."""
     m = model
@@ -104,8 +157,10 @@ def trotter_energy_ed_projector(model: "pqmc.Model"):
     return float(psi @ H @ psi / (psi @ psi)) / m.N
 
 
-def enumerate_energy(model: "pqmc.Model", chunk: int = 1 << 14):
-    """(E/N, D, <sign>) summed exactly over all 2^{(M+2) N} field configurations.
+def enumerate_energy(model: "pqmc.Model", chunk: int = 1 << 14, with_saf: bool = False):
+    """(E/N, D, <sign>) summed exactly over all 2^{(M+2) N} field configurations
+    ((E/N, D, S_AFM, <sign>) with ``with_saf``, S_AFM from the oracle's Wick
+    estimator ``pqmc.structure_factor``).
 
     Weight W(s) = W_up(s) W_dn(s), W_sigma = det(P^T S_{M+1} ... S_0 P); the
     decoupling prefactors are the same for every configuration and cancel."""
@@ -114,7 +169,7 @@ def enumerate_energy(model: "pqmc.Model", chunk: int = 1 << 14):
     if n_f > 24:
         raise ValueError("too many fields to enumerate")
     total = 1 << n_f
-    num_e = num_d = den = asum = 0.0
+    num_e = num_d = num_s = den = asum = 0.0
     for start in range(0, total, chunk):
         idx = np.arange(start, min(total, start + chunk), dtype=np.int64)
         bits = ((idx[:, None] >> np.arange(n_f)) & 1).astype(np.int8)
@@ -143,6 +198,12 @@ def enumerate_energy(model: "pqmc.Model", chunk: int = 1 << 14):
         e = (ekin + m.U * docc.sum(axis=1)) / m.N
         num_e += float(np.sum(W * e))
         num_d += float(np.sum(W * docc.mean(axis=1)))
+        if with_saf:
+            saf = np.array([pqmc.structure_factor(m.eps, G[1][b], G[-1][b])
+                            for b in range(len(idx))])
+            num_s += float(np.sum(W * saf))
         den += float(np.sum(W))
         asum += float(np.sum(np.abs(W)))
+    if with_saf:
+        return num_e / den, num_d / den, num_s / den, den / asum
     return num_e / den, num_d / den, den / asum

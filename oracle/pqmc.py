@@ -203,6 +203,38 @@ def estimators(model, Gup, Gdn):
     return (ekin + model.U * float(docc.sum())) / N, float(docc.mean())
 
 
+def structure_factor(eps, Gup, Gdn):
+    """Staggered spin structure factor S_AFM = (1/N^2) sum_ij eps_i eps_j
+    <S_i . S_j> at one field configuration, written out term by term with
+    Wick's theorem (the spin sectors do not mix: the field couples to n_up -
+    n_dn).  With Gb_ij = <c_i^dag c_j> = delta_ij - G_ji and G_ij = <c_i c_j^dag>
+    for each spin:
+
+      <S^z_i S^z_j> = 1/4 sum_{s,s'} s s' <n_is n_js'>,
+        <n_is n_js>  = Gb^s_ii Gb^s_jj + Gb^s_ij G^s_ij,
+        <n_is n_j-s> = Gb^s_ii Gb^-s_jj;
+      <S^+_i S^-_j> = <c_i,up^dag c_j,up> <c_i,dn c_j,dn^dag> = Gb^up_ij G^dn_ij,
+      <S^-_i S^+_j> = Gb^dn_ij G^up_ij;
+      S_i . S_j = S^z_i S^z_j + (S^+_i S^-_j + S^-_i S^+_j) / 2.
+    """
+    N = len(eps)
+    e = np.asarray(eps, dtype=np.float64)
+    I = np.eye(N)
+    Gbu, Gbd = I - Gup.T, I - Gdn.T
+    nu, nd = np.diag(Gbu), np.diag(Gbd)
+    total = 0.0
+    for i in range(N):
+        for j in range(N):
+            uu = nu[i] * nu[j] + Gbu[i, j] * Gup[i, j]
+            dd = nd[i] * nd[j] + Gbd[i, j] * Gdn[i, j]
+            ud = nu[i] * nd[j]
+            du = nd[i] * nu[j]
+            szsz = 0.25 * (uu + dd - ud - du)
+            flip = 0.5 * (Gbu[i, j] * Gdn[i, j] + Gbd[i, j] * Gup[i, j])
+            total += e[i] * e[j] * (szsz + flip)
+    return total / (N * N)
+
+
 # --------------------------------------------------------------------------- #
 # the Markov chain
 # --------------------------------------------------------------------------- #
@@ -222,7 +254,7 @@ class Chain:
             field = philox.initial_field(seed, chain_id, model.n_slices, model.N)
         self.field = np.array(field, dtype=np.int8).reshape(model.n_slices, model.N).copy()
         self.sweep_index = 0
-        self.measurements = []          # (sign, E/N, D) per measurement
+        self.measurements = []          # (sign, E/N, D, S_AFM) per measurement
         self.ratios = {}                # (sweep, l, i) -> (r_up, r_dn, u, accepted)
         self.checkpoint_greens = []     # (sweep, p, G_up, G_dn, drift, field snapshot)
         self.sign_mismatches = 0
@@ -350,7 +382,8 @@ class Chain:
 
     def _measure(self):
         e, d = estimators(self.m, self.G[1], self.G[-1])
-        self.measurements.append((self.sign, e, d))
+        saf = structure_factor(self.m.eps, self.G[1], self.G[-1])
+        self.measurements.append((self.sign, e, d, saf))
 
     # -- passes ----------------------------------------------------------------
     def _up_pass(self, measure):

@@ -162,7 +162,7 @@ def test_free_fermion_energy_matches_closed_form(l_half):
                    m_neel=0.5, g=0.0, stab_interval=3)
     ch = pqmc.Chain(m, seed=1).sweep(2)
     ref = pqmc.free_energy_closed_form(K, m.P[1], m.P[-1], l_half * 0.1) / 16
-    for sgn, e, _ in ch.measurements:
+    for sgn, e, *_ in ch.measurements:
         assert sgn == 1
         assert math.isclose(e, ref, abs_tol=1e-12)
 

@@ -84,3 +84,30 @@ def test_markov_chain_agrees_with_exact(name):
     assert abs(e - e_ex) < 3.5 * de + 1e-12, (e, de, e_ex)
     assert abs(d - d_ex) < 3.5 * dd + 1e-12, (d, dd, d_ex)
     assert ch.sign_mismatches == 0
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_structure_factor_enumeration_equals_fock_space(name):
+    """S_AFM: the Wick estimator summed over every field configuration
+    against the spin operators in Fock space (pins every term of the Wick
+    expansion, including the spin-flip part)."""
+    m = CASES[name]()
+    _, _, s_en, _ = ed.enumerate_energy(m, with_saf=True)
+    s_ed = ed.trotter_saf_ed(m)
+    assert math.isclose(s_en, s_ed, rel_tol=1e-11, abs_tol=1e-12)
+
+
+def test_structure_factor_of_a_neel_product_state():
+    """A classical Neel state (one up spin on every A site, one down on every
+    B site) has <S^z_i S^z_j> = eps_i eps_j / 4 and no spin-flip correlation
+    off the diagonal: S_AFM = 1/4 + (3/4 - 1/4) / N, from the Wick estimator
+    with the Green's functions of that Slater determinant."""
+    N = 6
+    eps = np.array([1, -1] * 3)
+    occ_up = np.diag((eps > 0).astype(float))
+    occ_dn = np.diag((eps < 0).astype(float))
+    Gup, Gdn = np.eye(N) - occ_up, np.eye(N) - occ_dn       # G_ij = <c_i c_j^dag>
+    s = pqmc.structure_factor(eps, Gup, Gdn)
+    # S^z part: (sum_i eps_i S^z_i)^2 / N^2 = (N/2)^2 / N^2 = 1/4; flip part on
+    # the diagonal: <S^+_i S^-_i + S^-_i S^+_i>/2 = 1/2 per site
+    assert math.isclose(s, 0.25 + 0.5 / N, rel_tol=1e-14)
