@@ -145,10 +145,11 @@ def run_gpu(args, precision_name, steps, warmup, ns=None):
     wrap_ms, prop_ms, flush_ms = (t / max(n, 1) for t, n in kt)
     launches = {"wrap": kt[0][1], "prop": kt[1][1], "slice_update": kt[2][1]}
     rel = sorted(i["max_rel_drift"] for i in infos)
-    energy = sign = None
+    energy = sign = saf = None
     if args.chains * (steps + warmup) >= 20:
         rec = np.concatenate([ctx.measurements(c) for ctx in ctxs for c in range(per)])
         energy, sign = weighted_mean(rec, 1), weighted_mean(rec, 0)
+        saf = weighted_mean(rec, 3)
     res = dict(ms=ms, wall=wall, updates=n_updates, accept=acc / max(prop, 1),
                max_drift=max(i["max_drift"] for i in infos),
                rel_drift={"max": rel[-1], "median": rel[len(rel) // 2],
@@ -157,7 +158,7 @@ def run_gpu(args, precision_name, steps, warmup, ns=None):
                flags=sorted({i["flags"] for i in infos}),
                sign_mismatch=sum(i["sign_mismatch"] for i in infos),
                wrap_ms=wrap_ms, prop_ms=prop_ms, flush_ms=flush_ms, launches=launches,
-               graph_ms=graph_ms, sign=sign, energy=energy)
+               graph_ms=graph_ms, sign=sign, energy=energy, structure_factor=saf)
     log(f"[{precision_name}] {steps} sweeps: {ms:.1f} ms (wall {wall * 1e3:.1f} ms), "
         f"{n_updates / (ms / 1e3):.4g} updates/s, acceptance {res['accept']:.3f}, "
         f"slice update {flush_ms:.3f} ms/launch, wrap GEMM {wrap_ms:.3f} ms/launch, "
@@ -296,7 +297,7 @@ def main():
             "delay_rank": args.k, "acceptance": round(main_res["accept"], 4),
             "max_drift": main_res["max_drift"], "rel_drift": main_res["rel_drift"],
             "flags": main_res["flags"], "energy_per_site": main_res["energy"],
-            "sign": main_res["sign"],
+            "structure_factor": main_res["structure_factor"], "sign": main_res["sign"],
         },
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,

@@ -139,7 +139,7 @@ gpqmc_status gpqmc_bind_workspace(gpqmc_ctx* ctx, void* device_ptr, size_t bytes
  * measurements and flags.  Synchronises.  Errors: ESTATE before bind. */
 gpqmc_status gpqmc_init_trial(gpqmc_ctx* ctx);
 
-/* Run n_sweeps passes.  measure != 0 records (sign, E/N, D) at tau = Theta
+/* Run n_sweeps passes.  measure != 0 records (sign, E/N, D, S_AFM) at tau = Theta
  * once per pass from the freshly recomputed Green's function.  Enqueue only.
  * Errors: ESTATE before init_trial. */
 gpqmc_status gpqmc_sweep(gpqmc_ctx* ctx, int32_t n_sweeps, int32_t measure);
@@ -147,15 +147,21 @@ gpqmc_status gpqmc_sweep(gpqmc_ctx* ctx, int32_t n_sweeps, int32_t measure);
 /* Sign-weighted estimates over the stored records of one chain
  * (chain = -1: all chains pooled), error by jackknife over bins of
  * 10 records: energy per site E/N = <s E>/<s> (Eq. 2 with U n_up n_dn),
- * double occupancy <s D>/<s>, average sign <s>.  Synchronises.
+ * double occupancy <s D>/<s>, average sign <s>, and the staggered spin
+ * structure factor S_AFM = (1/N^2) sum_ij eps_i eps_j <S_i . S_j> with the
+ * chain's sublattice signs eps (the antiferromagnetic order of the Hubbard
+ * study: Eq. 2 and the Results section).  Synchronises.
  * Errors: EINVAL (chain out of range or fewer than 20 records). */
 gpqmc_status gpqmc_measure_energy(gpqmc_ctx* ctx, int32_t chain, double* mean, double* err);
 gpqmc_status gpqmc_measure_double_occupancy(gpqmc_ctx* ctx, int32_t chain, double* mean,
                                             double* err);
 gpqmc_status gpqmc_measure_sign(gpqmc_ctx* ctx, int32_t chain, double* mean, double* err);
+gpqmc_status gpqmc_measure_structure_factor(gpqmc_ctx* ctx, int32_t chain, double* mean,
+                                            double* err);
 
-/* Raw records (sign, E/N, D) of one chain, oldest first; *n_out receives the
- * number written (<= capacity).  Synchronises. */
+/* Raw records of one chain, oldest first, four doubles each: (sign, E/N, D,
+ * S_AFM); out holds capacity records (4 * capacity doubles).  *n_out
+ * receives the number written (<= capacity).  Synchronises. */
 gpqmc_status gpqmc_get_measurements(gpqmc_ctx* ctx, int32_t chain, double* out,
                                     int32_t capacity, int32_t* n_out);
 

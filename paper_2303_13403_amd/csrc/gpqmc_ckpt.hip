@@ -657,23 +657,44 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const ChainDev* __restric
     st->gmax_bits = 0u;
   }
   if (mode != 2 && measure_here && ctl->measure) {
-    double ek = 0.0, dsum = 0.0;
+    // Wick estimates from the fresh FP64 G of both spins, G_ij = <c_i c_j^dag>
+    // and Gb_ij = <c_i^dag c_j> = delta_ij - G_ji: the energy, the double
+    // occupancy, and the staggered structure factor
+    //   N^2 S_AFM = sum_ij eps_i eps_j <S_i . S_j>
+    //             = mz^2 / 4 + sum_ij eps_i eps_j [(Gb^up_ij G^up_ij + Gb^dn_ij G^dn_ij) / 4
+    //                                            + (Gb^up_ij G^dn_ij + Gb^dn_ij G^up_ij) / 2],
+    //   mz = sum_i eps_i (Gb^up_ii - Gb^dn_ii)
+    const GLOBAL double* __restrict__ Gu = gp((const double*)C.G64[0]);
+    const GLOBAL double* __restrict__ Gd = gp((const double*)C.G64[1]);
+    const GLOBAL int8_t* __restrict__ eps = gp(C.eps);
+    double ek = 0.0, dsum = 0.0, spair = 0.0, mz = 0.0;
     for (int idx = tid; idx < N * N; idx += kThreads) {
       const int i = idx / N, j = idx - i * N;
+      const double dij = i == j ? 1.0 : 0.0;
+      const double gu = Gu[idx], gd = Gd[idx];
+      const double gbu = dij - Gu[(size_t)j * N + i], gbd = dij - Gd[(size_t)j * N + i];
       const double k = C.Khop[idx];
-      if (k != 0.0)
-        ek += k * ((i == j ? 2.0 : 0.0) - C.G64[0][(size_t)j * N + i] - C.G64[1][(size_t)j * N + i]);
+      if (k != 0.0) ek += k * (gbu + gbd);
+      const double ee = (double)eps[i] * (double)eps[j];
+      spair += ee * (0.25 * (gbu * gu + gbd * gd) + 0.5 * (gbu * gd + gbd * gu));
     }
-    for (int i = tid; i < N; i += kThreads)
-      dsum += (1.0 - C.G64[0][(size_t)i * N + i]) * (1.0 - C.G64[1][(size_t)i * N + i]);
+    for (int i = tid; i < N; i += kThreads) {
+      const double nu = 1.0 - Gu[(size_t)i * N + i], nd = 1.0 - Gd[(size_t)i * N + i];
+      dsum += nu * nd;
+      mz += (double)eps[i] * (nu - nd);
+    }
     ek = block_sum(ek, red);
     dsum = block_sum(dsum, red);
+    spair = block_sum(spair, red);
+    mz = block_sum(mz, red);
     if (tid == 0) {
       const int k = st->n_meas;
       if (k < C.meas_cap) {
-        C.meas[3 * k + 0] = (double)st->sign;
-        C.meas[3 * k + 1] = (ek + C.U_hub * dsum) / N;
-        C.meas[3 * k + 2] = dsum / N;
+        double* r = C.meas + (size_t)kMeasCols * k;
+        r[0] = (double)st->sign;
+        r[1] = (ek + C.U_hub * dsum) / N;
+        r[2] = dsum / N;
+        r[3] = (0.25 * mz * mz + spair) / ((double)N * N);
         st->n_meas = k + 1;
       } else {
         st->flags |= FLAG_MEAS_FULL;

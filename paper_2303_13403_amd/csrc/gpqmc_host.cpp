@@ -126,10 +126,11 @@ struct ChainHost {
   bool trace;
   bool field_set = false;
   std::vector<int8_t> field;
+  std::vector<int8_t> eps;    // sublattice signs (staggered structure factor)
   // workspace offsets
   size_t G[2], Gtmp[2], U2[2][2], Z[2], Xa[2], Ya[2], scan_ws[2], flist;
   size_t stack[2], slot_log[2], slot_sgn[2], Hw[2], Qc[2], Wm[2], Rinv[2], Xm[2], Ym[2], G64[2];
-  size_t field_off, st, meas, tr_ratio = 0, tr_green = 0, tr_drift = 0;
+  size_t field_off, eps_off, st, meas, tr_ratio = 0, tr_green = 0, tr_drift = 0;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -568,6 +569,7 @@ gpqmc_status gpqmc_create(int32_t n_chains, const gpqmc_chain_desc* chains,
       h.trial[sp] = jt->second;
     }
     h.field.assign((size_t)c->n_slices * N, 1);
+    h.eps.assign(d.sublattice, d.sublattice + N);
     c->ch.push_back(std::move(h));
   }
 
@@ -615,9 +617,10 @@ gpqmc_status gpqmc_create(int32_t n_chains, const gpqmc_chain_desc* chains,
       h.G64[sp] = take(nn * 8);
     }
     h.field_off = take((size_t)c->n_slices * N);
+    h.eps_off = take((size_t)N);
     h.st = take(sizeof(ChainState));
     h.flist = take((size_t)kSegMax * 4);
-    h.meas = take((size_t)c->meas_cap * 3 * 8);
+    h.meas = take((size_t)c->meas_cap * kMeasCols * 8);
     if (h.trace) {
       h.tr_ratio = take((size_t)c->n_slices * N * 2 * 8);
       h.tr_green = take((size_t)nck * 2 * nn * 8);
@@ -731,6 +734,7 @@ gpqmc_status gpqmc_bind_workspace(gpqmc_ctx* ctx, void* device_ptr, size_t bytes
     d.Kp = ctx->ws + L.off_Kp;
     d.Khop = ctx->at<double>(L.off_K);
     d.field = ctx->at<int8_t>(h.field_off);
+    d.eps = ctx->at<int8_t>(h.eps_off);
     d.st = ctx->at<ChainState>(h.st);
     d.flist = ctx->at<int>(h.flist);
     d.meas = ctx->at<double>(h.meas);
@@ -809,6 +813,8 @@ gpqmc_status gpqmc_bind_workspace(gpqmc_ctx* ctx, void* device_ptr, size_t bytes
     }
   }
   HIPCHK(up(ctx->off_chains, cd.data(), sizeof(ChainDev) * nc), "upload chains");
+  for (int i = 0; i < nc; ++i)
+    HIPCHK(up(ctx->ch[i].eps_off, ctx->ch[i].eps.data(), ctx->ch[i].eps.size()), "upload eps");
   for (int k = 0; k < E_COUNT; ++k)
     HIPCHK(up(ctx->off_ent[k], E[k].data(), sizeof(GemmEntry) * E[k].size()), "upload entries");
   for (int t = 0; t < T_COUNT; ++t)
@@ -902,28 +908,29 @@ gpqmc_status fetch_records(gpqmc_ctx* ctx, int chain, std::vector<double>& rec) 
     ChainState st;
     HIPCHK(hipMemcpy(&st, ctx->ws + ctx->ch[c].st, sizeof st, hipMemcpyDeviceToHost), "state");
     const size_t b = rec.size();
-    rec.resize(b + (size_t)st.n_meas * 3);
+    rec.resize(b + (size_t)st.n_meas * kMeasCols);
     if (st.n_meas > 0)
-      HIPCHK(hipMemcpy(rec.data() + b, ctx->ws + ctx->ch[c].meas, (size_t)st.n_meas * 3 * 8,
+      HIPCHK(hipMemcpy(rec.data() + b, ctx->ws + ctx->ch[c].meas, (size_t)st.n_meas * kMeasCols * 8,
                        hipMemcpyDeviceToHost), "records");
   }
   return GPQMC_OK;
 }
 
 // <s O>/<s> with a delete-one-bin jackknife over bins of 10 records;
-// which = 0: sign itself (plain binned mean), 1: energy, 2: double occupancy.
+// which = 0: sign itself (plain binned mean), 1: energy, 2: double occupancy,
+// 3: staggered structure factor.
 gpqmc_status weighted(gpqmc_ctx* ctx, int chain, int which, double* mean, double* err) {
   if (!ctx || !mean || !err) return GPQMC_EINVAL;
   if (chain < -1 || chain >= ctx->n_chains) return fail(ctx, GPQMC_EINVAL, "chain out of range");
   std::vector<double> rec;
   gpqmc_status st = fetch_records(ctx, chain, rec);
   if (st != GPQMC_OK) return st;
-  const size_t n = rec.size() / 3, bin = 10, nb = n / bin;
+  const size_t n = rec.size() / kMeasCols, bin = 10, nb = n / bin;
   if (nb < 2) return fail(ctx, GPQMC_EINVAL, "fewer than 20 measurement records");
   std::vector<double> s(nb, 0.0), so(nb, 0.0);
   for (size_t b = 0; b < nb; ++b)
     for (size_t k = 0; k < bin; ++k) {
-      const double* r = &rec[(b * bin + k) * 3];
+      const double* r = &rec[(b * bin + k) * kMeasCols];
       s[b] += r[0] / bin;
       so[b] += (which == 0 ? r[0] : r[0] * r[which]) / bin;
     }
@@ -967,6 +974,10 @@ gpqmc_status gpqmc_measure_double_occupancy(gpqmc_ctx* ctx, int32_t chain, doubl
 gpqmc_status gpqmc_measure_sign(gpqmc_ctx* ctx, int32_t chain, double* mean, double* err) {
   return weighted(ctx, chain, 0, mean, err);
 }
+gpqmc_status gpqmc_measure_structure_factor(gpqmc_ctx* ctx, int32_t chain, double* mean,
+                                            double* err) {
+  return weighted(ctx, chain, 3, mean, err);
+}
 
 gpqmc_status gpqmc_get_measurements(gpqmc_ctx* ctx, int32_t chain, double* out, int32_t capacity,
                                     int32_t* n_out) {
@@ -974,8 +985,8 @@ gpqmc_status gpqmc_get_measurements(gpqmc_ctx* ctx, int32_t chain, double* out, 
   std::vector<double> rec;
   gpqmc_status st = fetch_records(ctx, chain, rec);
   if (st != GPQMC_OK) return st;
-  const int n = std::min<int>((int)(rec.size() / 3), capacity);
-  memcpy(out, rec.data(), (size_t)n * 3 * 8);
+  const int n = std::min<int>((int)(rec.size() / kMeasCols), capacity);
+  memcpy(out, rec.data(), (size_t)n * kMeasCols * 8);
   *n_out = n;
   return GPQMC_OK;
 }

@@ -10,6 +10,7 @@ namespace gpqmc {
 constexpr int kThreads = 256;   // every kernel runs 256-thread workgroups (4 waves)
 constexpr int kBlock = 32;      // submatrix block of the flip scan (sites)
 constexpr int kSegMax = 64;     // largest delay rank: sites per scan segment
+constexpr int kMeasCols = 4;    // measurement record: sign, E/N, D, S_AFM
 constexpr int kMaxSites = 1024; // largest lattice
 constexpr int kTile = 64;       // GEMM output tile (kTile x kTile per workgroup)
 constexpr int kLdsDense = 128;  // small dense factorisations run in LDS up to this order
@@ -121,8 +122,9 @@ struct ChainDev {
   double* Ym[2];        // (L R)^{-1} L  (n x N)
   double* G64[2];       // last fresh Green's function (unscaled, at its checkpoint)
   int8_t* field;        // n_slices x N
+  const int8_t* eps;    // sublattice signs (N)
   ChainState* st;
-  double* meas;         // records (sign, E/N, D)
+  double* meas;         // records (sign, E/N, D, S_AFM), kMeasCols each
   int meas_cap;
   int pad2;
   double* trace_ratio;  // optional: (n_slices * N) x 2 ratios of the last pass

@@ -57,7 +57,8 @@ _lib = None
 EXPORTS = [
     "gpqmc_create", "gpqmc_workspace_bytes", "gpqmc_bind_workspace", "gpqmc_init_trial",
     "gpqmc_sweep", "gpqmc_measure_energy", "gpqmc_measure_double_occupancy",
-    "gpqmc_measure_sign", "gpqmc_get_measurements", "gpqmc_reset_measurements",
+    "gpqmc_measure_sign", "gpqmc_measure_structure_factor", "gpqmc_get_measurements",
+    "gpqmc_reset_measurements",
     "gpqmc_set_field", "gpqmc_get_field", "gpqmc_get_green", "gpqmc_get_chain_info",
     "gpqmc_set_debug", "gpqmc_get_trace", "gpqmc_debug_gemm", "gpqmc_chain_status",
     "gpqmc_time_kernel", "gpqmc_set_kernel_timing", "gpqmc_get_kernel_timing",
@@ -84,6 +85,7 @@ def load():
         "gpqmc_measure_energy": [VP, I32, P(D), P(D)],
         "gpqmc_measure_double_occupancy": [VP, I32, P(D), P(D)],
         "gpqmc_measure_sign": [VP, I32, P(D), P(D)],
+        "gpqmc_measure_structure_factor": [VP, I32, P(D), P(D)],
         "gpqmc_get_measurements": [VP, I32, P(D), I32, P(I32)],
         "gpqmc_reset_measurements": [VP],
         "gpqmc_set_field": [VP, I32, P(ctypes.c_int8)],
@@ -221,8 +223,12 @@ class Context:
     def measure_sign(self, chain: int = -1):
         return self._measure("gpqmc_measure_sign", chain)
 
+    def measure_structure_factor(self, chain: int = -1):
+        """S_AFM = (1/N^2) sum_ij eps_i eps_j <S_i . S_j> (sign-weighted)."""
+        return self._measure("gpqmc_measure_structure_factor", chain)
+
     def measurements(self, chain: int, capacity: int = 1 << 16) -> np.ndarray:
-        buf = np.zeros((capacity, 3), np.float64)
+        buf = np.zeros((capacity, 4), np.float64)       # sign, E/N, D, S_AFM
         n = ctypes.c_int32()
         self._call("gpqmc_get_measurements", chain, _dptr(buf), capacity, ctypes.byref(n))
         return buf[: n.value].copy()

@@ -30,7 +30,8 @@ def variational_scan(workload: Workload, gs: Sequence[float], m_neels: Sequence[
     """Sample E/N at Theta = 0 on the grid gs x m_neels.
 
     Returns ``(points, stats)``: one dict per grid point (g, m_neel, energy,
-    double_occupancy and sign as (mean, error), the records used) and a dict
+    double_occupancy, structure_factor and sign as (mean, error), the records
+    used) and a dict
     with the batch size, the timed sweeps and the HS-field updates per second.
     Chain ids are point * chains_per_point + c, so every chain draws its own
     Philox stream."""
@@ -59,6 +60,7 @@ def variational_scan(workload: Workload, gs: Sequence[float], m_neels: Sequence[
             points.append(dict(g=g, m_neel=m, records=len(rec),
                                energy=weighted_mean(rec, 1),
                                double_occupancy=weighted_mean(rec, 2),
+                               structure_factor=weighted_mean(rec, 3),
                                sign=weighted_mean(rec, 0)))
             if log is not None:
                 e = points[-1]["energy"]

@@ -1,7 +1,7 @@
 """Theta = 0 (variational) scans over the trial parameters (g, M_N) on the
 HIP path, against the oracle: the Markov trajectory with only the two
-projector slices, and the sampled variational energy against the exact
-Fock-space value <psi_G|H|psi_G>/<psi_G|psi_G> of tiny clusters."""
+projector slices, and the sampled variational energy and staggered structure
+factor against the exact Fock-space values of tiny clusters."""
 import numpy as np
 import pytest
 
@@ -65,6 +65,10 @@ def test_variational_scan_matches_exact_energies_2x2():
         assert p["records"] == 512 * 100
         assert 0 < err < 0.01
         assert abs(e - exact[(p["g"], p["m_neel"])]) < 4 * err + 1e-12, (p, exact)
+        # the staggered structure factor of the same state, exact in Fock space
+        s, serr = p["structure_factor"]
+        s_ex = ed.trotter_saf_ed(m)
+        assert 0 < serr < 0.01 and abs(s - s_ex) < 4 * serr + 1e-12, (p, s_ex)
     best = optimum(pts)
     ex_best = min(exact, key=exact.get)
     # the best exact energy is several standard errors clear of the next
