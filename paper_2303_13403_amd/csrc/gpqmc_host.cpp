@@ -163,6 +163,7 @@ struct gpqmc_ctx {
   std::vector<TileRef> tiles[6];
   size_t off_tiles[6] = {0};
   int n_min = 1 << 30;             // smallest lattice of the batch
+  bool large_tiles = true;         // every lattice fills 128 x 128 GEMM tiles well
   char* ws = nullptr;
   bool bound = false, initialized = false;
   long long sweeps_done = 0;       // passes enqueued since init_trial (mirrors the device counter)
@@ -262,7 +263,7 @@ struct Launcher {
     // lattices with N >= 128: the FP32 N x N x N products (wrap, slice
     // update) on the large-tile kernel; in FP64 the mode where the large tile
     // measured faster than the 64 x 64 kernel (the scaled wrap)
-    if (ctx->n_min >= 128) {
+    if (ctx->large_tiles) {
       const bool nnn = tk == T_NN && (mode == GM_STORE || mode == GM_WRAP || mode == GM_FLUSH);
       if (f32 && nnn)
         return launch_gemm_l(mode, ents(ctx, kind), ctx->at<TileRef>(ctx->off_tiles[T_NN_L]),
@@ -634,6 +635,11 @@ gpqmc_status gpqmc_create(int32_t n_chains, const gpqmc_chain_desc* chains,
   for (auto& h : c->ch) {
     c->n_max = std::max(c->n_max, h.N);
     c->n_min = std::min(c->n_min, h.N);
+    // 128 x 128 tiles for N >= 128 while at least 3/4 of the padded tile grid
+    // is real work (at N = 288, 56%, the 64 x 64 kernel measured 6% faster
+    // per sweep)
+    const long long padded = 128LL * ((h.N + 127) / 128);
+    if (h.N < 128 || 4LL * h.N * h.N < 3 * padded * padded) c->large_tiles = false;
     c->n_part = std::max(c->n_part, std::max(h.n[0], h.n[1]));
     for (int sp = 0; sp < 2; ++sp) {
       sz[T_NN].push_back({h.N, h.N});
