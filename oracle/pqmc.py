@@ -257,6 +257,7 @@ class Chain:
         self.measurements = []          # (sign, E/N, D, S_AFM) per measurement
         self.ratios = {}                # (sweep, l, i) -> (r_up, r_dn, u, accepted)
         self.checkpoint_greens = []     # (sweep, p, G_up, G_dn, drift, field snapshot)
+        self.checkpoint_logdets = []    # (sweep, p, {spin: (log|det(L_p R_p)|, sign)})
         self.sign_mismatches = 0
         self.max_drift = 0.0
         self.record_ratios = False
@@ -358,6 +359,7 @@ class Chain:
         m = self.m
         wsign = 1
         fresh = {}
+        logdet = {}
         drift = 0.0
         for s in SPINS:
             Q, lg, sg = self._orthonormalise(*run[s])
@@ -365,13 +367,17 @@ class Chain:
             Qo, lgo, sgo = self.stack[(p, s)]
             R, Lt = (Q, Qo) if up else (Qo, Q)
             X = Lt.T @ R
-            sgX, _ = np.linalg.slogdet(X)
+            sgX, lgX = np.linalg.slogdet(X)
             Gf = np.eye(m.N) - R @ np.linalg.solve(X, Lt.T)
             drift = max(drift, float(np.max(np.abs(self.G[s] - Gf))))
             fresh[s] = Gf
             self.G[s] = Gf
             self.stack[(p, s)] = (Q, lg, sg)
-            wsign *= int(sg * sgo * np.sign(sgX))
+            # W_sigma = det(L_p R_p) = det(T_L) det(T_R) det(Q_L^T Q_R): the
+            # accumulated triangular factors of both sides and the overlap
+            logdet[s] = (lg + lgo + float(lgX), int(sg * sgo * np.sign(sgX)))
+            wsign *= logdet[s][1]
+        self.checkpoint_logdets.append((self.sweep_index, p, logdet))
         self.max_drift = max(self.max_drift, drift)
         if wsign != self.sign:
             self.sign_mismatches += 1

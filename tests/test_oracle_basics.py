@@ -174,3 +174,22 @@ def test_free_fermion_long_projection_reaches_ground_state():
                    m_neel=0.5, g=0.0, stab_interval=4)
     ch = pqmc.Chain(m, seed=2).sweep(1)
     assert math.isclose(ch.measurements[0][1] * 16, -24.0, abs_tol=1e-8)
+
+
+def test_jackknife_reduces_to_binned_standard_error_without_sign():
+    """With every sign +1 the jackknife of sum(s O)/sum(s) is the standard
+    error of the bin means (delete-one estimates of a plain mean are the mean
+    shifted by (m - b_k)/(nb - 1)); a constant observable has zero error."""
+    from oracle import stats
+    rng = np.random.default_rng(3)
+    obs = rng.normal(size=200)
+    m1, e1 = stats.sign_weighted(np.ones(200), obs, bin_size=10)
+    bins = obs.reshape(20, 10).mean(axis=1)
+    assert m1 == pytest.approx(obs.mean(), rel=1e-13)
+    assert e1 == pytest.approx(bins.std(ddof=1) / np.sqrt(20), rel=1e-12)
+    m2, e2 = stats.mean_error(obs, bin_size=10)
+    assert (m2, e2) == pytest.approx((m1, e1), rel=1e-12)
+    signs = rng.choice([-1.0, 1.0], size=200, p=[0.3, 0.7])
+    m3, e3 = stats.sign_weighted(signs, np.full(200, 2.5), bin_size=10)
+    assert m3 == pytest.approx(2.5, rel=1e-14) and e3 < 1e-13
+

@@ -146,3 +146,32 @@ def test_doped_chain_tracks_sign_consistently():
     ch = pqmc.Chain(m, seed=9).sweep(6)
     assert ch.sign_mismatches == 0
     assert ch.max_drift < 1e-9
+
+
+@pytest.mark.parametrize("n_el,U,dtau,seed,tol", [(8, 4.0, 0.1, 11, 1e-10),
+                                                   (5, 10.0, 0.5, 8, 1e-8)])
+def test_checkpoint_logdet_equals_plain_product_determinant(n_el, U, dtau, seed, tol):
+    """log|W_sigma| and sgn W_sigma that a checkpoint assembles from the
+    accumulated triangular factors of both stored bases and det(L_p R_p) of the
+    orthonormal ones equal log|det(P^T S_{M+1} ... S_0 P)| of the plain product
+    of the same field (M = 6, so the product needs no stabilisation).  Covers
+    an up and a down pass, a half-filled lattice and a strongly coupled doped
+    one (dtau U = 5) whose trajectory visits a negative single-spin weight.
+    There |W| reaches 1e43 and the unstabilised product itself carries a
+    relative error near 1e-9, hence the looser tolerance on log|W|."""
+    m = _model(n=n_el, U=U, l_half=3, n_s=2, dtau=dtau)
+    c = pqmc.Chain(m, seed=seed, chain_id=0)
+    c.record_greens = True
+    c.sweep(2, measure=False)
+    assert len(c.checkpoint_logdets) == len(c.checkpoint_greens) > 6
+    negative = 0
+    for (sw, p, ld), (sw2, p2, _, _, _, fsnap) in zip(c.checkpoint_logdets, c.checkpoint_greens):
+        assert (sw, p) == (sw2, p2)
+        for s in pqmc.SPINS:
+            w = pqmc.weight(m, fsnap, s)
+            logabs, sgn = ld[s]
+            assert sgn == (1 if w > 0 else -1)
+            assert abs(logabs - math.log(abs(w))) < tol * max(1.0, abs(logabs))
+            negative += sgn < 0
+    if n_el != 8:
+        assert negative > 0, "the doped case should visit negative single-spin weights"
