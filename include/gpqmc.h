@@ -53,15 +53,29 @@ typedef enum {
   GPQMC_ESTATE = -6       /* call out of order (e.g. sweep before init_trial) */
 } gpqmc_status;
 
-/* GPQMC_FP64: every step in FP64 (FP64 MFMA for the contractions).
- * GPQMC_MIXED: the Green's-function work of every slice (kinetic wrap, delayed
- *   flush, submatrix scan) in FP32 on FP32 MFMA with FP32 accumulation; basis
- *   propagation, QR, (L R)^{-1}, the fresh Green's function, log|det| and sign
- *   in FP64.
+/* GPQMC_FP64: every step in FP64, with the equal-time Green's function kept
+ *   in factored form G = 1 - A B^T (A, B of size N x n_sigma; G itself is the
+ *   Method section's 1 - R (L R)^{-1} L).  Wrapping G over a slice is then the
+ *   propagation of both factors by e^{-+dtau K} e^{+-V} (2 N^2 n_sigma flops
+ *   each instead of 2 N^3 per side for the N x N matrix), and the flips of a
+ *   delay segment reach the factors by the Woodbury identity.
+ * GPQMC_FP64_WRAP: every step in FP64 with G wrapped as an N x N matrix,
+ *   e^{-dtau K} G e^{+dtau K}, and the basis propagated separately.
+ * GPQMC_MIXED: as GPQMC_FP64_WRAP but the Green's-function work of every slice
+ *   (kinetic wrap, delayed flush, submatrix scan) in FP32 on FP32 MFMA with
+ *   FP32 accumulation; basis propagation, QR, (L R)^{-1}, the fresh Green's
+ *   function, log|det| and sign in FP64.  While sampling the doped 16 x 16
+ *   workload its Green's function drifts far beyond 1e-5 relative between
+ *   re-stabilisations (the drift flag reports it).
  * GPQMC_MIXED_FP32_BASIS: as GPQMC_MIXED but the basis propagation e^{-dtau K}
  *   e^{V} U also in FP32 (its fresh Green's function carries an error of order
  *   eps_fp32 cond(L R), about 1e-5 on a 12 x 12 lattice). */
-typedef enum { GPQMC_FP64 = 0, GPQMC_MIXED = 1, GPQMC_MIXED_FP32_BASIS = 2 } gpqmc_precision;
+typedef enum {
+  GPQMC_FP64 = 0,
+  GPQMC_MIXED = 1,
+  GPQMC_MIXED_FP32_BASIS = 2,
+  GPQMC_FP64_WRAP = 3
+} gpqmc_precision;
 
 /* One Markov chain.  All chains of one context must share l_half,
  * stab_interval, delay_rank and precision; lattices, fillings and couplings
@@ -94,8 +108,8 @@ typedef struct {
   int32_t use_graph;          /* capture each pass in a HIP graph (default 1) */
   double drift_tol;           /* relative checkpoint drift (max |G_wrapped - G_fresh|
                                  over max |G_fresh|) above which a chain is flagged
-                                 (default 1e-1 with an FP32 Green's function,
-                                 1e-6 fp64) */
+                                 (default 1e-5, the mixed path's stated accuracy,
+                                 with an FP32 Green's function; 1e-6 in FP64) */
 } gpqmc_options;
 
 typedef struct {
@@ -181,6 +195,16 @@ gpqmc_status gpqmc_get_green(gpqmc_ctx* ctx, int32_t chain, int32_t spin, double
 /* Status record of one chain.  Synchronises. */
 gpqmc_status gpqmc_get_chain_info(gpqmc_ctx* ctx, int32_t chain, gpqmc_chain_info* info);
 
+/* log|W_sigma| and sgn W_sigma of the last checkpoint of one chain, where
+ * W_sigma = det(P_sigma^T S_{M+1} ... S_0 P_sigma) = det(L_p R_p) is the weight
+ * of spin sigma at the current field (Method section: the projected overlap
+ * whose ratio the flips sample).  It is assembled in FP64 from the
+ * accumulated log|det| of the triangular factors of both re-orthonormalised
+ * bases and log|det(L R)| of the orthonormal ones.  logabs and sign are
+ * caller arrays of two entries (spin up, down).  Valid after init_trial
+ * (position -1) and after every pass.  Synchronises.  Errors: EINVAL, ESTATE. */
+gpqmc_status gpqmc_logdet(gpqmc_ctx* ctx, int32_t chain, double* logabs, int32_t* sign);
+
 /* Testing hooks (off the hot path).
  * set_debug: bit 0 = reject every proposal (fixed-field parity runs).
  * get_trace: for a chain created with trace != 0, the ratios (r_up, r_dn) of
@@ -191,6 +215,11 @@ gpqmc_status gpqmc_get_chain_info(gpqmc_ctx* ctx, int32_t chain, gpqmc_chain_inf
 gpqmc_status gpqmc_set_debug(gpqmc_ctx* ctx, int32_t flags);
 gpqmc_status gpqmc_get_trace(gpqmc_ctx* ctx, int32_t chain, double* ratios, double* greens,
                              double* drifts, int32_t* n_checkpoints);
+
+/* For a chain created with trace != 0: (log|W_sigma|, sgn W_sigma) of spin
+ * up then down at every checkpoint of the last pass, n_ck x 2 x 2 doubles in
+ * pass order (see gpqmc_logdet).  Synchronises.  Errors: EINVAL. */
+gpqmc_status gpqmc_get_trace_logdet(gpqmc_ctx* ctx, int32_t chain, double* logdets);
 
 /* GEMM self test on caller device memory: C = op(A) B with one of the
  * library's MFMA tile kernels (precision GPQMC_FP64 or GPQMC_MIXED = FP32).
@@ -205,21 +234,27 @@ gpqmc_status gpqmc_debug_gemm(int32_t precision, int32_t M, int32_t N, int32_t K
 
 /* Average duration (ms) of one launch of a hot-path kernel for all chains,
  * timed with HIP events on the context's stream over reps back-to-back
- * launches on the chains' current data: kernel 0 = the kinetic-wrap GEMM
- * e^{-dtau K} G (every chain and spin), 1 = the basis-propagation GEMM,
- * 2 = the delayed update of the last slice, G - Xa Ya (its result goes to the
- * wrap scratch, G is left unchanged; meaningful after a sweep).
- * Writes only scratch that every pass rebuilds.  Synchronises.
- * Errors: ESTATE before init_trial. */
+ * launches on the chains' current data.  G-wrap engines: kernel 0 = the
+ * kinetic-wrap GEMM e^{-dtau K} G (every chain and spin), 1 = the
+ * basis-propagation GEMM, 2 = the delayed update of the last slice, G - Xa Ya
+ * (its result goes to the wrap scratch, G is left unchanged; meaningful after
+ * a sweep).  GPQMC_FP64 (factored): kernel 0 = the propagation of both
+ * factors of every chain and spin (into the idle buffers of the ping-pong
+ * pairs); kernels 1 and 2 are EINVAL.  Writes only scratch that every pass
+ * rebuilds.  Synchronises.  Errors: ESTATE before init_trial, EINVAL. */
 gpqmc_status gpqmc_time_kernel(gpqmc_ctx* ctx, int32_t kernel, int32_t reps, float* ms_per_launch);
 
 /* In-sweep kernel timing.  Bit t of mask (0..7) records a HIP event pair on
  * the context's stream around every launch, inside later sweeps, of timed
- * kernel t: 0 = the kinetic-wrap GEMM e^{-dtau K} G of every slice, 1 = the
- * B-scaled basis-propagation GEMM, 2 = the slice's delayed update
- * G <- D (G - Xa Ya) D^{-1}.  While mask is nonzero the passes are launched
- * directly rather than as HIP graphs.  Setting a mask (0 included) clears the
- * recorded launches.  Synchronises.  Errors: EINVAL for a mask outside 0..7. */
+ * kernel t.  G-wrap engines: 0 = the kinetic-wrap GEMM e^{-dtau K} G of every
+ * slice, 1 = the B-scaled basis-propagation GEMM, 2 = the slice's delayed
+ * update G <- D (G - Xa Ya) D^{-1}.  GPQMC_FP64 (factored): 0 = the
+ * propagation of both factors (one launch per bulk slice), 1 = the segment
+ * update of the dual factor Q <- Q - (Q Mf^T) Wf (one per delay segment),
+ * 2 = the flip scan (one per delay segment).  While mask is nonzero the
+ * passes are launched directly rather than as HIP graphs.  Setting a mask (0
+ * included) clears the recorded launches.  Synchronises.  Errors: EINVAL for a
+ * mask outside 0..7. */
 gpqmc_status gpqmc_set_kernel_timing(gpqmc_ctx* ctx, int32_t mask);
 
 /* Sum of the durations (ms) and the number of the launches of timed kernel
@@ -228,7 +263,8 @@ gpqmc_status gpqmc_set_kernel_timing(gpqmc_ctx* ctx, int32_t mask);
 gpqmc_status gpqmc_get_kernel_timing(gpqmc_ctx* ctx, int32_t kernel, float* total_ms,
                                      int32_t* launches);
 
-/* Debugging hooks (off the hot path; synchronise).  debug_step runs one
+/* Debugging hooks of the G-wrap engines (off the hot path; synchronise;
+ * GPQMC_FP64 contexts return EINVAL).  debug_step runs one
  * stage of slice l on every chain: 0 = the flip scan of sites [s0, s1),
  * 1 = appending that segment's factors to the slice's delayed update
  * G - Xa Ya, 2 = applying the delayed update to G (no frame change).

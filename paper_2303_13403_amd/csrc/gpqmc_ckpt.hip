@@ -589,13 +589,15 @@ __global__ __launch_bounds__(kThreads) void k_basis_to_fp64(const ChainDev* __re
 // mode 0: checkpoint of a pass (sign check, drift);  1: final checkpoint of
 // the initialisation (sign := recomputed);  2: store-only (initial stack).
 // The new orthonormal basis Qc goes to the stack slot and, in the basis
-// precision, becomes the active basis U[parity].
+// precision, becomes the active basis: U[parity] (side -1), the factored
+// engine's factor F[side][parity] (side 0 = A, 1 = B), or nothing (side 2:
+// the checkpoint produced the active factors itself).
 // ---------------------------------------------------------------------------
 template <typename Tu>
 __global__ __launch_bounds__(kThreads) void k_finalize(const ChainDev* __restrict__ chains,
                                                        const Ctl* __restrict__ ctl, int slot,
                                                        int mode, int measure_here, int ck_index,
-                                                       int parity) {
+                                                       int parity, int side) {
   const ChainDev& C = chains[xcd_remap(blockIdx.x, gridDim.x)];
   ChainState* st = C.st;
   const int N = C.N, tid = threadIdx.x;
@@ -603,7 +605,8 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const ChainDev* __restric
   for (int sp = 0; sp < 2; ++sp) {
     const size_t sz = (size_t)N * C.n[sp];
     GLOBAL double* dst = gp(C.stack[sp] + (size_t)slot * sz);
-    GLOBAL Tu* u = gp((Tu*)C.U[sp][parity]);
+    GLOBAL Tu* u = side < 0 ? gp((Tu*)C.U[sp][parity])
+                 : side < 2 ? gp((Tu*)C.F[side][sp][parity]) : nullptr;
     const GLOBAL double* __restrict__ qc = gp((const double*)C.Qc[sp]);
     // eight coalesced loads in flight per thread, then their stores
     constexpr int D = 8;
@@ -619,7 +622,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const ChainDev* __restric
         const size_t idx = b0 + (size_t)e * kThreads + tid;
         if (idx < sz) {
           dst[idx] = v[e];
-          u[idx] = (Tu)v[e];
+          if (u) u[idx] = (Tu)v[e];
         }
       }
     }
@@ -629,7 +632,18 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const ChainDev* __restric
     for (int sp = 0; sp < 2; ++sp) {
       const double nl = st->run_log[sp] + st->chk_log[sp];
       const int ns = st->run_sgn[sp] * st->chk_sgn[sp];
-      if (mode != 2) wsign *= ns * C.slot_sgn[sp][slot] * st->x_sgn[sp];
+      if (mode != 2) {
+        // W_sigma = det(L_p R_p): the accumulated triangular factors of both
+        // sides (the slot still holds the opposite side's) and det(L R) of the
+        // orthonormal bases
+        wsign *= ns * C.slot_sgn[sp][slot] * st->x_sgn[sp];
+        st->w_log[sp] = nl + C.slot_log[sp][slot] + st->x_log[sp];
+        st->w_sgn[sp] = ns * C.slot_sgn[sp][slot] * st->x_sgn[sp];
+        if (C.trace_logdet && ck_index >= 0) {
+          C.trace_logdet[((size_t)ck_index * 2 + sp) * 2 + 0] = st->w_log[sp];
+          C.trace_logdet[((size_t)ck_index * 2 + sp) * 2 + 1] = (double)st->w_sgn[sp];
+        }
+      }
       C.slot_log[sp][slot] = nl;
       C.slot_sgn[sp][slot] = ns;
       st->run_log[sp] = nl;
@@ -711,16 +725,17 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const ChainDev* __restric
 }
 
 // Store the trial orbitals as the basis of a stack slot (log|det| 0, sign +1);
-// optionally also start the active basis U[0] from them.
+// optionally also start the active basis from them: U[0] (side -1) or the
+// factored engine's factor F[side][0].
 template <typename Tu>
 __global__ __launch_bounds__(kThreads) void k_put_trial(const ChainDev* __restrict__ chains, int slot,
-                                                        int set_active) {
+                                                        int set_active, int side) {
   const ChainDev& C = chains[xcd_remap(blockIdx.x, gridDim.x)];
   const int tid = threadIdx.x;
   for (int sp = 0; sp < 2; ++sp) {
     const size_t sz = (size_t)C.N * C.n[sp];
     double* dst = C.stack[sp] + (size_t)slot * sz;
-    Tu* u = (Tu*)C.U[sp][0];
+    Tu* u = side < 0 ? (Tu*)C.U[sp][0] : (Tu*)C.F[side][sp][0];
     for (size_t idx = tid; idx < sz; idx += kThreads) {
       const double v = C.P[sp][idx];
       dst[idx] = v;
@@ -752,6 +767,29 @@ __global__ __launch_bounds__(kThreads) void k_dscale_u(const ChainDev* __restric
     for (int idx = threadIdx.x; idx < C.N * n; idx += kThreads) {
       const int i = idx / n;
       u[idx] *= (Tu)C.dval[b][sp][frow[i] > 0 ? 0 : 1];
+    }
+  }
+}
+
+// Factored engine, frame change of a slice without kinetic factor (or
+// outside a propagation GEMM): rows of A <- D_l^{+-1} A, B <- D_l^{-+1} B
+// (ainv: A takes D^{-1}); which: bit 0 = A, bit 1 = B.
+__global__ __launch_bounds__(kThreads) void k_dscale_f(const ChainDev* __restrict__ chains, int l,
+                                                       int M, int parity, int ainv, int which) {
+  const ChainDev& C = chains[xcd_remap(blockIdx.x, gridDim.x)];
+  const int b = (l == 0 || l == M + 1) ? 0 : 1;
+  const GLOBAL int8_t* frow = gp(C.field + (size_t)l * C.N);
+  for (int sp = 0; sp < 2; ++sp) {
+    const int n = C.n[sp];
+    for (int side = 0; side < 2; ++side) {
+      if (!(which & (1 << side))) continue;
+      const bool inv = (side == 0) == (ainv != 0);
+      GLOBAL double* f = gp((double*)C.F[side][sp][parity]);
+      for (int idx = threadIdx.x; idx < C.N * n; idx += kThreads) {
+        const int i = idx / n;
+        const int si = frow[i] > 0 ? 0 : 1;
+        f[idx] *= C.dval[b][sp][inv ? 1 - si : si];
+      }
     }
   }
 }
@@ -821,22 +859,28 @@ hipError_t launch_basis_to_fp64(int fp32b, const ChainDev* c, int nc, int parity
 }
 
 hipError_t launch_finalize(int fp32b, const ChainDev* c, int nc, const Ctl* ctl, int slot, int mode,
-                           int measure_here, int ck_index, int parity, hipStream_t s) {
+                           int measure_here, int ck_index, int parity, int side, hipStream_t s) {
   if (fp32b)
     hipLaunchKernelGGL(k_finalize<float>, dim3(nc), dim3(kThreads), 0, s, c, ctl, slot, mode,
-                       measure_here, ck_index, parity);
+                       measure_here, ck_index, parity, side);
   else
     hipLaunchKernelGGL(k_finalize<double>, dim3(nc), dim3(kThreads), 0, s, c, ctl, slot, mode,
-                       measure_here, ck_index, parity);
+                       measure_here, ck_index, parity, side);
   return hipGetLastError();
 }
 
 hipError_t launch_put_trial(int fp32b, const ChainDev* c, int nc, int slot, int set_active,
-                            hipStream_t s) {
+                            int side, hipStream_t s) {
   if (fp32b)
-    hipLaunchKernelGGL(k_put_trial<float>, dim3(nc), dim3(kThreads), 0, s, c, slot, set_active);
+    hipLaunchKernelGGL(k_put_trial<float>, dim3(nc), dim3(kThreads), 0, s, c, slot, set_active, side);
   else
-    hipLaunchKernelGGL(k_put_trial<double>, dim3(nc), dim3(kThreads), 0, s, c, slot, set_active);
+    hipLaunchKernelGGL(k_put_trial<double>, dim3(nc), dim3(kThreads), 0, s, c, slot, set_active, side);
+  return hipGetLastError();
+}
+
+hipError_t launch_dscale_f(const ChainDev* c, int nc, int l, int M, int parity, int ainv, int which,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_dscale_f, dim3(nc), dim3(kThreads), 0, s, c, l, M, parity, ainv, which);
   return hipGetLastError();
 }
 

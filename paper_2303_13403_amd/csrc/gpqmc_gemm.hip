@@ -4,6 +4,10 @@
 //   the slice's delayed update          G <- D (G - Xa Ya) D^{-1}
 //   the basis propagation               U <- e^{-dtau K} (D_l U)   /  D_l (e^{-dtau K} U)
 //   the checkpoint products (FP64)      U^T U, U R^{-1}, L^T R, (L R)^{-1} L, 1 - R Y
+// and, for the factored engine (G = 1 - A B^T, FP64), the propagation of both
+// factors with the frame change fused (A <- D^{+-1} K^{-+} A, B likewise), the
+// segment update Q <- Q - (Q Mf^T) Wf of the dual factor, and the checkpoint
+// products 1 - A B^T, L^T (L R)^{-T}, R (L R)^{-1}.
 // The tile list maps every workgroup to (entry, tile); entries are one chain
 // and one spin, so a launch covers the whole batch, uneven lattices included.
 #include <hip/hip_runtime.h>
@@ -44,14 +48,38 @@ __global__ __launch_bounds__(kThreads) void k_gemm(const GemmEntry* __restrict__
   if (bid >= n_tiles) return;
   const TileRef tr = tiles[bid];
   const GemmEntry& e = ents[tr.entry];
-  const int M = e.M, N = e.N, K = e.dynK ? *e.dynK : e.K;
+  const int M = e.M, N = e.dynN ? *e.dynN : e.N, K = e.dynK ? *e.dynK : e.K;
   const int m0 = tr.tm * kTile, n0 = tr.tn * kTile;
   if (m0 >= M || n0 >= N) return;
+  if (MODE == GM_SEGF && K == 0) return;   // no flip accepted: Q unchanged
 
   const int p = args.parity;
   const GLOBAL T* A = gp((const T*)e.A[0]);
   const GLOBAL T* B = gp((const T*)e.B[0]);
   GLOBAL T* C = gp((T*)e.C[0]);
+  // factored checkpoint operands: 0 = the new orthonormal basis Qc, 1 = the
+  // stack slot, 2 = the active factor of this entry
+  const double* slot_base = e.stack ? e.stack + (size_t)args.slot * e.slot_stride : nullptr;
+  auto fsel = [&](int sel, const void* fac) -> const GLOBAL T* {
+    return gp((const T*)(sel == 0 ? (const void*)e.Qc : sel == 1 ? (const void*)slot_base : fac));
+  };
+  if (MODE == GM_IMABT) {
+    A = gp((const T*)e.A[p]);
+    B = gp((const T*)e.B[p]);
+  } else if (MODE == GM_SEGP) {
+    A = gp((const T*)e.A[p]);
+  } else if (MODE == GM_SEGF) {
+    C = gp((T*)e.C[p]);
+  } else if (MODE == GM_BMAT) {
+    A = fsel(args.lsel, nullptr);
+    C = gp((T*)e.C[p]);
+  } else if (MODE == GM_AMAT) {
+    A = fsel(args.rsel, nullptr);
+    C = gp((T*)e.C[p]);
+  } else if (MODE == GM_GFRESH2) {
+    A = fsel(args.rsel, e.A[p]);
+    B = fsel(args.lsel, e.B[p]);
+  }
   if (MODE == GM_PROPB || MODE == GM_PROPR) {
     B = gp((const T*)e.B[p]);
     C = gp((T*)e.C[p ^ 1]);
@@ -167,14 +195,15 @@ __global__ __launch_bounds__(kThreads) void k_gemm(const GemmEntry* __restrict__
     sfield = gp(e.field + (size_t)args.scale_slice * e.n_sites);
     sbnd = (args.scale_slice == 0 || args.scale_slice == args.n_bulk_last + 1) ? 0 : 1;
   }
-  const bool inv = args.scale_inverse != 0;
+  const bool inv = (args.scale_inverse != 0) != (e.sinv != 0);
   // the tile's row factors d(i) and column factors 1/d(j) of the frame
-  // change, staged once (PROPR scales rows only, by d(i))
+  // change, staged once (PROPR scales rows only, by d(i), or by 1/d(i) for an
+  // entry marked sinv)
   __shared__ double drow[kTile], dcol[kTile];
   if (sfield) {
     if (tid < kTile) {
       const int i = m0 + tid;
-      drow[tid] = i < M ? dfac(e.dval, sbnd, sfield[i], MODE == GM_PROPR ? false : inv) : 0.0;
+      drow[tid] = i < M ? dfac(e.dval, sbnd, sfield[i], inv) : 0.0;
     } else if (tid < 2 * kTile) {
       const int j = n0 + tid - kTile;
       dcol[tid - kTile] = j < N ? dfac(e.dval, sbnd, sfield[j], !inv) : 0.0;
@@ -186,7 +215,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm(const GemmEntry* __restrict__
   // those loads are issued before the first store of the tile
   Tb prev[16];
   int ix = 0;
-  if (MODE == GM_GFRESH && args.check_drift) {
+  if ((MODE == GM_GFRESH || MODE == GM_GFRESH2) && args.check_drift) {
     const GLOBAL Tb* Cb = gp((const Tb*)e.C[1]);
     wt.each(wm, wn, lane, [&](int li, int lj, T) {
       const int i = m0 + li, j = n0 + lj;
@@ -223,11 +252,23 @@ __global__ __launch_bounds__(kThreads) void k_gemm(const GemmEntry* __restrict__
       double v = g;
       if (sfield) v *= drow[li] * dcol[lj];
       Cb[o2] = (Tb)v;
+    } else if (MODE == GM_GFRESH2) {
+      const double g = (i == j ? 1.0 : 0.0) - (double)acc;
+      C[o] = (T)g;
+      if (args.check_drift) {
+        const float d = (float)fabs((double)prev[k] - g);
+        dmax = (d != d) ? __builtin_inff() : fmaxf(dmax, d);
+        gmx = fmaxf(gmx, (float)fabs(g));
+      }
+    } else if (MODE == GM_IMABT) {
+      C[o] = (T)((i == j ? 1.0 : 0.0) - (double)acc);
+    } else if (MODE == GM_SEGF) {
+      C[o] = C[o] - acc;
     } else {
       C[o] = acc;
     }
   });
-  if (MODE == GM_GFRESH && args.check_drift) {
+  if ((MODE == GM_GFRESH || MODE == GM_GFRESH2) && args.check_drift) {
     __shared__ float red[2][4];
     dmax = wave_max(dmax);
     gmx = wave_max(gmx);
@@ -660,6 +701,12 @@ hipError_t launch_gemm(int fp32, int g_fp32, int mode, const GemmEntry* e, const
     case GM_GFRESH:
       return g_fp32 ? gemm_t<double, GM_GFRESH, false, false, float>(e, t, n, a, s)
                     : gemm_t<double, GM_GFRESH, false, false, double>(e, t, n, a, s);
+    case GM_IMABT: return gemm_t<double, GM_IMABT, false, true, double>(e, t, n, a, s);
+    case GM_SEGP: return gemm_t<double, GM_SEGP, false, true, double>(e, t, n, a, s);
+    case GM_SEGF: return gemm_t<double, GM_SEGF, false, false, double>(e, t, n, a, s);
+    case GM_BMAT: return gemm_t<double, GM_BMAT, false, true, double>(e, t, n, a, s);
+    case GM_AMAT: return gemm_t<double, GM_AMAT, false, false, double>(e, t, n, a, s);
+    case GM_GFRESH2: return gemm_t<double, GM_GFRESH2, false, true, double>(e, t, n, a, s);
     default: break;
   }
   if (fp32) {

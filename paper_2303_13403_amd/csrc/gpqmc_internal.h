@@ -68,6 +68,8 @@ struct ChainState {
   float last_rel_drift;
   long long accepted;   // accepted proposals
   long long proposed;   // proposals
+  double w_log[2];      // log|W_sigma| = log|det(L_p R_p)| at the last checkpoint
+  int w_sgn[2];         // sign of W_sigma at the last checkpoint
 };
 
 enum Flags : int {
@@ -130,6 +132,12 @@ struct ChainDev {
   double* trace_ratio;  // optional: (n_slices * N) x 2 ratios of the last pass
   double* trace_green;  // optional: checkpoints_per_pass x 2 x N x N
   double* trace_drift;  // optional: checkpoints_per_pass
+  double* trace_logdet; // optional: checkpoints_per_pass x 2 x (log|W_sigma|, sign)
+  // factored engine (FP64): G = 1 - A B^T with A, B of size N x n (ld n);
+  // F[0] = A (the R side), F[1] = B (the L side), ping-pong pair by parity
+  void* F[2][2][2];     // [side][spin][parity]
+  double* Mf[2];        // the moving factor's rows at the segment's accepted sites (kSegMax x n)
+  double* Wf[2];        // Woodbury core times the dual factor's rows at those sites (kSegMax x n)
 };
 
 // Control block (device memory), read by every kernel of a pass.
@@ -156,8 +164,10 @@ struct GemmEntry {
   int spin;
   ChainState* st;
   const int* dynK;      // if set, the chain's K is *dynK (the slice's accepted count)
-  int pad;
+  int sinv;             // the output row scaling uses D^{-1} (xor with GemmArgs::scale_inverse)
   double dval[2][2];    // [b][s] diagonal of D for this spin (see ChainDev)
+  const int* dynN;      // if set, the output has *dynN columns (the segment's accepted count)
+  void* pad2;
 };
 
 struct TileRef {
@@ -174,6 +184,7 @@ struct GemmArgs {
   int dir;              // 0 up pass (R is the new basis), 1 down pass (L is new)
   int n_bulk_last;      // M (bulk slices are 1..M)
   int check_drift;      // compare against the wrapped Green's function
+  int rsel, lsel;       // factored checkpoint operands: 0 = Qc, 1 = the stack slot, 2 = the factor
 };
 
 enum GemmMode : int {
@@ -187,6 +198,13 @@ enum GemmMode : int {
   GM_XMAT = 8,    // C = Lt^T R       (FP64)
   GM_YMAT = 9,    // C = Xinv Lt^T    (FP64)
   GM_GFRESH = 10, // C = 1 - R Y (FP64), drift, bulk copy with scaling
+  // factored engine (FP64), G = 1 - A B^T
+  GM_IMABT = 11,  // C = 1 - A[p] B[p]^T          (the wrapped G of a checkpoint)
+  GM_SEGP = 12,   // C = A[p] B^T, *dynN columns   (Q Mf^T of a segment)
+  GM_SEGF = 13,   // C[p] = C[p] - A B, K = *dynK  (Q <- Q - (Q Mf^T) Wf)
+  GM_BMAT = 14,   // C[p] = Ls Xinv^T              (L-side factor B = L^T (L R)^{-T})
+  GM_AMAT = 15,   // C[p] = Rs Xinv                (R-side factor A = R (L R)^{-1})
+  GM_GFRESH2 = 16,// C = 1 - Rs Ls^T, drift against C[1]
 };
 
 }  // namespace gpqmc

@@ -20,6 +20,15 @@
 // on it alone.  It ends by writing F and Z; k_xy appends the segment to Xa Ya,
 // and one GEMM per slice applies G <- G - Xa Ya (a delayed update of rank =
 // the slice's accepted flips), fused with the frame change.
+//
+// Factored engine (FACT): G = 1 - A B^T with A, B of size N x n; the block is
+// G_s[S,S] = 1 - A[S,:] B[S,:]^T, and at the segment's end the accepted flips
+// are folded into the factors by the Woodbury identity.  With Z = (Delta_F^{-1}
+// + X[F,F])^{-1} (X = 1 - G at the segment's start) the moving factor M (A on
+// an upward pass, B on a downward one) has its rows F scaled by 1 + Delta_F,
+// and the dual factor Q takes Q <- Q - (Q M[F,:]^T) W with W = Z^T Q[F,:]
+// (upward) or Z Q[F,:] (downward); the kernel writes M[F,:] (before scaling)
+// and W, and two GEMMs apply the update to Q.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -78,10 +87,10 @@ __device__ inline void lds_row_store(T* p, const T (&r)[kBlock]) {
   }
 }
 
-template <typename T>
+template <typename T, bool FACT>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 2 : 1))) void k_scan(const ChainDev* __restrict__ chains,
                                                    const Ctl* __restrict__ ctl, int l, int M,
-                                                   int s0, int s1) {
+                                                   int s0, int s1, int dir, int parity) {
   const ChainDev& C = chains[xcd_remap(blockIdx.x, gridDim.x)];
   ChainState* st = C.st;
   const int N = C.N;
@@ -148,8 +157,111 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof
   }
   // ---- G_s[S,S] = G0[S,S] - Xa[S, :fp] Ya[:fp, S]: the fp flips accepted in
   // earlier segments of this slice are not yet applied to G ----
-  const int fprev = (s0 == 0) ? 0 : st->ftot;
-  if (nseg <= kBlock) {
+  const int fprev = (FACT || s0 == 0) ? 0 : st->ftot;
+  if (FACT && nseg <= kBlock) {
+    // G_s[S,S] = 1 - A[S,:] B[S,:]^T for both spins: 128 threads per spin,
+    // thread t owns column t % 32 and rows t / 32 + 4 m; the inner dimension
+    // n runs in k-chunks of 32 with the rows of A and B read as contiguous
+    // 8-element pieces (A kept row-major in Rsf, B transposed in the Hs area)
+    const int s = tid >> 7, t = tid & 127, c = t & 31, rb = t >> 5;
+    const int nn = C.n[s];
+    const GLOBAL T* __restrict__ fa = gp((const T*)C.F[0][s][parity]);
+    const GLOBAL T* __restrict__ fb = gp((const T*)C.F[1][s][parity]);
+    T* As = Rsf + s * kBlock * KL;
+    T* Bs = &Hs[s][0][0];
+    T acc[kBlock / 4];
+#pragma unroll
+    for (int m = 0; m < kBlock / 4; ++m) {
+      const int row = rb + 4 * m;
+      acc[m] = (row < nseg && row == c) ? T(1) : T(0);
+    }
+    constexpr int E8 = 8;
+    const int lr = t >> 2, le = (t & 3) * E8;
+    T va[E8], vb[E8];
+    auto load_chunk = [&](int k0) {
+#pragma unroll
+      for (int e = 0; e < E8; ++e) {
+        const int k = k0 + le + e;
+        const bool ok = lr < nseg && k < nn;
+        va[e] = ok ? fa[(size_t)(s0 + lr) * nn + k] : T(0);
+        vb[e] = ok ? fb[(size_t)(s0 + lr) * nn + k] : T(0);
+      }
+    };
+    load_chunk(0);
+    for (int k0 = 0; k0 < nn; k0 += 32) {
+      __syncthreads();
+#pragma unroll
+      for (int e = 0; e < E8; ++e) {
+        As[lr * KL + le + e] = va[e];
+        Bs[(le + e) * KL + lr] = vb[e];
+      }
+      __syncthreads();
+      if (k0 + 32 < nn) load_chunk(k0 + 32);
+#pragma unroll 4
+      for (int k = 0; k < 32; ++k) {
+        const T bv = Bs[k * KL + c];
+#pragma unroll
+        for (int m = 0; m < kBlock / 4; ++m) acc[m] -= As[(rb + 4 * m) * KL + k] * bv;
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < kBlock / 4; ++m) {
+      const int row = rb + 4 * m;
+      if (row < nseg && c < nseg) Gss[s][row * LGS + c] = acc[m];
+    }
+  } else if (FACT) {
+    // segments of more than 32 sites: lane = column c, rows wave + 4 m, one
+    // spin at a time; A[S, k] (nseg x 32) row-major in Rsf, B[S, k] transposed
+    T* As = Rsf;
+    T* Bs = &Hs[0][0][0];
+    constexpr int LA = 36, LB = kSegMax + 4;
+    static_assert(32 * LB <= 2 * kBlock * (kBlock + 2), "B tile fits in Hs");
+    const int c = lane;
+    for (int s = 0; s < 2; ++s) {
+      const int nn = C.n[s];
+      const GLOBAL T* __restrict__ fa = gp((const T*)C.F[0][s][parity]);
+      const GLOBAL T* __restrict__ fb = gp((const T*)C.F[1][s][parity]);
+      T acc[kSegMax / 4];
+#pragma unroll
+      for (int m = 0; m < kSegMax / 4; ++m) {
+        const int row = wave + 4 * m;
+        acc[m] = (row < nseg && row == c) ? T(1) : T(0);
+      }
+      constexpr int NL = kSegMax * 32 / kThreads;
+      T va[NL], vb[NL];
+      auto load_chunk = [&](int k0) {
+#pragma unroll
+        for (int t = 0; t < NL; ++t) {
+          const int e = tid + t * kThreads, r = e >> 5, k = k0 + (e & 31);
+          const bool ok = r < nseg && k < nn;
+          va[t] = ok ? fa[(size_t)(s0 + r) * nn + k] : T(0);
+          vb[t] = ok ? fb[(size_t)(s0 + r) * nn + k] : T(0);
+        }
+      };
+      load_chunk(0);
+      for (int k0 = 0; k0 < nn; k0 += 32) {
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < NL; ++t) {
+          const int e = tid + t * kThreads;
+          As[(e >> 5) * LA + (e & 31)] = va[t];
+          Bs[(e & 31) * LB + (e >> 5)] = vb[t];
+        }
+        __syncthreads();
+        if (k0 + 32 < nn) load_chunk(k0 + 32);
+        for (int k = 0; k < 32; ++k) {
+          const T bv = Bs[k * LB + c];
+#pragma unroll
+          for (int m = 0; m < kSegMax / 4; ++m) acc[m] -= As[(wave + 4 * m) * LA + k] * bv;
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < kSegMax / 4; ++m) {
+        const int row = wave + 4 * m;
+        if (row < nseg && c < nseg) Gss[s][row * LGS + c] = acc[m];
+      }
+    }
+  } else if (nseg <= kBlock) {
     // segments of up to 32 sites: both spins in one pass, 128 threads per
     // spin, thread t of a spin owns column t % 32 and rows t / 32 + 4 m; the
     // rank-fprev correction runs in k-chunks of 32 with every operand row
@@ -462,6 +574,34 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof
   const int f = sh_f;
   for (int p = tid; p < f; p += kThreads) C.flist[p] = Fs[p];
   for (int i = tid; i < nseg; i += kThreads) frow[s0 + i] = fs[i];
+  if (FACT && f > 0) {
+    // Woodbury operands of the segment, per spin: Mf = M[F,:] (then M[F,:] is
+    // scaled by 1 + Delta_F), Wf = Z^T Q[F,:] (upward) or Z Q[F,:] (downward).
+    // The fields in fs are already flipped: the old value is -fs.
+    for (int s = 0; s < 2; ++s) {
+      const int nn = C.n[s];
+      GLOBAL T* __restrict__ Mv = gp((T*)C.F[dir][s][parity]);
+      const GLOBAL T* __restrict__ Qv = gp((const T*)C.F[1 - dir][s][parity]);
+      GLOBAL double* __restrict__ mf = gp(C.Mf[s]);
+      GLOBAL double* __restrict__ wf = gp(C.Wf[s]);
+      const GLOBAL T* __restrict__ Zg = Z[s];
+      for (int idx = tid; idx < f * nn; idx += kThreads) {
+        const int p = idx / nn, k = idx - p * nn;
+        const int site = Fs[p];
+        const int si_old = fs[site - s0] < 0 ? 0 : 1;
+        const size_t o = (size_t)site * nn + k;
+        const T v = Mv[o];
+        mf[(size_t)p * nn + k] = (double)v;
+        Mv[o] = v * (T)(1.0 + C.delta[bnd][s][si_old]);
+        T acc = T(0);
+        for (int q = 0; q < f; ++q) {
+          const T z = dir == 0 ? Zg[(size_t)q * LDZ + p] : Zg[(size_t)p * LDZ + q];
+          acc += z * Qv[(size_t)Fs[q] * nn + k];
+        }
+        wf[(size_t)p * nn + k] = (double)acc;
+      }
+    }
+  }
   if (tid == 0) {
     st->fcount = f;
     st->foff = fprev;
@@ -1251,12 +1391,19 @@ hipError_t launch_xy(int fp32, const ChainDev* c, int nc, int n_max, int s0, int
   return hipGetLastError();
 }
 
-hipError_t launch_scan(int fp32, const ChainDev* c, int nc, const Ctl* ctl, int l, int M, int s0,
-                       int s1, hipStream_t s) {
-  if (fp32)
-    hipLaunchKernelGGL(k_scan<float>, dim3(nc), dim3(kThreads), 0, s, c, ctl, l, M, s0, s1);
+// fact: the factored engine (FP64); dir and parity select its moving factor
+// and the active buffers
+hipError_t launch_scan(int fp32, int fact, const ChainDev* c, int nc, const Ctl* ctl, int l, int M,
+                       int s0, int s1, int dir, int parity, hipStream_t s) {
+  if (fact)
+    hipLaunchKernelGGL((k_scan<double, true>), dim3(nc), dim3(kThreads), 0, s, c, ctl, l, M, s0, s1,
+                       dir, parity);
+  else if (fp32)
+    hipLaunchKernelGGL((k_scan<float, false>), dim3(nc), dim3(kThreads), 0, s, c, ctl, l, M, s0, s1,
+                       0, 0);
   else
-    hipLaunchKernelGGL(k_scan<double>, dim3(nc), dim3(kThreads), 0, s, c, ctl, l, M, s0, s1);
+    hipLaunchKernelGGL((k_scan<double, false>), dim3(nc), dim3(kThreads), 0, s, c, ctl, l, M, s0, s1,
+                       0, 0);
   return hipGetLastError();
 }
 

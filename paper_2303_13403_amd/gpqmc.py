@@ -15,7 +15,7 @@ import numpy as np
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgpqmc.so")
 
 OK, EINVAL, ENOMEM, EHIP, EDEGENERATE, EUNSTABLE, ESTATE = 0, -1, -2, -3, -4, -5, -6
-FP64, MIXED, MIXED_FP32_BASIS = 0, 1, 2
+FP64, MIXED, MIXED_FP32_BASIS, FP64_WRAP = 0, 1, 2, 3
 _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EDEGENERATE",
            -5: "EUNSTABLE", -6: "ESTATE"}
 
@@ -60,7 +60,8 @@ EXPORTS = [
     "gpqmc_measure_sign", "gpqmc_measure_structure_factor", "gpqmc_get_measurements",
     "gpqmc_reset_measurements",
     "gpqmc_set_field", "gpqmc_get_field", "gpqmc_get_green", "gpqmc_get_chain_info",
-    "gpqmc_set_debug", "gpqmc_get_trace", "gpqmc_debug_gemm", "gpqmc_chain_status",
+    "gpqmc_set_debug", "gpqmc_get_trace", "gpqmc_get_trace_logdet", "gpqmc_logdet",
+    "gpqmc_debug_gemm", "gpqmc_chain_status",
     "gpqmc_time_kernel", "gpqmc_set_kernel_timing", "gpqmc_get_kernel_timing",
     "gpqmc_debug_step", "gpqmc_debug_read", "gpqmc_last_error", "gpqmc_destroy",
 ]
@@ -94,6 +95,8 @@ def load():
         "gpqmc_get_chain_info": [VP, I32, P(ChainInfo)],
         "gpqmc_set_debug": [VP, I32],
         "gpqmc_get_trace": [VP, I32, P(D), P(D), P(D), P(I32)],
+        "gpqmc_get_trace_logdet": [VP, I32, P(D)],
+        "gpqmc_logdet": [VP, I32, P(D), P(I32)],
         "gpqmc_debug_gemm": [I32, I32, I32, I32, I32, VP, I32, VP, I32, VP, I32, VP],
         "gpqmc_chain_status": [VP, I32],
         "gpqmc_time_kernel": [VP, I32, I32, P(ctypes.c_float)],
@@ -137,7 +140,8 @@ class Context:
     """
 
     def __init__(self, chains: Sequence[dict], device: str = "cuda:0", meas_capacity: int = 4096,
-                 use_graph: bool = True, drift_tol: float = 0.0, stream=None):
+                 use_graph: bool = True, drift_tol: float = 0.0, stream=None,
+                 workspace_fill: Optional[float] = None):
         import torch
 
         self.lib = load()
@@ -183,6 +187,12 @@ class Context:
         self._check(self.lib.gpqmc_workspace_bytes(self.ctx, ctypes.byref(nbytes)))
         self.workspace_bytes = nbytes.value
         self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        if workspace_fill is not None:
+            # testing: start from a known memory content (e.g. NaN) so that a
+            # read of memory the library never wrote shows up in the results
+            n8 = nbytes.value // 8
+            self.workspace[: n8 * 8].view(torch.float64).fill_(workspace_fill)
+            self.workspace[n8 * 8:].fill_(0)
         with torch.cuda.device(self.device):
             self._check(self.lib.gpqmc_bind_workspace(self.ctx,
                                                       ctypes.c_void_p(self.workspace.data_ptr()),
@@ -258,6 +268,22 @@ class Context:
         info = ChainInfo()
         self._call("gpqmc_get_chain_info", chain, ctypes.byref(info))
         return {k: getattr(info, k) for k, _ in ChainInfo._fields_}
+
+    def logdet(self, chain: int):
+        """((log|W_up|, log|W_dn|), (sgn W_up, sgn W_dn)) at the last checkpoint."""
+        la = np.zeros(2, np.float64)
+        sg = np.zeros(2, np.int32)
+        self._call("gpqmc_logdet", chain, _dptr(la), sg.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+        return la, sg
+
+    def trace_logdet(self, chain: int) -> np.ndarray:
+        """(n_ck, 2, 2): (log|W_sigma|, sgn W_sigma) of both spins at every
+        checkpoint of the last pass (chains created with trace)."""
+        nck = ctypes.c_int32()
+        self._call("gpqmc_get_trace", chain, None, None, None, ctypes.byref(nck))
+        out = np.zeros((nck.value, 2, 2), np.float64)
+        self._call("gpqmc_get_trace_logdet", chain, _dptr(out))
+        return out
 
     def status(self, chain: int) -> int:
         with self.torch.cuda.device(self.device):

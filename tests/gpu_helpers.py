@@ -6,12 +6,19 @@ import numpy as np
 from oracle import pqmc
 from paper_2303_13403_amd import gpqmc
 
-PREC = {"fp64": gpqmc.FP64, "mixed": gpqmc.MIXED, "mixed32b": gpqmc.MIXED_FP32_BASIS}
-# G and ratio tolerance, max|x - x_ref| / max|x_ref|: FP64 path 1e-10, mixed path
-# 1e-5; the FP32-basis variant is bounded by eps_fp32 cond(L R), stated as 1e-4
-TOL = {"fp64": 1e-10, "mixed": 1e-5, "mixed32b": 1e-4}
+# "fp64": the factored FP64 engine (G = 1 - A B^T); "fp64wrap": FP64 with G
+# wrapped as an N x N matrix; "mixed": FP32 Green's function of the wrap engine
+PREC = {"fp64": gpqmc.FP64, "fp64wrap": gpqmc.FP64_WRAP, "mixed": gpqmc.MIXED,
+        "mixed32b": gpqmc.MIXED_FP32_BASIS}
+# G and ratio tolerance, max|x - x_ref| / max|x_ref|: FP64 paths 1e-10, mixed
+# path 1e-5; the FP32-basis variant is bounded by eps_fp32 cond(L R), stated as 1e-4
+TOL = {"fp64": 1e-10, "fp64wrap": 1e-10, "mixed": 1e-5, "mixed32b": 1e-4}
 # acceptance draws this close to their threshold (relative) may decide differently
-TIE = {"fp64": 1e-9, "mixed": 1e-4, "mixed32b": 1e-3}
+TIE = {"fp64": 1e-9, "fp64wrap": 1e-9, "mixed": 1e-4, "mixed32b": 1e-3}
+
+
+def is_fp64(prec):
+    return prec in ("fp64", "fp64wrap")
 
 
 def rel_err(x, ref):
@@ -38,6 +45,7 @@ def oracle_fixed_pass(ch):
     ch.record_greens = True
     ch.ratios.clear()
     ch.checkpoint_greens.clear()
+    ch.checkpoint_logdets.clear()
     ch.follow = ch.field.copy()
     ch.follow_tol = math.inf
     try:
