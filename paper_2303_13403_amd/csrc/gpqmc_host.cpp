@@ -39,6 +39,9 @@ hipError_t launch_put_trial(int fp32b, const ChainDev* c, int nc, int slot, int 
                             int side, hipStream_t s);
 hipError_t launch_dscale_f(const ChainDev* c, int nc, int l, int M, int parity, int ainv, int which,
                            hipStream_t s);
+hipError_t launch_scan_f(const ChainDev* c, int nc, const Ctl* ctl, int l, int M, int s0, int s1,
+                         int dir, int parity, hipStream_t s);
+hipError_t launch_segupd_f(const ChainDev* c, int nc, int n_max, int dir, int parity, hipStream_t s);
 hipError_t launch_dscale_u(int fp32b, const ChainDev* c, int nc, int l, int M, int parity,
                            hipStream_t s);
 hipError_t launch_pass_end(const ChainDev* c, int nc, hipStream_t s);
@@ -438,17 +441,32 @@ struct Launcher {
   // the factors: upward D_l G_{l-1} D_l^{-1}, downward G_{l-1}; both have the
   // diagonal the ratio 1 + Delta (1 - G_ii) needs.
   // ---------------------------------------------------------------------------
+  // segments of up to 32 sites run the one-wave scan; with at most 128
+  // particles per spin the dual factor's update is the fused one-pass kernel;
+  // otherwise the general scan and two GEMMs (Q Mf^T, then Q - (Q Mf^T) Wf)
   hipError_t flips_f(int l, int dir, int parity) {
     hipError_t e;
     GemmArgs a = args();
     a.parity = parity;
+    const bool fast_scan = ctx->kseg <= kBlock;
+    const bool fast_upd = fast_scan && ctx->n_part <= 128;
+    const int tscan = ctx->timing_mask ? 2 : -1, tupd = ctx->timing_mask ? 1 : -1;
     for (int s0 = 0; s0 < ctx->n_max; s0 += ctx->kseg) {
-      if ((e = timed(ctx->timing_mask ? 2 : -1, [&] {
-             return launch_scan(0, 1, chains, nc, ctl, l, ctx->M, s0, s0 + ctx->kseg, dir, parity, s);
+      if ((e = timed(tscan, [&] {
+             return fast_scan ? launch_scan_f(chains, nc, ctl, l, ctx->M, s0, s0 + ctx->kseg, dir,
+                                              parity, s)
+                              : launch_scan(0, 1, chains, nc, ctl, l, ctx->M, s0, s0 + ctx->kseg,
+                                            dir, parity, s);
            })) != hipSuccess)
         return e;
-      if ((e = gemm(dir == 0 ? E_SEGP_UP : E_SEGP_DN, GM_SEGP, T_Nk, a)) != hipSuccess) return e;
-      if ((e = gemm(dir == 0 ? E_SEGF_UP : E_SEGF_DN, GM_SEGF, T_Nn, a)) != hipSuccess) return e;
+      if (fast_upd) {
+        if ((e = timed(tupd, [&] { return launch_segupd_f(chains, nc, ctx->n_max, dir, parity, s); })) !=
+            hipSuccess)
+          return e;
+      } else {
+        if ((e = gemm(dir == 0 ? E_SEGP_UP : E_SEGP_DN, GM_SEGP, T_Nk, a)) != hipSuccess) return e;
+        if ((e = gemm(dir == 0 ? E_SEGF_UP : E_SEGF_DN, GM_SEGF, T_Nn, a)) != hipSuccess) return e;
+      }
     }
     return hipSuccess;
   }

@@ -1408,3 +1408,404 @@ hipError_t launch_scan(int fp32, int fact, const ChainDev* c, int nc, const Ctl*
 }
 
 }  // namespace gpqmc
+
+namespace gpqmc {
+
+// ---------------------------------------------------------------------------
+// Factored engine, delay segments of up to kBlock (32) sites: one wave per
+// chain does the whole segment.
+//
+// Lane (s, a) = (lane / 32, lane % 32) keeps row a of the spin-s block
+// G_s[S,S] = 1 - A[S,:] B[S,:]^T in registers; the block is formed with the
+// rows of B staged through LDS in k-chunks.  Every proposal reads the two
+// diagonal entries with readlane; an accepted flip t at site j_t writes the
+// row X[j_t, S] (X = 1 - G) of the current block to LDS, where it both feeds
+// the Sherman-Morrison update of every lane's row and stays as history, and
+// every lane also keeps X[a, j_t].  Those rows and columns are the Schur
+// complements of K = Delta_F^{-1} + X_s[F,F] (X_s: the block at the segment's
+// start) in flip order, so they give K = L U directly:
+//   U[t][v] = X^{(t)}[j_t, j_v] + delta_tv / Delta_t   (v >= t),
+//   L[u][t] = X^{(t)}[j_u, j_t] / U[t][t]               (u > t),
+// with X^{(t)} the block before flip t.  The Woodbury core is Z = K^{-1}.  The
+// wave then writes, per spin, Mf = M[F,:] (the moving factor before the flip
+// scaling), scales M[F,:] by 1 + Delta_F, and solves Wf = Z^T Q[F,:]
+// (upward) or Z Q[F,:] (downward) column by column with the triangular
+// factors: lanes run over the n columns.  k_segupd_f then applies
+// Q <- Q - (Q Mf^T) Wf.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_scan_f(const ChainDev* __restrict__ chains,
+                                               const Ctl* __restrict__ ctl, int l, int M, int s0,
+                                               int s1, int dir, int parity) {
+  const ChainDev& C = chains[xcd_remap(blockIdx.x, gridDim.x)];
+  ChainState* st = C.st;
+  const int N = C.N, lane = threadIdx.x, s = lane >> 5, a = lane & 31;
+  if (s0 >= N) {   // uneven batch: this chain has no site in the segment
+    if (lane == 0) st->fcount = 0;
+    return;
+  }
+  const int send = min(s1, N), nseg = send - s0;
+  constexpr int KB = kBlock;
+  constexpr int KC = 16;          // k-chunk of the block formation
+  __shared__ double u_s[KB];
+  __shared__ int8_t fs[KB];
+  __shared__ int Fl[KB];
+  __shared__ double dF[2][KB];    // Delta of every accepted flip, per spin
+  // history rows X^{(t)}[j_t, S] (later the LU factors), and history columns
+  // X^{(t)}[S, j_t] (odd leading dimension: written by column); the block
+  // formation stages B through the column area first
+  __shared__ __align__(16) double hrow[2][KB][KB];
+  __shared__ __align__(16) double hcol[2][KB][KB + 1];
+  static_assert(2 * KC * KB <= 2 * KB * (KB + 1), "B staging fits in the column history");
+
+  const int bnd = (l == 0 || l == M + 1) ? 0 : 1;
+  int8_t* frow = C.field + (size_t)l * N;
+  const uint32_t sweep = (uint32_t)st->sweep;
+  const bool force_reject = ctl->force_reject != 0;
+  if (lane < nseg) {
+    uint32_t c[4] = {C.chain_id, sweep, (uint32_t)l, (uint32_t)(s0 + lane)};
+    philox4x32_10(c, C.key0, C.key1);
+    u_s[lane] = uniform53(c[0], c[1]);
+    fs[lane] = frow[s0 + lane];
+  }
+
+  // ---- G_s[S,S] = 1 - A[S,:] B[S,:]^T, row a of spin s in g ----
+  double g[KB];
+#pragma unroll
+  for (int c = 0; c < KB; ++c) g[c] = 0.0;
+  {
+    const int nn = C.n[s], nmax = max(C.n[0], C.n[1]);
+    const GLOBAL double* __restrict__ Ab = gp((const double*)C.F[0][s][parity]);
+    const GLOBAL double* __restrict__ Bb = gp((const double*)C.F[1][s][parity]);
+    double* Bs = &hcol[0][0][0];   // [spin][k][c]
+    const bool row_ok = a < nseg;
+    const size_t ro = (size_t)(s0 + a) * nn;
+    for (int k0 = 0; k0 < nmax; k0 += KC) {
+      double ar[KC];
+#pragma unroll
+      for (int kk = 0; kk < KC; ++kk) {
+        const int k = k0 + kk;
+        const bool ok = row_ok && k < nn;
+        ar[kk] = ok ? Ab[ro + k] : 0.0;
+        Bs[(s * KC + kk) * KB + a] = ok ? Bb[ro + k] : 0.0;
+      }
+      wave_sync();
+#pragma unroll
+      for (int kk = 0; kk < KC; ++kk) {
+        const double* brow = Bs + (s * KC + kk) * KB;
+#pragma unroll
+        for (int c = 0; c < KB; c += 2) {
+          const double2 b2 = *reinterpret_cast<const double2*>(brow + c);
+          g[c] -= ar[kk] * b2.x;
+          g[c + 1] -= ar[kk] * b2.y;
+        }
+      }
+      wave_sync();
+    }
+#pragma unroll
+    for (int c = 0; c < KB; ++c)
+      if (c == a) g[c] += 1.0;
+  }
+
+  // ---- sequential proposals ----
+  const bool zero_delta = C.delta[bnd][0][0] == 0.0 && C.delta[bnd][0][1] == 0.0;
+  const double dl_u0 = C.delta[bnd][0][0], dl_u1 = C.delta[bnd][0][1];
+  const double dl_d0 = C.delta[bnd][1][0], dl_d1 = C.delta[bnd][1][1];
+  double* const trace_ratio = C.trace_ratio;
+  int fc = 0, sign = st->sign, nacc = 0;
+#pragma unroll
+  for (int j = 0; j < KB; ++j) {
+    if (j < nseg) {
+      const int si = fs[j] > 0 ? 0 : 1;
+      const double du = si ? dl_u1 : dl_u0, dd = si ? dl_d1 : dl_d0;
+      const double ru = 1.0 + du * (1.0 - lane_value(g[j], j));
+      const double rd = 1.0 + dd * (1.0 - lane_value(g[j], 32 + j));
+      const bool accept = !force_reject && (u_s[j] < fabs(ru * rd));
+      if (lane == 0 && trace_ratio) {
+        trace_ratio[((size_t)l * N + s0 + j) * 2 + 0] = ru;
+        trace_ratio[((size_t)l * N + s0 + j) * 2 + 1] = rd;
+      }
+      if (accept) {
+        if (!zero_delta) {
+          const int t = fc;
+          // X[j, S] = e_j - G[j, S] from lane (s, j); X[a, j] from every lane
+          if (a == j) {
+#pragma unroll
+            for (int q = 0; q < KB; q += 2) {
+              double2 v;
+              v.x = (q == j ? 1.0 : 0.0) - g[q];
+              v.y = (q + 1 == j ? 1.0 : 0.0) - g[q + 1];
+              *reinterpret_cast<double2*>(&hrow[s][t][q]) = v;
+            }
+          }
+          hcol[s][t][a] = (a == j ? 1.0 : 0.0) - g[j];
+          wave_sync();
+          // Sherman-Morrison: G <- G - (Delta / r) G[:, j] X[j, :]
+          const double cg = (s == 0 ? du / ru : dd / rd) * g[j];
+#pragma unroll
+          for (int q = 0; q < KB; q += 2) {
+            const double2 x2 = *reinterpret_cast<const double2*>(&hrow[s][t][q]);
+            g[q] -= cg * x2.x;
+            g[q + 1] -= cg * x2.y;
+          }
+          if (lane == 0) {
+            Fl[t] = j;
+            dF[0][t] = du;
+            dF[1][t] = dd;
+          }
+          fc = t + 1;
+        }
+        if (lane == 0) fs[j] = (int8_t)(-fs[j]);
+        if (ru * rd < 0) sign = -sign;
+        nacc += 1;
+      }
+    }
+  }
+  wave_sync();
+  const int f = fc;
+  if (lane < nseg) frow[s0 + lane] = fs[lane];
+  if (lane < f) C.flist[lane] = s0 + Fl[lane];
+  if (lane == 0) {
+    st->fcount = f;
+    st->foff = 0;
+    st->ftot = f;
+    st->sign = sign;
+    st->accepted += nacc;
+    st->proposed += nseg;
+  }
+  if (f == 0) return;
+
+  // ---- K = Delta_F^{-1} + X_s[F,F] = L U: lane (s, u) assembles row u ----
+  {
+    double lu[KB];
+    const int ju = a < f ? Fl[a] : 0;
+#pragma unroll
+    for (int v = 0; v < KB; ++v) {
+      double x = (v == a) ? 1.0 : 0.0;   // identity padding beyond f
+      if (a < f && v < f) {
+        if (v < a) {
+          const double piv = hrow[s][v][Fl[v]] + 1.0 / dF[s][v];
+          x = hcol[s][v][ju] / piv;
+        } else {
+          x = hrow[s][a][Fl[v]] + (v == a ? 1.0 / dF[s][a] : 0.0);
+        }
+      }
+      lu[v] = x;
+    }
+    wave_sync();
+#pragma unroll
+    for (int v = 0; v < KB; v += 2)
+      *reinterpret_cast<double2*>(&hrow[s][a][v]) = make_double2(lu[v], lu[v + 1]);
+    wave_sync();
+  }
+  // LU[s][u][v]: U on and above the diagonal, L below; LT[s][v][u] = LU[s][u][v]
+  // (in the column-history area) so that every substitution step reads one
+  // contiguous row of either
+  double(*LT)[KB][KB] = reinterpret_cast<double(*)[KB][KB]>(&hcol[0][0][0]);
+  static_assert(sizeof(double) * 2 * KB * KB <= sizeof(hcol), "the transpose fits");
+#pragma unroll
+  for (int v = 0; v < KB; ++v) LT[s][v][a] = hrow[s][a][v];
+  wave_sync();
+  const double(*LU)[KB][KB] = hrow;
+
+  // ---- per spin: Mf, the flip scaling of M[F,:], and Wf ----
+  // One substitution step j: y_j is final (divided by the pivot when piv),
+  // then y_i -= row[i] y_j for the later (i > j, forward) or earlier (i < j,
+  // backward) unknowns; row is a contiguous LDS row, read with 128-bit loads.
+  auto step = [](double (&y)[KB], const double* row, int j, bool piv, bool fwd) {
+    double r[KB];
+#pragma unroll
+    for (int c = 0; c < KB; c += 2) {
+      const double2 v = *reinterpret_cast<const double2*>(row + c);
+      r[c] = v.x;
+      r[c + 1] = v.y;
+    }
+    const double yj = piv ? y[j] / r[j] : y[j];
+    y[j] = yj;
+#pragma unroll
+    for (int i = 0; i < KB; ++i)
+      if (fwd ? i > j : i < j) y[i] -= r[i] * yj;
+    __builtin_amdgcn_sched_barrier(0);   // one step's row live at a time
+  };
+  for (int sp = 0; sp < 2; ++sp) {
+    const int nn = C.n[sp];
+    GLOBAL double* __restrict__ Mv = gp((double*)C.F[dir][sp][parity]);
+    const GLOBAL double* __restrict__ Qv = gp((const double*)C.F[1 - dir][sp][parity]);
+    GLOBAL double* __restrict__ mf = gp(C.Mf[sp]);
+    GLOBAL double* __restrict__ wf = gp(C.Wf[sp]);
+    for (int k = lane; k < nn; k += 64) {
+      double y[KB];
+#pragma unroll
+      for (int p = 0; p < KB; ++p) {
+        y[p] = 0.0;
+        if (p < f) {
+          const size_t o = (size_t)(s0 + Fl[p]) * nn + k;
+          const double v = Mv[o];
+          mf[(size_t)p * nn + k] = v;
+          Mv[o] = v * (1.0 + dF[sp][p]);
+          y[p] = Qv[o];
+        }
+      }
+      if (dir == 0) {
+        // Wf = Z^T Q_F = L^{-T} U^{-T} Q_F.  U^T y = y: forward, step j uses
+        // column j of U^T = row j of U; L^T y = y: backward, step j uses
+        // column j of L^T = row j of L.
+#pragma unroll
+        for (int jj = 0; jj < KB; ++jj) step(y, LU[sp][jj], jj, true, true);
+#pragma unroll
+        for (int jj = KB - 1; jj >= 0; --jj) step(y, LU[sp][jj], jj, false, false);
+      } else {
+        // Wf = Z Q_F = U^{-1} L^{-1} Q_F.  L y = y: forward, step j uses
+        // column j of L = row j of LT; U y = y: backward, column j of U.
+#pragma unroll
+        for (int jj = 0; jj < KB; ++jj) step(y, LT[sp][jj], jj, false, true);
+#pragma unroll
+        for (int jj = KB - 1; jj >= 0; --jj) step(y, LT[sp][jj], jj, true, false);
+      }
+#pragma unroll
+      for (int p = 0; p < KB; ++p)
+        if (p < f) wf[(size_t)p * nn + k] = y[p];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Segment update of the dual factor, Q <- Q - (Q Mf^T) Wf (Q: N x n, Mf and
+// Wf: f x n, f <= 32, n <= 128), on MFMA (v_mfma_f64_16x16x4f64).  One
+// workgroup per chain and spin stages Mf and Wf in LDS once (zero-padded to
+// 32 rows and 128 columns) and walks the rows of Q in tiles of 256, 16 per
+// wave (16 waves, four per SIMD, so one wave's loads overlap another's
+// MFMA work).  Lane l
+// (row l % 16, g = l / 16) holds Q[row][16 b + g + 4 i] for every 16-column
+// block b and i = 0..3:
+//   P = Q_tile Mf^T: the k-steps of block b are k = 16 b + 4 i + {0..3} over
+//     the lane groups, so x[b][i] is the A operand of step i as loaded;
+//   P goes through LDS to become the B operand of C^T = Wf^T P^T, whose
+//     16 x 16 output block b has lane l holding C^T[16 b + 4 i + g][l % 16],
+//     the update of exactly x[b][i].
+// Q is read and written once, each row as whole 32-byte pieces.
+// Grid: chains x 2 spins.
+// ---------------------------------------------------------------------------
+constexpr int kUpdWaves = 16;               // waves per workgroup
+constexpr int kUpdThreads = 64 * kUpdWaves;
+constexpr int kUpdRows = 16 * kUpdWaves;     // rows of Q per tile (16 per wave)
+
+__global__ __launch_bounds__(kUpdThreads) void k_segupd_f(const ChainDev* __restrict__ chains,
+                                                          int dir, int parity) {
+  constexpr int KB = kBlock;
+  constexpr int NB = 8;                  // 16-column blocks of Q (n <= 128)
+  constexpr int LDM = NB * 16 + 1;       // Mf rows: odd stride (read by row in the MFMA)
+  constexpr int LDW = NB * 16;           // Wf rows
+  constexpr int LDP = KB + 1;
+  const int cs = xcd_remap(blockIdx.x, gridDim.x), sp = cs & 1;
+  const ChainDev& C = chains[cs >> 1];
+  const int N = C.N, nn = C.n[sp], tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int f = C.st->fcount;
+  if (f == 0) return;
+  __shared__ __align__(16) double Ms[KB * LDM];
+  __shared__ __align__(16) double Ws[KB * LDW];
+  __shared__ __align__(16) double Ps[kUpdWaves * 16 * LDP];   // P of every wave
+  {
+    // all loads of the staging in flight at once, then the LDS stores
+    const GLOBAL double* __restrict__ mf = gp((const double*)C.Mf[sp]);
+    const GLOBAL double* __restrict__ wf = gp((const double*)C.Wf[sp]);
+    constexpr int NS = KB * LDW / kUpdThreads;
+    static_assert(NS * kUpdThreads == KB * LDW, "staging covers the tiles");
+    double vm[NS], vw[NS];
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+      const int idx = tid + t * kUpdThreads, j = idx / LDW, k = idx - j * LDW;
+      const bool ok = j < f && k < nn;
+      vm[t] = ok ? mf[(size_t)j * nn + k] : 0.0;
+      vw[t] = ok ? wf[(size_t)j * nn + k] : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+      const int idx = tid + t * kUpdThreads, j = idx / LDW, k = idx - j * LDW;
+      Ms[j * LDM + k] = vm[t];
+      Ws[j * LDW + k] = vw[t];
+    }
+  }
+  __syncthreads();
+  const int nb = (nn + 15) / 16;
+  const int nks = (f + 3) / 4;
+  const int l16 = lane & 15, g = lane >> 4;
+  GLOBAL double* __restrict__ Qb = gp((double*)C.F[1 - dir][sp][parity]);
+  double* Pw = Ps + wave * 16 * LDP;
+  for (int row = wave * 16 + l16; row - l16 < N; row += kUpdRows) {
+    const bool rok = row < N;
+    GLOBAL double* __restrict__ q = Qb + (size_t)row * nn;
+    double x[NB][4];
+#pragma unroll
+    for (int bb = 0; bb < NB; ++bb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int k = 16 * bb + g + 4 * i;
+        x[bb][i] = (rok && bb < nb && k < nn) ? q[k] : 0.0;
+      }
+    // P = Q_tile Mf^T, two 16 x 16 blocks over the accepted flips
+    doublex4 pacc[2];
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) pacc[jb][r] = 0.0;
+#pragma unroll
+    for (int bb = 0; bb < NB; ++bb) {
+      if (bb < nb) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int k = 16 * bb + 4 * i + g;
+#pragma unroll
+          for (int jb = 0; jb < 2; ++jb)
+            pacc[jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[bb][i], Ms[(16 * jb + l16) * LDM + k],
+                                                            pacc[jb], 0, 0, 0);
+        }
+      }
+    }
+    // P to LDS (element (4 r + g, 16 jb + l16) of the wave's 16 x 32 block)
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Pw[(4 * r + g) * LDP + 16 * jb + l16] = pacc[jb][r];
+    wave_sync();
+    // C^T = Wf^T P^T per 16-column block of Q; K = f in steps of 4
+#pragma unroll
+    for (int bb = 0; bb < NB; ++bb) {
+      if (bb < nb) {
+        doublex4 acc;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[r] = 0.0;
+        for (int ks = 0; ks < nks; ++ks) {
+          const int kk = 4 * ks + g;
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Ws[kk * LDW + 16 * bb + l16], Pw[l16 * LDP + kk],
+                                                     acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) x[bb][i] -= acc[i];
+      }
+    }
+    wave_sync();   // P of this tile read before the next tile overwrites it
+#pragma unroll
+    for (int bb = 0; bb < NB; ++bb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int k = 16 * bb + g + 4 * i;
+        if (rok && bb < nb && k < nn) q[k] = x[bb][i];
+      }
+  }
+}
+
+hipError_t launch_scan_f(const ChainDev* c, int nc, const Ctl* ctl, int l, int M, int s0, int s1,
+                         int dir, int parity, hipStream_t s) {
+  hipLaunchKernelGGL(k_scan_f, dim3(nc), dim3(64), 0, s, c, ctl, l, M, s0, s1, dir, parity);
+  return hipGetLastError();
+}
+
+// n_max: the largest lattice of the batch (rows of Q per chain and spin)
+hipError_t launch_segupd_f(const ChainDev* c, int nc, int n_max, int dir, int parity,
+                           hipStream_t s) {
+  (void)n_max;
+  hipLaunchKernelGGL(k_segupd_f, dim3(2 * nc), dim3(kUpdThreads), 0, s, c, dir, parity);
+  return hipGetLastError();
+}
+
+}  // namespace gpqmc
