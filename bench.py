@@ -3,9 +3,14 @@
 Workload (the configuration the headline metric is quoted on): 16x16 periodic
 Hubbard model, t = 1, U = 3.5, 112 + 112 electrons (<n> = 0.875), dtau = 0.1,
 Theta = 10 (l_half = 100 slices per side, M + 2 = 202 slices), Neel trial
-M_N = 0.07 with Gutzwiller g = 0.55 and the trial-only shell-closing ramp,
-mixed precision (FP32-MFMA Green's-function work, FP64 bases and
-stabilisation), a batch of independent chains.
+M_N = 0.07 with Gutzwiller g = 0.55 and the trial-only shell-closing ramp, a
+batch of independent chains.
+
+The timed path is GPQMC_FP64: every step in FP64 with the Green's function
+kept as G = 1 - A B^T.  Two comparison legs are timed on the same batch: the
+FP64 path that wraps G as an N x N matrix (GPQMC_FP64_WRAP) and the mixed path
+with an FP32 Green's function (GPQMC_MIXED); each leg reports its checkpoint
+drift and whether it holds the 1e-5 relative G error bound while sampling.
 
 One step = one sweep (one pass over all 202 slices) of every chain of the
 batch; value = HS-field updates (proposals) per second over the timed steps,
@@ -18,6 +23,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -25,17 +31,23 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-from paper_2303_13403_amd.estimators import weighted_mean  # noqa: E402
+from paper_2303_13403_amd.estimators import pooled_over_chains, weighted_mean  # noqa: E402,F401
 
 METRIC = "HS-field updates/sec at 16×16, L=100; mixed vs FP64 GPU at 1e-5 rel G error"
 UNIT = "HS-field updates/s"
+G_BOUND = 1e-5              # relative G error bound of the metric (mixed path)
 PEAK_FP32_MFMA = 157.3e12   # MI355X dense FP32 matrix, FLOP/s
 PEAK_FP64_MFMA = 78.6e12
 PEAK_HBM = 8.0e12           # MI355X HBM3E, B/s
-# the dominant kernel (largest share of the sweep): the large-tile MFMA GEMM of
-# the kinetic wrap and the slice update; the roofline is taken on its wrap launch
-KERNEL_SRC = os.path.join(ROOT, "paper_2303_13403_amd", "csrc", "gpqmc_gemm.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_wrap_gemm_16x16_b2048.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_2303_13403_amd", "csrc", "gpqmc_scan.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_segment_update_16x16_b2048.txt")
+FLAGGED = 2 | 4 | 8         # NaN, singular L R, sign mismatch (chains left out of the estimates)
+
+# in-sweep timed kernel classes (gpqmc_set_kernel_timing) of each engine
+CLASSES = {
+    "fp64": ("propagation", "segment_update", "scan"),
+    "wrap": ("wrap", "propagation", "slice_update"),
+}
 
 
 def log(*a):
@@ -48,8 +60,9 @@ def kernel_sha() -> str:
 
 
 def read_traffic(chains_per_launch: int, precision: str):
-    """HBM bytes per launch of the wrap GEMM from the committed PMC summary, if
-    it was taken on the current kernel source, launch size and precision."""
+    """HBM bytes per launch of the segment update from the committed PMC
+    summary, if it was taken on the current kernel source, launch size and
+    precision."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     kv = {}
@@ -64,24 +77,39 @@ def read_traffic(chains_per_launch: int, precision: str):
     return float(kv["hbm_bytes_per_launch"])
 
 
+def finite_or_none(x):
+    return x if (x is not None and math.isfinite(x)) else None
+
+
 def workload(args, ns=None):
     from paper_2303_13403_amd.workloads import WORKLOADS
 
     return WORKLOADS[args.workload].replace(stab_interval=args.ns if ns is None else ns,
-                                      delay_rank=args.k)
+                                            delay_rank=args.k)
+
+
+def drift_stats(infos):
+    rel = sorted(i["max_rel_drift"] if math.isfinite(i["max_rel_drift"]) else math.inf
+                 for i in infos)
+    n = len(rel)
+    return {"max": finite_or_none(rel[-1]), "median": finite_or_none(rel[n // 2]),
+            "p90": finite_or_none(rel[min(n - 1, (9 * n) // 10)]),
+            "non_finite": sum(not math.isfinite(r) for r in rel),
+            "frac_above_1e-5": sum(r > G_BOUND for r in rel) / n}
 
 
 def run_gpu(args, precision_name, steps, warmup, ns=None):
-    """Time `steps` sweeps of every chain.  The chains are split into
-    args.groups contiguous groups, one context (and HIP stream) each, swept
-    concurrently: the latency-bound scan and append launches of one group
-    overlap the MFMA GEMMs of another."""
+    """Time `steps` sweeps of every chain after `warmup` unmeasured sweeps.
+    The chains are split into args.groups contiguous groups, one context (and
+    HIP stream) each, swept concurrently."""
     import numpy as np
     import torch
 
     from paper_2303_13403_amd import gpqmc
 
-    prec = {"mixed": gpqmc.MIXED, "fp64": gpqmc.FP64, "mixed32b": gpqmc.MIXED_FP32_BASIS}[precision_name]
+    prec = {"fp64": gpqmc.FP64, "fp64wrap": gpqmc.FP64_WRAP, "mixed": gpqmc.MIXED,
+            "mixed32b": gpqmc.MIXED_FP32_BASIS}[precision_name]
+    classes = CLASSES["fp64" if precision_name == "fp64" else "wrap"]
     w = workload(args, ns)
     G = args.groups
     if G < 1 or args.chains % G:
@@ -91,15 +119,15 @@ def run_gpu(args, precision_name, steps, warmup, ns=None):
     ctxs = []
     for g in range(G):
         chains = [gpqmc.chain_desc_arrays(w, g * per + c, prec) for c in range(per)]
-        ctxs.append(gpqmc.Context(chains, device="cuda:0", meas_capacity=max(64, steps + warmup + 4)))
+        ctxs.append(gpqmc.Context(chains, device="cuda:0", meas_capacity=max(8, steps + 2)))
     for ctx in ctxs:
         ctx.init_trial()
     log(f"[{precision_name}] {G} context(s) + init_trial: {time.time() - t0:.1f} s, "
         f"workspace {sum(c.workspace_bytes for c in ctxs) / 2**30:.2f} GiB")
+    # warm-up sweeps record nothing: the estimates below use the timed sweeps only
     for ctx in ctxs:
-        ctx.sweep(warmup, measure=True)
+        ctx.sweep(warmup, measure=False)
     torch.cuda.synchronize()
-    log(f"[{precision_name}] warmup {warmup} sweeps done")
 
     def all_infos():
         return [ctx.chain_info(c) for ctx in ctxs for c in range(per)]
@@ -109,8 +137,8 @@ def run_gpu(args, precision_name, steps, warmup, ns=None):
     prop0 = sum(i["proposed"] for i in infos0)
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = [torch.cuda.Event(enable_timing=True) for _ in ctxs]
-    # HIP events around every launch of the wrap, propagation and slice-update
-    # GEMMs inside the timed sweeps (on each context's stream)
+    # HIP events around every launch of the timed kernel classes inside the
+    # timed sweeps, on each context's stream
     for ctx in ctxs:
         ctx.set_kernel_timing(7)
     torch.cuda.synchronize()
@@ -130,40 +158,41 @@ def run_gpu(args, precision_name, steps, warmup, ns=None):
         return max(ev0.elapsed_time(e) for e in ev1), time.time() - w0
 
     ms, wall = timed(steps)
-    kt = []
-    for k in range(3):
+    kt = {}
+    for k, name in enumerate(classes):
         parts = [ctx.kernel_timing(k) for ctx in ctxs]
-        kt.append((sum(t for t, _ in parts), sum(n for _, n in parts)))
+        tot, n = sum(t for t, _ in parts), sum(n for _, n in parts)
+        kt[name] = {"ms_per_launch": tot / max(n, 1), "launches": n, "ms_total": tot}
     for ctx in ctxs:
         ctx.set_kernel_timing(0)
     infos = all_infos()
-    graph_ms = timed(steps)[0] if args.graph_check else None
     acc = sum(i["accepted"] for i in infos) - acc0
     prop = sum(i["proposed"] for i in infos) - prop0
     n_updates = (2 * w.l_half + 2) * w.n_sites * args.chains * steps
     assert prop == n_updates, (prop, n_updates)
-    wrap_ms, prop_ms, flush_ms = (t / max(n, 1) for t, n in kt)
-    launches = {"wrap": kt[0][1], "prop": kt[1][1], "slice_update": kt[2][1]}
-    rel = sorted(i["max_rel_drift"] for i in infos)
-    energy = sign = saf = None
-    if args.chains * (steps + warmup) >= 20:
-        rec = np.concatenate([ctx.measurements(c) for ctx in ctxs for c in range(per)])
-        energy, sign = weighted_mean(rec, 1), weighted_mean(rec, 0)
-        saf = weighted_mean(rec, 3)
+    # estimates from the timed sweeps' records, pooled with a delete-one-chain
+    # jackknife over the chains without a NaN, singular or sign-mismatch flag
+    # (the drift flag alone is reported, not excluded)
+    recs, n_flagged = [], 0
+    for ctx in ctxs:
+        for c in range(per):
+            if ctx.chain_info(c)["flags"] & FLAGGED:
+                n_flagged += 1
+                continue
+            recs.append(ctx.measurements(c))
+    est = {}
+    for name, col in (("sign", 0), ("energy_per_site", 1), ("double_occupancy", 2),
+                      ("structure_factor", 3)):
+        e = pooled_over_chains(recs, col) if recs else None
+        est[name] = None if e is None else [e[0], e[1]]
     res = dict(ms=ms, wall=wall, updates=n_updates, accept=acc / max(prop, 1),
-               max_drift=max(i["max_drift"] for i in infos),
-               rel_drift={"max": rel[-1], "median": rel[len(rel) // 2],
-                          "p90": rel[min(len(rel) - 1, (9 * len(rel)) // 10)],
-                          "frac_above_1e-5": sum(r > 1e-5 for r in rel) / len(rel)},
-               flags=sorted({i["flags"] for i in infos}),
-               sign_mismatch=sum(i["sign_mismatch"] for i in infos),
-               wrap_ms=wrap_ms, prop_ms=prop_ms, flush_ms=flush_ms, launches=launches,
-               graph_ms=graph_ms, sign=sign, energy=energy, structure_factor=saf)
+               rel_drift=drift_stats(infos), flags=sorted({i["flags"] for i in infos}),
+               n_flagged=n_flagged, sign_mismatch=sum(i["sign_mismatch"] for i in infos),
+               kernels=kt, estimates=est, stab_interval=w.stab_interval, delay_rank=w.delay_rank)
     log(f"[{precision_name}] {steps} sweeps: {ms:.1f} ms (wall {wall * 1e3:.1f} ms), "
         f"{n_updates / (ms / 1e3):.4g} updates/s, acceptance {res['accept']:.3f}, "
-        f"slice update {flush_ms:.3f} ms/launch, wrap GEMM {wrap_ms:.3f} ms/launch, "
-        f"max drift {res['max_drift']:.2e}, relative drift over chains {res['rel_drift']}, "
-        f"flags {res['flags']}")
+        f"kernels {json.dumps({k: round(v['ms_per_launch'], 4) for k, v in kt.items()})} ms/launch, "
+        f"relative drift {res['rel_drift']}, flags {res['flags']}, flagged chains {n_flagged}")
     for ctx in ctxs:
         ctx.close()
     del ctxs
@@ -171,28 +200,62 @@ def run_gpu(args, precision_name, steps, warmup, ns=None):
     return res
 
 
-def cpu_baseline(args, budget_s=30.0):
-    """The oracle on the host: one chain of the same workload, BLAS on one
-    thread, timed over whole sweeps after its initialisation."""
+# --------------------------------------------------------------------------- #
+# the oracle on the host cores
+# --------------------------------------------------------------------------- #
+def _oracle_worker(job):
+    """One oracle chain of the workload: time one sweep after initialisation
+    (BLAS on one thread).  Runs in a fresh process."""
+    wname, ns, k, chain_id = job
     from threadpoolctl import threadpool_limits
 
     from oracle import pqmc
+    from paper_2303_13403_amd.workloads import WORKLOADS
 
-    w = workload(args)
+    w = WORKLOADS[wname].replace(stab_interval=ns, delay_rank=k)
     with threadpool_limits(limits=1):
-        ch = pqmc.Chain(pqmc.Model.from_workload(w), seed=w.seed, chain_id=0)
+        ch = pqmc.Chain(pqmc.Model.from_workload(w), seed=w.seed, chain_id=chain_id)
         t0 = time.time()
-        n = 0
-        while True:
-            ch.sweep(1, measure=True)
-            n += 1
-            if time.time() - t0 > budget_s / 3 or n >= 3:
-                break
+        ch.sweep(1, measure=True)
         dt = time.time() - t0
-    upd = (2 * w.l_half + 2) * w.n_sites * n
-    return {"value": upd / dt, "unit": UNIT, "cores": 1, "kind": "oracle",
-            "sample": f"{n} sweep(s) of one {w.name} chain ({2 * w.l_half + 2} slices x "
-                      f"{w.n_sites} sites), serial FP64 NumPy, BLAS threads = 1, {dt:.1f} s"}
+    return (2 * w.l_half + 2) * w.n_sites, dt
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(args):
+    """The oracle (serial FP64 NumPy) on the host: one independent chain per
+    core, one sweep each, run concurrently in fresh processes; the aggregate
+    rate is the sum of the per-chain rates (wall time per process)."""
+    import multiprocessing as mp
+
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    cores = max(1, min(avail, args.cpu_cores))
+    w = workload(args)
+    jobs = [(args.workload, w.stab_interval, w.delay_rank, c) for c in range(cores)]
+    t0 = time.time()
+    with mp.get_context("spawn").Pool(cores) as pool:
+        out = pool.map(_oracle_worker, jobs)
+    wall = time.time() - t0
+    rates = [u / dt for u, dt in out]
+    return {"value": sum(rates), "unit": UNIT, "cores": cores, "kind": "oracle",
+            "per_core": sum(rates) / len(rates),
+            "cpu_model": cpu_model(), "host_cpus_visible": avail,
+            "sample": f"{cores} independent chains of the {w.name} workload (chain ids 0..{cores - 1}), "
+                      f"one sweep each ({2 * w.l_half + 2} slices x {w.n_sites} sites) after "
+                      f"initialisation, one process per core, serial FP64 NumPy with BLAS threads = 1; "
+                      f"{wall:.1f} s wall"}
 
 
 def copy_calibration(mib: int, reps: int = 5):
@@ -210,29 +273,41 @@ def copy_calibration(mib: int, reps: int = 5):
     print(json.dumps({"copy_calibration_bytes": n * 4, "reps": reps}), flush=True)
 
 
+def leg_summary(res):
+    value = res["updates"] / (res["ms"] / 1e3)
+    rd = res["rel_drift"]
+    return {"value": value, "unit": UNIT, "ms_per_step": res["ms"] / res.get("steps", 1),
+            "stab_interval": res["stab_interval"], "delay_rank": res["delay_rank"],
+            "acceptance": round(res["accept"], 4), "rel_drift": rd,
+            "holds_1e-5": rd["frac_above_1e-5"] == 0.0 and rd["non_finite"] == 0,
+            "flags": res["flags"], "n_flagged": res["n_flagged"],
+            "kernels_ms_per_launch": {k: v["ms_per_launch"] for k, v in res["kernels"].items()},
+            **res["estimates"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=6)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--chains", type=int, default=2048)
-    ap.add_argument("--workload", default="16x16", choices=["16x16", "honeycomb12x12"],
-                    help="16x16: the headline configuration; honeycomb12x12: the paper's "
-                         "lattice at 288 sites")
+    ap.add_argument("--workload", default="16x16", choices=["16x16", "honeycomb12x12", "12x12"],
+                    help="16x16: the headline configuration; 12x12: the half-filled 12x12 "
+                         "lattice; honeycomb12x12: the paper's lattice at 288 sites")
     ap.add_argument("--groups", type=int, default=1,
-                    help="chain groups, one context and HIP stream each, swept concurrently "
-                         "(the roofline kernel's launches then overlap other groups' work)")
-    ap.add_argument("--ns", type=int, default=5)
+                    help="chain groups, one context and HIP stream each, swept concurrently")
+    ap.add_argument("--ns", type=int, default=10)
     ap.add_argument("--k", type=int, default=32)
-    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64", "mixed32b"])
-    ap.add_argument("--fp64-steps", type=int, default=2,
-                    help="sweeps of the plain FP64 GPU path timed for comparison (0 = skip)")
-    ap.add_argument("--fp64-ns", type=int, default=10,
-                    help="stabilisation interval of the FP64 comparison (its relative drift "
-                         "stays below 1e-6 at 10 on this workload)")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp64wrap", "mixed", "mixed32b"])
+    ap.add_argument("--leg-steps", type=int, default=2,
+                    help="sweeps of each comparison leg (FP64 wrap, mixed); 0 = skip the legs")
+    ap.add_argument("--wrap-ns", type=int, default=10,
+                    help="stabilisation interval of the FP64 wrap leg")
+    ap.add_argument("--mixed-ns", type=int, default=5,
+                    help="stabilisation interval of the mixed leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--graph-check", action="store_true",
-                    help="also time the same number of sweeps launched as HIP graphs")
+    ap.add_argument("--cpu-cores", type=int, default=16,
+                    help="host cores for the oracle leg (one chain each; capped by the visible CPUs)")
     ap.add_argument("--autotune", action="store_true",
                     help="choose --k and --ns with the autotuner on this batch first (table on stderr)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -244,6 +319,12 @@ def main():
               "multi-GPU run are independent, so a node's throughput is N times one GPU's.",
               file=sys.stderr)
         sys.exit(2)
+    # the oracle leg runs first, in fresh processes, before this process
+    # touches the GPU
+    cpu = None
+    if not args.no_cpu_baseline and not args.copy_calibration:
+        cpu = cpu_baseline(args)
+        log(f"[cpu] oracle on {cpu['cores']} cores ({cpu['cpu_model']}): {cpu['value']:.4g} updates/s")
     import torch
 
     if not torch.cuda.is_available():
@@ -257,33 +338,68 @@ def main():
         from paper_2303_13403_amd import gpqmc
         from paper_2303_13403_amd.autotune import autotune
 
-        prec = {"mixed": gpqmc.MIXED, "fp64": gpqmc.FP64, "mixed32b": gpqmc.MIXED_FP32_BASIS}[args.precision]
-        best, _ = autotune([workload(args)] * args.chains, prec, delay_ranks=(16, 32, 64),
+        prec = {"mixed": gpqmc.MIXED, "fp64": gpqmc.FP64, "fp64wrap": gpqmc.FP64_WRAP,
+                "mixed32b": gpqmc.MIXED_FP32_BASIS}[args.precision]
+        best, _ = autotune([workload(args)] * args.chains, prec, delay_ranks=(16, 32),
                            stab_intervals=(5, 10, 20), log=log)
         args.k, args.ns = best.delay_rank, best.stab_interval
         log(f"autotune: k={args.k} n_s={args.ns}")
     w = workload(args)
     N, M = w.n_sites, 2 * w.l_half
     main_res = run_gpu(args, args.precision, args.steps, args.warmup)
-    fp64_res = None
-    if args.fp64_steps > 0 and args.precision != "fp64":
-        fp64_res = run_gpu(args, "fp64", args.fp64_steps, 1, ns=args.fp64_ns)
+    main_res["steps"] = args.steps
+    legs = {}
+    if args.leg_steps > 0:
+        for name, prec, ns in (("fp64_wrap_gpu", "fp64wrap", args.wrap_ns),
+                               ("mixed_gpu", "mixed", args.mixed_ns)):
+            if prec == args.precision:
+                continue
+            r = run_gpu(args, prec, args.leg_steps, 1, ns=ns)
+            r["steps"] = args.leg_steps
+            legs[name] = leg_summary(r)
 
     value = main_res["updates"] / (main_res["ms"] / 1e3)
-    # dominant kernel: the kinetic-wrap GEMM Gtmp = e^{-dtau K} G, MFMA-bound;
-    # algorithmic flops per launch = every chain of the group x 2 spins x 2 N^3
     per_launch = args.chains // args.groups
-    wrap_flops = 2.0 * per_launch * 2.0 * N ** 3
-    peak = PEAK_FP32_MFMA if args.precision != "fp64" else PEAK_FP64_MFMA
-    achieved = wrap_flops / (main_res["wrap_ms"] / 1e3)
-    traffic = read_traffic(per_launch, args.precision)
+    n_up = w.n_up
+    kt = main_res["kernels"]
+    rooflines = []
+    if args.precision == "fp64":
+        # segment update Q <- Q - (Q Mf^T) Wf, bound by HBM: algorithmic bytes
+        # per chain and spin = Q read and written (2 N n doubles) + Mf and Wf
+        # read (2 f n doubles), f = the mean accepted flips of a segment
+        f_mean = main_res["accept"] * args.k
+        seg_bytes = 2 * per_launch * 8.0 * (2 * N * n_up + 2 * f_mean * n_up)
+        seg_ms = kt["segment_update"]["ms_per_launch"]
+        seg_ach = seg_bytes / (seg_ms / 1e3)
+        rooflines.append({"bound": "hbm", "achieved": seg_ach / 1e9, "peak": PEAK_HBM / 1e9,
+                          "unit": "GB/s", "frac": seg_ach / PEAK_HBM,
+                          "traffic": read_traffic(per_launch, args.precision),
+                          "kernel": "k_segupd_f (Q <- Q - (Q Mf^T) Wf, every chain x 2 spins)",
+                          "bytes_per_launch": seg_bytes, "ms_per_launch": seg_ms,
+                          "ms_total": kt["segment_update"]["ms_total"],
+                          "timing": f"HIP events on the context's stream around each of the "
+                                    f"{kt['segment_update']['launches']} launches in the timed sweeps"})
+        # propagation of both factors, FP64 MFMA: 2 N^2 n flops per factor,
+        # chain and spin
+        prop_flops = per_launch * 2 * 2 * 2.0 * N * N * n_up
+        prop_ms = kt["propagation"]["ms_per_launch"]
+        prop_ach = prop_flops / (prop_ms / 1e3)
+        rooflines.append({"bound": "mfma", "achieved": prop_ach / 1e12, "peak": PEAK_FP64_MFMA / 1e12,
+                          "unit": "TFLOP/s", "frac": prop_ach / PEAK_FP64_MFMA, "traffic": None,
+                          "kernel": "k_gemm<double, PROPR> (A <- D e^{-+dtau K} A, B likewise; "
+                                    "every chain x 2 spins x 2 factors)",
+                          "flops_per_launch": prop_flops, "ms_per_launch": prop_ms,
+                          "ms_total": kt["propagation"]["ms_total"],
+                          "timing": f"HIP events around each of the {kt['propagation']['launches']} "
+                                    f"launches in the timed sweeps"})
+        rooflines.sort(key=lambda r: -r["ms_total"])
     out = {
         "metric": METRIC if args.workload == "16x16" else f"HS-field updates/sec, {w.name}",
         "value": value, "unit": UNIT, "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": main_res["ms"] / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "dtype": "f64" if args.precision in ("fp64", "fp64wrap") else "f32+f64",
         "data": "synthetic",
         "config": {
             "workload": (f"16x16 periodic Hubbard, U=3.5, 112+112 electrons, dtau=0.1, "
@@ -293,40 +409,37 @@ def main():
                          f"{M + 2} slices, Neel M_N={w.m_neel} + Gutzwiller g={w.g}, "
                          f"batch of {args.chains} chains"),
             "chains": args.chains, "chain_groups": args.groups,
-            "precision": args.precision, "stab_interval": args.ns,
-            "delay_rank": args.k, "acceptance": round(main_res["accept"], 4),
-            "max_drift": main_res["max_drift"], "rel_drift": main_res["rel_drift"],
-            "flags": main_res["flags"], "energy_per_site": main_res["energy"],
-            "structure_factor": main_res["structure_factor"], "sign": main_res["sign"],
+            "precision": {"fp64": "fp64, factored G = 1 - A B^T",
+                          "fp64wrap": "fp64, G wrapped as N x N",
+                          "mixed": "FP32 G, FP64 bases and checkpoints",
+                          "mixed32b": "FP32 G and bases"}[args.precision],
+            "stab_interval": args.ns, "delay_rank": args.k,
+            "acceptance": round(main_res["accept"], 4),
+            "rel_drift": main_res["rel_drift"],
+            "holds_1e-5": main_res["rel_drift"]["frac_above_1e-5"] == 0.0
+                          and main_res["rel_drift"]["non_finite"] == 0,
+            "flags": main_res["flags"], "n_flagged": main_res["n_flagged"],
+            "estimates_from": f"the {args.steps} timed sweeps (warm-up sweeps record nothing), "
+                              f"pooled over the chains without a NaN, singular or sign-mismatch "
+                              f"flag, delete-one-chain jackknife",
+            **main_res["estimates"],
         },
-        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
-                     "kernel": ("k_gemm_l STORE (e^{-dtau K} G, " if args.precision != "fp64" else
-                                "k_gemm<double> STORE (e^{-dtau K} G, ") +
-                               ("every chain x 2 spins" if args.groups == 1 else
-                                "every chain of a group x 2 spins") +
-                               ("; 128x128 MFMA tiles)" if args.precision != "fp64" else ")"),
-                     "flops_per_launch": wrap_flops, "ms_per_launch": main_res["wrap_ms"],
-                     "timing": f"HIP events on the context's stream around each of the "
-                               f"{main_res['launches']['wrap']} launches in the timed sweeps" +
-                               (f" ({args.groups} chain groups running concurrently)"
-                                if args.groups > 1 else "")},
-        "slice_update_gemm_ms": main_res["flush_ms"],
-        "propagation_gemm_ms": main_res["prop_ms"],
+        "kernels_ms_per_launch": {k: v["ms_per_launch"] for k, v in kt.items()},
+        "kernel_launches": {k: v["launches"] for k, v in kt.items()},
         "launch": (f"{args.groups} chain groups of {args.chains // args.groups}, one context and "
                    f"HIP stream each, swept concurrently; " if args.groups > 1 else
                    "one context; ") + "direct launches (kernel events in the timed sweeps)",
     }
-    if main_res["graph_ms"] is not None:
-        out["graph_ms_per_step"] = main_res["graph_ms"] / args.steps
-    if fp64_res is not None:
-        out["fp64_gpu"] = {"value": fp64_res["updates"] / (fp64_res["ms"] / 1e3), "unit": UNIT,
-                           "steps": args.fp64_steps, "stab_interval": args.fp64_ns,
-                           "wrap_gemm_ms_per_launch": fp64_res["wrap_ms"],
-                           "rel_drift": fp64_res["rel_drift"], "energy_per_site": fp64_res["energy"]}
-        out["mixed_over_fp64"] = value / out["fp64_gpu"]["value"]
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args)
+    if rooflines:
+        out["roofline"] = rooflines[0]
+        out["roofline_2"] = rooflines[1]
+    out.update(legs)
+    if "fp64_wrap_gpu" in legs:
+        out["speedup_over_fp64_wrap"] = value / legs["fp64_wrap_gpu"]["value"]
+    if "mixed_gpu" in legs:
+        out["mixed_over_this"] = legs["mixed_gpu"]["value"] / value
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

@@ -1426,12 +1426,9 @@ namespace gpqmc {
 // start) in flip order, so they give K = L U directly:
 //   U[t][v] = X^{(t)}[j_t, j_v] + delta_tv / Delta_t   (v >= t),
 //   L[u][t] = X^{(t)}[j_u, j_t] / U[t][t]               (u > t),
-// with X^{(t)} the block before flip t.  The Woodbury core is Z = K^{-1}.  The
-// wave then writes, per spin, Mf = M[F,:] (the moving factor before the flip
-// scaling), scales M[F,:] by 1 + Delta_F, and solves Wf = Z^T Q[F,:]
-// (upward) or Z Q[F,:] (downward) column by column with the triangular
-// factors: lanes run over the n columns.  k_segupd_f then applies
-// Q <- Q - (Q Mf^T) Wf.
+// with X^{(t)} the block before flip t.  The Woodbury core is Z = K^{-1}; the
+// wave writes the packed L U factors (32 x 32 per spin) to the Z buffer.
+// k_wf then forms the Woodbury rows and k_segupd_f applies them.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(64) void k_scan_f(const ChainDev* __restrict__ chains,
                                                const Ctl* __restrict__ ctl, int l, int M, int s0,
@@ -1597,20 +1594,53 @@ __global__ __launch_bounds__(64) void k_scan_f(const ChainDev* __restrict__ chai
       *reinterpret_cast<double2*>(&hrow[s][a][v]) = make_double2(lu[v], lu[v + 1]);
     wave_sync();
   }
-  // LU[s][u][v]: U on and above the diagonal, L below; LT[s][v][u] = LU[s][u][v]
-  // (in the column-history area) so that every substitution step reads one
-  // contiguous row of either
-  double(*LT)[KB][KB] = reinterpret_cast<double(*)[KB][KB]>(&hcol[0][0][0]);
-  static_assert(sizeof(double) * 2 * KB * KB <= sizeof(hcol), "the transpose fits");
+  // LU[s][u][v] (U on and above the diagonal, L below) to the chain's Z buffer
+  {
+    typedef double v2 __attribute__((ext_vector_type(2)));
+    GLOBAL double* __restrict__ z = gp((double*)C.Z[s]) + (size_t)a * KB;
 #pragma unroll
-  for (int v = 0; v < KB; ++v) LT[s][v][a] = hrow[s][a][v];
-  wave_sync();
-  const double(*LU)[KB][KB] = hrow;
+    for (int v = 0; v < KB; v += 2)
+      *reinterpret_cast<GLOBAL v2*>(z + v) = *reinterpret_cast<const v2*>(&hrow[s][a][v]);
+  }
+}
 
-  // ---- per spin: Mf, the flip scaling of M[F,:], and Wf ----
-  // One substitution step j: y_j is final (divided by the pivot when piv),
-  // then y_i -= row[i] y_j for the later (i > j, forward) or earlier (i < j,
-  // backward) unknowns; row is a contiguous LDS row, read with 128-bit loads.
+// ---------------------------------------------------------------------------
+// Woodbury rows of a segment (factored engine, after k_scan_f), one workgroup
+// per chain and spin, a thread per column k of the factors: Mf = M[F, k] (the
+// moving factor's rows at the accepted sites, then scaled by 1 + Delta_F),
+// and Wf = Z^T Q[F, k] (upward) or Z Q[F, k] (downward) with Z = (L U)^{-1}
+// from the LU factors the scan left in the Z buffer.  Delta_F follows from
+// the flipped fields of slice l.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(128) void k_wf(const ChainDev* __restrict__ chains, int l, int M,
+                                            int dir, int parity) {
+  constexpr int KB = kBlock;
+  const int cs = xcd_remap(blockIdx.x, gridDim.x), sp = cs & 1;
+  const ChainDev& C = chains[cs >> 1];
+  const int f = C.st->fcount;
+  if (f == 0) return;
+  const int N = C.N, nn = C.n[sp], tid = threadIdx.x;
+  __shared__ __align__(16) double LU[KB][KB];   // U on and above the diagonal, L below
+  __shared__ __align__(16) double LT[KB][KB];   // its transpose
+  __shared__ int Fs[KB];
+  __shared__ double dF[KB];
+  const GLOBAL double* __restrict__ z = gp((const double*)C.Z[sp]);
+  for (int idx = tid; idx < KB * KB; idx += 128) {
+    const double v = z[idx];
+    LU[idx / KB][idx % KB] = v;
+    LT[idx % KB][idx / KB] = v;
+  }
+  if (tid < f) {
+    const int site = C.flist[tid];
+    const int bnd = (l == 0 || l == M + 1) ? 0 : 1;
+    const int si_old = C.field[(size_t)l * N + site] < 0 ? 0 : 1;   // the field is flipped
+    Fs[tid] = site;
+    dF[tid] = C.delta[bnd][sp][si_old];
+  }
+  __syncthreads();
+  // one substitution step j: y_j final (divided by the pivot when piv), then
+  // y_i -= row[i] y_j for the later (fwd) or earlier unknowns; row is one
+  // contiguous LDS row, read with 128-bit loads
   auto step = [](double (&y)[KB], const double* row, int j, bool piv, bool fwd) {
     double r[KB];
 #pragma unroll
@@ -1624,47 +1654,43 @@ __global__ __launch_bounds__(64) void k_scan_f(const ChainDev* __restrict__ chai
 #pragma unroll
     for (int i = 0; i < KB; ++i)
       if (fwd ? i > j : i < j) y[i] -= r[i] * yj;
-    __builtin_amdgcn_sched_barrier(0);   // one step's row live at a time
+    __builtin_amdgcn_sched_barrier(0);
   };
-  for (int sp = 0; sp < 2; ++sp) {
-    const int nn = C.n[sp];
-    GLOBAL double* __restrict__ Mv = gp((double*)C.F[dir][sp][parity]);
-    const GLOBAL double* __restrict__ Qv = gp((const double*)C.F[1 - dir][sp][parity]);
-    GLOBAL double* __restrict__ mf = gp(C.Mf[sp]);
-    GLOBAL double* __restrict__ wf = gp(C.Wf[sp]);
-    for (int k = lane; k < nn; k += 64) {
-      double y[KB];
+  GLOBAL double* __restrict__ Mv = gp((double*)C.F[dir][sp][parity]);
+  const GLOBAL double* __restrict__ Qv = gp((const double*)C.F[1 - dir][sp][parity]);
+  GLOBAL double* __restrict__ mf = gp(C.Mf[sp]);
+  GLOBAL double* __restrict__ wf = gp(C.Wf[sp]);
+  for (int k = tid; k < nn; k += 128) {
+    double y[KB];
 #pragma unroll
-      for (int p = 0; p < KB; ++p) {
-        y[p] = 0.0;
-        if (p < f) {
-          const size_t o = (size_t)(s0 + Fl[p]) * nn + k;
-          const double v = Mv[o];
-          mf[(size_t)p * nn + k] = v;
-          Mv[o] = v * (1.0 + dF[sp][p]);
-          y[p] = Qv[o];
-        }
+    for (int p = 0; p < KB; ++p) {
+      y[p] = 0.0;
+      if (p < f) {
+        const size_t o = (size_t)Fs[p] * nn + k;
+        const double v = Mv[o];
+        mf[(size_t)p * nn + k] = v;
+        Mv[o] = v * (1.0 + dF[p]);
+        y[p] = Qv[o];
       }
-      if (dir == 0) {
-        // Wf = Z^T Q_F = L^{-T} U^{-T} Q_F.  U^T y = y: forward, step j uses
-        // column j of U^T = row j of U; L^T y = y: backward, step j uses
-        // column j of L^T = row j of L.
-#pragma unroll
-        for (int jj = 0; jj < KB; ++jj) step(y, LU[sp][jj], jj, true, true);
-#pragma unroll
-        for (int jj = KB - 1; jj >= 0; --jj) step(y, LU[sp][jj], jj, false, false);
-      } else {
-        // Wf = Z Q_F = U^{-1} L^{-1} Q_F.  L y = y: forward, step j uses
-        // column j of L = row j of LT; U y = y: backward, column j of U.
-#pragma unroll
-        for (int jj = 0; jj < KB; ++jj) step(y, LT[sp][jj], jj, false, true);
-#pragma unroll
-        for (int jj = KB - 1; jj >= 0; --jj) step(y, LT[sp][jj], jj, true, false);
-      }
-#pragma unroll
-      for (int p = 0; p < KB; ++p)
-        if (p < f) wf[(size_t)p * nn + k] = y[p];
     }
+    if (dir == 0) {
+      // Wf = Z^T Q_F = L^{-T} U^{-T} Q_F: U^T y = y forward (step j uses row
+      // j of U), then L^T y = y backward (row j of L)
+#pragma unroll
+      for (int jj = 0; jj < KB; ++jj) step(y, LU[jj], jj, true, true);
+#pragma unroll
+      for (int jj = KB - 1; jj >= 0; --jj) step(y, LU[jj], jj, false, false);
+    } else {
+      // Wf = Z Q_F = U^{-1} L^{-1} Q_F: L y = y forward (column j of L),
+      // then U y = y backward (column j of U)
+#pragma unroll
+      for (int jj = 0; jj < KB; ++jj) step(y, LT[jj], jj, false, true);
+#pragma unroll
+      for (int jj = KB - 1; jj >= 0; --jj) step(y, LT[jj], jj, true, false);
+    }
+#pragma unroll
+    for (int p = 0; p < KB; ++p)
+      if (p < f) wf[(size_t)p * nn + k] = y[p];
   }
 }
 
@@ -1797,6 +1823,8 @@ __global__ __launch_bounds__(kUpdThreads) void k_segupd_f(const ChainDev* __rest
 hipError_t launch_scan_f(const ChainDev* c, int nc, const Ctl* ctl, int l, int M, int s0, int s1,
                          int dir, int parity, hipStream_t s) {
   hipLaunchKernelGGL(k_scan_f, dim3(nc), dim3(64), 0, s, c, ctl, l, M, s0, s1, dir, parity);
+  if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
+  hipLaunchKernelGGL(k_wf, dim3(2 * nc), dim3(128), 0, s, c, l, M, dir, parity);
   return hipGetLastError();
 }
 
