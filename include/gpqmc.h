@@ -232,6 +232,23 @@ gpqmc_status gpqmc_debug_gemm(int32_t precision, int32_t M, int32_t N, int32_t K
                               const void* A, int32_t lda, const void* B, int32_t ldb, void* C,
                               int32_t ldc, void* hip_stream);
 
+/* Allocation-free variant of gpqmc_debug_gemm, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight loops, harnesses
+ * that forbid hipMalloc): the same C = op(A) B on the same MFMA tile kernels
+ * (same arguments, layouts and flags), but the GEMM descriptor lives in a
+ * file-scope device array of the library (256 KiB per GPU, held until the
+ * process ends) and is written there by a kernel, so the call makes no
+ * allocation and no host-to-device copy.  Enqueue only: it returns before the
+ * product is done (synchronise hip_stream before reading C).  At most 16368
+ * output tiles (64 x 64, or 128 x 128 with the large-tile flag); larger
+ * products return GPQMC_EINVAL.  Every call on one GPU uses that GPU's
+ * array: calls that overlap on one GPU (other streams or threads) race;
+ * calls in order on one stream do not.  Errors: EINVAL (sizes, flags,
+ * precision), EHIP. */
+gpqmc_status gpqmc_gemm_noalloc(int32_t precision, int32_t M, int32_t N, int32_t K, int32_t flags,
+                                const void* A, int32_t lda, const void* B, int32_t ldb, void* C,
+                                int32_t ldc, void* hip_stream);
+
 /* Average duration (ms) of one launch of a hot-path kernel for all chains,
  * timed with HIP events on the context's stream over reps back-to-back
  * launches on the chains' current data.  G-wrap engines: kernel 0 = the

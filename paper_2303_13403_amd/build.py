@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgpqmc.so")
-SOURCES = ["gpqmc_gemm.hip", "gpqmc_scan.hip", "gpqmc_ckpt.hip", "gpqmc_host.cpp"]
+SOURCES = ["gpqmc_gemm.hip", "gpqmc_scan.hip", "gpqmc_ckpt.hip", "gpqmc_host.cpp", "gpqmc_noalloc.hip"]
 ARCH = os.environ.get("GPQMC_ARCH", "gfx950")
 
 

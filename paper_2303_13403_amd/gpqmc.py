@@ -61,7 +61,7 @@ EXPORTS = [
     "gpqmc_reset_measurements",
     "gpqmc_set_field", "gpqmc_get_field", "gpqmc_get_green", "gpqmc_get_chain_info",
     "gpqmc_set_debug", "gpqmc_get_trace", "gpqmc_get_trace_logdet", "gpqmc_logdet",
-    "gpqmc_debug_gemm", "gpqmc_chain_status",
+    "gpqmc_debug_gemm", "gpqmc_gemm_noalloc", "gpqmc_chain_status",
     "gpqmc_time_kernel", "gpqmc_set_kernel_timing", "gpqmc_get_kernel_timing",
     "gpqmc_debug_step", "gpqmc_debug_read", "gpqmc_last_error", "gpqmc_destroy",
 ]
@@ -98,6 +98,7 @@ def load():
         "gpqmc_get_trace_logdet": [VP, I32, P(D)],
         "gpqmc_logdet": [VP, I32, P(D), P(I32)],
         "gpqmc_debug_gemm": [I32, I32, I32, I32, I32, VP, I32, VP, I32, VP, I32, VP],
+        "gpqmc_gemm_noalloc": [I32, I32, I32, I32, I32, VP, I32, VP, I32, VP, I32, VP],
         "gpqmc_chain_status": [VP, I32],
         "gpqmc_time_kernel": [VP, I32, I32, P(ctypes.c_float)],
         "gpqmc_set_kernel_timing": [VP, I32],
@@ -343,6 +344,27 @@ class Context:
             self.close()
         except Exception:
             pass
+
+
+def gemm_noalloc(A, B, C, trans_a: bool = False, precision: int = FP64, stream=None,
+                 large_tile: bool = False):
+    """C = op(A) B through gpqmc_gemm_noalloc into the caller's C (torch device
+    tensors, contiguous, in the precision's dtype); enqueued on ``stream``."""
+    import torch
+
+    lib = load()
+    M = A.shape[1] if trans_a else A.shape[0]
+    K = A.shape[0] if trans_a else A.shape[1]
+    N = B.shape[1]
+    assert C.shape == (M, N) and C.is_contiguous() and A.is_contiguous() and B.is_contiguous()
+    s = stream if stream is not None else torch.cuda.current_stream(A.device)
+    st = lib.gpqmc_gemm_noalloc(precision, M, N, K, (1 if trans_a else 0) | (2 if large_tile else 0),
+                                ctypes.c_void_p(A.data_ptr()), A.shape[1],
+                                ctypes.c_void_p(B.data_ptr()), B.shape[1],
+                                ctypes.c_void_p(C.data_ptr()), N, ctypes.c_void_p(s.cuda_stream))
+    if st != OK:
+        raise GpqmcError(st, "gemm_noalloc")
+    return C
 
 
 def debug_gemm(A, B, trans_a: bool = False, precision: int = FP64, stream=None,
