@@ -59,10 +59,10 @@ def kernel_sha() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def read_traffic(chains_per_launch: int, precision: str):
+def read_traffic(chains_per_launch: int, precision: str, workload: str = "16x16"):
     """HBM bytes per launch of the segment update from the committed PMC
-    summary, if it was taken on the current kernel source, launch size and
-    precision."""
+    summary, if it was taken on the current kernel source, workload, launch
+    size and precision."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     kv = {}
@@ -72,7 +72,8 @@ def read_traffic(chains_per_launch: int, precision: str):
             kv[k.strip()] = v.strip()
     if (kv.get("kernel_source_sha") != kernel_sha()
             or int(kv.get("chains_per_launch", -1)) != chains_per_launch
-            or kv.get("precision") != precision):
+            or kv.get("precision") != precision
+            or kv.get("workload", "16x16") != workload):
         return None
     return float(kv["hbm_bytes_per_launch"])
 
@@ -81,11 +82,35 @@ def finite_or_none(x):
     return x if (x is not None and math.isfinite(x)) else None
 
 
-def workload(args, ns=None):
-    from paper_2303_13403_amd.workloads import WORKLOADS
+DEFAULT_CHAINS = {"16x16": 2048, "12x12": 2048, "honeycomb12x12": 2048, "24x24": 512,
+                  "uneven": 256}
 
-    return WORKLOADS[args.workload].replace(stab_interval=args.ns if ns is None else ns,
-                                            delay_rank=args.k)
+
+def batch(args, ns=None):
+    """The workload of every chain of the batch (uneven: lattices drawn from
+    {6, 8, 10, 12}^2 and U from [2, 6], half filling, Theta = 5)."""
+    from paper_2303_13403_amd.workloads import WORKLOADS, batch_uneven
+
+    ns = args.ns if ns is None else ns
+    if args.workload == "uneven":
+        return batch_uneven(args.chains, precision="fp64", stab_interval=ns, delay_rank=args.k)
+    return [WORKLOADS[args.workload].replace(stab_interval=ns, delay_rank=args.k)] * args.chains
+
+
+def describe(args, ws):
+    w = ws[0]
+    M = 2 * w.l_half
+    if args.workload == "16x16":
+        return (f"16x16 periodic Hubbard, U=3.5, 112+112 electrons, dtau=0.1, Theta=10 "
+                f"(l_half=100, {M + 2} slices), Neel M_N=0.07 + Gutzwiller g=0.55, batch of "
+                f"{len(ws)} chains")
+    if args.workload == "uneven":
+        sizes = sorted({x.lx for x in ws})
+        return (f"batch of {len(ws)} independent half-filled chains, lattices L x L with L drawn "
+                f"from {sizes}, U uniform in [2, 6], dtau={w.dtau}, Theta={w.dtau * w.l_half:g} "
+                f"({M + 2} slices), Neel M_N={w.m_neel} + Gutzwiller g={w.g}")
+    return (f"{w.name}, {w.n_up}+{w.n_dn} electrons, dtau={w.dtau}, {M + 2} slices, Neel "
+            f"M_N={w.m_neel} + Gutzwiller g={w.g}, batch of {len(ws)} chains")
 
 
 def drift_stats(infos):
@@ -110,16 +135,19 @@ def run_gpu(args, precision_name, steps, warmup, ns=None):
     prec = {"fp64": gpqmc.FP64, "fp64wrap": gpqmc.FP64_WRAP, "mixed": gpqmc.MIXED,
             "mixed32b": gpqmc.MIXED_FP32_BASIS}[precision_name]
     classes = CLASSES["fp64" if precision_name == "fp64" else "wrap"]
-    w = workload(args, ns)
+    ws = batch(args, ns)
+    w = ws[0]
     G = args.groups
     if G < 1 or args.chains % G:
         raise SystemExit(f"--groups {G} must divide --chains {args.chains}")
     per = args.chains // G
     t0 = time.time()
     ctxs = []
+    ph = args.particle_hole and precision_name == "fp64"
     for g in range(G):
-        chains = [gpqmc.chain_desc_arrays(w, g * per + c, prec) for c in range(per)]
-        ctxs.append(gpqmc.Context(chains, device="cuda:0", meas_capacity=max(8, steps + 2)))
+        chains = [gpqmc.chain_desc_arrays(ws[g * per + c], g * per + c, prec) for c in range(per)]
+        ctxs.append(gpqmc.Context(chains, device="cuda:0", meas_capacity=max(8, steps + 2),
+                                  particle_hole=ph))
     for ctx in ctxs:
         ctx.init_trial()
     log(f"[{precision_name}] {G} context(s) + init_trial: {time.time() - t0:.1f} s, "
@@ -140,7 +168,7 @@ def run_gpu(args, precision_name, steps, warmup, ns=None):
     # HIP events around every launch of the timed kernel classes inside the
     # timed sweeps, on each context's stream
     for ctx in ctxs:
-        ctx.set_kernel_timing(7)
+        ctx.set_kernel_timing(0 if args.no_kernel_timing else 7)
     torch.cuda.synchronize()
 
     def timed(n):
@@ -168,7 +196,7 @@ def run_gpu(args, precision_name, steps, warmup, ns=None):
     infos = all_infos()
     acc = sum(i["accepted"] for i in infos) - acc0
     prop = sum(i["proposed"] for i in infos) - prop0
-    n_updates = (2 * w.l_half + 2) * w.n_sites * args.chains * steps
+    n_updates = (2 * w.l_half + 2) * sum(x.n_sites for x in ws) * steps
     assert prop == n_updates, (prop, n_updates)
     # estimates from the timed sweeps' records, pooled with a delete-one-chain
     # jackknife over the chains without a NaN, singular or sign-mismatch flag
@@ -188,7 +216,9 @@ def run_gpu(args, precision_name, steps, warmup, ns=None):
     res = dict(ms=ms, wall=wall, updates=n_updates, accept=acc / max(prop, 1),
                rel_drift=drift_stats(infos), flags=sorted({i["flags"] for i in infos}),
                n_flagged=n_flagged, sign_mismatch=sum(i["sign_mismatch"] for i in infos),
-               kernels=kt, estimates=est, stab_interval=w.stab_interval, delay_rank=w.delay_rank)
+               kernels=kt, estimates=est, stab_interval=w.stab_interval, delay_rank=w.delay_rank,
+               spins=[1 if i["particle_hole"] else 2 for i in infos],
+               n_particle_hole=sum(i["particle_hole"] for i in infos))
     log(f"[{precision_name}] {steps} sweeps: {ms:.1f} ms (wall {wall * 1e3:.1f} ms), "
         f"{n_updates / (ms / 1e3):.4g} updates/s, acceptance {res['accept']:.3f}, "
         f"kernels {json.dumps({k: round(v['ms_per_launch'], 4) for k, v in kt.items()})} ms/launch, "
@@ -206,13 +236,11 @@ def run_gpu(args, precision_name, steps, warmup, ns=None):
 def _oracle_worker(job):
     """One oracle chain of the workload: time one sweep after initialisation
     (BLAS on one thread).  Runs in a fresh process."""
-    wname, ns, k, chain_id = job
+    w, chain_id = job
     from threadpoolctl import threadpool_limits
 
     from oracle import pqmc
-    from paper_2303_13403_amd.workloads import WORKLOADS
 
-    w = WORKLOADS[wname].replace(stab_interval=ns, delay_rank=k)
     with threadpool_limits(limits=1):
         ch = pqmc.Chain(pqmc.Model.from_workload(w), seed=w.seed, chain_id=chain_id)
         t0 = time.time()
@@ -242,8 +270,9 @@ def cpu_baseline(args):
     except AttributeError:
         avail = os.cpu_count() or 1
     cores = max(1, min(avail, args.cpu_cores))
-    w = workload(args)
-    jobs = [(args.workload, w.stab_interval, w.delay_rank, c) for c in range(cores)]
+    ws = batch(args)
+    w = ws[0]
+    jobs = [(ws[c % len(ws)], c) for c in range(cores)]
     t0 = time.time()
     with mp.get_context("spawn").Pool(cores) as pool:
         out = pool.map(_oracle_worker, jobs)
@@ -252,8 +281,9 @@ def cpu_baseline(args):
     return {"value": sum(rates), "unit": UNIT, "cores": cores, "kind": "oracle",
             "per_core": sum(rates) / len(rates),
             "cpu_model": cpu_model(), "host_cpus_visible": avail,
-            "sample": f"{cores} independent chains of the {w.name} workload (chain ids 0..{cores - 1}), "
-                      f"one sweep each ({2 * w.l_half + 2} slices x {w.n_sites} sites) after "
+            "sample": f"{cores} independent chains of the {describe(args, ws)} workload "
+                      f"(chain ids 0..{cores - 1}), one sweep each ({2 * w.l_half + 2} slices x "
+                      f"the chain's sites) after "
                       f"initialisation, one process per core, serial FP64 NumPy with BLAS threads = 1; "
                       f"{wall:.1f} s wall"}
 
@@ -290,10 +320,19 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=6)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--chains", type=int, default=2048)
-    ap.add_argument("--workload", default="16x16", choices=["16x16", "honeycomb12x12", "12x12"],
+    ap.add_argument("--chains", type=int, default=None,
+                    help="chains in the batch (default 2048; 512 at 24x24; 256 for uneven)")
+    ap.add_argument("--workload", default="16x16",
+                    choices=["16x16", "honeycomb12x12", "12x12", "24x24", "uneven"],
                     help="16x16: the headline configuration; 12x12: the half-filled 12x12 "
-                         "lattice; honeycomb12x12: the paper's lattice at 288 sites")
+                         "lattice; 24x24: N = 576 at dtau = 0.05, Theta = 10; uneven: 256 chains "
+                         "on 6x6 .. 12x12 with U in [2, 6]; honeycomb12x12: the paper's lattice "
+                         "at 288 sites")
+    ap.add_argument("--no-kernel-timing", action="store_true",
+                    help="time the sweeps as captured HIP graphs, without the in-sweep kernel "
+                         "events (no roofline block)")
+    ap.add_argument("--particle-hole", action="store_true",
+                    help="the half-filling particle-hole shortcut (spin up only) wherever exact")
     ap.add_argument("--groups", type=int, default=1,
                     help="chain groups, one context and HIP stream each, swept concurrently")
     ap.add_argument("--ns", type=int, default=10)
@@ -314,6 +353,8 @@ def main():
                     help="only run device-to-device copies of MIB MiB (the reference kernel for "
                          "scaling the HBM traffic counters) and exit")
     args = ap.parse_args()
+    if args.chains is None:
+        args.chains = DEFAULT_CHAINS[args.workload]
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): the chains of a "
               "multi-GPU run are independent, so a node's throughput is N times one GPU's.",
@@ -340,12 +381,13 @@ def main():
 
         prec = {"mixed": gpqmc.MIXED, "fp64": gpqmc.FP64, "fp64wrap": gpqmc.FP64_WRAP,
                 "mixed32b": gpqmc.MIXED_FP32_BASIS}[args.precision]
-        best, _ = autotune([workload(args)] * args.chains, prec, delay_ranks=(16, 32),
+        best, _ = autotune(batch(args), prec, delay_ranks=(8, 16, 32),
                            stab_intervals=(5, 10, 20), log=log)
         args.k, args.ns = best.delay_rank, best.stab_interval
         log(f"autotune: k={args.k} n_s={args.ns}")
-    w = workload(args)
-    N, M = w.n_sites, 2 * w.l_half
+    ws = batch(args)
+    w = ws[0]
+    M = 2 * w.l_half
     main_res = run_gpu(args, args.precision, args.steps, args.warmup)
     main_res["steps"] = args.steps
     legs = {}
@@ -360,41 +402,50 @@ def main():
 
     value = main_res["updates"] / (main_res["ms"] / 1e3)
     per_launch = args.chains // args.groups
-    n_up = w.n_up
     kt = main_res["kernels"]
     rooflines = []
-    if args.precision == "fp64":
+    spins = main_res["spins"]
+    grp = ws[:per_launch]                  # the chains one launch covers
+    if args.precision == "fp64" and not args.no_kernel_timing:
         # segment update Q <- Q - (Q Mf^T) Wf, bound by HBM: algorithmic bytes
         # per chain and spin = Q read and written (2 N n doubles) + Mf and Wf
-        # read (2 f n doubles), f = the mean accepted flips of a segment
+        # read (2 f n doubles), f = the mean accepted flips of a segment; a
+        # chain takes part in ceil(N / k) of the ceil(N_max / k) launches of a
+        # slice (spin up only with the particle-hole shortcut)
         f_mean = main_res["accept"] * args.k
-        seg_bytes = 2 * per_launch * 8.0 * (2 * N * n_up + 2 * f_mean * n_up)
+        n_seg = math.ceil(max(x.n_sites for x in grp) / args.k)
+        seg_bytes = sum(spins[c] * math.ceil(x.n_sites / args.k) * 8.0 *
+                        (2 * x.n_sites * x.n_up + 2 * f_mean * x.n_up)
+                        for c, x in enumerate(grp)) / n_seg
         seg_ms = kt["segment_update"]["ms_per_launch"]
         seg_ach = seg_bytes / (seg_ms / 1e3)
         rooflines.append({"bound": "hbm", "achieved": seg_ach / 1e9, "peak": PEAK_HBM / 1e9,
                           "unit": "GB/s", "frac": seg_ach / PEAK_HBM,
-                          "traffic": read_traffic(per_launch, args.precision),
-                          "kernel": "k_segupd_f (Q <- Q - (Q Mf^T) Wf, every chain x 2 spins)",
+                          "traffic": None if args.particle_hole else
+                          read_traffic(per_launch, args.precision, args.workload),
+                          "kernel": "k_segupd_f (Q <- Q - (Q Mf^T) Wf, every chain and spin)"
+                                    if max(x.n_up for x in ws) <= 128 else
+                                    "k_gemm SEGP + SEGF (Q Mf^T, then Q - (Q Mf^T) Wf)",
                           "bytes_per_launch": seg_bytes, "ms_per_launch": seg_ms,
                           "ms_total": kt["segment_update"]["ms_total"],
                           "timing": f"HIP events on the context's stream around each of the "
                                     f"{kt['segment_update']['launches']} launches in the timed sweeps"})
         # propagation of both factors, FP64 MFMA: 2 N^2 n flops per factor,
         # chain and spin
-        prop_flops = per_launch * 2 * 2 * 2.0 * N * N * n_up
+        prop_flops = sum(spins[c] * 2 * 2.0 * x.n_sites ** 2 * x.n_up for c, x in enumerate(grp))
         prop_ms = kt["propagation"]["ms_per_launch"]
         prop_ach = prop_flops / (prop_ms / 1e3)
         rooflines.append({"bound": "mfma", "achieved": prop_ach / 1e12, "peak": PEAK_FP64_MFMA / 1e12,
                           "unit": "TFLOP/s", "frac": prop_ach / PEAK_FP64_MFMA, "traffic": None,
                           "kernel": "k_gemm<double, PROPR> (A <- D e^{-+dtau K} A, B likewise; "
-                                    "every chain x 2 spins x 2 factors)",
+                                    "every chain and spin x 2 factors)",
                           "flops_per_launch": prop_flops, "ms_per_launch": prop_ms,
                           "ms_total": kt["propagation"]["ms_total"],
                           "timing": f"HIP events around each of the {kt['propagation']['launches']} "
                                     f"launches in the timed sweeps"})
         rooflines.sort(key=lambda r: -r["ms_total"])
     out = {
-        "metric": METRIC if args.workload == "16x16" else f"HS-field updates/sec, {w.name}",
+        "metric": METRIC if args.workload == "16x16" else f"HS-field updates/sec, {describe(args, ws)}",
         "value": value, "unit": UNIT, "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": main_res["ms"] / args.steps, "higher_is_better": True,
@@ -402,13 +453,9 @@ def main():
         "dtype": "f64" if args.precision in ("fp64", "fp64wrap") else "f32+f64",
         "data": "synthetic",
         "config": {
-            "workload": (f"16x16 periodic Hubbard, U=3.5, 112+112 electrons, dtau=0.1, "
-                         f"Theta=10 (l_half=100, {M + 2} slices), Neel M_N=0.07 + Gutzwiller "
-                         f"g=0.55, batch of {args.chains} chains" if args.workload == "16x16" else
-                         f"{w.name}, {w.n_up}+{w.n_dn} electrons, dtau={w.dtau}, "
-                         f"{M + 2} slices, Neel M_N={w.m_neel} + Gutzwiller g={w.g}, "
-                         f"batch of {args.chains} chains"),
+            "workload": describe(args, ws),
             "chains": args.chains, "chain_groups": args.groups,
+            "particle_hole_chains": main_res["n_particle_hole"],
             "precision": {"fp64": "fp64, factored G = 1 - A B^T",
                           "fp64wrap": "fp64, G wrapped as N x N",
                           "mixed": "FP32 G, FP64 bases and checkpoints",
@@ -428,7 +475,9 @@ def main():
         "kernel_launches": {k: v["launches"] for k, v in kt.items()},
         "launch": (f"{args.groups} chain groups of {args.chains // args.groups}, one context and "
                    f"HIP stream each, swept concurrently; " if args.groups > 1 else
-                   "one context; ") + "direct launches (kernel events in the timed sweeps)",
+                   "one context; ") + ("each pass replayed as a captured HIP graph"
+                                       if args.no_kernel_timing else
+                                       "direct launches (kernel events in the timed sweeps)"),
     }
     if rooflines:
         out["roofline"] = rooflines[0]

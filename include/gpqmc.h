@@ -110,6 +110,25 @@ typedef struct {
                                  over max |G_fresh|) above which a chain is flagged
                                  (default 1e-5, the mixed path's stated accuracy,
                                  with an FP32 Green's function; 1e-6 in FP64) */
+  int32_t particle_hole;      /* nonzero: the half-filling particle-hole shortcut for
+                                 every chain where it is exact (default 0).  Such a
+                                 chain propagates, updates and re-stabilises spin up
+                                 only; spin down follows per field from
+                                 G_dn = 1 - E G_up^T E (E = diag(sublattice)), so its
+                                 ratio is r_dn = 1 + Delta_dn G_up,ii, its weight
+                                 log|W_dn| = log|W_up| - sum_{l,i} c_l s_{l,i} with the
+                                 same sign (c_l: lambda on the boundary slices, alpha
+                                 in the bulk), and the measurements use the mirrored
+                                 G_dn.  It is exact where the lattice is bipartite
+                                 under the sublattice signs (K_ij != 0 only between
+                                 opposite signs, zero diagonal), n_up = n_dn = N/2 and
+                                 there is no trial potential, so that the Neel trial
+                                 of spin down is the particle-hole image of spin up;
+                                 it needs the factored engine (GPQMC_FP64) with
+                                 delay_rank <= 32.  Other chains run both spins;
+                                 gpqmc_chain_info.particle_hole reports which.
+                                 Derived from the spin-channel HS decoupling of the
+                                 Method section (Eq. 1) and the Neel trial. */
 } gpqmc_options;
 
 typedef struct {
@@ -125,6 +144,8 @@ typedef struct {
   float max_rel_drift;        /* max over checkpoints of the drift divided by
                                  max |G_fresh| (largest over both spins) */
   float last_rel_drift;
+  int32_t particle_hole;      /* 1 if the chain runs the particle-hole shortcut */
+  int32_t reserved;
 } gpqmc_chain_info;
 
 typedef struct gpqmc_ctx gpqmc_ctx;

@@ -145,6 +145,7 @@ __global__ __launch_bounds__(kDenseThreads) void k_chol_inv(const ChainDev* __re
   const int lg = xcd_remap(blockIdx.x, gridDim.x);
   const ChainDev& C = chains[lg >> 1];
   const int sp = lg & 1, n = C.n[sp], tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (sp == 1 && C.ph) return;
   __shared__ double lds[kLdsDense * (kLdsDense + 1)];
   __shared__ double colk[kMaxSites];
   __shared__ int piv[kMaxSites];
@@ -199,6 +200,7 @@ __global__ __launch_bounds__(kDenseThreads) void k_gj_inv(const ChainDev* __rest
   const int lg = xcd_remap(blockIdx.x, gridDim.x);
   const ChainDev& C = chains[lg >> 1];
   const int sp = lg & 1, n = C.n[sp], tid = threadIdx.x;
+  if (sp == 1 && C.ph) return;
   __shared__ double lds[kLdsDense * (kLdsDense + 1)];
   __shared__ double colk[kMaxSites];
   __shared__ int piv[kMaxSites];
@@ -466,6 +468,7 @@ __global__ __launch_bounds__(TG * TG) void k_chol_inv_rt(const ChainDev* __restr
   const int lg = xcd_remap(blockIdx.x, gridDim.x);
   const ChainDev& C = chains[lg >> 1];
   const int sp = lg & 1, n = C.n[sp], tid = threadIdx.x;
+  if (sp == 1 && C.ph) return;
   GPQMC_RT_SHARED
   rt_clear(rk, rp, ck);
   RegTile<NB, TG> T;
@@ -558,6 +561,7 @@ __global__ __launch_bounds__(TG * TG) void k_gj_inv_rt(const ChainDev* __restric
   const int lg = xcd_remap(blockIdx.x, gridDim.x);
   const ChainDev& C = chains[lg >> 1];
   const int sp = lg & 1, n = C.n[sp], tid = threadIdx.x;
+  if (sp == 1 && C.ph) return;
   GPQMC_RT_SHARED
   rt_clear(rk, rp, ck);
   RegTile<NB, TG> T;
@@ -600,9 +604,9 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const ChainDev* __restric
                                                        int parity, int side) {
   const ChainDev& C = chains[xcd_remap(blockIdx.x, gridDim.x)];
   ChainState* st = C.st;
-  const int N = C.N, tid = threadIdx.x;
+  const int N = C.N, tid = threadIdx.x, nsp = C.ph ? 1 : 2;
   __shared__ double red[4];
-  for (int sp = 0; sp < 2; ++sp) {
+  for (int sp = 0; sp < nsp; ++sp) {
     const size_t sz = (size_t)N * C.n[sp];
     GLOBAL double* dst = gp(C.stack[sp] + (size_t)slot * sz);
     GLOBAL Tu* u = side < 0 ? gp((Tu*)C.U[sp][parity])
@@ -627,9 +631,38 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const ChainDev* __restric
       }
     }
   }
+  // particle-hole shortcut: log|W_1| - log|W_0| = -sum_{l,i} c_l s_{l,i}
+  // (det of the spin-1 slice product; the trial projections agree), from
+  // exact integer field sums of the boundary and the bulk slices
+  double ph_shift = 0.0;
+  if (C.ph && mode != 2) {
+    const int ns = C.n_slices;
+    const GLOBAL int8_t* __restrict__ fld = gp(C.field);
+    double sb = 0.0, sk = 0.0;
+    for (int idx = tid; idx < ns * N; idx += kThreads) {
+      const int l = idx / N;
+      const double v = (double)fld[idx];
+      if (l == 0 || l == ns - 1) sb += v; else sk += v;
+    }
+    sb = block_sum(sb, red);
+    sk = block_sum(sk, red);
+    ph_shift = -(C.coupling[0] * sb + C.coupling[1] * sk);
+  }
   if (tid == 0) {
     int wsign = 1;
     for (int sp = 0; sp < 2; ++sp) {
+      if (sp == 1 && C.ph) {
+        if (mode != 2) {
+          st->w_log[1] = st->w_log[0] + ph_shift;
+          st->w_sgn[1] = st->w_sgn[0];
+          wsign *= st->w_sgn[1];
+          if (C.trace_logdet && ck_index >= 0) {
+            C.trace_logdet[((size_t)ck_index * 2 + 1) * 2 + 0] = st->w_log[1];
+            C.trace_logdet[((size_t)ck_index * 2 + 1) * 2 + 1] = (double)st->w_sgn[1];
+          }
+        }
+        continue;
+      }
       const double nl = st->run_log[sp] + st->chk_log[sp];
       const int ns = st->run_sgn[sp] * st->chk_sgn[sp];
       if (mode != 2) {
@@ -678,22 +711,27 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const ChainDev* __restric
     //             = mz^2 / 4 + sum_ij eps_i eps_j [(Gb^up_ij G^up_ij + Gb^dn_ij G^dn_ij) / 4
     //                                            + (Gb^up_ij G^dn_ij + Gb^dn_ij G^up_ij) / 2],
     //   mz = sum_i eps_i (Gb^up_ii - Gb^dn_ii)
+    // (particle-hole shortcut: G^dn_ij = delta_ij - eps_i eps_j G^up_ji and
+    // Gb^dn_ij = eps_i eps_j G^up_ij)
+    const bool ph = C.ph != 0;
     const GLOBAL double* __restrict__ Gu = gp((const double*)C.G64[0]);
-    const GLOBAL double* __restrict__ Gd = gp((const double*)C.G64[1]);
+    const GLOBAL double* __restrict__ Gd = gp((const double*)C.G64[ph ? 0 : 1]);
     const GLOBAL int8_t* __restrict__ eps = gp(C.eps);
     double ek = 0.0, dsum = 0.0, spair = 0.0, mz = 0.0;
     for (int idx = tid; idx < N * N; idx += kThreads) {
       const int i = idx / N, j = idx - i * N;
       const double dij = i == j ? 1.0 : 0.0;
-      const double gu = Gu[idx], gd = Gd[idx];
-      const double gbu = dij - Gu[(size_t)j * N + i], gbd = dij - Gd[(size_t)j * N + i];
+      const double ee = (double)eps[i] * (double)eps[j];
+      const double gu = Gu[idx], gut = Gu[(size_t)j * N + i];
+      const double gd = ph ? dij - ee * gut : Gd[idx];
+      const double gbu = dij - gut, gbd = ph ? ee * gu : dij - Gd[(size_t)j * N + i];
       const double k = C.Khop[idx];
       if (k != 0.0) ek += k * (gbu + gbd);
-      const double ee = (double)eps[i] * (double)eps[j];
       spair += ee * (0.25 * (gbu * gu + gbd * gd) + 0.5 * (gbu * gd + gbd * gu));
     }
     for (int i = tid; i < N; i += kThreads) {
-      const double nu = 1.0 - Gu[(size_t)i * N + i], nd = 1.0 - Gd[(size_t)i * N + i];
+      const double nu = 1.0 - Gu[(size_t)i * N + i];
+      const double nd = ph ? Gu[(size_t)i * N + i] : 1.0 - Gd[(size_t)i * N + i];
       dsum += nu * nd;
       mz += (double)eps[i] * (nu - nd);
     }
@@ -718,7 +756,15 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const ChainDev* __restric
   if (mode != 2 && C.trace_green && ck_index >= 0) {
     for (int sp = 0; sp < 2; ++sp) {
       double* dst = C.trace_green + ((size_t)ck_index * 2 + sp) * N * N;
-      for (int idx = tid; idx < N * N; idx += kThreads) dst[idx] = C.G64[sp][idx];
+      if (sp == 1 && C.ph) {
+        for (int idx = tid; idx < N * N; idx += kThreads) {
+          const int i = idx / N, j = idx - i * N;
+          dst[idx] = (i == j ? 1.0 : 0.0) -
+                     (double)C.eps[i] * (double)C.eps[j] * C.G64[0][(size_t)j * N + i];
+        }
+      } else {
+        for (int idx = tid; idx < N * N; idx += kThreads) dst[idx] = C.G64[sp][idx];
+      }
     }
     if (tid == 0) C.trace_drift[ck_index] = st->last_drift;
   }
@@ -731,8 +777,8 @@ template <typename Tu>
 __global__ __launch_bounds__(kThreads) void k_put_trial(const ChainDev* __restrict__ chains, int slot,
                                                         int set_active, int side) {
   const ChainDev& C = chains[xcd_remap(blockIdx.x, gridDim.x)];
-  const int tid = threadIdx.x;
-  for (int sp = 0; sp < 2; ++sp) {
+  const int tid = threadIdx.x, nsp = C.ph ? 1 : 2;
+  for (int sp = 0; sp < nsp; ++sp) {
     const size_t sz = (size_t)C.N * C.n[sp];
     double* dst = C.stack[sp] + (size_t)slot * sz;
     Tu* u = side < 0 ? (Tu*)C.U[sp][0] : (Tu*)C.F[side][sp][0];
@@ -779,7 +825,7 @@ __global__ __launch_bounds__(kThreads) void k_dscale_f(const ChainDev* __restric
   const ChainDev& C = chains[xcd_remap(blockIdx.x, gridDim.x)];
   const int b = (l == 0 || l == M + 1) ? 0 : 1;
   const GLOBAL int8_t* frow = gp(C.field + (size_t)l * C.N);
-  for (int sp = 0; sp < 2; ++sp) {
+  for (int sp = 0; sp < (C.ph ? 1 : 2); ++sp) {
     const int n = C.n[sp];
     for (int side = 0; side < 2; ++side) {
       if (!(which & (1 << side))) continue;

@@ -129,6 +129,7 @@ struct ChainHost {
   double U, dtau, g, m_neel, alpha, lam;
   uint64_t seed, chain_id;
   bool trace;
+  bool ph = false;            // particle-hole shortcut: spin 1 derived from spin 0
   bool field_set = false;
   std::vector<int8_t> field;
   std::vector<int8_t> eps;    // sublattice signs (staggered structure factor)
@@ -614,9 +615,11 @@ Launcher make_launcher(gpqmc_ctx* ctx) {
   return L;
 }
 
-void build_tiles(std::vector<TileRef>& out, const std::vector<std::pair<int, int>>& mn, int tile) {
+void build_tiles(std::vector<TileRef>& out, const std::vector<std::pair<int, int>>& mn,
+                 const std::vector<char>& skip, int tile) {
   out.clear();
   for (size_t e = 0; e < mn.size(); ++e) {
+    if (skip[e]) continue;
     const int tm = (mn[e].first + tile - 1) / tile, tn = (mn[e].second + tile - 1) / tile;
     for (int a = 0; a < tm; ++a)
       for (int b = 0; b < tn; ++b) out.push_back(TileRef{(int)e, a, b, 0});
@@ -673,6 +676,7 @@ gpqmc_status gpqmc_create(int32_t n_chains, const gpqmc_chain_desc* chains,
     c->use_graph = opts->use_graph != 0;
     if (opts->drift_tol > 0) c->drift_tol = (float)opts->drift_tol;
   }
+  const bool ph_req = opts && opts->particle_hole != 0 && c->fact && c->kseg <= kBlock;
   if (!c->stream) c->use_graph = false;   // the null stream cannot be captured
   // checkpoints C = {-1, l_half, M+1} U {j n_s : 1 <= j n_s <= M}
   std::vector<int> ck = {-1, c->l_half, c->M + 1};
@@ -772,6 +776,18 @@ gpqmc_status gpqmc_create(int32_t n_chains, const gpqmc_chain_desc* chains,
       }
       h.trial[sp] = jt->second;
     }
+    // particle-hole shortcut: exact when the spin-down problem is the image
+    // of the spin-up one under c_i -> eps_i c_i^dag (bipartite hopping, half
+    // filling, no trial potential: the Neel trials map onto each other)
+    if (ph_req && N % 2 == 0 && d.n_up == N / 2 && d.n_dn == N / 2 && !d.trial_potential) {
+      bool bip = true;
+      for (int a = 0; a < N && bip; ++a) {
+        if (d.sublattice[a] != 1 && d.sublattice[a] != -1) bip = false;
+        for (int b = 0; b < N && bip; ++b)
+          if (d.hopping[(size_t)a * N + b] != 0.0 && d.sublattice[a] == d.sublattice[b]) bip = false;
+      }
+      h.ph = bip;
+    }
     h.field.assign((size_t)c->n_slices * N, 1);
     h.eps.assign(d.sublattice, d.sublattice + N);
     c->ch.push_back(std::move(h));
@@ -847,6 +863,7 @@ gpqmc_status gpqmc_create(int32_t n_chains, const gpqmc_chain_desc* chains,
   c->off_ctl = take(sizeof(Ctl));
   for (int k = 0; k < E_COUNT; ++k) c->off_ent[k] = take(sizeof(GemmEntry) * 4 * n_chains);
   std::vector<std::pair<int, int>> sz[T_COUNT];
+  std::vector<char> skip[T_COUNT];   // entries without tiles (spin 1 of particle-hole chains)
   for (auto& h : c->ch) {
     c->n_max = std::max(c->n_max, h.N);
     c->n_min = std::min(c->n_min, h.N);
@@ -865,10 +882,13 @@ gpqmc_status gpqmc_create(int32_t n_chains, const gpqmc_chain_desc* chains,
       sz[T_Nn4].push_back({h.N, h.n[sp]});   // factor A of this spin
       sz[T_Nn4].push_back({h.N, h.n[sp]});   // factor B
       sz[T_Nk].push_back({h.N, c->kseg});
+      const char sk = (sp == 1 && h.ph) ? 1 : 0;
+      for (int t = 0; t < T_COUNT; ++t) skip[t].push_back(sk);
+      skip[T_Nn4].push_back(sk);
     }
   }
   for (int t = 0; t < T_COUNT; ++t) {
-    build_tiles(c->tiles[t], sz[t], t == T_NN_L ? 128 : kTile);
+    build_tiles(c->tiles[t], sz[t], skip[t], t == T_NN_L ? 128 : kTile);
     c->off_tiles[t] = take(sizeof(TileRef) * c->tiles[t].size());
   }
   c->bytes = align256(off);
@@ -930,6 +950,10 @@ gpqmc_status gpqmc_bind_workspace(gpqmc_ctx* ctx, void* device_ptr, size_t bytes
       }
     }
     d.U_hub = h.U;
+    d.ph = h.ph ? 1 : 0;
+    d.coupling[0] = h.lam;
+    d.coupling[1] = h.alpha;
+    d.n_slices = ctx->n_slices;
     d.key0 = (uint32_t)(h.seed & 0xffffffffu);
     d.key1 = (uint32_t)(h.seed >> 32) ^ (uint32_t)TAG_ACCEPT;
     d.chain_id = (uint32_t)h.chain_id;
@@ -1314,7 +1338,21 @@ gpqmc_status gpqmc_get_green(gpqmc_ctx* ctx, int32_t chain, int32_t spin, double
   if (!ctx->initialized) return GPQMC_ESTATE;
   const ChainHost& h = ctx->ch[chain];
   HIPCHK(hipStreamSynchronize(ctx->stream), "sync");
-  HIPCHK(hipMemcpy(G, ctx->ws + h.G64[spin], (size_t)h.N * h.N * 8, hipMemcpyDeviceToHost), "G");
+  const bool mirror = spin == 1 && h.ph;
+  HIPCHK(hipMemcpy(G, ctx->ws + h.G64[mirror ? 0 : spin], (size_t)h.N * h.N * 8,
+                   hipMemcpyDeviceToHost),
+         "G");
+  if (mirror) {
+    // G_dn = 1 - E G_up^T E, E = diag(sublattice)
+    const int N = h.N;
+    for (int i = 0; i < N; ++i)
+      for (int j = i; j < N; ++j) {
+        const double e = (double)h.eps[i] * (double)h.eps[j];
+        const double gij = G[(size_t)i * N + j], gji = G[(size_t)j * N + i];
+        G[(size_t)i * N + j] = (i == j ? 1.0 : 0.0) - e * gji;
+        G[(size_t)j * N + i] = (i == j ? 1.0 : 0.0) - e * gij;
+      }
+  }
   return GPQMC_OK;
 }
 
@@ -1335,6 +1373,8 @@ gpqmc_status gpqmc_get_chain_info(gpqmc_ctx* ctx, int32_t chain, gpqmc_chain_inf
   info->proposed = st.proposed;
   info->max_rel_drift = st.max_rel_drift;
   info->last_rel_drift = st.last_rel_drift;
+  info->particle_hole = ctx->ch[chain].ph ? 1 : 0;
+  info->reserved = 0;
   return GPQMC_OK;
 }
 
@@ -1414,7 +1454,7 @@ gpqmc_status gpqmc_debug_gemm(int32_t precision, int32_t M, int32_t N, int32_t K
   e.ldb = ldb;
   e.ldc = ldc;
   std::vector<TileRef> tl;
-  build_tiles(tl, {{M, N}}, large ? 128 : kTile);
+  build_tiles(tl, {{M, N}}, {0}, large ? 128 : kTile);
   // test hook: a small descriptor buffer in device memory for this one call
   void* dbuf = nullptr;
   const size_t bytes = align256(sizeof e) + sizeof(TileRef) * tl.size();

@@ -95,7 +95,12 @@ struct ChainDev {
   double U_hub;           // Hubbard U (energy measurement)
   uint32_t key0, key1;    // Philox key (seed low word, seed high word ^ TAG_ACCEPT)
   uint32_t chain_id;
-  int pad1;
+  // 1: half-filling particle-hole shortcut (factored engine).  Only spin 0 is
+  // propagated, updated and re-stabilised; spin 1 follows from it per field:
+  // G_1 = 1 - E G_0^T E with E = diag(eps), and log|W_1| = log|W_0| -
+  // sum_{l,i} c_l s_{l,i}, sgn W_1 = sgn W_0.  Every kernel that works per
+  // (chain, spin) skips spin 1 of such a chain.
+  int ph;
   // Green's-function precision (float or double)
   void* G[2];           // equal-time Green's function in the current frame
   void* Gtmp[2];        // wrap intermediate
@@ -138,6 +143,9 @@ struct ChainDev {
   void* F[2][2][2];     // [side][spin][parity]
   double* Mf[2];        // the moving factor's rows at the segment's accepted sites (kSegMax x n)
   double* Wf[2];        // Woodbury core times the dual factor's rows at those sites (kSegMax x n)
+  double coupling[2];   // HS coupling c_b: 0 boundary slices (lambda), 1 bulk slices (alpha)
+  int n_slices;         // M + 2 (rows of the field)
+  int pad3;
 };
 
 // Control block (device memory), read by every kernel of a pass.

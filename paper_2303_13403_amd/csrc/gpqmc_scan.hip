@@ -1445,6 +1445,7 @@ __global__ __launch_bounds__(64) void k_scan_f(const ChainDev* __restrict__ chai
   constexpr int KC = 16;          // k-chunk of the block formation
   __shared__ double u_s[KB];
   __shared__ int8_t fs[KB];
+  __shared__ int8_t es[KB];       // sublattice signs of the segment's sites
   __shared__ int Fl[KB];
   __shared__ double dF[2][KB];    // Delta of every accepted flip, per spin
   // history rows X^{(t)}[j_t, S] (later the LU factors), and history columns
@@ -1463,9 +1464,12 @@ __global__ __launch_bounds__(64) void k_scan_f(const ChainDev* __restrict__ chai
     philox4x32_10(c, C.key0, C.key1);
     u_s[lane] = uniform53(c[0], c[1]);
     fs[lane] = frow[s0 + lane];
+    es[lane] = C.eps[s0 + lane];
   }
+  const bool ph = C.ph != 0;
 
-  // ---- G_s[S,S] = 1 - A[S,:] B[S,:]^T, row a of spin s in g ----
+  // ---- G_s[S,S] = 1 - A[S,:] B[S,:]^T, row a of spin s in g (with the
+  // particle-hole shortcut only spin 0 is formed from its factors) ----
   double g[KB];
 #pragma unroll
   for (int c = 0; c < KB; ++c) g[c] = 0.0;
@@ -1474,7 +1478,7 @@ __global__ __launch_bounds__(64) void k_scan_f(const ChainDev* __restrict__ chai
     const GLOBAL double* __restrict__ Ab = gp((const double*)C.F[0][s][parity]);
     const GLOBAL double* __restrict__ Bb = gp((const double*)C.F[1][s][parity]);
     double* Bs = &hcol[0][0][0];   // [spin][k][c]
-    const bool row_ok = a < nseg;
+    const bool row_ok = a < nseg && !(ph && s == 1);
     const size_t ro = (size_t)(s0 + a) * nn;
     for (int k0 = 0; k0 < nmax; k0 += KC) {
       double ar[KC];
@@ -1501,6 +1505,23 @@ __global__ __launch_bounds__(64) void k_scan_f(const ChainDev* __restrict__ chai
 #pragma unroll
     for (int c = 0; c < KB; ++c)
       if (c == a) g[c] += 1.0;
+  }
+  if (ph) {
+    // G_1[a][c] = delta_ac - eps_a eps_c G_0[c][a]: spin-0 lane c stores its
+    // row (stride KB + 1: conflict-free both ways), spin-1 lane a reads column a
+    double* T = &hcol[0][0][0];
+    if (s == 0) {
+#pragma unroll
+      for (int q = 0; q < KB; ++q) T[a * (KB + 1) + q] = g[q];
+    }
+    wave_sync();
+    if (s == 1 && a < nseg) {
+      const double ea = (double)es[a];
+#pragma unroll
+      for (int c = 0; c < KB; ++c)
+        if (c < nseg) g[c] = (c == a ? 1.0 : 0.0) - ea * (double)es[c] * T[c * (KB + 1) + a];
+    }
+    wave_sync();
   }
 
   // ---- sequential proposals ----
@@ -1618,7 +1639,7 @@ __global__ __launch_bounds__(128) void k_wf(const ChainDev* __restrict__ chains,
   const int cs = xcd_remap(blockIdx.x, gridDim.x), sp = cs & 1;
   const ChainDev& C = chains[cs >> 1];
   const int f = C.st->fcount;
-  if (f == 0) return;
+  if (f == 0 || (sp == 1 && C.ph)) return;
   const int N = C.N, nn = C.n[sp], tid = threadIdx.x;
   __shared__ __align__(16) double LU[KB][KB];   // U on and above the diagonal, L below
   __shared__ __align__(16) double LT[KB][KB];   // its transpose
@@ -1726,7 +1747,7 @@ __global__ __launch_bounds__(kUpdThreads) void k_segupd_f(const ChainDev* __rest
   const ChainDev& C = chains[cs >> 1];
   const int N = C.N, nn = C.n[sp], tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int f = C.st->fcount;
-  if (f == 0) return;
+  if (f == 0 || (sp == 1 && C.ph)) return;
   __shared__ __align__(16) double Ms[KB * LDM];
   __shared__ __align__(16) double Ws[KB * LDW];
   __shared__ __align__(16) double Ps[kUpdWaves * 16 * LDP];   // P of every wave

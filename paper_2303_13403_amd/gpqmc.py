@@ -36,7 +36,7 @@ class ChainDesc(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("meas_capacity", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("drift_tol", ctypes.c_double)]
+                ("drift_tol", ctypes.c_double), ("particle_hole", ctypes.c_int32)]
 
 
 class ChainInfo(ctypes.Structure):
@@ -44,7 +44,8 @@ class ChainInfo(ctypes.Structure):
                 ("sign_mismatch", ctypes.c_int32), ("sweep", ctypes.c_int32),
                 ("max_drift", ctypes.c_float), ("last_drift", ctypes.c_float),
                 ("accepted", ctypes.c_int64), ("proposed", ctypes.c_int64),
-                ("max_rel_drift", ctypes.c_float), ("last_rel_drift", ctypes.c_float)]
+                ("max_rel_drift", ctypes.c_float), ("last_rel_drift", ctypes.c_float),
+                ("particle_hole", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class GpqmcError(RuntimeError):
@@ -142,7 +143,7 @@ class Context:
 
     def __init__(self, chains: Sequence[dict], device: str = "cuda:0", meas_capacity: int = 4096,
                  use_graph: bool = True, drift_tol: float = 0.0, stream=None,
-                 workspace_fill: Optional[float] = None):
+                 workspace_fill: Optional[float] = None, particle_hole: bool = False):
         import torch
 
         self.lib = load()
@@ -173,7 +174,7 @@ class Context:
         self.sizes = [(descs[i].n_sites, descs[i].n_up, descs[i].n_dn) for i in range(len(chains))]
         self.l_half = descs[0].l_half
         self.n_slices = 2 * self.l_half + 2
-        opts = Options(meas_capacity, 1 if use_graph else 0, drift_tol)
+        opts = Options(meas_capacity, 1 if use_graph else 0, drift_tol, 1 if particle_hole else 0)
         ctx = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             st = self.lib.gpqmc_create(len(chains), descs, ctypes.byref(opts),

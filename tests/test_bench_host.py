@@ -54,6 +54,7 @@ def test_traffic_summary_is_used_only_for_the_same_kernel_and_launch(tmp_path, m
     assert bench.read_traffic(512, "mixed") == 12345.0
     assert bench.read_traffic(2048, "mixed") is None
     assert bench.read_traffic(512, "fp64") is None
+    assert bench.read_traffic(512, "mixed", "12x12") is None
     f.write_text(f.read_text().replace(bench.kernel_sha(), "0" * 16))
     assert bench.read_traffic(512, "mixed") is None
 
@@ -101,7 +102,7 @@ def test_cpu_baseline_runs_one_chain_per_core():
     chain each, the aggregate rate, the CPU model and the core count."""
     import argparse
 
-    a = argparse.Namespace(workload="4x4", ns=5, k=16, cpu_cores=2)
+    a = argparse.Namespace(workload="4x4", ns=5, k=16, cpu_cores=2, chains=2)
     out = bench.cpu_baseline(a)
     assert out["kind"] == "oracle" and out["cores"] == min(2, len(os.sched_getaffinity(0)))
     assert out["value"] > 0 and out["per_core"] > 0 and out["cpu_model"]

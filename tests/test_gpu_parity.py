@@ -117,9 +117,11 @@ FIXED = [
 LOGDET_TOL = {"fp64": 1e-10, "fp64wrap": 1e-10, "mixed": 1e-7, "mixed32b": 1e-5}
 
 
-def check_fixed_field(w, prec):
-    ctx = make_context([w], prec, trace=True).init_trial()
+def check_fixed_field(w, prec, **ctx_kw):
+    ctx = make_context([w], prec, trace=True, **ctx_kw).init_trial()
     ctx.set_debug(True)
+    if ctx_kw.get("particle_hole"):
+        assert ctx.chain_info(0)["particle_hole"] == 1
     ch = oracle_chain(w, 0)
     N = w.n_sites
     for sweep in range(2):                     # one upward and one downward pass
@@ -639,3 +641,74 @@ def test_fixed_field_12x12_mixed_at_its_configured_interval():
     assert res["fp64"][0] < 1e-10 and res["fp64"][1] < 1e-10
     assert res["mixed"][1] < 1e-5          # the fresh FP64 G at the checkpoints
     assert res["mixed"][0] < 1e-1          # the FP32 ratios: the stated error (see the printout)
+
+
+# --------------------------------------------------------------------------- #
+# particle-hole shortcut at half filling: spin up only, spin down derived; the
+# oracle runs both spins independently
+# --------------------------------------------------------------------------- #
+PH_FIXED = [
+    dict(L=4, l_half=6, n_s=3, k=8),
+    dict(L=4, l_half=0, n_s=1, k=8),                  # boundary slices only
+    dict(L=6, l_half=5, n_s=4, k=7),                  # ragged segments
+    dict(L=12, l_half=50, n_s=10, k=32),              # the 12x12 workload
+    dict(L=24, l_half=3, n_s=2, k=32),                # N_sigma = 288: general segment update
+    dict(L=4, l_half=6, n_s=3, k=8, g=0.0),          # no boundary coupling
+]
+
+
+@pytest.mark.parametrize("kw", PH_FIXED)
+def test_particle_hole_fixed_field_matches_two_spin_oracle(kw):
+    """Every ratio (both spins), every checkpoint G (spin down mirrored from
+    spin up) and every log|W_sigma| (spin down from the field sum) of an upward
+    and a downward pass against the oracle's independent two-spin run."""
+    g = kw.pop("g", None)
+    w = small("fp64", **kw)
+    if g is not None:
+        w = w.replace(g=g)
+    check_fixed_field(w, "fp64", particle_hole=True)
+
+
+@pytest.mark.parametrize("l1,l2", [(3, 3), (8, 8)])
+def test_particle_hole_fixed_field_honeycomb(l1, l2):
+    check_fixed_field(honey("fp64", l1, l2), "fp64", particle_hole=True)
+
+
+@pytest.mark.parametrize("kw,n_sweeps", [
+    (dict(L=4, l_half=6, n_s=3, k=8), 6),
+    (dict(L=6, l_half=5, n_s=4, k=7), 4),
+    (dict(L=8, l_half=10, n_s=5, k=32), 3),
+])
+def test_particle_hole_trajectory_follows_two_spin_oracle(kw, n_sweeps):
+    w = small("fp64", **kw)
+    ctx = make_context([w], "fp64", particle_hole=True).init_trial()
+    assert ctx.chain_info(0)["particle_hole"] == 1
+    ch = oracle_chain(w, 0)
+    indep = [oracle_chain(w, 0)]
+    follow_and_compare(ctx, [ch], "fp64", n_sweeps, indep)
+    assert np.array_equal(indep[0].field, ctx.get_field(0))
+    # the last fresh G (spin down mirrored on the host) at the pass's end
+    p_end = ch.m.M + 1 if n_sweeps % 2 else -1
+    f = ctx.get_field(0)
+    for sp, s in ((0, 1), (1, -1)):
+        assert rel_err(ctx.get_green(0, sp), pqmc.green_stable(ch.m, f, p_end, s)) < 1e-10
+    ctx.close()
+
+
+def test_particle_hole_only_where_exact():
+    """A batch of half-filled square and honeycomb chains, a doped chain and
+    a half-filled chain with a trial potential: the shortcut applies to the
+    first two only, and every chain follows the oracle."""
+    ws = [small("fp64", L=4, l_half=5, n_s=3, k=8),
+          honey("fp64", 3, 3, l_half=5, n_s=3, k=8),
+          small("fp64", L=4, l_half=5, n_s=3, k=8, U=3.0, n=5),
+          small("fp64", L=4, l_half=5, n_s=3, k=8, ramp=0.05)]
+    ctx = make_context(ws, "fp64", particle_hole=True).init_trial()
+    assert [ctx.chain_info(c)["particle_hole"] for c in range(4)] == [1, 1, 0, 0]
+    chains = [oracle_chain(w, c) for c, w in enumerate(ws)]
+    follow_and_compare(ctx, chains, "fp64", 3)
+    ctx.close()
+    # without the option no chain uses it
+    ctx = make_context(ws[:1], "fp64").init_trial()
+    assert ctx.chain_info(0)["particle_hole"] == 0
+    ctx.close()

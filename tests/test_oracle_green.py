@@ -137,6 +137,36 @@ def test_particle_hole_symmetry_half_filling():
     assert all(x[0] == 1 for x in ch.measurements)
 
 
+def test_particle_hole_weight_relation_half_filling():
+    """The weight relation the particle-hole shortcut uses: with the
+    spin-channel decoupling, D_dn = D_up^{-1} and E e^{+dtau K} E = e^{-dtau K}
+    (E = diag(eps), bipartite K), so E B_dn^{-T} E = B_up for every slice, and
+    Jacobi's complementary-minor identity with the Neel trials (the occupied
+    spin-down orbitals span the complement of E times the spin-up ones) gives
+    W_dn = det(B_dn(M+1) ... B_dn(0)) W_up = exp(-sum_{l,i} c_l s_{l,i}) W_up.
+    Checked on the plain products (M = 6) of random fields, including fields
+    with unequal boundary and bulk sums, and at g = 0 (boundary coupling 0)."""
+    for g in (0.6, 0.0):
+        m = _model(L=4, l_half=3, g=g)
+        for seed in range(4):
+            f = _field(m, seed)
+            if seed == 3:
+                f[0] = 1          # boundary and bulk sums of different size
+                f[1:m.M + 1] = -f[1:m.M + 1]
+            wu, wd = pqmc.weight(m, f, 1), pqmc.weight(m, f, -1)
+            shift = -sum(m.coupling(l) * float(f[l].astype(np.float64).sum())
+                         for l in range(m.n_slices))
+            assert np.sign(wu) == np.sign(wd)
+            assert abs(math.log(abs(wd)) - math.log(abs(wu)) - shift) < 1e-10 * max(1.0, abs(shift))
+    # the same relation fails away from half filling (the doped check must not
+    # pass by accident)
+    m = _model(L=4, n=5, l_half=3)
+    f = _field(m, 1)
+    shift = -sum(m.coupling(l) * float(f[l].astype(np.float64).sum()) for l in range(m.n_slices))
+    d = math.log(abs(pqmc.weight(m, f, -1))) - math.log(abs(pqmc.weight(m, f, 1)))
+    assert abs(d - shift) > 1e-3
+
+
 def test_doped_chain_tracks_sign_consistently():
     """Away from half filling the tracked sign must equal the sign recomputed
     from the stabilised determinants at every checkpoint."""
