@@ -13,8 +13,13 @@ problem by Gutzwiller projection", arXiv:2303.13403):
 * ``pqmc``    -- the projector determinant QMC chain with the Gutzwiller trial
   state (Method section, Eq. 1 read in the spin channel; the Neel trial after
   Eq. 2), rank-1 Sherman-Morrison updates, QR re-stabilisation, measurement.
+* ``tv``      -- the same chain for the spinless t-V model ("Repulsive
+  spinless honeycomb model", Eq. 3): bond fields decoupled in the density
+  channel, CDW trial with the bond Gutzwiller factor, rank-2 Woodbury updates,
+  a signful weight.
 * ``ed``      -- Fock-space exact diagonalisation of tiny clusters, and exact
-  enumeration of every auxiliary-field configuration; used as pins.
+  enumeration of every auxiliary-field configuration (both models); used as
+  pins.
 * ``stats``   -- binning / jackknife for sign-weighted averages.
 
 Every function pinned by ``tests/test_oracle_*.py`` against closed forms,

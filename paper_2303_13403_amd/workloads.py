@@ -23,9 +23,13 @@ import numpy as np
 __all__ = [
     "square_lattice",
     "honeycomb_lattice",
+    "honeycomb_bonds",
+    "ring_lattice",
     "shell_ramp",
     "Workload",
     "WORKLOADS",
+    "TVWorkload",
+    "TV_WORKLOADS",
     "batch_uneven",
 ]
 
@@ -79,6 +83,40 @@ def honeycomb_lattice(l1: int, l2: int, t: float = 1.0):
                 K[b, a] -= t
     eps = np.where(np.arange(n) % 2 == 0, 1, -1).astype(np.int8)
     return K, eps, cells
+
+
+def honeycomb_bonds(l1: int, l2: int) -> np.ndarray:
+    """Nearest-neighbour bonds (A, B) of the l1 x l2 periodic honeycomb lattice
+    of ``honeycomb_lattice``, grouped by direction: first every A site's bond
+    to the B site of its own cell, then to the B site of cell (x - 1, y), then
+    of cell (x, y - 1).  Each group is a perfect matching (no two bonds of a
+    group share a site), so any run of consecutive bonds inside a group is
+    site-disjoint.  Needs l1, l2 >= 2 (no doubled bonds)."""
+    if l1 < 2 or l2 < 2:
+        raise ValueError("honeycomb bonds need l1, l2 >= 2")
+    out = []
+    for dx, dy in ((0, 0), (-1, 0), (0, -1)):
+        for y in range(l2):
+            for x in range(l1):
+                a = 2 * (x + l1 * y)
+                b = 2 * ((x + dx) % l1 + l1 * ((y + dy) % l2)) + 1
+                out.append((a, b))
+    return np.array(out, dtype=np.int32)
+
+
+def ring_lattice(n: int, t: float = 1.0):
+    """Periodic ring of an even number n >= 4 of sites: ``(K, eps, bonds)``
+    with bonds (even site, odd site) grouped as (0,1), (2,3), ... then
+    (2,1), (4,3), ..., (0, n-1): two perfect matchings."""
+    if n < 4 or n % 2:
+        raise ValueError("the ring needs an even n >= 4")
+    K = np.zeros((n, n))
+    bonds = [(i, i + 1) for i in range(0, n, 2)] + [((i + 1) % n, i) for i in range(1, n, 2)]
+    for a, b in bonds:
+        K[a, b] -= t
+        K[b, a] -= t
+    eps = np.where(np.arange(n) % 2 == 0, 1, -1).astype(np.int8)
+    return K, eps, np.array(bonds, dtype=np.int32)
 
 
 def shell_ramp(lx: int, ly: int, delta: float = 0.1, tilt: float = 0.37):
@@ -160,6 +198,66 @@ WORKLOADS = {
     "honeycomb12x12": Workload("honeycomb 12x12 cells (288 sites) U=4 half filling Theta=5",
                                12, 12, 4.0, 144, 144, 0.1, 50, 0.21, 0.6, 5, 32, "mixed", 100,
                                lattice_kind="honeycomb"),
+}
+
+
+@dataclasses.dataclass
+class TVWorkload:
+    """Spinless t-V model (Eq. 3) at half filling: H = -t sum c^dag c +
+    V sum_<ij> (n_i - 1/2)(n_j - 1/2) on the honeycomb lattice (or a ring for
+    the smallest checks), trial e^{-g sum_<ij> n_i n_j} |psi_C> with |psi_C>
+    the ground state of K + Delta_C sum_i eps_i n_i (CDW mean field)."""
+    name: str
+    l1: int                # honeycomb cells per direction (ring: number of sites)
+    l2: int
+    V: float
+    dtau: float
+    l_half: int
+    delta_c: float         # CDW order parameter of the trial
+    g: float               # bond Gutzwiller parameter
+    stab_interval: int
+    delay_rank: int        # sites per scan segment: delay_rank / 2 bonds of one direction
+    sweeps: int
+    t: float = 1.0
+    seed: int = 13403
+    lattice_kind: str = "honeycomb"   # or "ring"
+
+    @property
+    def n_sites(self) -> int:
+        return 2 * self.l1 * self.l2 if self.lattice_kind == "honeycomb" else self.l1
+
+    @property
+    def n_particles(self) -> int:
+        return self.n_sites // 2
+
+    @property
+    def theta(self) -> float:
+        return self.l_half * self.dtau
+
+    def lattice(self):
+        """(K, eps, bonds)."""
+        if self.lattice_kind == "ring":
+            return ring_lattice(self.l1, self.t)
+        if self.lattice_kind != "honeycomb":
+            raise ValueError(f"unknown lattice kind {self.lattice_kind!r}")
+        K, eps, _ = honeycomb_lattice(self.l1, self.l2, self.t)
+        return K, eps, honeycomb_bonds(self.l1, self.l2)
+
+    def replace(self, **kw) -> "TVWorkload":
+        return dataclasses.replace(self, **kw)
+
+
+# The spinless t-V workloads: the paper's L = 15 honeycomb lattice (450 sites)
+# in the CDW phase (V = 1.6) and near the transition (V = 1.35), Theta = 5;
+# a 6x6-cell lattice for parity tests.  The paper does not print its trial
+# parameters for this model: Delta_C = 0.3 and g = 0.3 are a fixed choice.
+TV_WORKLOADS = {
+    "tv15_V1.6": TVWorkload("t-V honeycomb 15x15 (450 sites) V=1.6 half filling Theta=5",
+                            15, 15, 1.6, 0.1, 50, 0.3, 0.3, 10, 32, 100),
+    "tv15_V1.35": TVWorkload("t-V honeycomb 15x15 (450 sites) V=1.35 half filling Theta=5",
+                             15, 15, 1.35, 0.1, 50, 0.3, 0.3, 10, 32, 100),
+    "tv6": TVWorkload("t-V honeycomb 6x6 (72 sites) V=1.6 half filling Theta=2",
+                      6, 6, 1.6, 0.1, 20, 0.3, 0.3, 5, 32, 100),
 }
 
 
