@@ -83,15 +83,32 @@ def finite_or_none(x):
 
 
 DEFAULT_CHAINS = {"16x16": 2048, "12x12": 2048, "honeycomb12x12": 2048, "24x24": 512,
-                  "uneven": 256}
+                  "uneven": 256, "tv15_V1.6": 512, "tv15_V1.35": 512, "tv6": 2048}
+
+
+def is_tv(w) -> bool:
+    """A spinless t-V workload (bond fields, one species)."""
+    return hasattr(w, "V")
+
+
+def n_props(w) -> int:
+    """HS fields per slice: sites (Hubbard) or bonds (t-V)."""
+    return len(w.lattice()[2]) if is_tv(w) else w.n_sites
+
+
+def n_occ(w) -> int:
+    """Particles of one propagated species."""
+    return w.n_particles if is_tv(w) else w.n_up
 
 
 def batch(args, ns=None):
     """The workload of every chain of the batch (uneven: lattices drawn from
     {6, 8, 10, 12}^2 and U from [2, 6], half filling, Theta = 5)."""
-    from paper_2303_13403_amd.workloads import WORKLOADS, batch_uneven
+    from paper_2303_13403_amd.workloads import TV_WORKLOADS, WORKLOADS, batch_uneven
 
     ns = args.ns if ns is None else ns
+    if args.workload in TV_WORKLOADS:
+        return [TV_WORKLOADS[args.workload].replace(stab_interval=ns, delay_rank=args.k)] * args.chains
     if args.workload == "uneven":
         return batch_uneven(args.chains, precision="fp64", stab_interval=ns, delay_rank=args.k)
     return [WORKLOADS[args.workload].replace(stab_interval=ns, delay_rank=args.k)] * args.chains
@@ -109,6 +126,10 @@ def describe(args, ws):
         return (f"batch of {len(ws)} independent half-filled chains, lattices L x L with L drawn "
                 f"from {sizes}, U uniform in [2, 6], dtau={w.dtau}, Theta={w.dtau * w.l_half:g} "
                 f"({M + 2} slices), Neel M_N={w.m_neel} + Gutzwiller g={w.g}")
+    if is_tv(w):
+        return (f"{w.name}, spinless, {w.n_particles} particles, {n_props(w)} bond fields per "
+                f"slice, dtau={w.dtau}, {M + 2} slices, CDW trial Delta_C={w.delta_c} + bond "
+                f"Gutzwiller g={w.g}, batch of {len(ws)} chains")
     return (f"{w.name}, {w.n_up}+{w.n_dn} electrons, dtau={w.dtau}, {M + 2} slices, Neel "
             f"M_N={w.m_neel} + Gutzwiller g={w.g}, batch of {len(ws)} chains")
 
@@ -196,7 +217,7 @@ def run_gpu(args, precision_name, steps, warmup, ns=None):
     infos = all_infos()
     acc = sum(i["accepted"] for i in infos) - acc0
     prop = sum(i["proposed"] for i in infos) - prop0
-    n_updates = (2 * w.l_half + 2) * sum(x.n_sites for x in ws) * steps
+    n_updates = (2 * w.l_half + 2) * sum(n_props(x) for x in ws) * steps
     assert prop == n_updates, (prop, n_updates)
     # estimates from the timed sweeps' records, pooled with a delete-one-chain
     # jackknife over the chains without a NaN, singular or sign-mismatch flag
@@ -217,7 +238,7 @@ def run_gpu(args, precision_name, steps, warmup, ns=None):
                rel_drift=drift_stats(infos), flags=sorted({i["flags"] for i in infos}),
                n_flagged=n_flagged, sign_mismatch=sum(i["sign_mismatch"] for i in infos),
                kernels=kt, estimates=est, stab_interval=w.stab_interval, delay_rank=w.delay_rank,
-               spins=[1 if i["particle_hole"] else 2 for i in infos],
+               spins=[1 if (i["particle_hole"] or is_tv(w)) else 2 for i in infos],
                n_particle_hole=sum(i["particle_hole"] for i in infos))
     log(f"[{precision_name}] {steps} sweeps: {ms:.1f} ms (wall {wall * 1e3:.1f} ms), "
         f"{n_updates / (ms / 1e3):.4g} updates/s, acceptance {res['accept']:.3f}, "
@@ -239,14 +260,17 @@ def _oracle_worker(job):
     w, chain_id = job
     from threadpoolctl import threadpool_limits
 
-    from oracle import pqmc
+    from oracle import pqmc, tv
 
     with threadpool_limits(limits=1):
-        ch = pqmc.Chain(pqmc.Model.from_workload(w), seed=w.seed, chain_id=chain_id)
+        if is_tv(w):
+            ch = tv.TVChain(tv.TVModel.from_workload(w), seed=w.seed, chain_id=chain_id)
+        else:
+            ch = pqmc.Chain(pqmc.Model.from_workload(w), seed=w.seed, chain_id=chain_id)
         t0 = time.time()
         ch.sweep(1, measure=True)
         dt = time.time() - t0
-    return (2 * w.l_half + 2) * w.n_sites, dt
+    return (2 * w.l_half + 2) * n_props(w), dt
 
 
 def cpu_model() -> str:
@@ -323,11 +347,13 @@ def main():
     ap.add_argument("--chains", type=int, default=None,
                     help="chains in the batch (default 2048; 512 at 24x24; 256 for uneven)")
     ap.add_argument("--workload", default="16x16",
-                    choices=["16x16", "honeycomb12x12", "12x12", "24x24", "uneven"],
+                    choices=["16x16", "honeycomb12x12", "12x12", "24x24", "uneven", "tv15_V1.6",
+                             "tv15_V1.35", "tv6"],
                     help="16x16: the headline configuration; 12x12: the half-filled 12x12 "
                          "lattice; 24x24: N = 576 at dtau = 0.05, Theta = 10; uneven: 256 chains "
                          "on 6x6 .. 12x12 with U in [2, 6]; honeycomb12x12: the paper's lattice "
-                         "at 288 sites")
+                         "at 288 sites; tv15_V1.6 / tv15_V1.35: the spinless t-V model on the "
+                         "15x15-cell honeycomb lattice (450 sites)")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="time the sweeps as captured HIP graphs, without the in-sweep kernel "
                          "events (no roofline block)")
@@ -391,7 +417,7 @@ def main():
     main_res = run_gpu(args, args.precision, args.steps, args.warmup)
     main_res["steps"] = args.steps
     legs = {}
-    if args.leg_steps > 0:
+    if args.leg_steps > 0 and not is_tv(w):      # the t-V model runs on the factored engine only
         for name, prec, ns in (("fp64_wrap_gpu", "fp64wrap", args.wrap_ns),
                                ("mixed_gpu", "mixed", args.mixed_ns)):
             if prec == args.precision:
@@ -413,9 +439,11 @@ def main():
         # chain takes part in ceil(N / k) of the ceil(N_max / k) launches of a
         # slice (spin up only with the particle-hole shortcut)
         f_mean = main_res["accept"] * args.k
-        n_seg = math.ceil(max(x.n_sites for x in grp) / args.k)
-        seg_bytes = sum(spins[c] * math.ceil(x.n_sites / args.k) * 8.0 *
-                        (2 * x.n_sites * x.n_up + 2 * f_mean * x.n_up)
+        def segs(x):   # scan segments per slice: k sites, or k / 2 bonds (t-V)
+            return math.ceil(n_props(x) / (args.k // 2)) if is_tv(x) else math.ceil(x.n_sites / args.k)
+        n_seg = max(segs(x) for x in grp)
+        seg_bytes = sum(spins[c] * segs(x) * 8.0 *
+                        (2 * x.n_sites * n_occ(x) + 2 * f_mean * n_occ(x))
                         for c, x in enumerate(grp)) / n_seg
         seg_ms = kt["segment_update"]["ms_per_launch"]
         seg_ach = seg_bytes / (seg_ms / 1e3)
@@ -424,7 +452,7 @@ def main():
                           "traffic": None if args.particle_hole else
                           read_traffic(per_launch, args.precision, args.workload),
                           "kernel": "k_segupd_f (Q <- Q - (Q Mf^T) Wf, every chain and spin)"
-                                    if max(x.n_up for x in ws) <= 128 else
+                                    if max(n_occ(x) for x in ws) <= 128 else
                                     "k_gemm SEGP + SEGF (Q Mf^T, then Q - (Q Mf^T) Wf)",
                           "bytes_per_launch": seg_bytes, "ms_per_launch": seg_ms,
                           "ms_total": kt["segment_update"]["ms_total"],
@@ -432,7 +460,7 @@ def main():
                                     f"{kt['segment_update']['launches']} launches in the timed sweeps"})
         # propagation of both factors, FP64 MFMA: 2 N^2 n flops per factor,
         # chain and spin
-        prop_flops = sum(spins[c] * 2 * 2.0 * x.n_sites ** 2 * x.n_up for c, x in enumerate(grp))
+        prop_flops = sum(spins[c] * 2 * 2.0 * x.n_sites ** 2 * n_occ(x) for c, x in enumerate(grp))
         prop_ms = kt["propagation"]["ms_per_launch"]
         prop_ach = prop_flops / (prop_ms / 1e3)
         rooflines.append({"bound": "mfma", "achieved": prop_ach / 1e12, "peak": PEAK_FP64_MFMA / 1e12,

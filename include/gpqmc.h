@@ -77,9 +77,28 @@ typedef enum {
   GPQMC_FP64_WRAP = 3
 } gpqmc_precision;
 
+/* GPQMC_MODEL_HUBBARD: the Hubbard model of Eq. 2 with the Gutzwiller-
+ *   projected Neel trial (Method section), one HS field per site and slice,
+ *   decoupled in the spin channel.
+ * GPQMC_MODEL_TV: the spinless t-V model of Eq. 3 ("Repulsive spinless
+ *   honeycomb model"), H = K + V sum_b (n_i - 1/2)(n_j - 1/2) over the given
+ *   bonds b = (i, j), trial e^{-g sum_b n_i n_j} |psi_C> with |psi_C> the n_up
+ *   lowest orbitals of K + Delta_C diag(sublattice) (Delta_C in m_neel).  One
+ *   HS field per bond and slice, decoupled in the density channel:
+ *   e^{-x (n_i - 1/2)(n_j - 1/2)} = 1/2 e^{-x/4} sum_s e^{c s (n_i - n_j)},
+ *   cosh c = e^{x/2}, x = dtau V in the bulk and x = g on the two boundary
+ *   slices (exp(-g n_i n_j) equals this up to a constant at fixed particle
+ *   number when every site has the same number of bonds).  A bond flip is a
+ *   rank-2 change of D_l; its ratio det(1 + Delta_F (1 - G)[F, F]) can be
+ *   negative (the weight has a sign).  One species: n_dn = 0, U unused. */
+typedef enum {
+  GPQMC_MODEL_HUBBARD = 0,
+  GPQMC_MODEL_TV = 1
+} gpqmc_model;
+
 /* One Markov chain.  All chains of one context must share l_half,
- * stab_interval, delay_rank and precision; lattices, fillings and couplings
- * may differ per chain. */
+ * stab_interval, delay_rank, precision and model; lattices, fillings and
+ * couplings may differ per chain. */
 typedef struct {
   int32_t n_sites;            /* N, 1 .. 1024 */
   int32_t n_up, n_dn;         /* particles per spin, 1 .. N */
@@ -101,6 +120,23 @@ typedef struct {
   uint64_t chain_id;          /* counter word 0 of every draw of this chain */
   int32_t trace;              /* nonzero: record ratios and checkpoint Green's
                                  functions of the last pass (testing; large) */
+  int32_t model;              /* gpqmc_model (0 = Hubbard) */
+  double V;                   /* t-V: nearest-neighbour repulsion, >= 0 */
+  int32_t n_bonds;            /* t-V: number of bonds (HS fields per slice) */
+  const int32_t* bonds;       /* t-V: n_bonds x 2 sites (i, j), proposed in this order;
+                                 D_l at i takes e^{+c s_b}, at j e^{-c s_b}.  The library
+                                 cuts the list into scan segments of at most
+                                 delay_rank / 2 consecutive site-disjoint bonds (a
+                                 segment ends early where the next bond shares a site;
+                                 lists grouped into matchings, such as the three bond
+                                 directions of the honeycomb lattice, give full
+                                 segments).  No site may have more than 4 bonds.  The t-V model needs
+                                 GPQMC_FP64 and an even delay_rank <= 32.  Fields
+                                 (gpqmc_set_field / get_field) are then
+                                 (l_half * 2 + 2) x n_bonds; records hold (sign, E/N,
+                                 (1/n_bonds) sum_b <n_i n_j>, S_CDW = (1/N^2) sum_ij
+                                 eps_i eps_j <(n_i - 1/2)(n_j - 1/2)>); gpqmc_logdet and
+                                 gpqmc_get_green report spin 0 only. */
 } gpqmc_chain_desc;
 
 typedef struct {
@@ -260,7 +296,7 @@ gpqmc_status gpqmc_debug_gemm(int32_t precision, int32_t M, int32_t N, int32_t K
  * file-scope device array of the library (256 KiB per GPU, held until the
  * process ends) and is written there by a kernel, so the call makes no
  * allocation and no host-to-device copy.  Enqueue only: it returns before the
- * product is done (synchronise hip_stream before reading C).  At most 16368
+ * product is done (synchronise hip_stream before reading C).  At most 16352
  * output tiles (64 x 64, or 128 x 128 with the large-tile flag); larger
  * products return GPQMC_EINVAL.  Every call on one GPU uses that GPU's
  * array: calls that overlap on one GPU (other streams or threads) race;

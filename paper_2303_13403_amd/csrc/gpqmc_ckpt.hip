@@ -145,7 +145,7 @@ __global__ __launch_bounds__(kDenseThreads) void k_chol_inv(const ChainDev* __re
   const int lg = xcd_remap(blockIdx.x, gridDim.x);
   const ChainDev& C = chains[lg >> 1];
   const int sp = lg & 1, n = C.n[sp], tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  if (sp == 1 && C.ph) return;
+  if (sp >= C.nsp) return;
   __shared__ double lds[kLdsDense * (kLdsDense + 1)];
   __shared__ double colk[kMaxSites];
   __shared__ int piv[kMaxSites];
@@ -200,7 +200,7 @@ __global__ __launch_bounds__(kDenseThreads) void k_gj_inv(const ChainDev* __rest
   const int lg = xcd_remap(blockIdx.x, gridDim.x);
   const ChainDev& C = chains[lg >> 1];
   const int sp = lg & 1, n = C.n[sp], tid = threadIdx.x;
-  if (sp == 1 && C.ph) return;
+  if (sp >= C.nsp) return;
   __shared__ double lds[kLdsDense * (kLdsDense + 1)];
   __shared__ double colk[kMaxSites];
   __shared__ int piv[kMaxSites];
@@ -468,7 +468,7 @@ __global__ __launch_bounds__(TG * TG) void k_chol_inv_rt(const ChainDev* __restr
   const int lg = xcd_remap(blockIdx.x, gridDim.x);
   const ChainDev& C = chains[lg >> 1];
   const int sp = lg & 1, n = C.n[sp], tid = threadIdx.x;
-  if (sp == 1 && C.ph) return;
+  if (sp >= C.nsp) return;
   GPQMC_RT_SHARED
   rt_clear(rk, rp, ck);
   RegTile<NB, TG> T;
@@ -561,7 +561,7 @@ __global__ __launch_bounds__(TG * TG) void k_gj_inv_rt(const ChainDev* __restric
   const int lg = xcd_remap(blockIdx.x, gridDim.x);
   const ChainDev& C = chains[lg >> 1];
   const int sp = lg & 1, n = C.n[sp], tid = threadIdx.x;
-  if (sp == 1 && C.ph) return;
+  if (sp >= C.nsp) return;
   GPQMC_RT_SHARED
   rt_clear(rk, rp, ck);
   RegTile<NB, TG> T;
@@ -604,7 +604,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const ChainDev* __restric
                                                        int parity, int side) {
   const ChainDev& C = chains[xcd_remap(blockIdx.x, gridDim.x)];
   ChainState* st = C.st;
-  const int N = C.N, tid = threadIdx.x, nsp = C.ph ? 1 : 2;
+  const int N = C.N, tid = threadIdx.x, nsp = C.nsp;
   __shared__ double red[4];
   for (int sp = 0; sp < nsp; ++sp) {
     const size_t sz = (size_t)N * C.n[sp];
@@ -651,6 +651,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const ChainDev* __restric
   if (tid == 0) {
     int wsign = 1;
     for (int sp = 0; sp < 2; ++sp) {
+      if (sp == 1 && C.tv) break;   // one species: W = W_0
       if (sp == 1 && C.ph) {
         if (mode != 2) {
           st->w_log[1] = st->w_log[0] + ph_shift;
@@ -703,7 +704,48 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const ChainDev* __restric
     st->drift_bits = 0u;
     st->gmax_bits = 0u;
   }
-  if (mode != 2 && measure_here && ctl->measure) {
+  if (mode != 2 && measure_here && ctl->measure && C.tv) {
+    // spinless t-V, Wick with Gb_ij = <c_i^dag c_j> = delta_ij - G_ji:
+    //   <n_i n_j> = Gb_ii Gb_jj + Gb_ij G_ij (the diagonal included),
+    //   E = sum_ij K_ij Gb_ij + V sum_b <(n_i - 1/2)(n_j - 1/2)>,
+    //   N^2 S_CDW = (sum_i eps_i (n_i - 1/2))^2 + sum_ij eps_i eps_j Gb_ij G_ij
+    const GLOBAL double* __restrict__ G = gp((const double*)C.G64[0]);
+    const GLOBAL int8_t* __restrict__ eps = gp(C.eps);
+    double ek = 0.0, cross = 0.0, mc = 0.0, ev = 0.0, nnb = 0.0;
+    for (int idx = tid; idx < N * N; idx += kThreads) {
+      const int i = idx / N, j = idx - i * N;
+      const double gb = (i == j ? 1.0 : 0.0) - G[(size_t)j * N + i];
+      const double k = C.Khop[idx];
+      if (k != 0.0) ek += k * gb;
+      cross += (double)eps[i] * (double)eps[j] * gb * G[idx];
+    }
+    for (int i = tid; i < N; i += kThreads) mc += (double)eps[i] * (0.5 - G[(size_t)i * N + i]);
+    for (int b = tid; b < C.n_bonds; b += kThreads) {
+      const int i = C.bonds[2 * b], j = C.bonds[2 * b + 1];
+      const double ni = 1.0 - G[(size_t)i * N + i], nj = 1.0 - G[(size_t)j * N + j];
+      const double nn = ni * nj + (-G[(size_t)j * N + i]) * G[(size_t)i * N + j];
+      nnb += nn;
+      ev += nn - 0.5 * (ni + nj) + 0.25;
+    }
+    ek = block_sum(ek, red);
+    cross = block_sum(cross, red);
+    mc = block_sum(mc, red);
+    ev = block_sum(ev, red);
+    nnb = block_sum(nnb, red);
+    if (tid == 0) {
+      const int k = st->n_meas;
+      if (k < C.meas_cap) {
+        double* r = C.meas + (size_t)kMeasCols * k;
+        r[0] = (double)st->sign;
+        r[1] = (ek + C.V * ev) / N;
+        r[2] = nnb / C.n_bonds;
+        r[3] = (mc * mc + cross) / ((double)N * N);
+        st->n_meas = k + 1;
+      } else {
+        st->flags |= FLAG_MEAS_FULL;
+      }
+    }
+  } else if (mode != 2 && measure_here && ctl->measure) {
     // Wick estimates from the fresh FP64 G of both spins, G_ij = <c_i c_j^dag>
     // and Gb_ij = <c_i^dag c_j> = delta_ij - G_ji: the energy, the double
     // occupancy, and the staggered structure factor
@@ -754,7 +796,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const ChainDev* __restric
     }
   }
   if (mode != 2 && C.trace_green && ck_index >= 0) {
-    for (int sp = 0; sp < 2; ++sp) {
+    for (int sp = 0; sp < (C.tv ? 1 : 2); ++sp) {
       double* dst = C.trace_green + ((size_t)ck_index * 2 + sp) * N * N;
       if (sp == 1 && C.ph) {
         for (int idx = tid; idx < N * N; idx += kThreads) {
@@ -777,7 +819,7 @@ template <typename Tu>
 __global__ __launch_bounds__(kThreads) void k_put_trial(const ChainDev* __restrict__ chains, int slot,
                                                         int set_active, int side) {
   const ChainDev& C = chains[xcd_remap(blockIdx.x, gridDim.x)];
-  const int tid = threadIdx.x, nsp = C.ph ? 1 : 2;
+  const int tid = threadIdx.x, nsp = C.nsp;
   for (int sp = 0; sp < nsp; ++sp) {
     const size_t sz = (size_t)C.N * C.n[sp];
     double* dst = C.stack[sp] + (size_t)slot * sz;
@@ -812,7 +854,7 @@ __global__ __launch_bounds__(kThreads) void k_dscale_u(const ChainDev* __restric
     Tu* u = (Tu*)C.U[sp][parity];
     for (int idx = threadIdx.x; idx < C.N * n; idx += kThreads) {
       const int i = idx / n;
-      u[idx] *= (Tu)C.dval[b][sp][frow[i] > 0 ? 0 : 1];
+      u[idx] *= (Tu)C.dval[b][sp][kMexp + frow[i]];
     }
   }
 }
@@ -824,8 +866,8 @@ __global__ __launch_bounds__(kThreads) void k_dscale_f(const ChainDev* __restric
                                                        int M, int parity, int ainv, int which) {
   const ChainDev& C = chains[xcd_remap(blockIdx.x, gridDim.x)];
   const int b = (l == 0 || l == M + 1) ? 0 : 1;
-  const GLOBAL int8_t* frow = gp(C.field + (size_t)l * C.N);
-  for (int sp = 0; sp < (C.ph ? 1 : 2); ++sp) {
+  const GLOBAL int8_t* frow = gp(C.mexp + (size_t)l * C.N);
+  for (int sp = 0; sp < C.nsp; ++sp) {
     const int n = C.n[sp];
     for (int side = 0; side < 2; ++side) {
       if (!(which & (1 << side))) continue;
@@ -833,8 +875,7 @@ __global__ __launch_bounds__(kThreads) void k_dscale_f(const ChainDev* __restric
       GLOBAL double* f = gp((double*)C.F[side][sp][parity]);
       for (int idx = threadIdx.x; idx < C.N * n; idx += kThreads) {
         const int i = idx / n;
-        const int si = frow[i] > 0 ? 0 : 1;
-        f[idx] *= C.dval[b][sp][inv ? 1 - si : si];
+        f[idx] *= C.dval[b][sp][kMexp + (inv ? -(int)frow[i] : (int)frow[i])];
       }
     }
   }

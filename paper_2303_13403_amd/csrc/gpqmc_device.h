@@ -78,11 +78,11 @@ __device__ inline double block_sum(double v, double* red) {
   return red[0] + red[1] + red[2] + red[3];
 }
 
-// D_l diagonal for one site: d = exp(sigma c_b s); the inverse is the value of
-// the flipped field.
-__device__ inline double dfac(const double (&dv)[2][2], int b, int8_t s, bool inverse) {
-  const int si = (s > 0) ? 0 : 1;
-  return dv[b][inverse ? 1 - si : si];
+// D_l diagonal for one site with exponent m: exp(sigma c_b m); the inverse is
+// the value at -m.
+__device__ inline double dfac(const double (&dv)[2][2 * kMexp + 1], int b, int8_t m,
+                              bool inverse) {
+  return dv[b][kMexp + (inverse ? -(int)m : (int)m)];
 }
 
 // ---------------------------------------------------------------------------

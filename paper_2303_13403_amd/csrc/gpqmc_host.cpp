@@ -39,7 +39,7 @@ hipError_t launch_put_trial(int fp32b, const ChainDev* c, int nc, int slot, int 
                             int side, hipStream_t s);
 hipError_t launch_dscale_f(const ChainDev* c, int nc, int l, int M, int parity, int ainv, int which,
                            hipStream_t s);
-hipError_t launch_scan_f(const ChainDev* c, int nc, const Ctl* ctl, int l, int M, int s0, int s1,
+hipError_t launch_scan_f(int tv, const ChainDev* c, int nc, const Ctl* ctl, int l, int M, int s0, int s1,
                          int dir, int parity, hipStream_t s);
 hipError_t launch_segupd_f(const ChainDev* c, int nc, int n_max, int dir, int parity, hipStream_t s);
 hipError_t launch_dscale_u(int fp32b, const ChainDev* c, int nc, int l, int M, int parity,
@@ -130,6 +130,11 @@ struct ChainHost {
   uint64_t seed, chain_id;
   bool trace;
   bool ph = false;            // particle-hole shortcut: spin 1 derived from spin 0
+  bool tv = false;            // spinless t-V model (bond fields, one species)
+  int nprop = 0;              // proposals per slice: N sites, or the bonds (t-V)
+  double V = 0.0;             // t-V repulsion
+  std::vector<int> bonds;     // t-V: nprop x 2 sites
+  std::vector<int> seg_start; // t-V: first bond of every scan segment, then n_bonds
   bool field_set = false;
   std::vector<int8_t> field;
   std::vector<int8_t> eps;    // sublattice signs (staggered structure factor)
@@ -140,6 +145,7 @@ struct ChainHost {
          Ym[2] = {0, 0}, G64[2];
   size_t F[2][2][2] = {}, Mf[2] = {0, 0}, Wf[2] = {0, 0}, Pscr[2] = {0, 0};  // factored engine
   size_t field_off, eps_off, st, meas, tr_ratio = 0, tr_green = 0, tr_drift = 0, tr_logdet = 0;
+  size_t mexp_off = 0, bonds_off = 0, dflist = 0;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -156,6 +162,8 @@ struct gpqmc_ctx {
   int fact = 0;            // 1: factored engine G = 1 - A B^T (FP64); 0: G wrapped as an N x N matrix
   int l_half = 0, M = 0, n_s = 1, kseg = 64, n_slices = 2;  // kseg: delay rank (sites per flush)
   int n_max = 0;                   // largest lattice of the batch
+  int nprop_max = 0;               // most proposals per slice (sites, or t-V bonds) in the batch
+  int tv = 0;                      // 1: spinless t-V chains (every chain of the context)
   int n_part = 0;                  // largest particle number (either spin) of the batch
   int meas_cap = 4096;
   bool use_graph = true;
@@ -452,9 +460,12 @@ struct Launcher {
     const bool fast_scan = ctx->kseg <= kBlock;
     const bool fast_upd = fast_scan && ctx->n_part <= 128;
     const int tscan = ctx->timing_mask ? 2 : -1, tupd = ctx->timing_mask ? 1 : -1;
-    for (int s0 = 0; s0 < ctx->n_max; s0 += ctx->kseg) {
+    // segments: kseg sites from s0, or (t-V) the chain's segment s0 of its
+    // bond list (nprop_max is then the most segments of a chain)
+    const int step = ctx->tv ? 1 : ctx->kseg;
+    for (int s0 = 0; s0 < ctx->nprop_max; s0 += step) {
       if ((e = timed(tscan, [&] {
-             return fast_scan ? launch_scan_f(chains, nc, ctl, l, ctx->M, s0, s0 + ctx->kseg, dir,
+             return fast_scan ? launch_scan_f(ctx->tv, chains, nc, ctl, l, ctx->M, s0, s0 + step, dir,
                                               parity, s)
                               : launch_scan(0, 1, chains, nc, ctl, l, ctx->M, s0, s0 + ctx->kseg,
                                             dir, parity, s);
@@ -661,6 +672,11 @@ gpqmc_status gpqmc_create(int32_t n_chains, const gpqmc_chain_desc* chains,
   c->fp32 = (d0.precision == GPQMC_FP64 || d0.precision == GPQMC_FP64_WRAP) ? 0 : 1;
   c->fp32b = d0.precision == GPQMC_MIXED_FP32_BASIS ? 1 : 0;
   c->fact = d0.precision == GPQMC_FP64 ? 1 : 0;
+  if (d0.model != GPQMC_MODEL_HUBBARD && d0.model != GPQMC_MODEL_TV)
+    return bad(GPQMC_EINVAL, "model must be GPQMC_MODEL_HUBBARD or GPQMC_MODEL_TV");
+  c->tv = d0.model == GPQMC_MODEL_TV ? 1 : 0;
+  if (c->tv && (!c->fact || d0.delay_rank % 2 != 0 || d0.delay_rank > kBlock))
+    return bad(GPQMC_EINVAL, "the t-V model needs GPQMC_FP64 and an even delay_rank <= 32");
   if (c->l_half < 0 || c->n_s < 1 || c->kseg < 1 || c->kseg > kSegMax)
     return bad(GPQMC_EINVAL, "need l_half >= 0, stab_interval >= 1, 1 <= delay_rank <= 64");
   c->M = 2 * c->l_half;
@@ -676,7 +692,7 @@ gpqmc_status gpqmc_create(int32_t n_chains, const gpqmc_chain_desc* chains,
     c->use_graph = opts->use_graph != 0;
     if (opts->drift_tol > 0) c->drift_tol = (float)opts->drift_tol;
   }
-  const bool ph_req = opts && opts->particle_hole != 0 && c->fact && c->kseg <= kBlock;
+  const bool ph_req = opts && opts->particle_hole != 0 && c->fact && c->kseg <= kBlock && !c->tv;
   if (!c->stream) c->use_graph = false;   // the null stream cannot be captured
   // checkpoints C = {-1, l_half, M+1} U {j n_s : 1 <= j n_s <= M}
   std::vector<int> ck = {-1, c->l_half, c->M + 1};
@@ -691,16 +707,18 @@ gpqmc_status gpqmc_create(int32_t n_chains, const gpqmc_chain_desc* chains,
     const gpqmc_chain_desc& d = chains[i];
     char buf[200];
     if (d.l_half != c->l_half || d.stab_interval != c->n_s || d.delay_rank != c->kseg ||
-        d.precision != d0.precision) {
-      snprintf(buf, sizeof buf, "chain %d: l_half, stab_interval, delay_rank and precision must "
-               "match chain 0", i);
+        d.precision != d0.precision || d.model != d0.model) {
+      snprintf(buf, sizeof buf, "chain %d: l_half, stab_interval, delay_rank, precision and model "
+               "must match chain 0", i);
       return bad(GPQMC_EINVAL, buf);
     }
     const int N = d.n_sites;
-    if (N < 1 || N > kMaxSites || d.n_up < 1 || d.n_up > N || d.n_dn < 1 || d.n_dn > N ||
-        !d.hopping || !d.sublattice || !(d.U >= 0) || !(d.dtau > 0) || !(d.g >= 0)) {
-      snprintf(buf, sizeof buf, "chain %d: need 1 <= N <= %d, 1 <= n_up, n_dn <= N, U >= 0, "
-               "dtau > 0, g >= 0 and non-NULL hopping and sublattice", i, kMaxSites);
+    if (N < 1 || N > kMaxSites || d.n_up < 1 || d.n_up > N ||
+        (c->tv ? d.n_dn != 0 : (d.n_dn < 1 || d.n_dn > N)) || !d.hopping || !d.sublattice ||
+        !(d.U >= 0) || !(d.dtau > 0) || !(d.g >= 0) || (c->tv && !(d.V >= 0))) {
+      snprintf(buf, sizeof buf, "chain %d: need 1 <= N <= %d, 1 <= n_up <= N, 1 <= n_dn <= N "
+               "(t-V: n_dn = 0, V >= 0), U >= 0, dtau > 0, g >= 0 and non-NULL hopping and "
+               "sublattice", i, kMaxSites);
       return bad(GPQMC_EINVAL, buf);
     }
     ChainHost h;
@@ -711,7 +729,10 @@ gpqmc_status gpqmc_create(int32_t n_chains, const gpqmc_chain_desc* chains,
     h.dtau = d.dtau;
     h.g = d.g;
     h.m_neel = d.m_neel;
-    h.alpha = d.U == 0 ? 0.0 : std::acosh(std::exp(0.5 * d.dtau * d.U));
+    // density-channel bond decoupling (t-V) or spin-channel site decoupling
+    // (Hubbard), cosh c = exp(x / 2) with x = dtau V or dtau U
+    const double x_bulk = c->tv ? d.dtau * d.V : d.dtau * d.U;
+    h.alpha = x_bulk == 0 ? 0.0 : std::acosh(std::exp(0.5 * x_bulk));
     h.lam = d.g == 0 ? 0.0 : std::acosh(std::exp(0.5 * d.g));
     h.seed = d.seed;
     h.chain_id = d.chain_id;
@@ -747,7 +768,8 @@ gpqmc_status gpqmc_create(int32_t n_chains, const gpqmc_chain_desc* chains,
     }
     h.lat = it->second;
     // Neel trial per spin: lowest n_sigma eigenvectors of K + sigma M_N eps + v
-    for (int sp = 0; sp < 2; ++sp) {
+    // (t-V: the CDW trial of the one species, K + Delta_C eps with Delta_C = M_N)
+    for (int sp = 0; sp < (c->tv ? 1 : 2); ++sp) {
       const double sigma = sp == 0 ? 1.0 : -1.0;
       std::vector<double> hm(d.hopping, d.hopping + (size_t)N * N);
       for (int a = 0; a < N; ++a) {
@@ -776,6 +798,43 @@ gpqmc_status gpqmc_create(int32_t n_chains, const gpqmc_chain_desc* chains,
       }
       h.trial[sp] = jt->second;
     }
+    if (c->tv) {
+      h.trial[1] = h.trial[0];   // no second species (never read)
+      h.tv = true;
+      h.V = d.V;
+      if (!d.bonds || d.n_bonds < 1) return bad(GPQMC_EINVAL, "t-V chain without bonds");
+      h.bonds.assign(d.bonds, d.bonds + 2 * (size_t)d.n_bonds);
+      std::vector<int> deg(N, 0);
+      for (int b = 0; b < d.n_bonds; ++b) {
+        const int bi = h.bonds[2 * b], bj = h.bonds[2 * b + 1];
+        if (bi < 0 || bi >= N || bj < 0 || bj >= N || bi == bj)
+          return bad(GPQMC_EINVAL, "t-V bond with a site out of range or twice");
+        if (++deg[bi] > kMexp || ++deg[bj] > kMexp) {
+          snprintf(buf, sizeof buf, "t-V: more than %d bonds at a site", kMexp);
+          return bad(GPQMC_EINVAL, buf);
+        }
+      }
+      // scan segments: runs of consecutive bonds, at most delay_rank / 2 and
+      // site-disjoint (a new segment starts where the next bond would share a
+      // site), so that a segment's block holds distinct sites
+      h.seg_start.assign(1, 0);
+      std::vector<char> used(N, 0);
+      int cnt = 0;
+      for (int b = 0; b < d.n_bonds; ++b) {
+        const int bi = h.bonds[2 * b], bj = h.bonds[2 * b + 1];
+        if (cnt == c->kseg / 2 || used[bi] || used[bj]) {
+          h.seg_start.push_back(b);
+          std::fill(used.begin(), used.end(), 0);
+          cnt = 0;
+        }
+        used[bi] = used[bj] = 1;
+        ++cnt;
+      }
+      h.seg_start.push_back(d.n_bonds);
+      h.nprop = d.n_bonds;
+    } else {
+      h.nprop = N;
+    }
     // particle-hole shortcut: exact when the spin-down problem is the image
     // of the spin-up one under c_i -> eps_i c_i^dag (bipartite hopping, half
     // filling, no trial potential: the Neel trials map onto each other)
@@ -788,7 +847,7 @@ gpqmc_status gpqmc_create(int32_t n_chains, const gpqmc_chain_desc* chains,
       }
       h.ph = bip;
     }
-    h.field.assign((size_t)c->n_slices * N, 1);
+    h.field.assign((size_t)c->n_slices * h.nprop, 1);
     h.eps.assign(d.sublattice, d.sublattice + N);
     c->ch.push_back(std::move(h));
   }
@@ -847,13 +906,16 @@ gpqmc_status gpqmc_create(int32_t n_chains, const gpqmc_chain_desc* chains,
       h.Xm[sp] = take((size_t)h.n[sp] * h.n[sp] * 8);
       h.G64[sp] = take(nn * 8);
     }
-    h.field_off = take((size_t)c->n_slices * N);
+    h.field_off = take((size_t)c->n_slices * h.nprop);
+    h.mexp_off = h.tv ? take((size_t)c->n_slices * N) : h.field_off;
+    if (h.tv) h.bonds_off = take((h.bonds.size() + h.seg_start.size()) * 4);
+    h.dflist = take((size_t)2 * kSegMax * 8);
     h.eps_off = take((size_t)N);
     h.st = take(sizeof(ChainState));
     h.flist = take((size_t)kSegMax * 4);
     h.meas = take((size_t)c->meas_cap * kMeasCols * 8);
     if (h.trace) {
-      h.tr_ratio = take((size_t)c->n_slices * N * 2 * 8);
+      h.tr_ratio = take((size_t)c->n_slices * h.nprop * 2 * 8);
       h.tr_green = take((size_t)nck * 2 * nn * 8);
       h.tr_drift = take((size_t)nck * 8);
       h.tr_logdet = take((size_t)nck * 2 * 2 * 8);
@@ -866,6 +928,7 @@ gpqmc_status gpqmc_create(int32_t n_chains, const gpqmc_chain_desc* chains,
   std::vector<char> skip[T_COUNT];   // entries without tiles (spin 1 of particle-hole chains)
   for (auto& h : c->ch) {
     c->n_max = std::max(c->n_max, h.N);
+    c->nprop_max = std::max(c->nprop_max, h.tv ? (int)h.seg_start.size() - 1 : h.nprop);
     c->n_min = std::min(c->n_min, h.N);
     // 128 x 128 tiles for N >= 128 while at least 3/4 of the padded tile grid
     // is real work (at N = 288, 56%, the 64 x 64 kernel measured 6% faster
@@ -882,7 +945,7 @@ gpqmc_status gpqmc_create(int32_t n_chains, const gpqmc_chain_desc* chains,
       sz[T_Nn4].push_back({h.N, h.n[sp]});   // factor A of this spin
       sz[T_Nn4].push_back({h.N, h.n[sp]});   // factor B
       sz[T_Nk].push_back({h.N, c->kseg});
-      const char sk = (sp == 1 && h.ph) ? 1 : 0;
+      const char sk = (sp == 1 && (h.ph || h.tv)) ? 1 : 0;
       for (int t = 0; t < T_COUNT; ++t) skip[t].push_back(sk);
       skip[T_Nn4].push_back(sk);
     }
@@ -942,15 +1005,24 @@ gpqmc_status gpqmc_bind_workspace(gpqmc_ctx* ctx, void* device_ptr, size_t bytes
       const double cpl = b == 0 ? h.lam : h.alpha;
       for (int sp = 0; sp < 2; ++sp) {
         const double sigma = sp == 0 ? 1.0 : -1.0;
+        for (int m = -kMexp; m <= kMexp; ++m) d.dval[b][sp][m + kMexp] = std::exp(sigma * cpl * m);
         for (int si = 0; si < 2; ++si) {
           const double s = si == 0 ? 1.0 : -1.0;
-          d.dval[b][sp][si] = std::exp(sigma * cpl * s);
           d.delta[b][sp][si] = std::exp(-2.0 * sigma * cpl * s) - 1.0;
         }
       }
     }
     d.U_hub = h.U;
     d.ph = h.ph ? 1 : 0;
+    d.tv = h.tv ? 1 : 0;
+    d.nsp = (h.ph || h.tv) ? 1 : 2;
+    d.n_bonds = h.tv ? h.nprop : 0;
+    d.V = h.V;
+    d.bonds = h.tv ? ctx->at<int>(h.bonds_off) : nullptr;
+    d.seg_start = h.tv ? ctx->at<int>(h.bonds_off) + h.bonds.size() : nullptr;
+    d.n_seg = h.tv ? (int)h.seg_start.size() - 1 : 0;
+    d.mexp = ctx->at<int8_t>(h.mexp_off);
+    d.dflist = ctx->at<double>(h.dflist);
     d.coupling[0] = h.lam;
     d.coupling[1] = h.alpha;
     d.n_slices = ctx->n_slices;
@@ -1005,12 +1077,12 @@ gpqmc_status gpqmc_bind_workspace(gpqmc_ctx* ctx, void* device_ptr, size_t bytes
       const int ei = 2 * i + sp;
       GemmEntry base;
       memset(&base, 0, sizeof base);
-      base.field = d.field;
+      base.field = d.mexp;
       base.n_sites = N;
       base.spin = sp;
       base.st = d.st;
       for (int b = 0; b < 2; ++b)
-        for (int si = 0; si < 2; ++si) base.dval[b][si] = d.dval[b][sp][si];
+        for (int m = 0; m <= 2 * kMexp; ++m) base.dval[b][m] = d.dval[b][sp][m];
       auto mk = [&](const void* A0, const void* A1, const void* B0, const void* B1, void* C0,
                     void* C1, int M_, int N_, int K_, int lda, int ldb, int ldc) {
         GemmEntry e = base;
@@ -1122,8 +1194,14 @@ gpqmc_status gpqmc_bind_workspace(gpqmc_ctx* ctx, void* device_ptr, size_t bytes
     }
   }
   HIPCHK(up(ctx->off_chains, cd.data(), sizeof(ChainDev) * nc), "upload chains");
-  for (int i = 0; i < nc; ++i)
+  for (int i = 0; i < nc; ++i) {
     HIPCHK(up(ctx->ch[i].eps_off, ctx->ch[i].eps.data(), ctx->ch[i].eps.size()), "upload eps");
+    if (ctx->ch[i].tv) {
+      std::vector<int> bs(ctx->ch[i].bonds);
+      bs.insert(bs.end(), ctx->ch[i].seg_start.begin(), ctx->ch[i].seg_start.end());
+      HIPCHK(up(ctx->ch[i].bonds_off, bs.data(), bs.size() * 4), "upload bonds");
+    }
+  }
   for (int k = 0; k < E_COUNT; ++k)
     HIPCHK(up(ctx->off_ent[k], E[k].data(), sizeof(GemmEntry) * E[k].size()), "upload entries");
   for (int t = 0; t < T_COUNT; ++t)
@@ -1146,14 +1224,27 @@ gpqmc_status gpqmc_init_trial(gpqmc_ctx* ctx) {
     if (!h.field_set) {
       const uint32_t k0 = (uint32_t)(h.seed & 0xffffffffu), k1 = (uint32_t)(h.seed >> 32) ^ TAG_INIT;
       for (int l = 0; l < ctx->n_slices; ++l)
-        for (int s = 0; s < h.N; ++s) {
+        for (int s = 0; s < h.nprop; ++s) {
           uint32_t c[4] = {(uint32_t)h.chain_id, 0u, (uint32_t)l, (uint32_t)s};
           philox4x32_10(c, k0, k1);
-          h.field[(size_t)l * h.N + s] = (c[0] & 1u) ? 1 : -1;
+          h.field[(size_t)l * h.nprop + s] = (c[0] & 1u) ? 1 : -1;
         }
     }
     HIPCHK(hipMemcpyAsync(ctx->ws + h.field_off, h.field.data(), h.field.size(),
                           hipMemcpyHostToDevice, ctx->stream), "upload field");
+    std::vector<int8_t> mexp;
+    if (h.tv) {
+      // site exponents: +s_b at a bond's A end, -s_b at its B end
+      mexp.assign((size_t)ctx->n_slices * h.N, 0);
+      for (int l = 0; l < ctx->n_slices; ++l)
+        for (int b = 0; b < h.nprop; ++b) {
+          const int8_t sb = h.field[(size_t)l * h.nprop + b];
+          mexp[(size_t)l * h.N + h.bonds[2 * b]] += sb;
+          mexp[(size_t)l * h.N + h.bonds[2 * b + 1]] -= sb;
+        }
+      HIPCHK(hipMemcpyAsync(ctx->ws + h.mexp_off, mexp.data(), mexp.size(), hipMemcpyHostToDevice,
+                            ctx->stream), "upload site exponents");
+    }
     ChainState st;
     memset(&st, 0, sizeof st);
     st.sign = 1;
@@ -1337,6 +1428,7 @@ gpqmc_status gpqmc_get_green(gpqmc_ctx* ctx, int32_t chain, int32_t spin, double
   if (!ctx || !G || chain < 0 || chain >= ctx->n_chains || spin < 0 || spin > 1) return GPQMC_EINVAL;
   if (!ctx->initialized) return GPQMC_ESTATE;
   const ChainHost& h = ctx->ch[chain];
+  if (h.tv && spin == 1) return fail(ctx, GPQMC_EINVAL, "t-V chains have one species (spin 0)");
   HIPCHK(hipStreamSynchronize(ctx->stream), "sync");
   const bool mirror = spin == 1 && h.ph;
   HIPCHK(hipMemcpy(G, ctx->ws + h.G64[mirror ? 0 : spin], (size_t)h.N * h.N * 8,
@@ -1424,7 +1516,7 @@ gpqmc_status gpqmc_get_trace(gpqmc_ctx* ctx, int32_t chain, double* ratios, doub
   const int nck = ctx->n_ck_pass();
   if (n_checkpoints) *n_checkpoints = nck;
   if (ratios)
-    HIPCHK(hipMemcpy(ratios, ctx->ws + h.tr_ratio, (size_t)ctx->n_slices * N * 2 * 8,
+    HIPCHK(hipMemcpy(ratios, ctx->ws + h.tr_ratio, (size_t)ctx->n_slices * h.nprop * 2 * 8,
                      hipMemcpyDeviceToHost), "ratios");
   if (greens)
     HIPCHK(hipMemcpy(greens, ctx->ws + h.tr_green, (size_t)nck * 2 * N * N * 8,

@@ -9,6 +9,7 @@ namespace gpqmc {
 
 constexpr int kThreads = 256;   // every kernel runs 256-thread workgroups (4 waves)
 constexpr int kBlock = 32;      // submatrix block of the flip scan (sites)
+constexpr int kMexp = 4;        // largest |site exponent| of D_l (t-V: bonds per site)
 constexpr int kSegMax = 64;     // largest delay rank: sites per scan segment
 constexpr int kMeasCols = 4;    // measurement record: sign, E/N, D, S_AFM
 constexpr int kMaxSites = 1024; // largest lattice
@@ -87,11 +88,14 @@ struct ChainDev {
   int N;                // sites
   int n[2];             // particles per spin (0 = up, 1 = down)
   int pad0;
-  // diagonal of D_l for spin sigma: d = dval[b][sigma][s] with b = 0 boundary
-  // (projector coupling lambda), 1 bulk (Hubbard coupling alpha), s = 0 for
-  // field +1 and 1 for field -1: exp(sigma_sign * c_b * s_sign).
-  double dval[2][2][2];
-  double delta[2][2][2];  // flip factor Delta = exp(-2 sigma c_b s) - 1, same indexing
+  // diagonal of D_l for spin sigma at a site with exponent m (the entry of
+  // mexp): d = dval[b][sigma][m + kMexp] = exp(sigma_sign * c_b * m), b = 0
+  // boundary (projector coupling lambda), 1 bulk (coupling alpha)
+  double dval[2][2][2 * kMexp + 1];
+  // flip factor Delta = exp(-2 sigma c_b s) - 1 of a field s (index 0: s = +1,
+  // 1: s = -1); for a t-V bond (i, j) the A end i takes sigma = up, the B end j
+  // sigma = down
+  double delta[2][2][2];
   double U_hub;           // Hubbard U (energy measurement)
   uint32_t key0, key1;    // Philox key (seed low word, seed high word ^ TAG_ACCEPT)
   uint32_t chain_id;
@@ -101,6 +105,17 @@ struct ChainDev {
   // sum_{l,i} c_l s_{l,i}, sgn W_1 = sgn W_0.  Every kernel that works per
   // (chain, spin) skips spin 1 of such a chain.
   int ph;
+  int nsp;              // species whose factors are propagated: 2, or 1 (particle-hole, t-V)
+  int tv;               // 1: spinless t-V model (bond fields; spin 0 only)
+  int n_bonds;          // t-V: bonds (proposals per slice); the Hubbard model: 0
+  double V;             // t-V: nearest-neighbour repulsion (energy measurement)
+  const int* bonds;     // t-V: n_bonds x 2 sites (A end, B end) in proposal order
+  const int* seg_start; // t-V: first bond of every scan segment (n_seg + 1 entries)
+  int n_seg;            // t-V: scan segments per slice
+  int8_t* mexp;         // n_slices x N site exponents of D_l: the HS field itself for the
+                        // Hubbard model; for t-V the sum over a site's bonds of
+                        // +s_b (A end) or -s_b (B end)
+  double* dflist;       // Delta of every accepted flip of the last segment, [spin][kSegMax]
   // Green's-function precision (float or double)
   void* G[2];           // equal-time Green's function in the current frame
   void* Gtmp[2];        // wrap intermediate
@@ -128,7 +143,7 @@ struct ChainDev {
   double* Xm[2];        // L R (n x n), inverted in place
   double* Ym[2];        // (L R)^{-1} L  (n x N)
   double* G64[2];       // last fresh Green's function (unscaled, at its checkpoint)
-  int8_t* field;        // n_slices x N
+  int8_t* field;        // n_slices x N HS fields (t-V: n_slices x n_bonds bond fields)
   const int8_t* eps;    // sublattice signs (N)
   ChainState* st;
   double* meas;         // records (sign, E/N, D, S_AFM), kMeasCols each
@@ -167,13 +182,13 @@ struct GemmEntry {
   int slot_stride;      // elements per stack slot
   int M, N, K;          // static sizes
   int lda, ldb, ldc, ldc2;
-  const int8_t* field;  // base of the chain's field
+  const int8_t* field;  // base of the chain's site exponents (ChainDev::mexp)
   int n_sites;
   int spin;
   ChainState* st;
   const int* dynK;      // if set, the chain's K is *dynK (the slice's accepted count)
   int sinv;             // the output row scaling uses D^{-1} (xor with GemmArgs::scale_inverse)
-  double dval[2][2];    // [b][s] diagonal of D for this spin (see ChainDev)
+  double dval[2][2 * kMexp + 1];   // [b][m + kMexp] diagonal of D for this spin (see ChainDev)
   const int* dynN;      // if set, the output has *dynN columns (the segment's accepted count)
   void* pad2;
 };

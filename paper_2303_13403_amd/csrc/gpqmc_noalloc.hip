@@ -29,8 +29,8 @@ using namespace gpqmc;
 
 namespace {
 
-constexpr size_t kScratchBytes = 256 * 1024;   // GemmEntry + up to 16368 output tiles
-constexpr size_t kTileOffset = 256;            // TileRef list after the (256-byte) entry
+constexpr size_t kScratchBytes = 256 * 1024;   // GemmEntry + up to 16352 output tiles
+constexpr size_t kTileOffset = 512;            // TileRef list after the entry (512-byte slot)
 constexpr int kMaxTiles = (int)((kScratchBytes - kTileOffset) / sizeof(TileRef));
 constexpr int kMaxDevices = 64;
 static_assert(sizeof(GemmEntry) <= kTileOffset, "the entry fits before the tile list");

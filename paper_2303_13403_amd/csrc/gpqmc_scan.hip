@@ -1411,6 +1411,16 @@ hipError_t launch_scan(int fp32, int fact, const ChainDev* c, int nc, const Ctl*
 
 namespace gpqmc {
 
+// fn(integral_constant<int, k>) for k = B .. E - 1, unrolled at compile time
+// (the register tile of the scan is indexed by constants only)
+template <int B, int E, typename Fn>
+__device__ __forceinline__ void static_for(Fn&& fn) {
+  if constexpr (B < E) {
+    fn(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(fn);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Factored engine, delay segments of up to kBlock (32) sites: one wave per
 // chain does the whole segment.
@@ -1430,22 +1440,34 @@ namespace gpqmc {
 // wave writes the packed L U factors (32 x 32 per spin) to the Z buffer.
 // k_wf then forms the Woodbury rows and k_segupd_f applies them.
 // ---------------------------------------------------------------------------
+template <bool TV>
 __global__ __launch_bounds__(64) void k_scan_f(const ChainDev* __restrict__ chains,
                                                const Ctl* __restrict__ ctl, int l, int M, int s0,
                                                int s1, int dir, int parity) {
   const ChainDev& C = chains[xcd_remap(blockIdx.x, gridDim.x)];
   ChainState* st = C.st;
   const int N = C.N, lane = threadIdx.x, s = lane >> 5, a = lane & 31;
-  if (s0 >= N) {   // uneven batch: this chain has no site in the segment
+  // proposals of a slice: sites [s0, s1) (Hubbard), or the bonds of the
+  // chain's scan segment s0 (t-V, two block rows per bond)
+  const int nprop = TV ? C.n_bonds : N;
+  if (TV ? s0 >= C.n_seg : s0 >= nprop) {   // this chain has no proposal in the segment
     if (lane == 0) st->fcount = 0;
     return;
   }
-  const int send = min(s1, N), nseg = send - s0;
+  if (TV) {
+    const int k = s0;
+    s0 = C.seg_start[k];
+    s1 = C.seg_start[k + 1];
+  }
+  const int send = min(s1, nprop), nseg = send - s0;
+  const int nrow = TV ? 2 * nseg : nseg;   // block rows (sites)
   constexpr int KB = kBlock;
   constexpr int KC = 16;          // k-chunk of the block formation
   __shared__ double u_s[KB];
-  __shared__ int8_t fs[KB];
-  __shared__ int8_t es[KB];       // sublattice signs of the segment's sites
+  __shared__ int8_t fs[KB];       // fields of the segment's proposals
+  __shared__ int8_t fs0[KB];      // the same before the scan
+  __shared__ int8_t es[KB];       // sublattice signs of the block's sites
+  __shared__ int srow[KB];        // site of every block row
   __shared__ int Fl[KB];
   __shared__ double dF[2][KB];    // Delta of every accepted flip, per spin
   // history rows X^{(t)}[j_t, S] (later the LU factors), and history columns
@@ -1456,7 +1478,7 @@ __global__ __launch_bounds__(64) void k_scan_f(const ChainDev* __restrict__ chai
   static_assert(2 * KC * KB <= 2 * KB * (KB + 1), "B staging fits in the column history");
 
   const int bnd = (l == 0 || l == M + 1) ? 0 : 1;
-  int8_t* frow = C.field + (size_t)l * N;
+  int8_t* frow = C.field + (size_t)l * nprop;
   const uint32_t sweep = (uint32_t)st->sweep;
   const bool force_reject = ctl->force_reject != 0;
   if (lane < nseg) {
@@ -1464,8 +1486,17 @@ __global__ __launch_bounds__(64) void k_scan_f(const ChainDev* __restrict__ chai
     philox4x32_10(c, C.key0, C.key1);
     u_s[lane] = uniform53(c[0], c[1]);
     fs[lane] = frow[s0 + lane];
-    es[lane] = C.eps[s0 + lane];
+    fs0[lane] = fs[lane];
   }
+  int my_site = 0;
+  if (a < nrow) {
+    my_site = TV ? C.bonds[2 * (s0 + (a >> 1)) + (a & 1)] : s0 + a;
+    if (s == 0) {
+      srow[a] = my_site;
+      es[a] = C.eps[my_site];
+    }
+  }
+  wave_sync();
   const bool ph = C.ph != 0;
 
   // ---- G_s[S,S] = 1 - A[S,:] B[S,:]^T, row a of spin s in g (with the
@@ -1478,8 +1509,8 @@ __global__ __launch_bounds__(64) void k_scan_f(const ChainDev* __restrict__ chai
     const GLOBAL double* __restrict__ Ab = gp((const double*)C.F[0][s][parity]);
     const GLOBAL double* __restrict__ Bb = gp((const double*)C.F[1][s][parity]);
     double* Bs = &hcol[0][0][0];   // [spin][k][c]
-    const bool row_ok = a < nseg && !(ph && s == 1);
-    const size_t ro = (size_t)(s0 + a) * nn;
+    const bool row_ok = a < nrow && s < C.nsp;
+    const size_t ro = (size_t)my_site * nn;
     for (int k0 = 0; k0 < nmax; k0 += KC) {
       double ar[KC];
 #pragma unroll
@@ -1530,6 +1561,70 @@ __global__ __launch_bounds__(64) void k_scan_f(const ChainDev* __restrict__ chai
   const double dl_d0 = C.delta[bnd][1][0], dl_d1 = C.delta[bnd][1][1];
   double* const trace_ratio = C.trace_ratio;
   int fc = 0, sign = st->sign, nacc = 0;
+  if constexpr (TV) {
+    // one rank-1 step of the block at row j with flip factor dl and ratio rl:
+    // X[j, S] to the history rows, X[S, j] to the history columns,
+    // G <- G - (dl / rl) G[:, j] X[j, :]
+    auto rank1 = [&](auto jc, double dl, double rl, double dl_other) {
+      constexpr int j = decltype(jc)::value;
+      const int t = fc;
+      if (a == j) {
+#pragma unroll
+        for (int q = 0; q < KB; q += 2) {
+          double2 v;
+          v.x = (q == j ? 1.0 : 0.0) - g[q];
+          v.y = (q + 1 == j ? 1.0 : 0.0) - g[q + 1];
+          *reinterpret_cast<double2*>(&hrow[s][t][q]) = v;
+        }
+      }
+      hcol[s][t][a] = (a == j ? 1.0 : 0.0) - g[j];
+      wave_sync();
+      const double cg = (dl / rl) * g[j];
+#pragma unroll
+      for (int q = 0; q < KB; q += 2) {
+        const double2 x2 = *reinterpret_cast<const double2*>(&hrow[s][t][q]);
+        g[q] -= cg * x2.x;
+        g[q + 1] -= cg * x2.y;
+      }
+      if (lane == 0) {
+        Fl[t] = j;
+        dF[0][t] = dl;
+        dF[1][t] = dl_other;
+      }
+      fc = t + 1;
+    };
+    // bond (i, j) = block rows (2t, 2t + 1): Delta_i = e^{-2 c s} - 1 (the up
+    // entry), Delta_j = e^{+2 c s} - 1 (the down entry); the ratio
+    // det(1 + Delta_F X[F, F]) is the product of two rank-1 ratios, the
+    // second taken after the first update
+    static_for<0, KB / 2>([&](auto tc) {
+      constexpr int t = decltype(tc)::value, p = 2 * t, q = 2 * t + 1;
+      if (t < nseg) {
+        const int si = fs[t] > 0 ? 0 : 1;
+        const double di = C.delta[bnd][0][si], dj = C.delta[bnd][1][si];
+        const double gpp = lane_value(g[p], p), gpq = lane_value(g[q], p);
+        const double gqp = lane_value(g[p], q), gqq = lane_value(g[q], q);
+        const double r1 = 1.0 + di * (1.0 - gpp);
+        const double r2 = 1.0 + dj * ((1.0 - gqq) - (di / r1) * gqp * gpq);
+        const double r = r1 * r2;
+        const bool accept = !force_reject && (u_s[t] < fabs(r));
+        if (lane == 0 && trace_ratio) {
+          trace_ratio[((size_t)l * nprop + s0 + t) * 2 + 0] = r;
+          trace_ratio[((size_t)l * nprop + s0 + t) * 2 + 1] = 0.0;
+        }
+        if (accept) {
+          if (!zero_delta) {
+            rank1(std::integral_constant<int, p>{}, di, r1, 0.0);
+            const double r2b = 1.0 + dj * (1.0 - lane_value(g[q], q));
+            rank1(std::integral_constant<int, q>{}, dj, r2b, 0.0);
+          }
+          if (lane == 0) fs[t] = (int8_t)(-fs[t]);
+          if (r < 0) sign = -sign;
+          nacc += 1;
+        }
+      }
+    });
+  } else {
 #pragma unroll
   for (int j = 0; j < KB; ++j) {
     if (j < nseg) {
@@ -1578,10 +1673,23 @@ __global__ __launch_bounds__(64) void k_scan_f(const ChainDev* __restrict__ chai
       }
     }
   }
+  }
   wave_sync();
   const int f = fc;
   if (lane < nseg) frow[s0 + lane] = fs[lane];
-  if (lane < f) C.flist[lane] = s0 + Fl[lane];
+  if constexpr (TV) {
+    // site exponents of the flipped bonds: the A end changes by -2 s_old, the
+    // B end by +2 s_old
+    if (s == 0 && a < nrow) {
+      const int8_t so = fs0[a >> 1];
+      if (fs[a >> 1] != so) {
+        int8_t* m = C.mexp + (size_t)l * N + srow[a];
+        *m = (int8_t)(*m + ((a & 1) ? 2 * so : -2 * so));
+      }
+    }
+  }
+  if (lane < f) C.flist[lane] = srow[Fl[lane]];
+  if (s < C.nsp && a < f) C.dflist[s * kSegMax + a] = dF[s][a];
   if (lane == 0) {
     st->fcount = f;
     st->foff = 0;
@@ -1616,7 +1724,7 @@ __global__ __launch_bounds__(64) void k_scan_f(const ChainDev* __restrict__ chai
     wave_sync();
   }
   // LU[s][u][v] (U on and above the diagonal, L below) to the chain's Z buffer
-  {
+  if (s < C.nsp) {
     typedef double v2 __attribute__((ext_vector_type(2)));
     GLOBAL double* __restrict__ z = gp((double*)C.Z[s]) + (size_t)a * KB;
 #pragma unroll
@@ -1639,8 +1747,8 @@ __global__ __launch_bounds__(128) void k_wf(const ChainDev* __restrict__ chains,
   const int cs = xcd_remap(blockIdx.x, gridDim.x), sp = cs & 1;
   const ChainDev& C = chains[cs >> 1];
   const int f = C.st->fcount;
-  if (f == 0 || (sp == 1 && C.ph)) return;
-  const int N = C.N, nn = C.n[sp], tid = threadIdx.x;
+  if (f == 0 || sp >= C.nsp) return;
+  const int nn = C.n[sp], tid = threadIdx.x;
   __shared__ __align__(16) double LU[KB][KB];   // U on and above the diagonal, L below
   __shared__ __align__(16) double LT[KB][KB];   // its transpose
   __shared__ int Fs[KB];
@@ -1652,11 +1760,8 @@ __global__ __launch_bounds__(128) void k_wf(const ChainDev* __restrict__ chains,
     LT[idx % KB][idx / KB] = v;
   }
   if (tid < f) {
-    const int site = C.flist[tid];
-    const int bnd = (l == 0 || l == M + 1) ? 0 : 1;
-    const int si_old = C.field[(size_t)l * N + site] < 0 ? 0 : 1;   // the field is flipped
-    Fs[tid] = site;
-    dF[tid] = C.delta[bnd][sp][si_old];
+    Fs[tid] = C.flist[tid];
+    dF[tid] = C.dflist[sp * kSegMax + tid];
   }
   __syncthreads();
   // one substitution step j: y_j final (divided by the pivot when piv), then
@@ -1747,7 +1852,7 @@ __global__ __launch_bounds__(kUpdThreads) void k_segupd_f(const ChainDev* __rest
   const ChainDev& C = chains[cs >> 1];
   const int N = C.N, nn = C.n[sp], tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int f = C.st->fcount;
-  if (f == 0 || (sp == 1 && C.ph)) return;
+  if (f == 0 || sp >= C.nsp) return;
   __shared__ __align__(16) double Ms[KB * LDM];
   __shared__ __align__(16) double Ws[KB * LDW];
   __shared__ __align__(16) double Ps[kUpdWaves * 16 * LDP];   // P of every wave
@@ -1841,9 +1946,12 @@ __global__ __launch_bounds__(kUpdThreads) void k_segupd_f(const ChainDev* __rest
   }
 }
 
-hipError_t launch_scan_f(const ChainDev* c, int nc, const Ctl* ctl, int l, int M, int s0, int s1,
-                         int dir, int parity, hipStream_t s) {
-  hipLaunchKernelGGL(k_scan_f, dim3(nc), dim3(64), 0, s, c, ctl, l, M, s0, s1, dir, parity);
+hipError_t launch_scan_f(int tv, const ChainDev* c, int nc, const Ctl* ctl, int l, int M, int s0,
+                         int s1, int dir, int parity, hipStream_t s) {
+  if (tv)
+    hipLaunchKernelGGL(k_scan_f<true>, dim3(nc), dim3(64), 0, s, c, ctl, l, M, s0, s1, dir, parity);
+  else
+    hipLaunchKernelGGL(k_scan_f<false>, dim3(nc), dim3(64), 0, s, c, ctl, l, M, s0, s1, dir, parity);
   if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
   hipLaunchKernelGGL(k_wf, dim3(2 * nc), dim3(128), 0, s, c, l, M, dir, parity);
   return hipGetLastError();

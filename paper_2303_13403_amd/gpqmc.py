@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgpqmc.so
 
 OK, EINVAL, ENOMEM, EHIP, EDEGENERATE, EUNSTABLE, ESTATE = 0, -1, -2, -3, -4, -5, -6
 FP64, MIXED, MIXED_FP32_BASIS, FP64_WRAP = 0, 1, 2, 3
+MODEL_HUBBARD, MODEL_TV = 0, 1
 _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EDEGENERATE",
            -5: "EUNSTABLE", -6: "ESTATE"}
 
@@ -31,6 +32,8 @@ class ChainDesc(ctypes.Structure):
         ("l_half", ctypes.c_int32), ("stab_interval", ctypes.c_int32),
         ("delay_rank", ctypes.c_int32), ("precision", ctypes.c_int32),
         ("seed", ctypes.c_uint64), ("chain_id", ctypes.c_uint64), ("trace", ctypes.c_int32),
+        ("model", ctypes.c_int32), ("V", ctypes.c_double), ("n_bonds", ctypes.c_int32),
+        ("bonds", ctypes.POINTER(ctypes.c_int32)),
     ]
 
 
@@ -124,7 +127,16 @@ def _dptr(a):
 
 
 def chain_desc_arrays(w, chain_id: int, precision: int, trace: bool = False, seed=None):
-    """Host arrays of one chain described by a workloads.Workload."""
+    """Host arrays of one chain described by a workloads.Workload (Hubbard) or
+    workloads.TVWorkload (spinless t-V)."""
+    if hasattr(w, "V"):
+        K, eps, bonds = w.lattice()
+        return dict(K=np.ascontiguousarray(K, np.float64), eps=np.ascontiguousarray(eps, np.int8),
+                    pot=None, n_up=w.n_particles, n_dn=0, U=0.0, dtau=w.dtau, g=w.g,
+                    m_neel=w.delta_c, l_half=w.l_half, n_s=w.stab_interval, k=w.delay_rank,
+                    precision=precision, seed=w.seed if seed is None else seed,
+                    chain_id=chain_id, trace=trace, model=MODEL_TV, V=w.V,
+                    bonds=np.ascontiguousarray(bonds, np.int32))
     K, eps, _ = w.lattice()
     pot = w.trial_potential()
     return dict(K=np.ascontiguousarray(K, np.float64), eps=np.ascontiguousarray(eps, np.int8),
@@ -170,7 +182,17 @@ class Context:
             d.precision = c["precision"]
             d.seed, d.chain_id = int(c["seed"]), int(c["chain_id"])
             d.trace = 1 if c.get("trace") else 0
+            d.model = c.get("model", MODEL_HUBBARD)
+            if d.model == MODEL_TV:
+                bonds = np.ascontiguousarray(c["bonds"], np.int32)
+                self._keep.append(bonds)
+                d.V = c["V"]
+                d.n_bonds = len(bonds)
+                d.bonds = bonds.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
         self.n_chains = len(chains)
+        # HS fields per slice: sites, or bonds (t-V)
+        self.nprop = [len(c["bonds"]) if c.get("model", MODEL_HUBBARD) == MODEL_TV
+                      else np.asarray(c["K"]).shape[0] for c in chains]
         self.sizes = [(descs[i].n_sites, descs[i].n_up, descs[i].n_dn) for i in range(len(chains))]
         self.l_half = descs[0].l_half
         self.n_slices = 2 * self.l_half + 2
@@ -250,13 +272,12 @@ class Context:
 
     # -- state and testing hooks ----------------------------------------------------
     def set_field(self, chain: int, field):
-        N = self.sizes[chain][0]
-        f = np.ascontiguousarray(np.asarray(field, np.int8).reshape(self.n_slices, N))
+        f = np.ascontiguousarray(np.asarray(field, np.int8).reshape(self.n_slices,
+                                                                     self.nprop[chain]))
         self._call("gpqmc_set_field", chain, f.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)))
 
     def get_field(self, chain: int) -> np.ndarray:
-        N = self.sizes[chain][0]
-        f = np.zeros((self.n_slices, N), np.int8)
+        f = np.zeros((self.n_slices, self.nprop[chain]), np.int8)
         self._call("gpqmc_get_field", chain, f.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)))
         return f
 
@@ -295,11 +316,12 @@ class Context:
         self._call("gpqmc_set_debug", 1 if force_reject else 0)
 
     def trace(self, chain: int):
-        """(ratios (M+2, N, 2), greens (n_ck, 2, N, N), drifts (n_ck,)) of the last pass."""
+        """(ratios (M+2, P, 2), greens (n_ck, 2, N, N), drifts (n_ck,)) of the last
+        pass; P = N sites (Hubbard: r_up, r_dn) or the bonds (t-V: r, 0)."""
         N = self.sizes[chain][0]
         nck = ctypes.c_int32()
         self._call("gpqmc_get_trace", chain, None, None, None, ctypes.byref(nck))
-        r = np.zeros((self.n_slices, N, 2), np.float64)
+        r = np.zeros((self.n_slices, self.nprop[chain], 2), np.float64)
         g = np.zeros((nck.value, 2, N, N), np.float64)
         d = np.zeros(nck.value, np.float64)
         self._call("gpqmc_get_trace", chain, _dptr(r), _dptr(g), _dptr(d), ctypes.byref(nck))
