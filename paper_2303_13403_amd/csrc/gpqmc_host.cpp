@@ -41,6 +41,7 @@ hipError_t launch_dscale_f(const ChainDev* c, int nc, int l, int M, int parity, 
                            hipStream_t s);
 hipError_t launch_scan_f(int tv, const ChainDev* c, int nc, const Ctl* ctl, int l, int M, int s0, int s1,
                          int dir, int parity, hipStream_t s);
+hipError_t launch_wf(const ChainDev* c, int nc, int dir, int parity, hipStream_t s);
 hipError_t launch_segupd_f(const ChainDev* c, int nc, int n_max, int dir, int parity, hipStream_t s);
 hipError_t launch_dscale_u(int fp32b, const ChainDev* c, int nc, int l, int M, int parity,
                            hipStream_t s);
@@ -472,10 +473,14 @@ struct Launcher {
            })) != hipSuccess)
         return e;
       if (fast_upd) {
+        // the fused update forms Mf and Wf itself
         if ((e = timed(tupd, [&] { return launch_segupd_f(chains, nc, ctx->n_max, dir, parity, s); })) !=
             hipSuccess)
           return e;
       } else {
+        if (fast_scan && (e = timed(tscan, [&] { return launch_wf(chains, nc, dir, parity, s); })) !=
+                             hipSuccess)
+          return e;
         if ((e = gemm(dir == 0 ? E_SEGP_UP : E_SEGP_DN, GM_SEGP, T_Nk, a)) != hipSuccess) return e;
         if ((e = gemm(dir == 0 ? E_SEGF_UP : E_SEGF_DN, GM_SEGF, T_Nn, a)) != hipSuccess) return e;
       }

@@ -1440,6 +1440,69 @@ __device__ __forceinline__ void static_for(Fn&& fn) {
 // wave writes the packed L U factors (32 x 32 per spin) to the Z buffer.
 // k_wf then forms the Woodbury rows and k_segupd_f applies them.
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// Block of a scan segment, G_s[S, S] = 1 - A[S, :] B[S, :]^T for every chain
+// and propagated spin (S: the sites [s0, s1), or for the t-V model the ends of
+// the bonds of the chain's segment s0), to the chain's scan buffer as a
+// 32 x 32 row-major block with identity padding beyond the segment.  One
+// workgroup of four waves per chain and spin; wave w forms the 16 x 16 tile
+// (rows 16 (w / 2), columns 16 (w % 2)) on MFMA with its operands loaded
+// straight from memory, all loads of a 128-column chunk in flight at once.
+// (Formed inside the one-wave scan, the same block kept a single wave per
+// SIMD waiting on its loads.)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_block(const ChainDev* __restrict__ chains, int tv, int s0,
+                                               int s1, int parity) {
+  const int cs = xcd_remap(blockIdx.x, gridDim.x), sp = cs & 1;
+  const ChainDev& C = chains[cs >> 1];
+  if (sp >= C.nsp) return;
+  const int N = C.N, nn = C.n[sp];
+  const int nprop = tv ? C.n_bonds : N;
+  int b0 = s0, b1 = s1;
+  if (tv) {
+    if (s0 >= C.n_seg) return;
+    b0 = C.seg_start[s0];
+    b1 = C.seg_start[s0 + 1];
+  } else if (s0 >= N) {
+    return;
+  }
+  const int nseg = min(b1, nprop) - b0, nrow = tv ? 2 * nseg : nseg;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, l16 = lane & 15, g = lane >> 4;
+  const int tm = wave >> 1, tn = wave & 1;
+  const int ra = 16 * tm + l16, rc = 16 * tn + l16;
+  auto site = [&](int r) { return tv ? C.bonds[2 * (b0 + (r >> 1)) + (r & 1)] : b0 + r; };
+  const bool oka = ra < nrow, okc = rc < nrow;
+  const GLOBAL double* __restrict__ Ar =
+      gp((const double*)C.F[0][sp][parity]) + (oka ? (size_t)site(ra) * nn : 0);
+  const GLOBAL double* __restrict__ Br =
+      gp((const double*)C.F[1][sp][parity]) + (okc ? (size_t)site(rc) * nn : 0);
+  // D[m][n] = sum_k A[S_(16 tm + m)][k] B[S_(16 tn + n)][k]; the k-step st of a
+  // chunk takes k = k0 + 4 st + g in lane group g; lane (l16, g) receives
+  // D[g + 4 i][l16]
+  doublex4 acc;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) acc[i] = 0.0;
+  constexpr int CH = 32;
+  for (int k0 = 0; k0 < nn; k0 += 4 * CH) {
+    double av[CH], bv[CH];
+#pragma unroll
+    for (int st = 0; st < CH; ++st) {
+      const int k = k0 + 4 * st + g;
+      av[st] = (oka && k < nn) ? Ar[k] : 0.0;
+      bv[st] = (okc && k < nn) ? Br[k] : 0.0;
+    }
+#pragma unroll
+    for (int st = 0; st < CH; ++st)
+      if (k0 + 4 * st < nn) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[st], bv[st], acc, 0, 0, 0);
+  }
+  GLOBAL double* __restrict__ blk = gp((double*)C.scan_ws[sp]);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int r = 16 * tm + g + 4 * i;
+    blk[(size_t)r * kBlock + rc] = (r == rc ? 1.0 : 0.0) - acc[i];
+  }
+}
+
 template <bool TV>
 __global__ __launch_bounds__(64) void k_scan_f(const ChainDev* __restrict__ chains,
                                                const Ctl* __restrict__ ctl, int l, int M, int s0,
@@ -1462,7 +1525,6 @@ __global__ __launch_bounds__(64) void k_scan_f(const ChainDev* __restrict__ chai
   const int send = min(s1, nprop), nseg = send - s0;
   const int nrow = TV ? 2 * nseg : nseg;   // block rows (sites)
   constexpr int KB = kBlock;
-  constexpr int KC = 16;          // k-chunk of the block formation
   __shared__ double u_s[KB];
   __shared__ int8_t fs[KB];       // fields of the segment's proposals
   __shared__ int8_t fs0[KB];      // the same before the scan
@@ -1471,11 +1533,9 @@ __global__ __launch_bounds__(64) void k_scan_f(const ChainDev* __restrict__ chai
   __shared__ int Fl[KB];
   __shared__ double dF[2][KB];    // Delta of every accepted flip, per spin
   // history rows X^{(t)}[j_t, S] (later the LU factors), and history columns
-  // X^{(t)}[S, j_t] (odd leading dimension: written by column); the block
-  // formation stages B through the column area first
+  // X^{(t)}[S, j_t] (odd leading dimension: written by column)
   __shared__ __align__(16) double hrow[2][KB][KB];
   __shared__ __align__(16) double hcol[2][KB][KB + 1];
-  static_assert(2 * KC * KB <= 2 * KB * (KB + 1), "B staging fits in the column history");
 
   const int bnd = (l == 0 || l == M + 1) ? 0 : 1;
   int8_t* frow = C.field + (size_t)l * nprop;
@@ -1499,43 +1559,19 @@ __global__ __launch_bounds__(64) void k_scan_f(const ChainDev* __restrict__ chai
   wave_sync();
   const bool ph = C.ph != 0;
 
-  // ---- G_s[S,S] = 1 - A[S,:] B[S,:]^T, row a of spin s in g (with the
-  // particle-hole shortcut only spin 0 is formed from its factors) ----
+  // ---- G_s[S,S] = 1 - A[S,:] B[S,:]^T (formed by k_block), row a of spin s
+  // in g; with the particle-hole shortcut spin 1 is mirrored below ----
   double g[KB];
-#pragma unroll
-  for (int c = 0; c < KB; ++c) g[c] = 0.0;
   {
-    const int nn = C.n[s], nmax = max(C.n[0], C.n[1]);
-    const GLOBAL double* __restrict__ Ab = gp((const double*)C.F[0][s][parity]);
-    const GLOBAL double* __restrict__ Bb = gp((const double*)C.F[1][s][parity]);
-    double* Bs = &hcol[0][0][0];   // [spin][k][c]
-    const bool row_ok = a < nrow && s < C.nsp;
-    const size_t ro = (size_t)my_site * nn;
-    for (int k0 = 0; k0 < nmax; k0 += KC) {
-      double ar[KC];
+    typedef double v2 __attribute__((ext_vector_type(2)));
+    const GLOBAL double* __restrict__ blk = gp((const double*)C.scan_ws[s]) + (size_t)a * KB;
+    const bool ok = s < C.nsp;
 #pragma unroll
-      for (int kk = 0; kk < KC; ++kk) {
-        const int k = k0 + kk;
-        const bool ok = row_ok && k < nn;
-        ar[kk] = ok ? Ab[ro + k] : 0.0;
-        Bs[(s * KC + kk) * KB + a] = ok ? Bb[ro + k] : 0.0;
-      }
-      wave_sync();
-#pragma unroll
-      for (int kk = 0; kk < KC; ++kk) {
-        const double* brow = Bs + (s * KC + kk) * KB;
-#pragma unroll
-        for (int c = 0; c < KB; c += 2) {
-          const double2 b2 = *reinterpret_cast<const double2*>(brow + c);
-          g[c] -= ar[kk] * b2.x;
-          g[c + 1] -= ar[kk] * b2.y;
-        }
-      }
-      wave_sync();
+    for (int c = 0; c < KB; c += 2) {
+      const v2 v = ok ? *reinterpret_cast<const GLOBAL v2*>(blk + c) : v2{0.0, 0.0};
+      g[c] = ok ? v.x : (c == a ? 1.0 : 0.0);
+      g[c + 1] = ok ? v.y : (c + 1 == a ? 1.0 : 0.0);
     }
-#pragma unroll
-    for (int c = 0; c < KB; ++c)
-      if (c == a) g[c] += 1.0;
   }
   if (ph) {
     // G_1[a][c] = delta_ac - eps_a eps_c G_0[c][a]: spin-0 lane c stores its
@@ -1701,7 +1737,12 @@ __global__ __launch_bounds__(64) void k_scan_f(const ChainDev* __restrict__ chai
   if (f == 0) return;
 
   // ---- K = Delta_F^{-1} + X_s[F,F] = L U: lane (s, u) assembles row u ----
+  // the reciprocal pivots 1 / U[v][v], one per lane
+  __shared__ double pinv[2][KB];
   {
+    const double dinv = a < f ? 1.0 / dF[s][a] : 0.0;
+    if (a < f) pinv[s][a] = 1.0 / (hrow[s][a][Fl[a]] + dinv);
+    wave_sync();
     double lu[KB];
     const int ju = a < f ? Fl[a] : 0;
 #pragma unroll
@@ -1709,10 +1750,9 @@ __global__ __launch_bounds__(64) void k_scan_f(const ChainDev* __restrict__ chai
       double x = (v == a) ? 1.0 : 0.0;   // identity padding beyond f
       if (a < f && v < f) {
         if (v < a) {
-          const double piv = hrow[s][v][Fl[v]] + 1.0 / dF[s][v];
-          x = hcol[s][v][ju] / piv;
+          x = hcol[s][v][ju] * pinv[s][v];
         } else {
-          x = hrow[s][a][Fl[v]] + (v == a ? 1.0 / dF[s][a] : 0.0);
+          x = hrow[s][a][Fl[v]] + (v == a ? dinv : 0.0);
         }
       }
       lu[v] = x;
@@ -1723,131 +1763,124 @@ __global__ __launch_bounds__(64) void k_scan_f(const ChainDev* __restrict__ chai
       *reinterpret_cast<double2*>(&hrow[s][a][v]) = make_double2(lu[v], lu[v + 1]);
     wave_sync();
   }
-  // LU[s][u][v] (U on and above the diagonal, L below) to the chain's Z buffer
+  // ---- the Woodbury core Z = K^{-1} = U^{-1} L^{-1}: lane (s, c) forms
+  // column c (L y = e_c forward, then U z = y backward, over the f accepted
+  // flips; beyond f, K and Z are the identity) and writes it to the chain's
+  // Z buffer (row-major, 32 x 32) ----
   if (s < C.nsp) {
-    typedef double v2 __attribute__((ext_vector_type(2)));
-    GLOBAL double* __restrict__ z = gp((double*)C.Z[s]) + (size_t)a * KB;
+    double zc[KB];
 #pragma unroll
-    for (int v = 0; v < KB; v += 2)
-      *reinterpret_cast<GLOBAL v2*>(z + v) = *reinterpret_cast<const v2*>(&hrow[s][a][v]);
+    for (int i = 0; i < KB; ++i) {
+      double v = (i == a) ? 1.0 : 0.0;
+      if (i < f && a < f) {
+        const double* row = &hrow[s][i][0];
+#pragma unroll
+        for (int j = 0; j < i; ++j) v -= row[j] * zc[j];
+      }
+      zc[i] = v;
+    }
+#pragma unroll
+    for (int i = KB - 1; i >= 0; --i) {
+      if (i < f && a < f) {
+        const double* row = &hrow[s][i][0];
+        double v = zc[i];
+#pragma unroll
+        for (int j = i + 1; j < KB; ++j)
+          if (j < f) v -= row[j] * zc[j];
+        zc[i] = v * pinv[s][i];
+      }
+    }
+    GLOBAL double* __restrict__ z = gp((double*)C.Z[s]);
+#pragma unroll
+    for (int i = 0; i < KB; ++i) z[(size_t)i * KB + a] = zc[i];
   }
 }
 
 // ---------------------------------------------------------------------------
-// Woodbury rows of a segment (factored engine, after k_scan_f), one workgroup
-// per chain and spin, a thread per column k of the factors: Mf = M[F, k] (the
-// moving factor's rows at the accepted sites, then scaled by 1 + Delta_F),
-// and Wf = Z^T Q[F, k] (upward) or Z Q[F, k] (downward) with Z = (L U)^{-1}
-// from the LU factors the scan left in the Z buffer.  Delta_F follows from
-// the flipped fields of slice l.
+// Woodbury rows of a segment for the general segment update (N_sigma > 128;
+// factored engine, after k_scan_f), one workgroup per chain and spin, a thread
+// per column k of the factors: Mf = M[F, k] (the moving factor's rows at the
+// accepted sites, which are then scaled by 1 + Delta_F), and Wf = Z^T Q[F, k]
+// (upward) or Z Q[F, k] (downward) with the Woodbury core Z = K^{-1} the scan
+// left in the Z buffer.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(128) void k_wf(const ChainDev* __restrict__ chains, int l, int M,
-                                            int dir, int parity) {
+__global__ __launch_bounds__(128) void k_wf(const ChainDev* __restrict__ chains, int dir,
+                                            int parity) {
   constexpr int KB = kBlock;
   const int cs = xcd_remap(blockIdx.x, gridDim.x), sp = cs & 1;
   const ChainDev& C = chains[cs >> 1];
   const int f = C.st->fcount;
   if (f == 0 || sp >= C.nsp) return;
   const int nn = C.n[sp], tid = threadIdx.x;
-  __shared__ __align__(16) double LU[KB][KB];   // U on and above the diagonal, L below
-  __shared__ __align__(16) double LT[KB][KB];   // its transpose
+  __shared__ double Zs[KB][KB + 1];   // Zs[p][q]: coefficient of Q[F_q] in Wf row p
   __shared__ int Fs[KB];
   __shared__ double dF[KB];
   const GLOBAL double* __restrict__ z = gp((const double*)C.Z[sp]);
   for (int idx = tid; idx < KB * KB; idx += 128) {
-    const double v = z[idx];
-    LU[idx / KB][idx % KB] = v;
-    LT[idx % KB][idx / KB] = v;
+    const int r = idx / KB, c = idx % KB;
+    if (dir == 0)
+      Zs[c][r] = z[idx];
+    else
+      Zs[r][c] = z[idx];
   }
   if (tid < f) {
     Fs[tid] = C.flist[tid];
     dF[tid] = C.dflist[sp * kSegMax + tid];
   }
   __syncthreads();
-  // one substitution step j: y_j final (divided by the pivot when piv), then
-  // y_i -= row[i] y_j for the later (fwd) or earlier unknowns; row is one
-  // contiguous LDS row, read with 128-bit loads
-  auto step = [](double (&y)[KB], const double* row, int j, bool piv, bool fwd) {
-    double r[KB];
-#pragma unroll
-    for (int c = 0; c < KB; c += 2) {
-      const double2 v = *reinterpret_cast<const double2*>(row + c);
-      r[c] = v.x;
-      r[c + 1] = v.y;
-    }
-    const double yj = piv ? y[j] / r[j] : y[j];
-    y[j] = yj;
-#pragma unroll
-    for (int i = 0; i < KB; ++i)
-      if (fwd ? i > j : i < j) y[i] -= r[i] * yj;
-    __builtin_amdgcn_sched_barrier(0);
-  };
   GLOBAL double* __restrict__ Mv = gp((double*)C.F[dir][sp][parity]);
   const GLOBAL double* __restrict__ Qv = gp((const double*)C.F[1 - dir][sp][parity]);
   GLOBAL double* __restrict__ mf = gp(C.Mf[sp]);
   GLOBAL double* __restrict__ wf = gp(C.Wf[sp]);
   for (int k = tid; k < nn; k += 128) {
+#pragma unroll 4
+    for (int p = 0; p < f; ++p) {
+      const size_t o = (size_t)Fs[p] * nn + k;
+      const double v = Mv[o];
+      mf[(size_t)p * nn + k] = v;
+      Mv[o] = v * (1.0 + dF[p]);
+    }
     double y[KB];
 #pragma unroll
-    for (int p = 0; p < KB; ++p) {
-      y[p] = 0.0;
-      if (p < f) {
-        const size_t o = (size_t)Fs[p] * nn + k;
-        const double v = Mv[o];
-        mf[(size_t)p * nn + k] = v;
-        Mv[o] = v * (1.0 + dF[p]);
-        y[p] = Qv[o];
-      }
+    for (int q = 0; q < KB; ++q) y[q] = q < f ? Qv[(size_t)Fs[q] * nn + k] : 0.0;
+#pragma unroll 1
+    for (int p = 0; p < f; ++p) {
+      double w = 0.0;
+#pragma unroll
+      for (int q = 0; q < KB; ++q) w += Zs[p][q] * y[q];
+      wf[(size_t)p * nn + k] = w;
     }
-    if (dir == 0) {
-      // Wf = Z^T Q_F = L^{-T} U^{-T} Q_F: U^T y = y forward (step j uses row
-      // j of U), then L^T y = y backward (row j of L)
-#pragma unroll
-      for (int jj = 0; jj < KB; ++jj) step(y, LU[jj], jj, true, true);
-#pragma unroll
-      for (int jj = KB - 1; jj >= 0; --jj) step(y, LU[jj], jj, false, false);
-    } else {
-      // Wf = Z Q_F = U^{-1} L^{-1} Q_F: L y = y forward (column j of L),
-      // then U y = y backward (column j of U)
-#pragma unroll
-      for (int jj = 0; jj < KB; ++jj) step(y, LT[jj], jj, false, true);
-#pragma unroll
-      for (int jj = KB - 1; jj >= 0; --jj) step(y, LT[jj], jj, true, false);
-    }
-#pragma unroll
-    for (int p = 0; p < KB; ++p)
-      if (p < f) wf[(size_t)p * nn + k] = y[p];
   }
 }
 
 // ---------------------------------------------------------------------------
 // Segment update of the dual factor, Q <- Q - (Q Mf^T) Wf (Q: N x n, Mf and
 // Wf: f x n, f <= 32, n <= 128), on MFMA (v_mfma_f64_16x16x4f64).  One
-// workgroup per chain and spin stages Mf and Wf in LDS once (zero-padded to
-// 32 rows and 128 columns) and walks the rows of Q in tiles of 256, 16 per
-// wave (16 waves, four per SIMD, so one wave's loads overlap another's
-// MFMA work).  Lane l
-// (row l % 16, g = l / 16) holds Q[row][16 b + g + 4 i] for every 16-column
-// block b and i = 0..3:
-//   P = Q_tile Mf^T: the k-steps of block b are k = 16 b + 4 i + {0..3} over
-//     the lane groups, so x[b][i] is the A operand of step i as loaded;
-//   P goes through LDS to become the B operand of C^T = Wf^T P^T, whose
-//     16 x 16 output block b has lane l holding C^T[16 b + 4 i + g][l % 16],
-//     the update of exactly x[b][i].
-// Q is read and written once, each row as whole 32-byte pieces.
-// Grid: chains x 2 spins.
+// workgroup of 8 waves per chain and spin stages Mf and Wf in LDS once
+// (zero-padded to 32 rows and 128 columns; 70 KB, so two workgroups share a
+// CU and one's staging overlaps the other's streaming) and walks the rows of
+// Q in tiles of 128, 16 per wave.  Q is read and written once, each row as
+// whole 32-byte pieces.  Grid: chains x 2 spins.
 // ---------------------------------------------------------------------------
-constexpr int kUpdWaves = 16;               // waves per workgroup
+constexpr int kUpdWaves = 8;                // waves per workgroup (two workgroups per CU)
 constexpr int kUpdThreads = 64 * kUpdWaves;
 constexpr int kUpdRows = 16 * kUpdWaves;     // rows of Q per tile (16 per wave)
 
-__global__ __launch_bounds__(kUpdThreads) void k_segupd_f(const ChainDev* __restrict__ chains,
-                                                          int dir, int parity) {
+// Lane (l16, g) = (lane % 16, lane / 16) keeps x[bb][i] = Q[row][16 bb + g + 4 i]
+// of its row.  The v_mfma_f64_16x16x4f64 result holds D[g + 4 i][l16] in lane
+// (l16, g).  First product, P^T = Mf Q^T (A = Mf rows from LDS, B = the row's
+// Q values): lane (l16, g) receives P[row][16 jb + g + 4 r], which is exactly
+// its B operand of the second product Out^T = Wf^T P^T (k slot g of step
+// (jb, r) = flip 16 jb + g + 4 r), whose result D[g + 4 i][l16] =
+// Out[row][16 bb + g + 4 i] lands on x[bb][i].  P never leaves the registers.
+// Strides: Mf rows 130 doubles (A reads of a half-wave hit banks 4 l16 + 2 g),
+// Wf rows 144 (banks 2 l16 + 32 g): both conflict-free.
+__global__ __launch_bounds__(kUpdThreads) __attribute__((amdgpu_waves_per_eu(4)))
+void k_segupd_f(const ChainDev* __restrict__ chains, int dir, int parity) {
   constexpr int KB = kBlock;
   constexpr int NB = 8;                  // 16-column blocks of Q (n <= 128)
-  constexpr int LDM = NB * 16 + 1;       // Mf rows: odd stride (read by row in the MFMA)
-  constexpr int LDW = NB * 16;           // Wf rows
-  constexpr int LDP = KB + 1;
+  constexpr int LDM = NB * 16 + 2;
+  constexpr int LDW = NB * 16 + 16;
   const int cs = xcd_remap(blockIdx.x, gridDim.x), sp = cs & 1;
   const ChainDev& C = chains[cs >> 1];
   const int N = C.N, nn = C.n[sp], tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -1855,34 +1888,64 @@ __global__ __launch_bounds__(kUpdThreads) void k_segupd_f(const ChainDev* __rest
   if (f == 0 || sp >= C.nsp) return;
   __shared__ __align__(16) double Ms[KB * LDM];
   __shared__ __align__(16) double Ws[KB * LDW];
-  __shared__ __align__(16) double Ps[kUpdWaves * 16 * LDP];   // P of every wave
-  {
-    // all loads of the staging in flight at once, then the LDS stores
-    const GLOBAL double* __restrict__ mf = gp((const double*)C.Mf[sp]);
-    const GLOBAL double* __restrict__ wf = gp((const double*)C.Wf[sp]);
-    constexpr int NS = KB * LDW / kUpdThreads;
-    static_assert(NS * kUpdThreads == KB * LDW, "staging covers the tiles");
-    double vm[NS], vw[NS];
-#pragma unroll
-    for (int t = 0; t < NS; ++t) {
-      const int idx = tid + t * kUpdThreads, j = idx / LDW, k = idx - j * LDW;
-      const bool ok = j < f && k < nn;
-      vm[t] = ok ? mf[(size_t)j * nn + k] : 0.0;
-      vw[t] = ok ? wf[(size_t)j * nn + k] : 0.0;
-    }
-#pragma unroll
-    for (int t = 0; t < NS; ++t) {
-      const int idx = tid + t * kUpdThreads, j = idx / LDW, k = idx - j * LDW;
-      Ms[j * LDM + k] = vm[t];
-      Ws[j * LDW + k] = vw[t];
-    }
+  __shared__ int Fs[KB];
+  __shared__ double dFs[KB];
+  if (tid < f) {
+    Fs[tid] = C.flist[tid];
+    dFs[tid] = C.dflist[sp * kSegMax + tid];
   }
   __syncthreads();
-  const int nb = (nn + 15) / 16;
-  const int nks = (f + 3) / 4;
-  const int l16 = lane & 15, g = lane >> 4;
+  GLOBAL double* __restrict__ Mv = gp((double*)C.F[dir][sp][parity]);
   GLOBAL double* __restrict__ Qb = gp((double*)C.F[1 - dir][sp][parity]);
-  double* Pw = Ps + wave * 16 * LDP;
+  const int nb = (nn + 15) / 16;
+  const int njb = f > 16 ? 2 : 1;        // 16-flip blocks with accepted flips
+  const int l16 = lane & 15, g = lane >> 4;
+  {
+    // Mf = M[F, :] (the moving factor's rows at the accepted sites, zero-padded
+    // to 32 x 128) to LDS; those rows of M are then scaled by 1 + Delta_F.  All
+    // loads in flight at once, then the stores.
+    constexpr int NC = NB * 16;
+    constexpr int NS = KB * NC / kUpdThreads;
+    static_assert(NS * kUpdThreads == KB * NC, "staging covers the tiles");
+    double vm[NS];
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+      const int idx = tid + t * kUpdThreads, j = idx / NC, k = idx - j * NC;
+      vm[t] = (j < f && k < nn) ? Mv[(size_t)Fs[j] * nn + k] : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+      const int idx = tid + t * kUpdThreads, j = idx / NC, k = idx - j * NC;
+      Ms[j * LDM + k] = vm[t];
+      if (j < f && k < nn) Mv[(size_t)Fs[j] * nn + k] = vm[t] * (1.0 + dFs[j]);
+    }
+  }
+  {
+    // Wf = Z^T Q[F, :] (upward) or Z Q[F, :] (downward) on MFMA, 16 x 16
+    // tiles (flip block pb, column block cb) spread over the waves, from the
+    // rows of Q before any of them is updated; K = the accepted flips
+    const GLOBAL double* __restrict__ zg = gp((const double*)C.Z[sp]);
+    const int ntiles = njb * nb;
+    for (int t = wave; t < ntiles; t += kUpdWaves) {
+      const int pb = t / nb, cb = t - pb * nb, col = 16 * cb + l16;
+      doublex4 acc;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc[i] = 0.0;
+#pragma unroll
+      for (int st = 0; st < KB / 4; ++st) {
+        const int q = 4 * st + g;
+        const bool ok = q < f;
+        const double za = ok ? (dir == 0 ? zg[(size_t)q * KB + 16 * pb + l16]
+                                         : zg[(size_t)(16 * pb + l16) * KB + q])
+                             : 0.0;
+        const double qb = (ok && col < nn) ? Qb[(size_t)Fs[ok ? q : 0] * nn + col] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(za, qb, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) Ws[(16 * pb + g + 4 * i) * LDW + col] = acc[i];
+    }
+  }
+  __syncthreads();   // Q[F, :] read by every wave before any row of Q is updated
   for (int row = wave * 16 + l16; row - l16 < N; row += kUpdRows) {
     const bool rok = row < N;
     GLOBAL double* __restrict__ q = Qb + (size_t)row * nn;
@@ -1894,7 +1957,7 @@ __global__ __launch_bounds__(kUpdThreads) void k_segupd_f(const ChainDev* __rest
         const int k = 16 * bb + g + 4 * i;
         x[bb][i] = (rok && bb < nb && k < nn) ? q[k] : 0.0;
       }
-    // P = Q_tile Mf^T, two 16 x 16 blocks over the accepted flips
+    // P^T = Mf Q^T: pacc[jb][r] = P[row][16 jb + g + 4 r]
     doublex4 pacc[2];
 #pragma unroll
     for (int jb = 0; jb < 2; ++jb)
@@ -1905,37 +1968,34 @@ __global__ __launch_bounds__(kUpdThreads) void k_segupd_f(const ChainDev* __rest
       if (bb < nb) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const int k = 16 * bb + 4 * i + g;
+          const int k = 16 * bb + g + 4 * i;
 #pragma unroll
           for (int jb = 0; jb < 2; ++jb)
-            pacc[jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[bb][i], Ms[(16 * jb + l16) * LDM + k],
-                                                            pacc[jb], 0, 0, 0);
+            if (jb < njb)
+              pacc[jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(Ms[(16 * jb + l16) * LDM + k], x[bb][i],
+                                                              pacc[jb], 0, 0, 0);
         }
       }
     }
-    // P to LDS (element (4 r + g, 16 jb + l16) of the wave's 16 x 32 block)
-#pragma unroll
-    for (int jb = 0; jb < 2; ++jb)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) Pw[(4 * r + g) * LDP + 16 * jb + l16] = pacc[jb][r];
-    wave_sync();
-    // C^T = Wf^T P^T per 16-column block of Q; K = f in steps of 4
+    // Out^T = Wf^T P^T per 16-column block of Q, over the flips
 #pragma unroll
     for (int bb = 0; bb < NB; ++bb) {
       if (bb < nb) {
         doublex4 acc;
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc[r] = 0.0;
-        for (int ks = 0; ks < nks; ++ks) {
-          const int kk = 4 * ks + g;
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Ws[kk * LDW + 16 * bb + l16], Pw[l16 * LDP + kk],
-                                                     acc, 0, 0, 0);
-        }
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb)
+          if (jb < njb) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              acc = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                  Ws[(16 * jb + g + 4 * r) * LDW + 16 * bb + l16], pacc[jb][r], acc, 0, 0, 0);
+          }
 #pragma unroll
         for (int i = 0; i < 4; ++i) x[bb][i] -= acc[i];
       }
     }
-    wave_sync();   // P of this tile read before the next tile overwrites it
 #pragma unroll
     for (int bb = 0; bb < NB; ++bb)
 #pragma unroll
@@ -1948,12 +2008,17 @@ __global__ __launch_bounds__(kUpdThreads) void k_segupd_f(const ChainDev* __rest
 
 hipError_t launch_scan_f(int tv, const ChainDev* c, int nc, const Ctl* ctl, int l, int M, int s0,
                          int s1, int dir, int parity, hipStream_t s) {
+  hipLaunchKernelGGL(k_block, dim3(2 * nc), dim3(256), 0, s, c, tv, s0, s1, parity);
+  if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
   if (tv)
     hipLaunchKernelGGL(k_scan_f<true>, dim3(nc), dim3(64), 0, s, c, ctl, l, M, s0, s1, dir, parity);
   else
     hipLaunchKernelGGL(k_scan_f<false>, dim3(nc), dim3(64), 0, s, c, ctl, l, M, s0, s1, dir, parity);
-  if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
-  hipLaunchKernelGGL(k_wf, dim3(2 * nc), dim3(128), 0, s, c, l, M, dir, parity);
+  return hipGetLastError();
+}
+
+hipError_t launch_wf(const ChainDev* c, int nc, int dir, int parity, hipStream_t s) {
+  hipLaunchKernelGGL(k_wf, dim3(2 * nc), dim3(128), 0, s, c, dir, parity);
   return hipGetLastError();
 }
 
