@@ -1476,24 +1476,35 @@ __global__ __launch_bounds__(256) void k_block(const ChainDev* __restrict__ chai
       gp((const double*)C.F[0][sp][parity]) + (oka ? (size_t)site(ra) * nn : 0);
   const GLOBAL double* __restrict__ Br =
       gp((const double*)C.F[1][sp][parity]) + (okc ? (size_t)site(rc) * nn : 0);
-  // D[m][n] = sum_k A[S_(16 tm + m)][k] B[S_(16 tn + n)][k]; the k-step st of a
-  // chunk takes k = k0 + 4 st + g in lane group g; lane (l16, g) receives
-  // D[g + 4 i][l16]
+  // D[m][n] = sum_k A[S_(16 tm + m)][k] B[S_(16 tn + n)][k]; MFMA step (st, e)
+  // of a 128-column chunk takes k = k0 + 8 st + 2 g + e in lane group g, so
+  // each lane loads pairs of doubles and the four lanes of a row read 64
+  // contiguous bytes per load; lane (l16, g) receives D[g + 4 i][l16]
   doublex4 acc;
 #pragma unroll
   for (int i = 0; i < 4; ++i) acc[i] = 0.0;
-  constexpr int CH = 32;
-  for (int k0 = 0; k0 < nn; k0 += 4 * CH) {
-    double av[CH], bv[CH];
+  constexpr int CH = 16;   // (st) steps of 8 columns per chunk
+  typedef double v2 __attribute__((ext_vector_type(2)));
+  const bool vec = (nn & 1) == 0;   // rows start 16-byte aligned
+  for (int k0 = 0; k0 < nn; k0 += 8 * CH) {
+    v2 av[CH], bv[CH];
 #pragma unroll
     for (int st = 0; st < CH; ++st) {
-      const int k = k0 + 4 * st + g;
-      av[st] = (oka && k < nn) ? Ar[k] : 0.0;
-      bv[st] = (okc && k < nn) ? Br[k] : 0.0;
+      const int k = k0 + 8 * st + 2 * g;
+      if (vec && k + 1 < nn) {
+        av[st] = oka ? *reinterpret_cast<const GLOBAL v2*>(Ar + k) : v2{0.0, 0.0};
+        bv[st] = okc ? *reinterpret_cast<const GLOBAL v2*>(Br + k) : v2{0.0, 0.0};
+      } else {
+        av[st] = v2{(oka && k < nn) ? Ar[k] : 0.0, (oka && k + 1 < nn) ? Ar[k + 1] : 0.0};
+        bv[st] = v2{(okc && k < nn) ? Br[k] : 0.0, (okc && k + 1 < nn) ? Br[k + 1] : 0.0};
+      }
     }
 #pragma unroll
     for (int st = 0; st < CH; ++st)
-      if (k0 + 4 * st < nn) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[st], bv[st], acc, 0, 0, 0);
+      if (k0 + 8 * st < nn) {
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[st].x, bv[st].x, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[st].y, bv[st].y, acc, 0, 0, 0);
+      }
   }
   GLOBAL double* __restrict__ blk = gp((double*)C.scan_ws[sp]);
 #pragma unroll
