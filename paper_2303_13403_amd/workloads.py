@@ -253,9 +253,9 @@ class TVWorkload:
 # parameters for this model: Delta_C = 0.3 and g = 0.3 are a fixed choice.
 TV_WORKLOADS = {
     "tv15_V1.6": TVWorkload("t-V honeycomb 15x15 (450 sites) V=1.6 half filling Theta=5",
-                            15, 15, 1.6, 0.1, 50, 0.3, 0.3, 10, 32, 100),
+                            15, 15, 1.6, 0.1, 50, 0.3, 0.3, 5, 32, 100),
     "tv15_V1.35": TVWorkload("t-V honeycomb 15x15 (450 sites) V=1.35 half filling Theta=5",
-                             15, 15, 1.35, 0.1, 50, 0.3, 0.3, 10, 32, 100),
+                             15, 15, 1.35, 0.1, 50, 0.3, 0.3, 5, 32, 100),
     "tv6": TVWorkload("t-V honeycomb 6x6 (72 sites) V=1.6 half filling Theta=2",
                       6, 6, 1.6, 0.1, 20, 0.3, 0.3, 5, 32, 100),
 }
