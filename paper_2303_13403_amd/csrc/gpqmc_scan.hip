@@ -1867,37 +1867,41 @@ __global__ __launch_bounds__(128) void k_wf(const ChainDev* __restrict__ chains,
 // ---------------------------------------------------------------------------
 // Segment update of the dual factor, Q <- Q - (Q Mf^T) Wf (Q: N x n, Mf and
 // Wf: f x n, f <= 32, n <= 128), on MFMA (v_mfma_f64_16x16x4f64).  One
-// workgroup of 8 waves per chain and spin stages Mf and Wf in LDS once
-// (zero-padded to 32 rows and 128 columns; 70 KB, so two workgroups share a
-// CU and one's staging overlaps the other's streaming) and walks the rows of
-// Q in tiles of 128, 16 per wave.  Q is read and written once, each row as
-// whole 32-byte pieces.  Grid: chains x 2 spins.
+// workgroup of 8 waves per chain and spin stages Mf (transposed) and Wf in
+// LDS once (zero-padded to 32 flips and 128 columns; 74 KB, so two
+// workgroups share a CU and one's staging overlaps the other's streaming)
+// and walks the rows of Q in tiles of 128, 16 per wave.  Q is read and
+// written once, each lane moving 32 contiguous bytes of a row per column
+// block (two 16-byte accesses).  Grid: chains x 2 spins.
 // ---------------------------------------------------------------------------
 constexpr int kUpdWaves = 8;                // waves per workgroup (two workgroups per CU)
 constexpr int kUpdThreads = 64 * kUpdWaves;
 constexpr int kUpdRows = 16 * kUpdWaves;     // rows of Q per tile (16 per wave)
 
-// Lane (l16, g) = (lane % 16, lane / 16) keeps x[bb][i] = Q[row][16 bb + g + 4 i]
-// of its row.  The v_mfma_f64_16x16x4f64 result holds D[g + 4 i][l16] in lane
-// (l16, g).  First product, P^T = Mf Q^T (A = Mf rows from LDS, B = the row's
-// Q values): lane (l16, g) receives P[row][16 jb + g + 4 r], which is exactly
-// its B operand of the second product Out^T = Wf^T P^T (k slot g of step
-// (jb, r) = flip 16 jb + g + 4 r), whose result D[g + 4 i][l16] =
-// Out[row][16 bb + g + 4 i] lands on x[bb][i].  P never leaves the registers.
-// Strides: Mf rows 130 doubles (A reads of a half-wave hit banks 4 l16 + 2 g),
-// Wf rows 144 (banks 2 l16 + 32 g): both conflict-free.
+// Lane (l16, g) = (lane % 16, lane / 16) keeps x[bb][i] = Q[row][16 bb + 4 g + i]
+// of its row l16: the contraction order over the columns is free, so MFMA
+// step i of column block bb gives k slot g the column 16 bb + 4 g + i.  First
+// product, P^T = Mf Q^T (A = Mf from LDS, B = the row's Q values): lane
+// (l16, g) receives P[row][16 jb + g + 4 r], which is exactly its B operand
+// of the second product Out^T = Wf'^T P^T (k slot g of step (jb, r) = flip
+// 16 jb + g + 4 r; steps past the last flip are skipped).  The output rows
+// of the second product are the columns of Q permuted by
+// m = g' + 4 i' -> 4 g' + i', so its result D[g + 4 i][l16] lands on x[bb][i]
+// and P never leaves the registers.  LDS strides: Mf^T rows (one per column
+// of Q) 36 doubles, Wf rows 144: every operand read of a half-wave hits 32
+// distinct double slots.
 __global__ __launch_bounds__(kUpdThreads) __attribute__((amdgpu_waves_per_eu(4)))
 void k_segupd_f(const ChainDev* __restrict__ chains, int dir, int parity) {
   constexpr int KB = kBlock;
   constexpr int NB = 8;                  // 16-column blocks of Q (n <= 128)
-  constexpr int LDM = NB * 16 + 2;
+  constexpr int LDT = KB + 4;
   constexpr int LDW = NB * 16 + 16;
   const int cs = xcd_remap(blockIdx.x, gridDim.x), sp = cs & 1;
   const ChainDev& C = chains[cs >> 1];
   const int N = C.N, nn = C.n[sp], tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int f = C.st->fcount;
   if (f == 0 || sp >= C.nsp) return;
-  __shared__ __align__(16) double Ms[KB * LDM];
+  __shared__ __align__(16) double MsT[NB * 16 * LDT];
   __shared__ __align__(16) double Ws[KB * LDW];
   __shared__ int Fs[KB];
   __shared__ double dFs[KB];
@@ -1913,8 +1917,8 @@ void k_segupd_f(const ChainDev* __restrict__ chains, int dir, int parity) {
   const int l16 = lane & 15, g = lane >> 4;
   {
     // Mf = M[F, :] (the moving factor's rows at the accepted sites, zero-padded
-    // to 32 x 128) to LDS; those rows of M are then scaled by 1 + Delta_F.  All
-    // loads in flight at once, then the stores.
+    // to 32 x 128), stored transposed; those rows of M are then scaled by
+    // 1 + Delta_F.  All loads in flight at once, then the stores.
     constexpr int NC = NB * 16;
     constexpr int NS = KB * NC / kUpdThreads;
     static_assert(NS * kUpdThreads == KB * NC, "staging covers the tiles");
@@ -1927,7 +1931,7 @@ void k_segupd_f(const ChainDev* __restrict__ chains, int dir, int parity) {
 #pragma unroll
     for (int t = 0; t < NS; ++t) {
       const int idx = tid + t * kUpdThreads, j = idx / NC, k = idx - j * NC;
-      Ms[j * LDM + k] = vm[t];
+      MsT[k * LDT + j] = vm[t];
       if (j < f && k < nn) Mv[(size_t)Fs[j] * nn + k] = vm[t] * (1.0 + dFs[j]);
     }
   }
@@ -1957,6 +1961,9 @@ void k_segupd_f(const ChainDev* __restrict__ chains, int dir, int parity) {
     }
   }
   __syncthreads();   // Q[F, :] read by every wave before any row of Q is updated
+  typedef double v2 __attribute__((ext_vector_type(2)));
+  const bool vec = (nn & 1) == 0;        // rows start 16-byte aligned
+  const int cm = 4 * (l16 & 3) + (l16 >> 2);   // column of Q of output row l16
   for (int row = wave * 16 + l16; row - l16 < N; row += kUpdRows) {
     const bool rok = row < N;
     GLOBAL double* __restrict__ q = Qb + (size_t)row * nn;
@@ -1964,9 +1971,16 @@ void k_segupd_f(const ChainDev* __restrict__ chains, int dir, int parity) {
 #pragma unroll
     for (int bb = 0; bb < NB; ++bb)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int k = 16 * bb + g + 4 * i;
-        x[bb][i] = (rok && bb < nb && k < nn) ? q[k] : 0.0;
+      for (int h = 0; h < 2; ++h) {
+        const int k = 16 * bb + 4 * g + 2 * h;
+        if (vec && rok && k + 1 < nn) {
+          const v2 v = *reinterpret_cast<const GLOBAL v2*>(q + k);
+          x[bb][2 * h] = v.x;
+          x[bb][2 * h + 1] = v.y;
+        } else {
+          x[bb][2 * h] = (rok && k < nn) ? q[k] : 0.0;
+          x[bb][2 * h + 1] = (rok && k + 1 < nn) ? q[k + 1] : 0.0;
+        }
       }
     // P^T = Mf Q^T: pacc[jb][r] = P[row][16 jb + g + 4 r]
     doublex4 pacc[2];
@@ -1979,16 +1993,16 @@ void k_segupd_f(const ChainDev* __restrict__ chains, int dir, int parity) {
       if (bb < nb) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const int k = 16 * bb + g + 4 * i;
+          const int k = 16 * bb + 4 * g + i;
 #pragma unroll
           for (int jb = 0; jb < 2; ++jb)
             if (jb < njb)
-              pacc[jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(Ms[(16 * jb + l16) * LDM + k], x[bb][i],
+              pacc[jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(MsT[k * LDT + 16 * jb + l16], x[bb][i],
                                                               pacc[jb], 0, 0, 0);
         }
       }
     }
-    // Out^T = Wf^T P^T per 16-column block of Q, over the flips
+    // Out^T = Wf'^T P^T per 16-column block of Q, over the accepted flips
 #pragma unroll
     for (int bb = 0; bb < NB; ++bb) {
       if (bb < nb) {
@@ -2000,8 +2014,9 @@ void k_segupd_f(const ChainDev* __restrict__ chains, int dir, int parity) {
           if (jb < njb) {
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-              acc = __builtin_amdgcn_mfma_f64_16x16x4f64(
-                  Ws[(16 * jb + g + 4 * r) * LDW + 16 * bb + l16], pacc[jb][r], acc, 0, 0, 0);
+              if (16 * jb + 4 * r < f)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                    Ws[(16 * jb + g + 4 * r) * LDW + 16 * bb + cm], pacc[jb][r], acc, 0, 0, 0);
           }
 #pragma unroll
         for (int i = 0; i < 4; ++i) x[bb][i] -= acc[i];
@@ -2010,9 +2025,14 @@ void k_segupd_f(const ChainDev* __restrict__ chains, int dir, int parity) {
 #pragma unroll
     for (int bb = 0; bb < NB; ++bb)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int k = 16 * bb + g + 4 * i;
-        if (rok && bb < nb && k < nn) q[k] = x[bb][i];
+      for (int h = 0; h < 2; ++h) {
+        const int k = 16 * bb + 4 * g + 2 * h;
+        if (vec && rok && k + 1 < nn) {
+          *reinterpret_cast<GLOBAL v2*>(q + k) = v2{x[bb][2 * h], x[bb][2 * h + 1]};
+        } else {
+          if (rok && k < nn) q[k] = x[bb][2 * h];
+          if (rok && k + 1 < nn) q[k + 1] = x[bb][2 * h + 1];
+        }
       }
   }
 }
