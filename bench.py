@@ -439,15 +439,19 @@ def main():
     if args.precision == "fp64" and not args.no_kernel_timing:
         # segment update Q <- Q - (Q Mf^T) Wf, bound by HBM: algorithmic bytes
         # per chain and spin = Q read and written (2 N n doubles) + Mf and Wf
-        # read (2 f n doubles), f = the mean accepted flips of a segment; a
-        # chain takes part in ceil(N / k) of the ceil(N_max / k) launches of a
-        # slice (spin up only with the particle-hole shortcut)
+        # read (2 f n doubles), f = the mean accepted flips of a segment; the
+        # same launch forms the next segment's block (all but the last segment
+        # of a slice): its k rows of both factors read (2 k n doubles) and the
+        # k x k block written.  A chain takes part in ceil(N / k) of the
+        # ceil(N_max / k) launches of a slice (spin up only with the
+        # particle-hole shortcut)
         f_mean = main_res["accept"] * args.k
         def segs(x):   # scan segments per slice: k sites, or k / 2 bonds (t-V)
             return math.ceil(n_props(x) / (args.k // 2)) if is_tv(x) else math.ceil(x.n_sites / args.k)
         n_seg = max(segs(x) for x in grp)
-        seg_bytes = sum(spins[c] * segs(x) * 8.0 *
-                        (2 * x.n_sites * n_occ(x) + 2 * f_mean * n_occ(x))
+        seg_bytes = sum(spins[c] * 8.0 *
+                        (segs(x) * (2 * x.n_sites * n_occ(x) + 2 * f_mean * n_occ(x))
+                         + (segs(x) - 1) * (2 * args.k * n_occ(x) + args.k ** 2))
                         for c, x in enumerate(grp)) / n_seg
         seg_ms = kt["segment_update"]["ms_per_launch"]
         seg_ach = seg_bytes / (seg_ms / 1e3)
@@ -455,7 +459,8 @@ def main():
                           "unit": "GB/s", "frac": seg_ach / PEAK_HBM,
                           "traffic": None if args.particle_hole else
                           read_traffic(per_launch, args.precision, args.workload),
-                          "kernel": "k_segupd_f (Q <- Q - (Q Mf^T) Wf, every chain and spin)"
+                          "kernel": "k_segupd_f (Q <- Q - (Q Mf^T) Wf and the next segment's "
+                                    "block, every chain and spin)"
                                     if max(n_occ(x) for x in ws) <= 128 else
                                     "k_gemm SEGP + SEGF (Q Mf^T, then Q - (Q Mf^T) Wf)",
                           "bytes_per_launch": seg_bytes, "ms_per_launch": seg_ms,

@@ -40,9 +40,10 @@ hipError_t launch_put_trial(int fp32b, const ChainDev* c, int nc, int slot, int 
 hipError_t launch_dscale_f(const ChainDev* c, int nc, int l, int M, int parity, int ainv, int which,
                            hipStream_t s);
 hipError_t launch_scan_f(int tv, const ChainDev* c, int nc, const Ctl* ctl, int l, int M, int s0, int s1,
-                         int dir, int parity, hipStream_t s);
+                         int dir, int parity, int form_block, hipStream_t s);
 hipError_t launch_wf(const ChainDev* c, int nc, int dir, int parity, hipStream_t s);
-hipError_t launch_segupd_f(const ChainDev* c, int nc, int n_max, int dir, int parity, hipStream_t s);
+hipError_t launch_segupd_f(int tv, const ChainDev* c, int nc, int dir, int parity, int ns0, int ns1,
+                           hipStream_t s);
 hipError_t launch_dscale_u(int fp32b, const ChainDev* c, int nc, int l, int M, int parity,
                            hipStream_t s);
 hipError_t launch_pass_end(const ChainDev* c, int nc, hipStream_t s);
@@ -464,19 +465,23 @@ struct Launcher {
     // segments: kseg sites from s0, or (t-V) the chain's segment s0 of its
     // bond list (nprop_max is then the most segments of a chain)
     const int step = ctx->tv ? 1 : ctx->kseg;
+    bool have_block = false;   // the segment's block was formed by the previous update
     for (int s0 = 0; s0 < ctx->nprop_max; s0 += step) {
       if ((e = timed(tscan, [&] {
              return fast_scan ? launch_scan_f(ctx->tv, chains, nc, ctl, l, ctx->M, s0, s0 + step, dir,
-                                              parity, s)
+                                              parity, have_block ? 0 : 1, s)
                               : launch_scan(0, 1, chains, nc, ctl, l, ctx->M, s0, s0 + ctx->kseg,
                                             dir, parity, s);
            })) != hipSuccess)
         return e;
       if (fast_upd) {
-        // the fused update forms Mf and Wf itself
-        if ((e = timed(tupd, [&] { return launch_segupd_f(chains, nc, ctx->n_max, dir, parity, s); })) !=
-            hipSuccess)
+        // the fused update forms Mf and Wf itself, and the next segment's block
+        const int ns0 = s0 + step < ctx->nprop_max ? s0 + step : -1;
+        if ((e = timed(tupd, [&] {
+               return launch_segupd_f(ctx->tv, chains, nc, dir, parity, ns0, ns0 + step, s);
+             })) != hipSuccess)
           return e;
+        have_block = ns0 >= 0;
       } else {
         if (fast_scan && (e = timed(tscan, [&] { return launch_wf(chains, nc, dir, parity, s); })) !=
                              hipSuccess)

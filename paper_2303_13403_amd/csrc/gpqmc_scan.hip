@@ -1441,21 +1441,18 @@ __device__ __forceinline__ void static_for(Fn&& fn) {
 // k_wf then forms the Woodbury rows and k_segupd_f applies them.
 // ---------------------------------------------------------------------------
 // ---------------------------------------------------------------------------
-// Block of a scan segment, G_s[S, S] = 1 - A[S, :] B[S, :]^T for every chain
-// and propagated spin (S: the sites [s0, s1), or for the t-V model the ends of
-// the bonds of the chain's segment s0), to the chain's scan buffer as a
-// 32 x 32 row-major block with identity padding beyond the segment.  One
-// workgroup of four waves per chain and spin; wave w forms the 16 x 16 tile
-// (rows 16 (w / 2), columns 16 (w % 2)) on MFMA with its operands loaded
-// straight from memory, all loads of a 128-column chunk in flight at once.
-// (Formed inside the one-wave scan, the same block kept a single wave per
-// SIMD waiting on its loads.)
+// Block of a scan segment, G_s[S, S] = 1 - A[S, :] B[S, :]^T for one chain and
+// propagated spin (S: the sites [s0, s1), or for the t-V model the ends of the
+// bonds of the chain's segment s0), to the chain's scan buffer as a 32 x 32
+// row-major block with identity padding beyond the segment.  Wave w (0..3)
+// forms the 16 x 16 tile (rows 16 (w / 2), columns 16 (w % 2)) on MFMA with
+// its operands loaded straight from memory, all loads of a chunk of 8 CH
+// columns in flight at once.  (Formed inside the one-wave scan, the same block
+// kept a single wave per SIMD waiting on its loads.)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_block(const ChainDev* __restrict__ chains, int tv, int s0,
-                                               int s1, int parity) {
-  const int cs = xcd_remap(blockIdx.x, gridDim.x), sp = cs & 1;
-  const ChainDev& C = chains[cs >> 1];
-  if (sp >= C.nsp) return;
+template <int CH>
+__device__ __forceinline__ void form_block(const ChainDev& C, int sp, int tv, int s0, int s1,
+                                           int parity, int wave, int lane) {
   const int N = C.N, nn = C.n[sp];
   const int nprop = tv ? C.n_bonds : N;
   int b0 = s0, b1 = s1;
@@ -1467,7 +1464,7 @@ __global__ __launch_bounds__(256) void k_block(const ChainDev* __restrict__ chai
     return;
   }
   const int nseg = min(b1, nprop) - b0, nrow = tv ? 2 * nseg : nseg;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, l16 = lane & 15, g = lane >> 4;
+  const int l16 = lane & 15, g = lane >> 4;
   const int tm = wave >> 1, tn = wave & 1;
   const int ra = 16 * tm + l16, rc = 16 * tn + l16;
   auto site = [&](int r) { return tv ? C.bonds[2 * (b0 + (r >> 1)) + (r & 1)] : b0 + r; };
@@ -1477,13 +1474,12 @@ __global__ __launch_bounds__(256) void k_block(const ChainDev* __restrict__ chai
   const GLOBAL double* __restrict__ Br =
       gp((const double*)C.F[1][sp][parity]) + (okc ? (size_t)site(rc) * nn : 0);
   // D[m][n] = sum_k A[S_(16 tm + m)][k] B[S_(16 tn + n)][k]; MFMA step (st, e)
-  // of a 128-column chunk takes k = k0 + 8 st + 2 g + e in lane group g, so
-  // each lane loads pairs of doubles and the four lanes of a row read 64
-  // contiguous bytes per load; lane (l16, g) receives D[g + 4 i][l16]
+  // of a chunk takes k = k0 + 8 st + 2 g + e in lane group g, so each lane
+  // loads pairs of doubles and the four lanes of a row read 64 contiguous
+  // bytes per load; lane (l16, g) receives D[g + 4 i][l16]
   doublex4 acc;
 #pragma unroll
   for (int i = 0; i < 4; ++i) acc[i] = 0.0;
-  constexpr int CH = 16;   // (st) steps of 8 columns per chunk
   typedef double v2 __attribute__((ext_vector_type(2)));
   const bool vec = (nn & 1) == 0;   // rows start 16-byte aligned
   for (int k0 = 0; k0 < nn; k0 += 8 * CH) {
@@ -1512,6 +1508,16 @@ __global__ __launch_bounds__(256) void k_block(const ChainDev* __restrict__ chai
     const int r = 16 * tm + g + 4 * i;
     blk[(size_t)r * kBlock + rc] = (r == rc ? 1.0 : 0.0) - acc[i];
   }
+}
+
+// The block of a segment whose previous segment's update did not form it (the
+// first segment of a slice): one workgroup of four waves per chain and spin.
+__global__ __launch_bounds__(256) void k_block(const ChainDev* __restrict__ chains, int tv, int s0,
+                                               int s1, int parity) {
+  const int cs = xcd_remap(blockIdx.x, gridDim.x), sp = cs & 1;
+  const ChainDev& C = chains[cs >> 1];
+  if (sp >= C.nsp) return;
+  form_block<16>(C, sp, tv, s0, s1, parity, threadIdx.x >> 6, threadIdx.x & 63);
 }
 
 template <bool TV>
@@ -1890,72 +1896,84 @@ constexpr int kUpdRows = 16 * kUpdWaves;     // rows of Q per tile (16 per wave)
 // and P never leaves the registers.  LDS strides: Mf^T rows (one per column
 // of Q) 36 doubles, Wf rows 144: every operand read of a half-wave hits 32
 // distinct double slots.
-__global__ __launch_bounds__(kUpdThreads) __attribute__((amdgpu_waves_per_eu(4)))
-void k_segupd_f(const ChainDev* __restrict__ chains, int dir, int parity) {
+__device__ __forceinline__ void segupd_body(const ChainDev& C, int sp, int f, int N, int nn,
+                                            int dir, int parity, int tid, int lane, int wave) {
   constexpr int KB = kBlock;
   constexpr int NB = 8;                  // 16-column blocks of Q (n <= 128)
   constexpr int LDT = KB + 4;
   constexpr int LDW = NB * 16 + 16;
-  const int cs = xcd_remap(blockIdx.x, gridDim.x), sp = cs & 1;
-  const ChainDev& C = chains[cs >> 1];
-  const int N = C.N, nn = C.n[sp], tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int f = C.st->fcount;
-  if (f == 0 || sp >= C.nsp) return;
   __shared__ __align__(16) double MsT[NB * 16 * LDT];
   __shared__ __align__(16) double Ws[KB * LDW];
   __shared__ int Fs[KB];
   __shared__ double dFs[KB];
-  if (tid < f) {
-    Fs[tid] = C.flist[tid];
-    dFs[tid] = C.dflist[sp * kSegMax + tid];
-  }
-  __syncthreads();
   GLOBAL double* __restrict__ Mv = gp((double*)C.F[dir][sp][parity]);
   GLOBAL double* __restrict__ Qb = gp((double*)C.F[1 - dir][sp][parity]);
   const int nb = (nn + 15) / 16;
   const int njb = f > 16 ? 2 : 1;        // 16-flip blocks with accepted flips
   const int l16 = lane & 15, g = lane >> 4;
-  {
-    // Mf = M[F, :] (the moving factor's rows at the accepted sites, zero-padded
-    // to 32 x 128), stored transposed; those rows of M are then scaled by
-    // 1 + Delta_F.  All loads in flight at once, then the stores.
-    constexpr int NC = NB * 16;
-    constexpr int NS = KB * NC / kUpdThreads;
-    static_assert(NS * kUpdThreads == KB * NC, "staging covers the tiles");
-    double vm[NS];
+  // Staging: Mf = M[F, :] (the moving factor's rows at the accepted sites,
+  // zero-padded to 32 x 128) to LDS, transposed, after which those rows of M
+  // are scaled by 1 + Delta_F; and Wf = Z^T Q[F, :] (upward) or Z Q[F, :]
+  // (downward) on MFMA, 16 x 16 tiles (flip block pb, column block cb), at
+  // most two per wave, from the rows of Q before any of them is updated.  The
+  // Z operands load before F is known, then every gathered row at once.
+  const GLOBAL double* __restrict__ zg = gp((const double*)C.Z[sp]);
+  const int ntiles = njb * nb;
+  static_assert(2 * kUpdWaves >= 2 * NB, "two Wf tiles per wave cover 32 flips x 128 columns");
+  double za[2][KB / 4];
 #pragma unroll
-    for (int t = 0; t < NS; ++t) {
-      const int idx = tid + t * kUpdThreads, j = idx / NC, k = idx - j * NC;
-      vm[t] = (j < f && k < nn) ? Mv[(size_t)Fs[j] * nn + k] : 0.0;
-    }
+  for (int u = 0; u < 2; ++u) {
+    const int t = wave + u * kUpdWaves, pb = t / nb;
 #pragma unroll
-    for (int t = 0; t < NS; ++t) {
-      const int idx = tid + t * kUpdThreads, j = idx / NC, k = idx - j * NC;
-      MsT[k * LDT + j] = vm[t];
-      if (j < f && k < nn) Mv[(size_t)Fs[j] * nn + k] = vm[t] * (1.0 + dFs[j]);
+    for (int st = 0; st < KB / 4; ++st) {
+      const int q = 4 * st + g;
+      const bool ok = t < ntiles && q < f;
+      za[u][st] = ok ? (dir == 0 ? zg[(size_t)q * KB + 16 * pb + l16]
+                                 : zg[(size_t)(16 * pb + l16) * KB + q])
+                     : 0.0;
     }
   }
-  {
-    // Wf = Z^T Q[F, :] (upward) or Z Q[F, :] (downward) on MFMA, 16 x 16
-    // tiles (flip block pb, column block cb) spread over the waves, from the
-    // rows of Q before any of them is updated; K = the accepted flips
-    const GLOBAL double* __restrict__ zg = gp((const double*)C.Z[sp]);
-    const int ntiles = njb * nb;
-    for (int t = wave; t < ntiles; t += kUpdWaves) {
-      const int pb = t / nb, cb = t - pb * nb, col = 16 * cb + l16;
+  if (tid < f) {
+    Fs[tid] = C.flist[tid];
+    dFs[tid] = C.dflist[sp * kSegMax + tid];
+  }
+  __syncthreads();
+  constexpr int NC = NB * 16;
+  constexpr int NS = KB * NC / kUpdThreads;
+  static_assert(NS * kUpdThreads == KB * NC, "staging covers the tiles");
+  double vm[NS], qv[2][KB / 4];
+#pragma unroll
+  for (int t = 0; t < NS; ++t) {
+    const int idx = tid + t * kUpdThreads, j = idx / NC, k = idx - j * NC;
+    vm[t] = (j < f && k < nn) ? Mv[(size_t)Fs[j] * nn + k] : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int t = wave + u * kUpdWaves, col = 16 * (t % nb) + l16;
+#pragma unroll
+    for (int st = 0; st < KB / 4; ++st) {
+      const int q = 4 * st + g;
+      const bool ok = t < ntiles && q < f && col < nn;
+      qv[u][st] = ok ? Qb[(size_t)Fs[ok ? q : 0] * nn + col] : 0.0;
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NS; ++t) {
+    const int idx = tid + t * kUpdThreads, j = idx / NC, k = idx - j * NC;
+    MsT[k * LDT + j] = vm[t];
+    if (j < f && k < nn) Mv[(size_t)Fs[j] * nn + k] = vm[t] * (1.0 + dFs[j]);
+  }
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int t = wave + u * kUpdWaves;
+    if (t < ntiles) {
+      const int pb = t / nb, col = 16 * (t - pb * nb) + l16;
       doublex4 acc;
 #pragma unroll
       for (int i = 0; i < 4; ++i) acc[i] = 0.0;
 #pragma unroll
-      for (int st = 0; st < KB / 4; ++st) {
-        const int q = 4 * st + g;
-        const bool ok = q < f;
-        const double za = ok ? (dir == 0 ? zg[(size_t)q * KB + 16 * pb + l16]
-                                         : zg[(size_t)(16 * pb + l16) * KB + q])
-                             : 0.0;
-        const double qb = (ok && col < nn) ? Qb[(size_t)Fs[ok ? q : 0] * nn + col] : 0.0;
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(za, qb, acc, 0, 0, 0);
-      }
+      for (int st = 0; st < KB / 4; ++st)
+        if (4 * st < f) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(za[u][st], qv[u][st], acc, 0, 0, 0);
 #pragma unroll
       for (int i = 0; i < 4; ++i) Ws[(16 * pb + g + 4 * i) * LDW + col] = acc[i];
     }
@@ -2037,10 +2055,31 @@ void k_segupd_f(const ChainDev* __restrict__ chains, int dir, int parity) {
   }
 }
 
+__global__ __launch_bounds__(kUpdThreads) __attribute__((amdgpu_waves_per_eu(4)))
+void k_segupd_f(const ChainDev* __restrict__ chains, int dir, int parity, int tv, int ns0,
+                int ns1) {
+  const int cs = xcd_remap(blockIdx.x, gridDim.x), sp = cs & 1;
+  const ChainDev& C = chains[cs >> 1];
+  const int N = C.N, nn = C.n[sp], tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int f = C.st->fcount;
+  if (sp >= C.nsp) return;
+  if (f > 0) segupd_body(C, sp, f, N, nn, dir, parity, tid, lane, wave);
+  // the next segment's block from the updated factors (ns0 < 0: none)
+  if (ns0 >= 0) {
+    __syncthreads();   // every row of the dual factor written
+    if (wave < 4) form_block<8>(C, sp, tv, ns0, ns1, parity, wave, lane);
+  }
+}
+
+
+// form_block: launch k_block first (the segment's block was not formed by
+// the previous segment's update)
 hipError_t launch_scan_f(int tv, const ChainDev* c, int nc, const Ctl* ctl, int l, int M, int s0,
-                         int s1, int dir, int parity, hipStream_t s) {
-  hipLaunchKernelGGL(k_block, dim3(2 * nc), dim3(256), 0, s, c, tv, s0, s1, parity);
-  if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
+                         int s1, int dir, int parity, int form_block, hipStream_t s) {
+  if (form_block) {
+    hipLaunchKernelGGL(k_block, dim3(2 * nc), dim3(256), 0, s, c, tv, s0, s1, parity);
+    if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
+  }
   if (tv)
     hipLaunchKernelGGL(k_scan_f<true>, dim3(nc), dim3(64), 0, s, c, ctl, l, M, s0, s1, dir, parity);
   else
@@ -2054,10 +2093,12 @@ hipError_t launch_wf(const ChainDev* c, int nc, int dir, int parity, hipStream_t
 }
 
 // n_max: the largest lattice of the batch (rows of Q per chain and spin)
-hipError_t launch_segupd_f(const ChainDev* c, int nc, int n_max, int dir, int parity,
+// ns0 >= 0: the update also forms the block of the segment [ns0, ns1) (t-V:
+// the chains' segment ns0), which the next scan then reads
+hipError_t launch_segupd_f(int tv, const ChainDev* c, int nc, int dir, int parity, int ns0, int ns1,
                            hipStream_t s) {
-  (void)n_max;
-  hipLaunchKernelGGL(k_segupd_f, dim3(2 * nc), dim3(kUpdThreads), 0, s, c, dir, parity);
+  hipLaunchKernelGGL(k_segupd_f, dim3(2 * nc), dim3(kUpdThreads), 0, s, c, dir, parity, tv, ns0,
+                     ns1);
   return hipGetLastError();
 }
 
