@@ -474,7 +474,7 @@ def main():
         prop_ach = prop_flops / (prop_ms / 1e3)
         rooflines.append({"bound": "mfma", "achieved": prop_ach / 1e12, "peak": PEAK_FP64_MFMA / 1e12,
                           "unit": "TFLOP/s", "frac": prop_ach / PEAK_FP64_MFMA, "traffic": None,
-                          "kernel": "k_gemm<double, PROPR> (A <- D e^{-+dtau K} A, B likewise; "
+                          "kernel": "k_prop (A <- D e^{-+dtau K} A, B likewise; "
                                     "every chain and spin x 2 factors)",
                           "flops_per_launch": prop_flops, "ms_per_launch": prop_ms,
                           "ms_total": kt["propagation"]["ms_total"],

@@ -681,6 +681,144 @@ hipError_t launch_gemm_l64(int mode, const GemmEntry* e, const TileRef* t, int n
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Basis propagation of the factored engine, C[p^1] = D (A B[p]): A is the
+// lattice exponential e^{-+dtau K} (N x N, one copy shared by the chains of a
+// lattice, so it stays in L2) and B[p] a factor (N x n, n <= 16 NBC).  One
+// workgroup of four waves per 64 rows of the output and all of its n columns
+// (no column tiles padded past n); wave w owns rows 16 w .. 16 w + 15 and the
+// NBC 16-column blocks.  The A operand is read straight from memory into
+// registers: the contraction order is free, so MFMA step s of a 16-wide
+// k-tile gives k slot g the index k0 + 4 g + s and a lane loads 32 contiguous
+// bytes of its row.  The k-tiles of B (16 x n) are double-buffered in LDS
+// with the next one prefetched into registers: one barrier per k-tile.  Row
+// stride of the LDS tile 16 NBC + 4 doubles: the rows 4 g + s of a half-wave's
+// B operand reads are 4 rows apart and land on opposite bank halves.
+// ---------------------------------------------------------------------------
+template <int NBC>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
+void k_prop(const GemmEntry* __restrict__ ents, const TileRef* __restrict__ tiles, int n_tiles,
+            GemmArgs args) {
+  constexpr int PK = 16;                 // k-tile
+  constexpr int LDB = 16 * NBC + 4;
+  constexpr int NPR = 8 * NBC;           // pairs of columns per k row
+  constexpr int NPAIR = PK * NPR;        // pairs of a k-tile
+  constexpr int PER = (NPAIR + kThreads - 1) / kThreads;
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  if (bid >= n_tiles) return;
+  const TileRef tr = tiles[bid];
+  const GemmEntry& e = ents[tr.entry];
+  const int M = e.M, n = e.N, K = e.K, m0 = tr.tm * kTile;
+  if (m0 >= M) return;
+  const int p = args.parity;
+  const GLOBAL double* __restrict__ A = gp((const double*)e.A[0]);
+  const GLOBAL double* __restrict__ B = gp((const double*)e.B[p]);
+  GLOBAL double* __restrict__ C = gp((double*)e.C[p ^ 1]);
+  const int lda = e.lda, ldb = e.ldb, ldc = e.ldc;
+  typedef double v2 __attribute__((ext_vector_type(2)));
+  const bool avec = (lda & 1) == 0 && (reinterpret_cast<uintptr_t>(A) & 15) == 0;
+  const bool bvec = (ldb & 1) == 0 && (reinterpret_cast<uintptr_t>(B) & 15) == 0;
+  __shared__ __align__(16) double Bs[2][PK * LDB];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, l16 = lane & 15, g = lane >> 4;
+  const int nbc = (n + 15) / 16;
+  const int row = m0 + 16 * wave + l16;
+  const bool rok = row < M;
+  const GLOBAL double* __restrict__ Ar = A + (size_t)(rok ? row : 0) * lda;
+  v2 rbv[PER];
+  auto load_b = [&](int kb) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int idx = tid + u * kThreads, k = idx / NPR, j = 2 * (idx - k * NPR), kk = kb + k;
+      const bool ok = idx < NPAIR && kk < K;
+      const GLOBAL double* src = B + (ok ? (size_t)kk * ldb + j : 0);
+      if (bvec && ok && j + 1 < n) {
+        rbv[u] = *reinterpret_cast<const GLOBAL v2*>(src);
+      } else {
+        rbv[u] = v2{(ok && j < n) ? src[0] : 0.0, (ok && j + 1 < n) ? src[1] : 0.0};
+      }
+    }
+  };
+  auto store_b = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int idx = tid + u * kThreads, k = idx / NPR, j = 2 * (idx - k * NPR);
+      if (idx < NPAIR) *reinterpret_cast<v2*>(&Bs[buf][k * LDB + j]) = rbv[u];
+    }
+  };
+  v2 ra[2], rn[2];
+  auto load_a = [&](int kb, v2 (&r)[2]) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int k = kb + 4 * g + 2 * h;
+      if (avec && rok && k + 1 < K) {
+        r[h] = *reinterpret_cast<const GLOBAL v2*>(Ar + k);
+      } else {
+        r[h] = v2{(rok && k < K) ? Ar[k] : 0.0, (rok && k + 1 < K) ? Ar[k + 1] : 0.0};
+      }
+    }
+  };
+  doublex4 acc[NBC];
+#pragma unroll
+  for (int c = 0; c < NBC; ++c)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[c][i] = 0.0;
+  const int nk = (K + PK - 1) / PK;
+  load_b(0);
+  load_a(0, ra);
+  store_b(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) {
+      load_b((kt + 1) * PK);
+      load_a((kt + 1) * PK, rn);
+    }
+    const double* bs = Bs[cur];
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const double a = st == 0 ? ra[0].x : st == 1 ? ra[0].y : st == 2 ? ra[1].x : ra[1].y;
+#pragma unroll
+      for (int c = 0; c < NBC; ++c)
+        if (c < nbc)
+          acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bs[(4 * g + st) * LDB + 16 * c + l16],
+                                                        acc[c], 0, 0, 0);
+    }
+    if (kt + 1 < nk) {
+      store_b(cur ^ 1);
+      ra[0] = rn[0];
+      ra[1] = rn[1];
+    }
+    __syncthreads();
+  }
+  // epilogue: rows scaled by the slice's D (or D^{-1} for an entry marked sinv)
+  const GLOBAL int8_t* sfield =
+      args.scale_slice >= 0 ? gp(e.field + (size_t)args.scale_slice * e.n_sites) : nullptr;
+  const int sbnd = (args.scale_slice == 0 || args.scale_slice == args.n_bulk_last + 1) ? 0 : 1;
+  const bool inv = (args.scale_inverse != 0) != (e.sinv != 0);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int r = m0 + 16 * wave + g + 4 * i;
+    if (r >= M) continue;
+    const double d = sfield ? dfac(e.dval, sbnd, sfield[r], inv) : 1.0;
+#pragma unroll
+    for (int c = 0; c < NBC; ++c) {
+      const int j = 16 * c + l16;
+      if (c < nbc && j < n) C[(size_t)r * ldc + j] = acc[c][i] * d;
+    }
+  }
+}
+
+// the factored engine's propagation over a tile list of (entry, 64-row tile)
+hipError_t launch_prop(int nmax, const GemmEntry* e, const TileRef* t, int n, GemmArgs a,
+                       hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (nmax <= 112)
+    hipLaunchKernelGGL(k_prop<7>, dim3(n), dim3(kThreads), 0, s, e, t, n, a);
+  else
+    hipLaunchKernelGGL(k_prop<8>, dim3(n), dim3(kThreads), 0, s, e, t, n, a);
+  return hipGetLastError();
+}
+
 template <typename T, int MODE, bool TA, bool TB, typename Tb>
 static hipError_t gemm_t(const GemmEntry* e, const TileRef* t, int n, GemmArgs a, hipStream_t s) {
   if (n <= 0) return hipSuccess;

@@ -22,6 +22,8 @@ hipError_t launch_gemm(int fp32, int g_fp32, int mode, const GemmEntry* e, const
                        GemmArgs a, hipStream_t s);
 hipError_t launch_gemm_l(int mode, const GemmEntry* e, const TileRef* t, int n, GemmArgs a,
                          hipStream_t s);
+hipError_t launch_prop(int nmax, const GemmEntry* e, const TileRef* t, int n, GemmArgs a,
+                       hipStream_t s);
 hipError_t launch_gemm_l64(int mode, const GemmEntry* e, const TileRef* t, int n, GemmArgs a,
                            hipStream_t s);
 hipError_t launch_gemm_plain(int fp32, int transA, const GemmEntry* e, const TileRef* t, int n,
@@ -218,7 +220,7 @@ enum EntryKind { E_WRAP1_UP = 0, E_WRAP2_UP, E_WRAP1_DN, E_WRAP2_DN, E_FLUSH, E_
                  E_COUNT };
 // T_NN_L: 128 x 128 tiles of the large-tile kernels; T_Nn4: N x n outputs of
 // both factors of both spins; T_Nk: N x (delay rank) outputs
-enum TileKind { T_NN = 0, T_Nn, T_nn, T_nN, T_NN_L, T_Nn4, T_Nk, T_COUNT };
+enum TileKind { T_NN = 0, T_Nn, T_nn, T_nN, T_NN_L, T_Nn4, T_Nk, T_NP, T_COUNT };
 static_assert(E_COUNT <= 32, "entry kinds");
 static_assert(T_COUNT <= (int)(sizeof(gpqmc_ctx::off_tiles) / sizeof(size_t)), "tile kinds");
 
@@ -312,6 +314,11 @@ struct Launcher {
         return launch_gemm_l64(mode, ents(ctx, kind), ctx->at<TileRef>(ctx->off_tiles[T_NN_L]),
                                (int)ctx->tiles[T_NN_L].size(), a, s);
     }
+    // the factored engine's propagation of both factors: 64-row tiles over all
+    // n columns (k_prop)
+    if (mode == GM_PROPR && tk == T_Nn4 && !f32 && ctx->n_part <= 128)
+      return launch_prop(ctx->n_part, ents(ctx, kind), ctx->at<TileRef>(ctx->off_tiles[T_NP]),
+                         (int)ctx->tiles[T_NP].size(), a, s);
     return launch_gemm(f32, ctx->fp32, mode, ents(ctx, kind), ctx->at<TileRef>(ctx->off_tiles[tk]),
                        (int)ctx->tiles[tk].size(), a, s);
   }
@@ -636,12 +643,14 @@ Launcher make_launcher(gpqmc_ctx* ctx) {
   return L;
 }
 
+// whole_n: one tile over all columns of each row tile
 void build_tiles(std::vector<TileRef>& out, const std::vector<std::pair<int, int>>& mn,
-                 const std::vector<char>& skip, int tile) {
+                 const std::vector<char>& skip, int tile, bool whole_n = false) {
   out.clear();
   for (size_t e = 0; e < mn.size(); ++e) {
     if (skip[e]) continue;
-    const int tm = (mn[e].first + tile - 1) / tile, tn = (mn[e].second + tile - 1) / tile;
+    const int tm = (mn[e].first + tile - 1) / tile;
+    const int tn = whole_n ? 1 : (mn[e].second + tile - 1) / tile;
     for (int a = 0; a < tm; ++a)
       for (int b = 0; b < tn; ++b) out.push_back(TileRef{(int)e, a, b, 0});
   }
@@ -954,14 +963,17 @@ gpqmc_status gpqmc_create(int32_t n_chains, const gpqmc_chain_desc* chains,
       sz[T_NN_L].push_back({h.N, h.N});
       sz[T_Nn4].push_back({h.N, h.n[sp]});   // factor A of this spin
       sz[T_Nn4].push_back({h.N, h.n[sp]});   // factor B
+      sz[T_NP].push_back({h.N, h.n[sp]});    // the same two, 64-row tiles over all columns
+      sz[T_NP].push_back({h.N, h.n[sp]});
       sz[T_Nk].push_back({h.N, c->kseg});
       const char sk = (sp == 1 && (h.ph || h.tv)) ? 1 : 0;
       for (int t = 0; t < T_COUNT; ++t) skip[t].push_back(sk);
       skip[T_Nn4].push_back(sk);
+      skip[T_NP].push_back(sk);
     }
   }
   for (int t = 0; t < T_COUNT; ++t) {
-    build_tiles(c->tiles[t], sz[t], skip[t], t == T_NN_L ? 128 : kTile);
+    build_tiles(c->tiles[t], sz[t], skip[t], t == T_NN_L ? 128 : kTile, t == T_NP);
     c->off_tiles[t] = take(sizeof(TileRef) * c->tiles[t].size());
   }
   c->bytes = align256(off);
