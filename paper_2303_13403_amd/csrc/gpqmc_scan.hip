@@ -1521,7 +1521,7 @@ __global__ __launch_bounds__(256) void k_block(const ChainDev* __restrict__ chai
 }
 
 template <bool TV>
-__global__ __launch_bounds__(64) void k_scan_f(const ChainDev* __restrict__ chains,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_scan_f(const ChainDev* __restrict__ chains,
                                                const Ctl* __restrict__ ctl, int l, int M, int s0,
                                                int s1, int dir, int parity) {
   const ChainDev& C = chains[xcd_remap(blockIdx.x, gridDim.x)];
@@ -1549,10 +1549,11 @@ __global__ __launch_bounds__(64) void k_scan_f(const ChainDev* __restrict__ chai
   __shared__ int srow[KB];        // site of every block row
   __shared__ int Fl[KB];
   __shared__ double dF[2][KB];    // Delta of every accepted flip, per spin
-  // history rows X^{(t)}[j_t, S] (later the LU factors), and history columns
-  // X^{(t)}[S, j_t] (odd leading dimension: written by column)
+  // history rows X^{(t)}[j_t, S] (later the LU factors); the history columns
+  // X^{(t)}[a, j_t] stay in each lane's registers (hc, indexed by the site
+  // j_t), and tpos maps a site to its flip index (-1: not flipped)
   __shared__ __align__(16) double hrow[2][KB][KB];
-  __shared__ __align__(16) double hcol[2][KB][KB + 1];
+  __shared__ int8_t tpos[KB];
 
   const int bnd = (l == 0 || l == M + 1) ? 0 : 1;
   int8_t* frow = C.field + (size_t)l * nprop;
@@ -1565,6 +1566,7 @@ __global__ __launch_bounds__(64) void k_scan_f(const ChainDev* __restrict__ chai
     fs[lane] = frow[s0 + lane];
     fs0[lane] = fs[lane];
   }
+  if (lane < KB) tpos[lane] = -1;
   int my_site = 0;
   if (a < nrow) {
     my_site = TV ? C.bonds[2 * (s0 + (a >> 1)) + (a & 1)] : s0 + a;
@@ -1579,6 +1581,7 @@ __global__ __launch_bounds__(64) void k_scan_f(const ChainDev* __restrict__ chai
   // ---- G_s[S,S] = 1 - A[S,:] B[S,:]^T (formed by k_block), row a of spin s
   // in g; with the particle-hole shortcut spin 1 is mirrored below ----
   double g[KB];
+  double hc[KB];   // hc[j] = X^{(t)}[a, j] of the flip t at site j
   {
     typedef double v2 __attribute__((ext_vector_type(2)));
     const GLOBAL double* __restrict__ blk = gp((const double*)C.scan_ws[s]) + (size_t)a * KB;
@@ -1593,7 +1596,7 @@ __global__ __launch_bounds__(64) void k_scan_f(const ChainDev* __restrict__ chai
   if (ph) {
     // G_1[a][c] = delta_ac - eps_a eps_c G_0[c][a]: spin-0 lane c stores its
     // row (stride KB + 1: conflict-free both ways), spin-1 lane a reads column a
-    double* T = &hcol[0][0][0];
+    double* T = &hrow[0][0][0];   // 32 x 33 doubles, before any history row
     if (s == 0) {
 #pragma unroll
       for (int q = 0; q < KB; ++q) T[a * (KB + 1) + q] = g[q];
@@ -1630,7 +1633,7 @@ __global__ __launch_bounds__(64) void k_scan_f(const ChainDev* __restrict__ chai
           *reinterpret_cast<double2*>(&hrow[s][t][q]) = v;
         }
       }
-      hcol[s][t][a] = (a == j ? 1.0 : 0.0) - g[j];
+      hc[j] = (a == j ? 1.0 : 0.0) - g[j];
       wave_sync();
       const double cg = (dl / rl) * g[j];
 #pragma unroll
@@ -1641,6 +1644,7 @@ __global__ __launch_bounds__(64) void k_scan_f(const ChainDev* __restrict__ chai
       }
       if (lane == 0) {
         Fl[t] = j;
+        tpos[j] = (int8_t)t;
         dF[0][t] = dl;
         dF[1][t] = dl_other;
       }
@@ -1703,7 +1707,7 @@ __global__ __launch_bounds__(64) void k_scan_f(const ChainDev* __restrict__ chai
               *reinterpret_cast<double2*>(&hrow[s][t][q]) = v;
             }
           }
-          hcol[s][t][a] = (a == j ? 1.0 : 0.0) - g[j];
+          hc[j] = (a == j ? 1.0 : 0.0) - g[j];
           wave_sync();
           // Sherman-Morrison: G <- G - (Delta / r) G[:, j] X[j, :]
           const double cg = (s == 0 ? du / ru : dd / rd) * g[j];
@@ -1715,6 +1719,7 @@ __global__ __launch_bounds__(64) void k_scan_f(const ChainDev* __restrict__ chai
           }
           if (lane == 0) {
             Fl[t] = j;
+            tpos[j] = (int8_t)t;
             dF[0][t] = du;
             dF[1][t] = dd;
           }
@@ -1753,31 +1758,29 @@ __global__ __launch_bounds__(64) void k_scan_f(const ChainDev* __restrict__ chai
   }
   if (f == 0) return;
 
-  // ---- K = Delta_F^{-1} + X_s[F,F] = L U: lane (s, u) assembles row u ----
-  // the reciprocal pivots 1 / U[v][v], one per lane
+  // ---- K = Delta_F^{-1} + X_s[F,F] = L U, packed in place of the history
+  // rows; first the reciprocal pivots 1 / U[v][v], one per lane ----
   __shared__ double pinv[2][KB];
   {
     const double dinv = a < f ? 1.0 / dF[s][a] : 0.0;
     if (a < f) pinv[s][a] = 1.0 / (hrow[s][a][Fl[a]] + dinv);
     wave_sync();
-    double lu[KB];
-    const int ju = a < f ? Fl[a] : 0;
-#pragma unroll
-    for (int v = 0; v < KB; ++v) {
-      double x = (v == a) ? 1.0 : 0.0;   // identity padding beyond f
-      if (a < f && v < f) {
-        if (v < a) {
-          x = hcol[s][v][ju] * pinv[s][v];
-        } else {
-          x = hrow[s][a][Fl[v]] + (v == a ? dinv : 0.0);
-        }
-      }
-      lu[v] = x;
+    // U: lane (s, u) compacts its history row u to the flip order,
+    // U[u][v] = X^{(u)}[j_u, j_v] + delta_uv / Delta_u for v >= u; in place,
+    // since j_v >= v grows with v, no column is overwritten before it is read
+    if (a < f) {
+      double* row = &hrow[s][a][0];
+      for (int v = a; v < f; ++v) row[v] = row[Fl[v]] + (v == a ? dinv : 0.0);
     }
-    wave_sync();
+    // L: the lane of site j_u holds X^{(v)}[j_u, j_v] for the earlier flips v
+    // in hc[j_v]: L[u][v] = X^{(v)}[j_u, j_v] / U[v][v] (columns v < u of row
+    // u, which the compaction above leaves alone)
+    const int u = tpos[a];
 #pragma unroll
-    for (int v = 0; v < KB; v += 2)
-      *reinterpret_cast<double2*>(&hrow[s][a][v]) = make_double2(lu[v], lu[v + 1]);
+    for (int j = 0; j < KB; ++j) {
+      const int v = tpos[j];
+      if (v >= 0 && v < u) hrow[s][u][v] = hc[j] * pinv[s][v];
+    }
     wave_sync();
   }
   // ---- the Woodbury core Z = K^{-1} = U^{-1} L^{-1}: lane (s, c) forms
