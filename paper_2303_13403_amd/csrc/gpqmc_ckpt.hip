@@ -463,8 +463,10 @@ __device__ inline void rt_clear(double (*rk)[kRtMax], double (*rp)[kRtMax], doub
   __shared__ double pabs[kRtMax];
 
 // Cholesky W = R^T R (R upper) of the Gram matrix, then R^{-1}, in registers.
+// (At most 168 registers for the 7 x 7 tiles: three workgroups per CU.)
 template <int NB, int TG>
-__global__ __launch_bounds__(TG * TG) void k_chol_inv_rt(const ChainDev* __restrict__ chains) {
+__global__ __launch_bounds__(TG * TG) __attribute__((amdgpu_waves_per_eu(NB == 7 ? 3 : 1)))
+void k_chol_inv_rt(const ChainDev* __restrict__ chains) {
   const int lg = xcd_remap(blockIdx.x, gridDim.x);
   const ChainDev& C = chains[lg >> 1];
   const int sp = lg & 1, n = C.n[sp], tid = threadIdx.x;
@@ -557,7 +559,8 @@ __global__ __launch_bounds__(TG * TG) void k_chol_inv_rt(const ChainDev* __restr
 // Inverse of X = L R (n x n) in place, partial pivoting; log|det X| and its
 // sign go to the chain state.
 template <int NB, int TG>
-__global__ __launch_bounds__(TG * TG) void k_gj_inv_rt(const ChainDev* __restrict__ chains) {
+__global__ __launch_bounds__(TG * TG) __attribute__((amdgpu_waves_per_eu(NB == 7 ? 3 : 1)))
+void k_gj_inv_rt(const ChainDev* __restrict__ chains) {
   const int lg = xcd_remap(blockIdx.x, gridDim.x);
   const ChainDev& C = chains[lg >> 1];
   const int sp = lg & 1, n = C.n[sp], tid = threadIdx.x;
