@@ -1444,28 +1444,35 @@ __device__ __forceinline__ void static_for(Fn&& fn) {
 // Block of a scan segment, G_s[S, S] = 1 - A[S, :] B[S, :]^T for one chain and
 // propagated spin (S: the sites [s0, s1), or for the t-V model the ends of the
 // bonds of the chain's segment s0), to the chain's scan buffer as a 32 x 32
-// row-major block with identity padding beyond the segment.  Wave w (0..3)
-// forms the 16 x 16 tile (rows 16 (w / 2), columns 16 (w % 2)) on MFMA with
-// its operands loaded straight from memory, all loads of a chunk of 8 CH
-// columns in flight at once.  (Formed inside the one-wave scan, the same block
-// kept a single wave per SIMD waiting on its loads.)
+// row-major block with identity padding beyond the segment.  Tile t (0..3)
+// is the 16 x 16 part (rows 16 (t / 2), columns 16 (t % 2)), formed on MFMA
+// by one wave over a range of the columns of the factors with its operands
+// loaded straight from memory, all loads of a chunk of 8 CH columns in
+// flight at once.  (Formed inside the one-wave scan, the same block kept a
+// single wave per SIMD waiting on its loads.)
 // ---------------------------------------------------------------------------
 template <int CH>
-__device__ __forceinline__ void form_block(const ChainDev& C, int sp, int tv, int s0, int s1,
-                                           int parity, int wave, int lane) {
+__device__ __forceinline__ doublex4 block_acc(const ChainDev& C, int sp, int tv, int s0, int s1,
+                                              int parity, int tile, int lane, int kbeg, int kend,
+                                              bool& valid) {
+  doublex4 acc;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) acc[i] = 0.0;
+  valid = false;
   const int N = C.N, nn = C.n[sp];
   const int nprop = tv ? C.n_bonds : N;
   int b0 = s0, b1 = s1;
   if (tv) {
-    if (s0 >= C.n_seg) return;
+    if (s0 >= C.n_seg) return acc;
     b0 = C.seg_start[s0];
     b1 = C.seg_start[s0 + 1];
   } else if (s0 >= N) {
-    return;
+    return acc;
   }
+  valid = true;
   const int nseg = min(b1, nprop) - b0, nrow = tv ? 2 * nseg : nseg;
   const int l16 = lane & 15, g = lane >> 4;
-  const int tm = wave >> 1, tn = wave & 1;
+  const int tm = tile >> 1, tn = tile & 1;
   const int ra = 16 * tm + l16, rc = 16 * tn + l16;
   auto site = [&](int r) { return tv ? C.bonds[2 * (b0 + (r >> 1)) + (r & 1)] : b0 + r; };
   const bool oka = ra < nrow, okc = rc < nrow;
@@ -1473,35 +1480,41 @@ __device__ __forceinline__ void form_block(const ChainDev& C, int sp, int tv, in
       gp((const double*)C.F[0][sp][parity]) + (oka ? (size_t)site(ra) * nn : 0);
   const GLOBAL double* __restrict__ Br =
       gp((const double*)C.F[1][sp][parity]) + (okc ? (size_t)site(rc) * nn : 0);
-  // D[m][n] = sum_k A[S_(16 tm + m)][k] B[S_(16 tn + n)][k]; MFMA step (st, e)
-  // of a chunk takes k = k0 + 8 st + 2 g + e in lane group g, so each lane
-  // loads pairs of doubles and the four lanes of a row read 64 contiguous
-  // bytes per load; lane (l16, g) receives D[g + 4 i][l16]
-  doublex4 acc;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) acc[i] = 0.0;
+  // D[m][n] = sum_k A[S_(16 tm + m)][k] B[S_(16 tn + n)][k] over [kbeg, kend)
+  // (kbeg a multiple of 8); MFMA step (st, e) of a chunk takes
+  // k = k0 + 8 st + 2 g + e in lane group g, so each lane loads pairs of
+  // doubles and the four lanes of a row read 64 contiguous bytes per load;
+  // lane (l16, g) receives D[g + 4 i][l16]
   typedef double v2 __attribute__((ext_vector_type(2)));
   const bool vec = (nn & 1) == 0;   // rows start 16-byte aligned
-  for (int k0 = 0; k0 < nn; k0 += 8 * CH) {
+  for (int k0 = kbeg; k0 < kend; k0 += 8 * CH) {
     v2 av[CH], bv[CH];
 #pragma unroll
     for (int st = 0; st < CH; ++st) {
       const int k = k0 + 8 * st + 2 * g;
-      if (vec && k + 1 < nn) {
+      if (vec && k + 1 < kend) {
         av[st] = oka ? *reinterpret_cast<const GLOBAL v2*>(Ar + k) : v2{0.0, 0.0};
         bv[st] = okc ? *reinterpret_cast<const GLOBAL v2*>(Br + k) : v2{0.0, 0.0};
       } else {
-        av[st] = v2{(oka && k < nn) ? Ar[k] : 0.0, (oka && k + 1 < nn) ? Ar[k + 1] : 0.0};
-        bv[st] = v2{(okc && k < nn) ? Br[k] : 0.0, (okc && k + 1 < nn) ? Br[k + 1] : 0.0};
+        av[st] = v2{(oka && k < kend) ? Ar[k] : 0.0, (oka && k + 1 < kend) ? Ar[k + 1] : 0.0};
+        bv[st] = v2{(okc && k < kend) ? Br[k] : 0.0, (okc && k + 1 < kend) ? Br[k + 1] : 0.0};
       }
     }
 #pragma unroll
     for (int st = 0; st < CH; ++st)
-      if (k0 + 8 * st < nn) {
+      if (k0 + 8 * st < kend) {
         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[st].x, bv[st].x, acc, 0, 0, 0);
         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[st].y, bv[st].y, acc, 0, 0, 0);
       }
   }
+  return acc;
+}
+
+// the tile's part of the block, 1 - D, to the chain's scan buffer
+__device__ __forceinline__ void block_store(const ChainDev& C, int sp, int tile, int lane,
+                                            const doublex4& acc) {
+  const int l16 = lane & 15, g = lane >> 4;
+  const int tm = tile >> 1, rc = 16 * (tile & 1) + l16;
   GLOBAL double* __restrict__ blk = gp((double*)C.scan_ws[sp]);
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
@@ -1517,7 +1530,10 @@ __global__ __launch_bounds__(256) void k_block(const ChainDev* __restrict__ chai
   const int cs = xcd_remap(blockIdx.x, gridDim.x), sp = cs & 1;
   const ChainDev& C = chains[cs >> 1];
   if (sp >= C.nsp) return;
-  form_block<16>(C, sp, tv, s0, s1, parity, threadIdx.x >> 6, threadIdx.x & 63);
+  const int tile = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  bool valid;
+  const doublex4 acc = block_acc<16>(C, sp, tv, s0, s1, parity, tile, lane, 0, C.n[sp], valid);
+  if (valid) block_store(C, sp, tile, lane, acc);
 }
 
 template <bool TV>
@@ -1899,16 +1915,15 @@ constexpr int kUpdRows = 16 * kUpdWaves;     // rows of Q per tile (16 per wave)
 // and P never leaves the registers.  LDS strides: Mf^T rows (one per column
 // of Q) 36 doubles, Wf rows 144: every operand read of a half-wave hits 32
 // distinct double slots.
+constexpr int kUpdLDT = kBlock + 4;          // LDS row of Mf^T (one per column of Q)
+constexpr int kUpdLDW = 8 * 16 + 16;         // LDS row of Wf
 __device__ __forceinline__ void segupd_body(const ChainDev& C, int sp, int f, int N, int nn,
-                                            int dir, int parity, int tid, int lane, int wave) {
+                                            int dir, int parity, int tid, int lane, int wave,
+                                            double* MsT, double* Ws, int* Fs, double* dFs) {
   constexpr int KB = kBlock;
   constexpr int NB = 8;                  // 16-column blocks of Q (n <= 128)
-  constexpr int LDT = KB + 4;
-  constexpr int LDW = NB * 16 + 16;
-  __shared__ __align__(16) double MsT[NB * 16 * LDT];
-  __shared__ __align__(16) double Ws[KB * LDW];
-  __shared__ int Fs[KB];
-  __shared__ double dFs[KB];
+  constexpr int LDT = kUpdLDT;
+  constexpr int LDW = kUpdLDW;
   GLOBAL double* __restrict__ Mv = gp((double*)C.F[dir][sp][parity]);
   GLOBAL double* __restrict__ Qb = gp((double*)C.F[1 - dir][sp][parity]);
   const int nb = (nn + 15) / 16;
@@ -2066,11 +2081,34 @@ void k_segupd_f(const ChainDev* __restrict__ chains, int dir, int parity, int tv
   const int N = C.N, nn = C.n[sp], tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int f = C.st->fcount;
   if (sp >= C.nsp) return;
-  if (f > 0) segupd_body(C, sp, f, N, nn, dir, parity, tid, lane, wave);
-  // the next segment's block from the updated factors (ns0 < 0: none)
+  __shared__ __align__(16) double MsT[8 * 16 * kUpdLDT];
+  __shared__ __align__(16) double Ws[kBlock * kUpdLDW];
+  __shared__ int Fs[kBlock];
+  __shared__ double dFs[kBlock];
+  if (f > 0) segupd_body(C, sp, f, N, nn, dir, parity, tid, lane, wave, MsT, Ws, Fs, dFs);
+  // the next segment's block from the updated factors (ns0 < 0: none): wave
+  // w forms tile w % 4 over one half of the columns, the second half's
+  // partial sums meet the first's in LDS
   if (ns0 >= 0) {
-    __syncthreads();   // every row of the dual factor written
-    if (wave < 4) form_block<8>(C, sp, tv, ns0, ns1, parity, wave, lane);
+    __syncthreads();   // every row of the dual factor written, MsT free
+    const int tile = wave & 3, half = wave >> 2;
+    const int kh = min(8 * ((nn + 15) / 16), nn);   // a multiple of 8
+    bool valid;
+    doublex4 acc = block_acc<8>(C, sp, tv, ns0, ns1, parity, tile, lane, half ? kh : 0,
+                                half ? nn : kh, valid);
+    if (valid) {   // the same for the whole workgroup
+      double* part = MsT + (size_t)(tile * 64 + lane) * 4;
+      if (half) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) part[i] = acc[i];
+      }
+      __syncthreads();
+      if (!half) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i] += part[i];
+        block_store(C, sp, tile, lane, acc);
+      }
+    }
   }
 }
 
