@@ -687,23 +687,40 @@ hipError_t launch_gemm_l64(int mode, const GemmEntry* e, const TileRef* t, int n
 // lattice, so it stays in L2) and B[p] a factor (N x n, n <= 16 NBC).  One
 // workgroup of four waves per 64 rows of the output and all of its n columns
 // (no column tiles padded past n); wave w owns rows 16 w .. 16 w + 15 and the
-// NBC 16-column blocks.  The A operand is read straight from memory into
-// registers: the contraction order is free, so MFMA step s of a 16-wide
-// k-tile gives k slot g the index k0 + 4 g + s and a lane loads 32 contiguous
-// bytes of its row.  The k-tiles of B (16 x n) are double-buffered in LDS
-// with the next one prefetched into registers: one barrier per k-tile.  Row
-// stride of the LDS tile 16 NBC + 4 doubles: the rows 4 g + s of a half-wave's
-// B operand reads are 4 rows apart and land on opposite bank halves.
+// NBC 16-column blocks, MFMA k-steps of 4 over k-tiles of 16.
+//
+// With every row 16-byte aligned (even N and n), both operands of a k-tile
+// go to LDS by direct loads (global_load_lds_dwordx4: no registers, no LDS
+// store instructions), two stages, the next k-tile's loads in flight during
+// the current one's MFMAs, one barrier per k-tile.  Each load instruction
+// places 64 chunks of 16 bytes side by side; the lanes pick their chunks so
+// that the operand reads are conflict-free:
+//   A stage: [8 pairs of k][64 rows] (a half-wave reads 16 rows x one pair);
+//   B stage: [16 k][8 NBC pairs], rows of 112 doubles (NBC = 7: consecutive
+//   rows land on opposite bank halves) or 128 with the pair index of odd
+//   rows XOR 8 (NBC = 8).
+// Rows past M and k past K load clamped in-range addresses; the A operand is
+// zeroed past K and rows past M are not stored.  Otherwise the A operand is
+// read straight into registers (k slot g of step s taking k = k0 + 4 g + s)
+// and the B k-tiles go through registers into a double-buffered LDS tile.
 // ---------------------------------------------------------------------------
-template <int NBC>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
+#define GLOBAL_V __attribute__((address_space(1))) void
+#define LOCAL_V __attribute__((address_space(3))) void
+constexpr int kPropSA = 8 * 64 * 2;                  // doubles of an A stage
+constexpr int kPropSB = 1024 * 2;                     // doubles of a B stage (1024 chunks)
+constexpr int kPropStage = kPropSA + kPropSB;
+
+// FULL: every entry of the launch has NBC column blocks (no per-block guard)
+template <int NBC, bool FULL>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3)))
 void k_prop(const GemmEntry* __restrict__ ents, const TileRef* __restrict__ tiles, int n_tiles,
             GemmArgs args) {
   constexpr int PK = 16;                 // k-tile
-  constexpr int LDB = 16 * NBC + 4;
+  constexpr int LDB = 16 * NBC + 4;      // register path: LDS row of a B k-tile
   constexpr int NPR = 8 * NBC;           // pairs of columns per k row
   constexpr int NPAIR = PK * NPR;        // pairs of a k-tile
   constexpr int PER = (NPAIR + kThreads - 1) / kThreads;
+  static_assert(NPAIR <= 1024 && 2 * PK * LDB <= 2 * kPropStage, "stages hold the tiles");
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
   if (bid >= n_tiles) return;
   const TileRef tr = tiles[bid];
@@ -711,84 +728,139 @@ void k_prop(const GemmEntry* __restrict__ ents, const TileRef* __restrict__ tile
   const int M = e.M, n = e.N, K = e.K, m0 = tr.tm * kTile;
   if (m0 >= M) return;
   const int p = args.parity;
-  const GLOBAL double* __restrict__ A = gp((const double*)e.A[0]);
-  const GLOBAL double* __restrict__ B = gp((const double*)e.B[p]);
+  const double* Ap = (const double*)e.A[0];
+  const double* Bp = (const double*)e.B[p];
+  const GLOBAL double* __restrict__ A = gp(Ap);
+  const GLOBAL double* __restrict__ B = gp(Bp);
   GLOBAL double* __restrict__ C = gp((double*)e.C[p ^ 1]);
   const int lda = e.lda, ldb = e.ldb, ldc = e.ldc;
   typedef double v2 __attribute__((ext_vector_type(2)));
-  const bool avec = (lda & 1) == 0 && (reinterpret_cast<uintptr_t>(A) & 15) == 0;
-  const bool bvec = (ldb & 1) == 0 && (reinterpret_cast<uintptr_t>(B) & 15) == 0;
-  __shared__ __align__(16) double Bs[2][PK * LDB];
+  const bool avec = (lda & 1) == 0 && (reinterpret_cast<uintptr_t>(Ap) & 15) == 0;
+  const bool bvec = (ldb & 1) == 0 && (reinterpret_cast<uintptr_t>(Bp) & 15) == 0;
+  __shared__ __align__(16) double ring[2 * kPropStage];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, l16 = lane & 15, g = lane >> 4;
-  const int nbc = (n + 15) / 16;
-  const int row = m0 + 16 * wave + l16;
-  const bool rok = row < M;
-  const GLOBAL double* __restrict__ Ar = A + (size_t)(rok ? row : 0) * lda;
-  v2 rbv[PER];
-  auto load_b = [&](int kb) {
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int idx = tid + u * kThreads, k = idx / NPR, j = 2 * (idx - k * NPR), kk = kb + k;
-      const bool ok = idx < NPAIR && kk < K;
-      const GLOBAL double* src = B + (ok ? (size_t)kk * ldb + j : 0);
-      if (bvec && ok && j + 1 < n) {
-        rbv[u] = *reinterpret_cast<const GLOBAL v2*>(src);
-      } else {
-        rbv[u] = v2{(ok && j < n) ? src[0] : 0.0, (ok && j + 1 < n) ? src[1] : 0.0};
-      }
-    }
-  };
-  auto store_b = [&](int buf) {
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int idx = tid + u * kThreads, k = idx / NPR, j = 2 * (idx - k * NPR);
-      if (idx < NPAIR) *reinterpret_cast<v2*>(&Bs[buf][k * LDB + j]) = rbv[u];
-    }
-  };
-  v2 ra[2], rn[2];
-  auto load_a = [&](int kb, v2 (&r)[2]) {
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int k = kb + 4 * g + 2 * h;
-      if (avec && rok && k + 1 < K) {
-        r[h] = *reinterpret_cast<const GLOBAL v2*>(Ar + k);
-      } else {
-        r[h] = v2{(rok && k < K) ? Ar[k] : 0.0, (rok && k + 1 < K) ? Ar[k + 1] : 0.0};
-      }
-    }
-  };
+  const int nbc = FULL ? NBC : (n + 15) / 16;
+  const int nk = (K + PK - 1) / PK;
   doublex4 acc[NBC];
 #pragma unroll
   for (int c = 0; c < NBC; ++c)
 #pragma unroll
     for (int i = 0; i < 4; ++i) acc[c][i] = 0.0;
-  const int nk = (K + PK - 1) / PK;
-  load_b(0);
-  load_a(0, ra);
-  store_b(0);
-  __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    const int cur = kt & 1;
-    if (kt + 1 < nk) {
-      load_b((kt + 1) * PK);
-      load_a((kt + 1) * PK, rn);
-    }
-    const double* bs = Bs[cur];
+
+  if (avec && bvec && (K & 1) == 0 && (n & 1) == 0) {
+    // ---- direct-to-LDS path ----
+    const int arow = min(m0 + lane, M - 1);
+    auto issue = [&](int kt) {
+      const int k0 = kt * PK;
+      double* st = ring + (kt & 1) * kPropStage;
 #pragma unroll
-    for (int st = 0; st < 4; ++st) {
-      const double a = st == 0 ? ra[0].x : st == 1 ? ra[0].y : st == 2 ? ra[1].x : ra[1].y;
+      for (int u = 0; u < 2; ++u) {
+        const int kp = 2 * wave + u, kk = min(k0 + 2 * kp, K - 2);
+        __builtin_amdgcn_global_load_lds((const GLOBAL_V*)(Ap + (size_t)arow * lda + kk),
+                                         (LOCAL_V*)(st + kp * 64 * 2), 16, 0, 0);
+      }
 #pragma unroll
-      for (int c = 0; c < NBC; ++c)
-        if (c < nbc)
-          acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bs[(4 * g + st) * LDB + 16 * c + l16],
-                                                        acc[c], 0, 0, 0);
+      for (int u = 0; u < 4; ++u) {
+        const int base = (wave * 4 + u) * 64, c = base + lane;
+        const int k = c / NPR;
+        const int pd = c - k * NPR;
+        const int ps = NBC == 8 ? (pd ^ ((k & 1) << 3)) : pd;   // source pair of this slot
+        const int kk = min(k0 + k, K - 1), jj = min(2 * ps, n - 2);
+        __builtin_amdgcn_global_load_lds((const GLOBAL_V*)(Bp + (size_t)kk * ldb + jj),
+                                         (LOCAL_V*)(st + kPropSA + base * 2), 16, 0, 0);
+      }
+    };
+    issue(0);
+    for (int kt = 0; kt < nk; ++kt) {
+      // this wave's loads of stage kt have landed, then every wave's have; the
+      // barrier also ends every wave's reads of the stage the next loads fill
+      __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+      __builtin_amdgcn_sched_barrier(0);
+      __builtin_amdgcn_s_barrier();
+      __builtin_amdgcn_sched_barrier(0);
+      if (kt + 1 < nk) issue(kt + 1);
+      const double* st = ring + (kt & 1) * kPropStage;
+      const int k0 = kt * PK;
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) {
+        const int k = 4 * s4 + g;
+        double a = st[((k >> 1) * 64 + 16 * wave + l16) * 2 + (k & 1)];
+        a = k0 + k < K ? a : 0.0;
+        const int bx = NBC == 8 ? ((k & 1) << 4) : 0;
+#pragma unroll
+        for (int c = 0; c < NBC; ++c)
+          if (FULL || c < nbc)
+            acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                a, st[kPropSA + k * 2 * NPR + ((16 * c + l16) ^ bx)], acc[c], 0, 0, 0);
+      }
+      __builtin_amdgcn_sched_barrier(0);
     }
-    if (kt + 1 < nk) {
-      store_b(cur ^ 1);
-      ra[0] = rn[0];
-      ra[1] = rn[1];
-    }
+  } else {
+    // ---- register path ----
+    double* Bs0 = ring;
+    double* Bs1 = ring + PK * LDB;
+    const int row = m0 + 16 * wave + l16;
+    const bool rok = row < M;
+    const GLOBAL double* __restrict__ Ar = A + (size_t)(rok ? row : 0) * lda;
+    v2 rbv[PER];
+    auto load_b = [&](int kb) {
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int idx = tid + u * kThreads, k = idx / NPR, j = 2 * (idx - k * NPR), kk = kb + k;
+        const bool ok = idx < NPAIR && kk < K;
+        const GLOBAL double* src = B + (ok ? (size_t)kk * ldb + j : 0);
+        if (bvec && ok && j + 1 < n) {
+          rbv[u] = *reinterpret_cast<const GLOBAL v2*>(src);
+        } else {
+          rbv[u] = v2{(ok && j < n) ? src[0] : 0.0, (ok && j + 1 < n) ? src[1] : 0.0};
+        }
+      }
+    };
+    auto store_b = [&](double* bs) {
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int idx = tid + u * kThreads, k = idx / NPR, j = 2 * (idx - k * NPR);
+        if (idx < NPAIR) *reinterpret_cast<v2*>(&bs[k * LDB + j]) = rbv[u];
+      }
+    };
+    v2 ra[2], rn[2];
+    auto load_a = [&](int kb, v2 (&r)[2]) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int k = kb + 4 * g + 2 * h;
+        if (avec && rok && k + 1 < K) {
+          r[h] = *reinterpret_cast<const GLOBAL v2*>(Ar + k);
+        } else {
+          r[h] = v2{(rok && k < K) ? Ar[k] : 0.0, (rok && k + 1 < K) ? Ar[k + 1] : 0.0};
+        }
+      }
+    };
+    load_b(0);
+    load_a(0, ra);
+    store_b(Bs0);
     __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+      if (kt + 1 < nk) {
+        load_b((kt + 1) * PK);
+        load_a((kt + 1) * PK, rn);
+      }
+      const double* bs = (kt & 1) ? Bs1 : Bs0;
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        const double a = st == 0 ? ra[0].x : st == 1 ? ra[0].y : st == 2 ? ra[1].x : ra[1].y;
+#pragma unroll
+        for (int c = 0; c < NBC; ++c)
+          if (FULL || c < nbc)
+            acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bs[(4 * g + st) * LDB + 16 * c + l16],
+                                                          acc[c], 0, 0, 0);
+      }
+      if (kt + 1 < nk) {
+        store_b((kt & 1) ? Bs0 : Bs1);
+        ra[0] = rn[0];
+        ra[1] = rn[1];
+      }
+      __syncthreads();
+    }
   }
   // epilogue: rows scaled by the slice's D (or D^{-1} for an entry marked sinv)
   const GLOBAL int8_t* sfield =
@@ -808,14 +880,24 @@ void k_prop(const GemmEntry* __restrict__ ents, const TileRef* __restrict__ tile
   }
 }
 
-// the factored engine's propagation over a tile list of (entry, 64-row tile)
-hipError_t launch_prop(int nmax, const GemmEntry* e, const TileRef* t, int n, GemmArgs a,
-                       hipStream_t s) {
+// the factored engine's propagation over a tile list of (entry, 64-row tile);
+// nmin, nmax: the fewest and most columns of the launch's factors
+hipError_t launch_prop(int nmin, int nmax, const GemmEntry* e, const TileRef* t, int n,
+                       GemmArgs a, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  if (nmax <= 112)
-    hipLaunchKernelGGL(k_prop<7>, dim3(n), dim3(kThreads), 0, s, e, t, n, a);
-  else
-    hipLaunchKernelGGL(k_prop<8>, dim3(n), dim3(kThreads), 0, s, e, t, n, a);
+  const int nb = (nmax + 15) / 16;
+  const bool full = (nmin + 15) / 16 == nb;
+  if (nb <= 7) {
+    if (full && nb == 7)
+      hipLaunchKernelGGL((k_prop<7, true>), dim3(n), dim3(kThreads), 0, s, e, t, n, a);
+    else
+      hipLaunchKernelGGL((k_prop<7, false>), dim3(n), dim3(kThreads), 0, s, e, t, n, a);
+  } else {
+    if (full)
+      hipLaunchKernelGGL((k_prop<8, true>), dim3(n), dim3(kThreads), 0, s, e, t, n, a);
+    else
+      hipLaunchKernelGGL((k_prop<8, false>), dim3(n), dim3(kThreads), 0, s, e, t, n, a);
+  }
   return hipGetLastError();
 }
 

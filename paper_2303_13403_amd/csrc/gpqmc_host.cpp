@@ -22,8 +22,8 @@ hipError_t launch_gemm(int fp32, int g_fp32, int mode, const GemmEntry* e, const
                        GemmArgs a, hipStream_t s);
 hipError_t launch_gemm_l(int mode, const GemmEntry* e, const TileRef* t, int n, GemmArgs a,
                          hipStream_t s);
-hipError_t launch_prop(int nmax, const GemmEntry* e, const TileRef* t, int n, GemmArgs a,
-                       hipStream_t s);
+hipError_t launch_prop(int nmin, int nmax, const GemmEntry* e, const TileRef* t, int n,
+                       GemmArgs a, hipStream_t s);
 hipError_t launch_gemm_l64(int mode, const GemmEntry* e, const TileRef* t, int n, GemmArgs a,
                            hipStream_t s);
 hipError_t launch_gemm_plain(int fp32, int transA, const GemmEntry* e, const TileRef* t, int n,
@@ -169,6 +169,7 @@ struct gpqmc_ctx {
   int nprop_max = 0;               // most proposals per slice (sites, or t-V bonds) in the batch
   int tv = 0;                      // 1: spinless t-V chains (every chain of the context)
   int n_part = 0;                  // largest particle number (either spin) of the batch
+  int n_part_min = 1 << 30;        // smallest particle number of a propagated spin
   int meas_cap = 4096;
   bool use_graph = true;
   float drift_tol = 1e-3f;
@@ -317,8 +318,8 @@ struct Launcher {
     // the factored engine's propagation of both factors: 64-row tiles over all
     // n columns (k_prop)
     if (mode == GM_PROPR && tk == T_Nn4 && !f32 && ctx->n_part <= 128)
-      return launch_prop(ctx->n_part, ents(ctx, kind), ctx->at<TileRef>(ctx->off_tiles[T_NP]),
-                         (int)ctx->tiles[T_NP].size(), a, s);
+      return launch_prop(ctx->n_part_min, ctx->n_part, ents(ctx, kind),
+                         ctx->at<TileRef>(ctx->off_tiles[T_NP]), (int)ctx->tiles[T_NP].size(), a, s);
     return launch_gemm(f32, ctx->fp32, mode, ents(ctx, kind), ctx->at<TileRef>(ctx->off_tiles[tk]),
                        (int)ctx->tiles[tk].size(), a, s);
   }
@@ -955,6 +956,7 @@ gpqmc_status gpqmc_create(int32_t n_chains, const gpqmc_chain_desc* chains,
     const long long padded = 128LL * ((h.N + 127) / 128);
     if (h.N < 128 || 4LL * h.N * h.N < 3 * padded * padded) c->large_tiles = false;
     c->n_part = std::max(c->n_part, std::max(h.n[0], h.n[1]));
+    c->n_part_min = std::min(c->n_part_min, (h.ph || h.tv) ? h.n[0] : std::min(h.n[0], h.n[1]));
     for (int sp = 0; sp < 2; ++sp) {
       sz[T_NN].push_back({h.N, h.N});
       sz[T_Nn].push_back({h.N, h.n[sp]});
