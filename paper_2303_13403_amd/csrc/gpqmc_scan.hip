@@ -1524,16 +1524,33 @@ __device__ __forceinline__ void block_store(const ChainDev& C, int sp, int tile,
 }
 
 // The block of a segment whose previous segment's update did not form it (the
-// first segment of a slice): one workgroup of four waves per chain and spin.
-__global__ __launch_bounds__(256) void k_block(const ChainDev* __restrict__ chains, int tv, int s0,
+// first segment of a slice): one workgroup of eight waves per chain and spin,
+// wave w forming tile w % 4 over one half of the columns; the second half's
+// partial sums meet the first's in LDS.
+__global__ __launch_bounds__(512) void k_block(const ChainDev* __restrict__ chains, int tv, int s0,
                                                int s1, int parity) {
   const int cs = xcd_remap(blockIdx.x, gridDim.x), sp = cs & 1;
   const ChainDev& C = chains[cs >> 1];
   if (sp >= C.nsp) return;
-  const int tile = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __shared__ double part[4 * 64 * 4];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int tile = wave & 3, half = wave >> 2, nn = C.n[sp];
+  const int kh = min(8 * ((nn + 15) / 16), nn);   // a multiple of 8
   bool valid;
-  const doublex4 acc = block_acc<16>(C, sp, tv, s0, s1, parity, tile, lane, 0, C.n[sp], valid);
-  if (valid) block_store(C, sp, tile, lane, acc);
+  doublex4 acc = block_acc<8>(C, sp, tv, s0, s1, parity, tile, lane, half ? kh : 0,
+                              half ? nn : kh, valid);
+  if (!valid) return;   // the same for the whole workgroup
+  double* pp = part + (tile * 64 + lane) * 4;
+  if (half) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) pp[i] = acc[i];
+  }
+  __syncthreads();
+  if (!half) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[i] += pp[i];
+    block_store(C, sp, tile, lane, acc);
+  }
 }
 
 template <bool TV>
@@ -2118,7 +2135,7 @@ void k_segupd_f(const ChainDev* __restrict__ chains, int dir, int parity, int tv
 hipError_t launch_scan_f(int tv, const ChainDev* c, int nc, const Ctl* ctl, int l, int M, int s0,
                          int s1, int dir, int parity, int form_block, hipStream_t s) {
   if (form_block) {
-    hipLaunchKernelGGL(k_block, dim3(2 * nc), dim3(256), 0, s, c, tv, s0, s1, parity);
+    hipLaunchKernelGGL(k_block, dim3(2 * nc), dim3(512), 0, s, c, tv, s0, s1, parity);
     if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
   }
   if (tv)
