@@ -696,9 +696,9 @@ hipError_t launch_gemm_l64(int mode, const GemmEntry* e, const TileRef* t, int n
 // places 64 chunks of 16 bytes side by side; the lanes pick their chunks so
 // that the operand reads are conflict-free:
 //   A stage: [8 pairs of k][64 rows] (a half-wave reads 16 rows x one pair);
-//   B stage: [16 k][8 NBC pairs], rows of 112 doubles (NBC = 7: consecutive
-//   rows land on opposite bank halves) or 128 with the pair index of odd
-//   rows XOR 8 (NBC = 8).
+//   B stage: [16 k][8 NBC pairs], rows of 16 NBC doubles (odd NBC:
+//   consecutive rows land on opposite bank halves; even NBC: the pair index of
+//   odd rows XOR 8).
 // Rows past M and k past K load clamped in-range addresses; the A operand is
 // zeroed past K and rows past M are not stored.  Otherwise the A operand is
 // read straight into registers (k slot g of step s taking k = k0 + 4 g + s)
@@ -720,6 +720,8 @@ void k_prop(const GemmEntry* __restrict__ ents, const TileRef* __restrict__ tile
   constexpr int NPR = 8 * NBC;           // pairs of columns per k row
   constexpr int NPAIR = PK * NPR;        // pairs of a k-tile
   constexpr int PER = (NPAIR + kThreads - 1) / kThreads;
+  constexpr int BI = (NPAIR + 255) / 256;   // direct loads of a B stage per wave
+  constexpr bool SWZ = (NBC & 1) == 0;
   static_assert(NPAIR <= 1024 && 2 * PK * LDB <= 2 * kPropStage, "stages hold the tiles");
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
   if (bid >= n_tiles) return;
@@ -760,11 +762,11 @@ void k_prop(const GemmEntry* __restrict__ ents, const TileRef* __restrict__ tile
                                          (LOCAL_V*)(st + kp * 64 * 2), 16, 0, 0);
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int base = (wave * 4 + u) * 64, c = base + lane;
+      for (int u = 0; u < BI; ++u) {
+        const int base = (wave * BI + u) * 64, c = base + lane;
         const int k = c / NPR;
         const int pd = c - k * NPR;
-        const int ps = NBC == 8 ? (pd ^ ((k & 1) << 3)) : pd;   // source pair of this slot
+        const int ps = SWZ ? (pd ^ ((k & 1) << 3)) : pd;   // source pair of this slot
         const int kk = min(k0 + k, K - 1), jj = min(2 * ps, n - 2);
         __builtin_amdgcn_global_load_lds((const GLOBAL_V*)(Bp + (size_t)kk * ldb + jj),
                                          (LOCAL_V*)(st + kPropSA + base * 2), 16, 0, 0);
@@ -786,7 +788,7 @@ void k_prop(const GemmEntry* __restrict__ ents, const TileRef* __restrict__ tile
         const int k = 4 * s4 + g;
         double a = st[((k >> 1) * 64 + 16 * wave + l16) * 2 + (k & 1)];
         a = k0 + k < K ? a : 0.0;
-        const int bx = NBC == 8 ? ((k & 1) << 4) : 0;
+        const int bx = SWZ ? ((k & 1) << 4) : 0;
 #pragma unroll
         for (int c = 0; c < NBC; ++c)
           if (FULL || c < nbc)
@@ -886,18 +888,28 @@ hipError_t launch_prop(int nmin, int nmax, const GemmEntry* e, const TileRef* t,
                        GemmArgs a, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const int nb = (nmax + 15) / 16;
-  const bool full = (nmin + 15) / 16 == nb;
-  if (nb <= 7) {
-    if (full && nb == 7)
-      hipLaunchKernelGGL((k_prop<7, true>), dim3(n), dim3(kThreads), 0, s, e, t, n, a);
-    else
-      hipLaunchKernelGGL((k_prop<7, false>), dim3(n), dim3(kThreads), 0, s, e, t, n, a);
-  } else {
-    if (full)
-      hipLaunchKernelGGL((k_prop<8, true>), dim3(n), dim3(kThreads), 0, s, e, t, n, a);
-    else
-      hipLaunchKernelGGL((k_prop<8, false>), dim3(n), dim3(kThreads), 0, s, e, t, n, a);
+  if ((nmin + 15) / 16 == nb) {   // every factor has nb column blocks
+    switch (nb) {
+#define GPQMC_PROP_FULL(B)                                                                  \
+  case B:                                                                                   \
+    hipLaunchKernelGGL((k_prop<B, true>), dim3(n), dim3(kThreads), 0, s, e, t, n, a);       \
+    return hipGetLastError();
+      GPQMC_PROP_FULL(1)
+      GPQMC_PROP_FULL(2)
+      GPQMC_PROP_FULL(3)
+      GPQMC_PROP_FULL(4)
+      GPQMC_PROP_FULL(5)
+      GPQMC_PROP_FULL(6)
+      GPQMC_PROP_FULL(7)
+      GPQMC_PROP_FULL(8)
+#undef GPQMC_PROP_FULL
+      default: break;
+    }
   }
+  if (nb <= 7)
+    hipLaunchKernelGGL((k_prop<7, false>), dim3(n), dim3(kThreads), 0, s, e, t, n, a);
+  else
+    hipLaunchKernelGGL((k_prop<8, false>), dim3(n), dim3(kThreads), 0, s, e, t, n, a);
   return hipGetLastError();
 }
 
