@@ -1802,8 +1802,23 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     // U[u][v] = X^{(u)}[j_u, j_v] + delta_uv / Delta_u for v >= u; in place,
     // since j_v >= v grows with v, no column is overwritten before it is read
     if (a < f) {
+      // eight reads in flight, then their writes: a chunk's writes land left
+      // of every later chunk's reads
       double* row = &hrow[s][a][0];
-      for (int v = a; v < f; ++v) row[v] = row[Fl[v]] + (v == a ? dinv : 0.0);
+#pragma unroll
+      for (int c0 = 0; c0 < KB; c0 += 8) {
+        double tv[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int v = c0 + q;
+          tv[q] = (v >= a && v < f) ? row[Fl[v] & (KB - 1)] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int v = c0 + q;
+          if (v >= a && v < f) row[v] = tv[q] + (v == a ? dinv : 0.0);
+        }
+      }
     }
     // L: the lane of site j_u holds X^{(v)}[j_u, j_v] for the earlier flips v
     // in hc[j_v]: L[u][v] = X^{(v)}[j_u, j_v] / U[v][v] (columns v < u of row
@@ -1821,26 +1836,38 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   // flips; beyond f, K and Z are the identity) and writes it to the chain's
   // Z buffer (row-major, 32 x 32) ----
   if (s < C.nsp) {
+    // two accumulators per dot product and 16-byte row reads; past f the
+    // packed rows hold finite history entries and y, z are zero there, so
+    // the sums run over whole rows without a guard per entry
     double zc[KB];
 #pragma unroll
     for (int i = 0; i < KB; ++i) {
-      double v = (i == a) ? 1.0 : 0.0;
+      double v0 = (i == a) ? 1.0 : 0.0, v1 = 0.0;
       if (i < f && a < f) {
         const double* row = &hrow[s][i][0];
 #pragma unroll
-        for (int j = 0; j < i; ++j) v -= row[j] * zc[j];
+        for (int j = 0; j + 1 < i; j += 2) {
+          const double2 r = *reinterpret_cast<const double2*>(row + j);
+          v0 -= r.x * zc[j];
+          v1 -= r.y * zc[j + 1];
+        }
+        if (i & 1) v0 -= row[i - 1] * zc[i - 1];
       }
-      zc[i] = v;
+      zc[i] = v0 + v1;
     }
 #pragma unroll
     for (int i = KB - 1; i >= 0; --i) {
       if (i < f && a < f) {
         const double* row = &hrow[s][i][0];
-        double v = zc[i];
+        double v0 = zc[i], v1 = 0.0;
+        if (((i + 1) & 1) && i + 1 < KB) v0 -= row[i + 1] * zc[i + 1];
 #pragma unroll
-        for (int j = i + 1; j < KB; ++j)
-          if (j < f) v -= row[j] * zc[j];
-        zc[i] = v * pinv[s][i];
+        for (int j = (i + 2) & ~1; j + 1 < KB; j += 2) {
+          const double2 r = *reinterpret_cast<const double2*>(row + j);
+          v0 -= r.x * zc[j];
+          v1 -= r.y * zc[j + 1];
+        }
+        zc[i] = (v0 + v1) * pinv[s][i];
       }
     }
     GLOBAL double* __restrict__ z = gp((double*)C.Z[s]);
