@@ -1426,19 +1426,20 @@ __device__ __forceinline__ void static_for(Fn&& fn) {
 // chain does the whole segment.
 //
 // Lane (s, a) = (lane / 32, lane % 32) keeps row a of the spin-s block
-// G_s[S,S] = 1 - A[S,:] B[S,:]^T in registers; the block is formed with the
-// rows of B staged through LDS in k-chunks.  Every proposal reads the two
-// diagonal entries with readlane; an accepted flip t at site j_t writes the
-// row X[j_t, S] (X = 1 - G) of the current block to LDS, where it both feeds
-// the Sherman-Morrison update of every lane's row and stays as history, and
-// every lane also keeps X[a, j_t].  Those rows and columns are the Schur
+// G_s[S,S] = 1 - A[S,:] B[S,:]^T in registers (the block comes from the
+// chain's scan buffer, formed by k_block or by the previous segment's
+// update).  Every proposal reads the two diagonal entries with readlane; an
+// accepted flip t at site j_t writes the row X[j_t, S] (X = 1 - G) of the
+// current block to LDS, where it both feeds the Sherman-Morrison update of
+// every lane's row and stays as history, and every lane also keeps X[a, j_t]
+// in a register indexed by j_t.  Those rows and columns are the Schur
 // complements of K = Delta_F^{-1} + X_s[F,F] (X_s: the block at the segment's
 // start) in flip order, so they give K = L U directly:
 //   U[t][v] = X^{(t)}[j_t, j_v] + delta_tv / Delta_t   (v >= t),
 //   L[u][t] = X^{(t)}[j_u, j_t] / U[t][t]               (u > t),
-// with X^{(t)} the block before flip t.  The Woodbury core is Z = K^{-1}; the
-// wave writes the packed L U factors (32 x 32 per spin) to the Z buffer.
-// k_wf then forms the Woodbury rows and k_segupd_f applies them.
+// with X^{(t)} the block before flip t.  The wave then writes the Woodbury
+// core Z = K^{-1} (32 x 32 per spin) to the Z buffer; k_segupd_f (or, with
+// more than 128 particles, k_wf and two GEMMs) applies it.
 // ---------------------------------------------------------------------------
 // ---------------------------------------------------------------------------
 // Block of a scan segment, G_s[S, S] = 1 - A[S, :] B[S, :]^T for one chain and
@@ -1592,12 +1593,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   int8_t* frow = C.field + (size_t)l * nprop;
   const uint32_t sweep = (uint32_t)st->sweep;
   const bool force_reject = ctl->force_reject != 0;
+  // lane j < 32 also keeps proposal j's uniform and field in registers (read
+  // by readlane in the site loop)
+  double my_u = 0.0;
+  int my_f = 1;
   if (lane < nseg) {
     uint32_t c[4] = {C.chain_id, sweep, (uint32_t)l, (uint32_t)(s0 + lane)};
     philox4x32_10(c, C.key0, C.key1);
-    u_s[lane] = uniform53(c[0], c[1]);
-    fs[lane] = frow[s0 + lane];
-    fs0[lane] = fs[lane];
+    my_u = uniform53(c[0], c[1]);
+    u_s[lane] = my_u;
+    my_f = frow[s0 + lane];
+    fs[lane] = (int8_t)my_f;
+    fs0[lane] = (int8_t)my_f;
   }
   if (lane < KB) tpos[lane] = -1;
   int my_site = 0;
@@ -1718,11 +1725,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
 #pragma unroll
   for (int j = 0; j < KB; ++j) {
     if (j < nseg) {
-      const int si = fs[j] > 0 ? 0 : 1;
+      const int si = __builtin_amdgcn_readlane(my_f, j) > 0 ? 0 : 1;
       const double du = si ? dl_u1 : dl_u0, dd = si ? dl_d1 : dl_d0;
       const double ru = 1.0 + du * (1.0 - lane_value(g[j], j));
       const double rd = 1.0 + dd * (1.0 - lane_value(g[j], 32 + j));
-      const bool accept = !force_reject && (u_s[j] < fabs(ru * rd));
+      const bool accept = !force_reject && (lane_value(my_u, j) < fabs(ru * rd));
       if (lane == 0 && trace_ratio) {
         trace_ratio[((size_t)l * N + s0 + j) * 2 + 0] = ru;
         trace_ratio[((size_t)l * N + s0 + j) * 2 + 1] = rd;
@@ -1758,7 +1765,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
           }
           fc = t + 1;
         }
-        if (lane == 0) fs[j] = (int8_t)(-fs[j]);
+        if (lane == j) my_f = -my_f;
         if (ru * rd < 0) sign = -sign;
         nacc += 1;
       }
@@ -1767,7 +1774,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   }
   wave_sync();
   const int f = fc;
-  if (lane < nseg) frow[s0 + lane] = fs[lane];
+  if (lane < nseg) frow[s0 + lane] = TV ? fs[lane] : (int8_t)my_f;
   if constexpr (TV) {
     // site exponents of the flipped bonds: the A end changes by -2 s_old, the
     // B end by +2 s_old
