@@ -360,6 +360,16 @@ def test_mixed_batch_of_odd_and_even_lattices_follows_oracle():
     ctx.close()
 
 
+@pytest.mark.parametrize("ph", [False, True])
+def test_fixed_field_pass_18x18_wide_segment_update(ph):
+    """18x18 at half filling (N = 324, 162 + 162 electrons, k = 32): more than
+    128 particles per spin, so the one-wave scan feeds the Woodbury rows and
+    the two segment GEMMs, and the propagation takes the general GEMM; with
+    and without the particle-hole shortcut."""
+    w = small("fp64", L=18, l_half=3, n_s=2, k=32)
+    check_fixed_field(w, "fp64", **({"particle_hole": True} if ph else {}))
+
+
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_fixed_field_pass_24x24(prec):
     """The large workload (N = 576, 288 + 288 electrons, dtau = 0.05, k = 64):

@@ -72,6 +72,8 @@ FIXED = [
     (dict(l=3, l_half=0, n_s=1, k=8), TOL),                    # boundary slices only
     (dict(l=3, V=0.0, g=0.0, l_half=3, n_s=2, k=8), TOL),      # no field acts
     (dict(l=8, kind="ring", l_half=3, n_s=2, k=6), TOL),       # a ring of 8 sites, 3 per segment
+    (dict(l=12, l_half=2, n_s=2, k=32), TOL),                  # 288 sites, 144 particles: the
+                                                               # general segment update
 ]
 
 
