@@ -685,9 +685,10 @@ hipError_t launch_gemm_l64(int mode, const GemmEntry* e, const TileRef* t, int n
 // Basis propagation of the factored engine, C[p^1] = D (A B[p]): A is the
 // lattice exponential e^{-+dtau K} (N x N, one copy shared by the chains of a
 // lattice, so it stays in L2) and B[p] a factor (N x n, n <= 16 NBC).  One
-// workgroup of four waves per 64 rows of the output and all of its n columns
-// (no column tiles padded past n); wave w owns rows 16 w .. 16 w + 15 and the
-// NBC 16-column blocks, MFMA k-steps of 4 over k-tiles of 16.
+// workgroup of W waves (8, or 4 where 128-row tiles would be mostly padding)
+// per 16 W rows of the output and all of its n columns (no column tiles
+// padded past n); wave w owns rows 16 w .. 16 w + 15 and the NBC 16-column
+// blocks, MFMA k-steps of 4 over k-tiles of 16.
 //
 // With every row 16-byte aligned (even N and n), both operands of a k-tile
 // go to LDS by direct loads (global_load_lds_dwordx4: no registers, no LDS
@@ -695,7 +696,7 @@ hipError_t launch_gemm_l64(int mode, const GemmEntry* e, const TileRef* t, int n
 // the current one's MFMAs, one barrier per k-tile.  Each load instruction
 // places 64 chunks of 16 bytes side by side; the lanes pick their chunks so
 // that the operand reads are conflict-free:
-//   A stage: [8 pairs of k][64 rows] (a half-wave reads 16 rows x one pair);
+//   A stage: [8 pairs of k][16 W rows] (a half-wave reads 16 rows x one pair);
 //   B stage: [16 k][8 NBC pairs], rows of 16 NBC doubles (odd NBC:
 //   consecutive rows land on opposite bank halves; even NBC: the pair index of
 //   odd rows XOR 8).
@@ -706,28 +707,30 @@ hipError_t launch_gemm_l64(int mode, const GemmEntry* e, const TileRef* t, int n
 // ---------------------------------------------------------------------------
 #define GLOBAL_V __attribute__((address_space(1))) void
 #define LOCAL_V __attribute__((address_space(3))) void
-constexpr int kPropSA = 8 * 64 * 2;                  // doubles of an A stage
 constexpr int kPropSB = 1024 * 2;                     // doubles of a B stage (1024 chunks)
-constexpr int kPropStage = kPropSA + kPropSB;
 
 // FULL: every entry of the launch has NBC column blocks (no per-block guard)
-template <int NBC, bool FULL>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3)))
+template <int NBC, bool FULL, int W>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(W == 8 ? 4 : 3)))
 void k_prop(const GemmEntry* __restrict__ ents, const TileRef* __restrict__ tiles, int n_tiles,
             GemmArgs args) {
+  constexpr int kPropThreads = 64 * W;
+  constexpr int kPropRows = 16 * W;      // output rows per workgroup
+  constexpr int kPropSA = 8 * kPropRows * 2;   // doubles of an A stage
+  constexpr int kPropStage = kPropSA + kPropSB;
   constexpr int PK = 16;                 // k-tile
   constexpr int LDB = 16 * NBC + 4;      // register path: LDS row of a B k-tile
   constexpr int NPR = 8 * NBC;           // pairs of columns per k row
   constexpr int NPAIR = PK * NPR;        // pairs of a k-tile
-  constexpr int PER = (NPAIR + kThreads - 1) / kThreads;
-  constexpr int BI = (NPAIR + 255) / 256;   // direct loads of a B stage per wave
+  constexpr int PER = (NPAIR + kPropThreads - 1) / kPropThreads;
+  constexpr int BI = (NPAIR + kPropThreads - 1) / kPropThreads;   // direct loads of a B stage per wave
   constexpr bool SWZ = (NBC & 1) == 0;
   static_assert(NPAIR <= 1024 && 2 * PK * LDB <= 2 * kPropStage, "stages hold the tiles");
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
   if (bid >= n_tiles) return;
   const TileRef tr = tiles[bid];
   const GemmEntry& e = ents[tr.entry];
-  const int M = e.M, n = e.N, K = e.K, m0 = tr.tm * kTile;
+  const int M = e.M, n = e.N, K = e.K, m0 = tr.tm * kPropRows;
   if (m0 >= M) return;
   const int p = args.parity;
   const double* Ap = (const double*)e.A[0];
@@ -751,15 +754,16 @@ void k_prop(const GemmEntry* __restrict__ ents, const TileRef* __restrict__ tile
 
   if (avec && bvec && (K & 1) == 0 && (n & 1) == 0) {
     // ---- direct-to-LDS path ----
-    const int arow = min(m0 + lane, M - 1);
     auto issue = [&](int kt) {
       const int k0 = kt * PK;
       double* st = ring + (kt & 1) * kPropStage;
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
-        const int kp = 2 * wave + u, kk = min(k0 + 2 * kp, K - 2);
+        const int c = (wave * 2 + u) * 64;   // chunk base: pair c / 128, rows c % 128 + lane
+        const int kp = c / kPropRows, arow = min(m0 + c % kPropRows + lane, M - 1);
+        const int kk = min(k0 + 2 * kp, K - 2);
         __builtin_amdgcn_global_load_lds((const GLOBAL_V*)(Ap + (size_t)arow * lda + kk),
-                                         (LOCAL_V*)(st + kp * 64 * 2), 16, 0, 0);
+                                         (LOCAL_V*)(st + c * 2), 16, 0, 0);
       }
 #pragma unroll
       for (int u = 0; u < BI; ++u) {
@@ -786,7 +790,7 @@ void k_prop(const GemmEntry* __restrict__ ents, const TileRef* __restrict__ tile
 #pragma unroll
       for (int s4 = 0; s4 < 4; ++s4) {
         const int k = 4 * s4 + g;
-        double a = st[((k >> 1) * 64 + 16 * wave + l16) * 2 + (k & 1)];
+        double a = st[((k >> 1) * kPropRows + 16 * wave + l16) * 2 + (k & 1)];
         a = k0 + k < K ? a : 0.0;
         const int bx = SWZ ? ((k & 1) << 4) : 0;
 #pragma unroll
@@ -808,7 +812,7 @@ void k_prop(const GemmEntry* __restrict__ ents, const TileRef* __restrict__ tile
     auto load_b = [&](int kb) {
 #pragma unroll
       for (int u = 0; u < PER; ++u) {
-        const int idx = tid + u * kThreads, k = idx / NPR, j = 2 * (idx - k * NPR), kk = kb + k;
+        const int idx = tid + u * kPropThreads, k = idx / NPR, j = 2 * (idx - k * NPR), kk = kb + k;
         const bool ok = idx < NPAIR && kk < K;
         const GLOBAL double* src = B + (ok ? (size_t)kk * ldb + j : 0);
         if (bvec && ok && j + 1 < n) {
@@ -821,7 +825,7 @@ void k_prop(const GemmEntry* __restrict__ ents, const TileRef* __restrict__ tile
     auto store_b = [&](double* bs) {
 #pragma unroll
       for (int u = 0; u < PER; ++u) {
-        const int idx = tid + u * kThreads, k = idx / NPR, j = 2 * (idx - k * NPR);
+        const int idx = tid + u * kPropThreads, k = idx / NPR, j = 2 * (idx - k * NPR);
         if (idx < NPAIR) *reinterpret_cast<v2*>(&bs[k * LDB + j]) = rbv[u];
       }
     };
@@ -882,17 +886,25 @@ void k_prop(const GemmEntry* __restrict__ ents, const TileRef* __restrict__ tile
   }
 }
 
-// the factored engine's propagation over a tile list of (entry, 64-row tile);
-// nmin, nmax: the fewest and most columns of the launch's factors
-hipError_t launch_prop(int nmin, int nmax, const GemmEntry* e, const TileRef* t, int n,
+// the factored engine's propagation over a tile list of (entry, row tile);
+// nmin, nmax: the fewest and most columns of the launch's factors; rows: the
+// output rows of a tile (64 or 128, as the tile list was built)
+hipError_t launch_prop(int nmin, int nmax, int rows, const GemmEntry* e, const TileRef* t, int n,
                        GemmArgs a, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const int nb = (nmax + 15) / 16;
+#define LAUNCH_PROP(B, F)                                                                    \
+  do {                                                                                       \
+    if (rows == 128)                                                                         \
+      hipLaunchKernelGGL((k_prop<B, F, 8>), dim3(n), dim3(512), 0, s, e, t, n, a);           \
+    else                                                                                     \
+      hipLaunchKernelGGL((k_prop<B, F, 4>), dim3(n), dim3(256), 0, s, e, t, n, a);           \
+  } while (0)
   if ((nmin + 15) / 16 == nb) {   // every factor has nb column blocks
     switch (nb) {
-#define GPQMC_PROP_FULL(B)                                                                  \
-  case B:                                                                                   \
-    hipLaunchKernelGGL((k_prop<B, true>), dim3(n), dim3(kThreads), 0, s, e, t, n, a);       \
+#define GPQMC_PROP_FULL(B) \
+  case B:                  \
+    LAUNCH_PROP(B, true);  \
     return hipGetLastError();
       GPQMC_PROP_FULL(1)
       GPQMC_PROP_FULL(2)
@@ -907,9 +919,10 @@ hipError_t launch_prop(int nmin, int nmax, const GemmEntry* e, const TileRef* t,
     }
   }
   if (nb <= 7)
-    hipLaunchKernelGGL((k_prop<7, false>), dim3(n), dim3(kThreads), 0, s, e, t, n, a);
+    LAUNCH_PROP(7, false);
   else
-    hipLaunchKernelGGL((k_prop<8, false>), dim3(n), dim3(kThreads), 0, s, e, t, n, a);
+    LAUNCH_PROP(8, false);
+#undef LAUNCH_PROP
   return hipGetLastError();
 }
 

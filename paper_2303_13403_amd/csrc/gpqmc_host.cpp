@@ -22,7 +22,7 @@ hipError_t launch_gemm(int fp32, int g_fp32, int mode, const GemmEntry* e, const
                        GemmArgs a, hipStream_t s);
 hipError_t launch_gemm_l(int mode, const GemmEntry* e, const TileRef* t, int n, GemmArgs a,
                          hipStream_t s);
-hipError_t launch_prop(int nmin, int nmax, const GemmEntry* e, const TileRef* t, int n,
+hipError_t launch_prop(int nmin, int nmax, int rows, const GemmEntry* e, const TileRef* t, int n,
                        GemmArgs a, hipStream_t s);
 hipError_t launch_gemm_l64(int mode, const GemmEntry* e, const TileRef* t, int n, GemmArgs a,
                            hipStream_t s);
@@ -170,6 +170,7 @@ struct gpqmc_ctx {
   int tv = 0;                      // 1: spinless t-V chains (every chain of the context)
   int n_part = 0;                  // largest particle number (either spin) of the batch
   int n_part_min = 1 << 30;        // smallest particle number of a propagated spin
+  int prop_rows = 128;             // output rows of a propagation tile (64 or 128)
   int meas_cap = 4096;
   bool use_graph = true;
   float drift_tol = 1e-3f;
@@ -315,10 +316,10 @@ struct Launcher {
         return launch_gemm_l64(mode, ents(ctx, kind), ctx->at<TileRef>(ctx->off_tiles[T_NN_L]),
                                (int)ctx->tiles[T_NN_L].size(), a, s);
     }
-    // the factored engine's propagation of both factors: 64-row tiles over all
+    // the factored engine's propagation of both factors: row tiles over all
     // n columns (k_prop)
     if (mode == GM_PROPR && tk == T_Nn4 && !f32 && ctx->n_part <= 128)
-      return launch_prop(ctx->n_part_min, ctx->n_part, ents(ctx, kind),
+      return launch_prop(ctx->n_part_min, ctx->n_part, ctx->prop_rows, ents(ctx, kind),
                          ctx->at<TileRef>(ctx->off_tiles[T_NP]), (int)ctx->tiles[T_NP].size(), a, s);
     return launch_gemm(f32, ctx->fp32, mode, ents(ctx, kind), ctx->at<TileRef>(ctx->off_tiles[tk]),
                        (int)ctx->tiles[tk].size(), a, s);
@@ -957,6 +958,8 @@ gpqmc_status gpqmc_create(int32_t n_chains, const gpqmc_chain_desc* chains,
     if (h.N < 128 || 4LL * h.N * h.N < 3 * padded * padded) c->large_tiles = false;
     c->n_part = std::max(c->n_part, std::max(h.n[0], h.n[1]));
     c->n_part_min = std::min(c->n_part_min, (h.ph || h.tv) ? h.n[0] : std::min(h.n[0], h.n[1]));
+    // 128-row propagation tiles only where they waste no more rows than 64-row ones
+    if ((h.N + 127) / 128 * 128 > (h.N + 63) / 64 * 64) c->prop_rows = 64;
     for (int sp = 0; sp < 2; ++sp) {
       sz[T_NN].push_back({h.N, h.N});
       sz[T_Nn].push_back({h.N, h.n[sp]});
@@ -965,7 +968,7 @@ gpqmc_status gpqmc_create(int32_t n_chains, const gpqmc_chain_desc* chains,
       sz[T_NN_L].push_back({h.N, h.N});
       sz[T_Nn4].push_back({h.N, h.n[sp]});   // factor A of this spin
       sz[T_Nn4].push_back({h.N, h.n[sp]});   // factor B
-      sz[T_NP].push_back({h.N, h.n[sp]});    // the same two, 64-row tiles over all columns
+      sz[T_NP].push_back({h.N, h.n[sp]});    // the same two, row tiles over all columns
       sz[T_NP].push_back({h.N, h.n[sp]});
       sz[T_Nk].push_back({h.N, c->kseg});
       const char sk = (sp == 1 && (h.ph || h.tv)) ? 1 : 0;
@@ -975,7 +978,8 @@ gpqmc_status gpqmc_create(int32_t n_chains, const gpqmc_chain_desc* chains,
     }
   }
   for (int t = 0; t < T_COUNT; ++t) {
-    build_tiles(c->tiles[t], sz[t], skip[t], t == T_NN_L ? 128 : kTile, t == T_NP);
+    build_tiles(c->tiles[t], sz[t], skip[t],
+                t == T_NN_L ? 128 : t == T_NP ? c->prop_rows : kTile, t == T_NP);
     c->off_tiles[t] = take(sizeof(TileRef) * c->tiles[t].size());
   }
   c->bytes = align256(off);
