@@ -687,8 +687,8 @@ hipError_t launch_gemm_l64(int mode, const GemmEntry* e, const TileRef* t, int n
 // lattice, so it stays in L2) and B[p] a factor (N x n, n <= 16 NBC).  One
 // workgroup of W waves (8, or 4 for a batch where 128-row tiles would pad
 // more rows than 64-row ones) per 16 W rows of the output and all of its n
-// columns (no column tiles padded past n); wave w owns rows 16 w .. 16 w + 15 and the NBC 16-column
-// blocks, MFMA k-steps of 4 over k-tiles of 16.
+// columns (no column tiles padded past n); wave w owns rows 16 w .. 16 w + 15
+// and the NBC 16-column blocks, MFMA k-steps of 4 over k-tiles of 16.
 //
 // With every row 16-byte aligned (even N and n), both operands of a k-tile
 // go to LDS by direct loads (global_load_lds_dwordx4: no registers, no LDS
