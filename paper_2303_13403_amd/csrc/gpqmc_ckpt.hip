@@ -462,7 +462,14 @@ __device__ inline void rt_clear(double (*rk)[kRtMax], double (*rp)[kRtMax], doub
   __shared__ int piv[kRtMax], colmap[kRtMax];           \
   __shared__ double pabs[kRtMax];
 
-// Cholesky W = R^T R (R upper) of the Gram matrix, then R^{-1}, in registers.
+// Cholesky factor of the Gram matrix W = R^T R (R upper) and its inverse in
+// one pass of n elimination steps, in registers.  Eliminating below each
+// pivot of W without pivoting gives W = L U with L unit lower; applying the
+// same row operations to the identity gives L^{-1}, which is kept in place in
+// the eliminated slots (as in an in-place Gauss-Jordan inverse).  Since
+// L = R^T diag(R)^{-1}, U = diag(R) R and R_jj = sqrt(U_jj), the inverse is
+// R^{-1} = (L^{-1})^T diag(R)^{-1}.  The trailing block stays symmetric, so
+// the multipliers of step j are read from row j.
 // (At most 168 registers for the 7 x 7 tiles: three workgroups per CU.)
 template <int NB, int TG>
 __global__ __launch_bounds__(TG * TG) __attribute__((amdgpu_waves_per_eu(NB == 7 ? 3 : 1)))
@@ -471,89 +478,77 @@ void k_chol_inv_rt(const ChainDev* __restrict__ chains) {
   const ChainDev& C = chains[lg >> 1];
   const int sp = lg & 1, n = C.n[sp], tid = threadIdx.x;
   if (sp >= C.nsp) return;
-  GPQMC_RT_SHARED
-  rt_clear(rk, rp, ck);
+  // row j of step j (double-buffered; entries beyond n stay zero) and the
+  // pivots U_jj
+  __shared__ double rk[2][kRtMax], pabs[kRtMax];
+  for (int i = tid; i < 2 * kRtMax; i += blockDim.x) rk[i / kRtMax][i % kRtMax] = 0.0;
   RegTile<NB, TG> T;
   T.load(gp(C.Wm[sp]), n);
-  double lsum = 0.0;
   bool bad = false;
   for (int j = 0; j < n; ++j) {
     const int jb = j & 1;
     T.put_row(j, rk[jb]);
     __syncthreads();
-    const double d2 = rk[jb][j];
-    if (!(d2 > 0.0)) {   // not positive definite (or NaN): flag, keep going finitely
-      bad = true;
-      if (tid == 0) pabs[j] = 1.0;   // no contribution to log|det R|
+    const double u = rk[jb][j];
+    // not positive definite (or NaN): flag, take no multipliers at this
+    // step and R_jj = 1, so that every value stays finite
+    const bool ok = u > 0.0;
+    if (!ok) bad = true;
+    if (tid == 0) pabs[j] = ok ? u : 1.0;
+    const double iu = ok ? 1.0 / u : 0.0;
+    // rows below j: row -= l_rj (row j), every column; the slot of column j
+    // then receives L^{-1}_rj = -l_rj
+    double rc[NB], rl[NB];
 #pragma unroll
-      for (int a = 0; a < NB; ++a)
-#pragma unroll
-        for (int b = 0; b < NB; ++b)
-          if (T.ti + TG * a == j && T.tj + TG * b == j) T.m[a][b] = 1.0;
-      continue;
-    }
-    const double d = sqrt(d2), id = 1.0 / d;
-    if (tid == 0) pabs[j] = d;   // logged after the loop
-    // normalised row j at the thread's columns (zero left of j) and rows
-    // (zero at and above j): one FMA per element updates the trailing matrix
-    // (its lower triangle too, which is cleared at the end) and leaves the
-    // finished rows unchanged; row j itself is then rewritten
-    double rc[NB], rr[NB];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const int c = T.tj + TG * b;
-      rc[b] = c >= j ? rk[jb][c] * id : 0.0;
-    }
+    for (int b = 0; b < NB; ++b) rc[b] = rk[jb][T.tj + TG * b];
 #pragma unroll
     for (int a = 0; a < NB; ++a) {
       const int r = T.ti + TG * a;
-      rr[a] = r > j ? rk[jb][r] * id : 0.0;
+      rl[a] = r > j ? rk[jb][r] * iu : 0.0;
     }
 #pragma unroll
     for (int a = 0; a < NB; ++a)
 #pragma unroll
-      for (int b = 0; b < NB; ++b) T.m[a][b] = fma(-rr[a], rc[b], T.m[a][b]);
-    const int aj = j / TG;
-    const bool lj = T.ti == j % TG;
-#pragma unroll
-    for (int a = 0; a < NB; ++a)
-      if (a == aj) {
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-          const int c = T.tj + TG * b;
-          const double rowj = (c == j) ? d : rc[b];
-          T.m[a][b] = (lj & (c >= j)) ? rowj : T.m[a][b];
-        }
-      }
-  }
-  // clear the lower triangle
-#pragma unroll
-  for (int a = 0; a < NB; ++a)
+      for (int b = 0; b < NB; ++b) T.m[a][b] = fma(-rl[a], rc[b], T.m[a][b]);
+    const int bj = j / TG;
+    const bool lj = T.tj == j % TG;
 #pragma unroll
     for (int b = 0; b < NB; ++b)
-      if (T.tj + TG * b < T.ti + TG * a) T.m[a][b] = 0.0;
-  // log|det R| = sum of log R_jj: the logs on n threads at once, summed in
-  // order by thread 0
+      if (b == bj) {
+#pragma unroll
+        for (int a = 0; a < NB; ++a) T.m[a][b] = lj ? -rl[a] : T.m[a][b];
+      }
+  }
+  // 1 / R_rr of the thread's rows, then log|det R| = (1/2) sum of log U_jj:
+  // the logs on n threads at once, summed in order by thread 0
+  __syncthreads();
+  double rs[NB];
+#pragma unroll
+  for (int a = 0; a < NB; ++a) {
+    const int r = T.ti + TG * a;
+    rs[a] = r < n ? 1.0 / sqrt(pabs[r]) : 0.0;
+  }
   __syncthreads();
   for (int c = tid; c < n; c += blockDim.x) pabs[c] = log(pabs[c]);
   __syncthreads();
-  if (tid == 0)
-    for (int c = 0; c < n; ++c) lsum += pabs[c];
   if (tid == 0) {
-    C.st->chk_log[sp] = lsum;
+    double lsum = 0.0;
+    for (int c = 0; c < n; ++c) lsum += pabs[c];
+    C.st->chk_log[sp] = 0.5 * lsum;
     C.st->chk_sgn[sp] = 1;
     if (bad) atomicOr(&C.st->flags, (int)FLAG_SINGULAR);
   }
-  double la;
-  int sg;
-  // the inverse's first step rewrites rk[0], which the last Cholesky step
-  // (j = n - 1 even) may still be reading
-  __syncthreads();
-  rt_invert<NB, TG>(T, true, rk, rp, ck, cv, ci, piv, colmap, pabs, false, la, sg);
-  if (sg != 0)
-    rt_store<NB, TG>(T, gp(C.Rinv[sp]), colmap, true);
-  else if (tid == 0)
-    atomicOr(&C.st->flags, (int)FLAG_SINGULAR);
+  // R^{-1}[c][r] = L^{-1}[r][c] / R_rr (r > c), 1 / R_rr on the diagonal, zero
+  // below it: each element goes to its transposed place
+  GLOBAL double* __restrict__ g = gp(C.Rinv[sp]);
+#pragma unroll
+  for (int a = 0; a < NB; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int r = T.ti + TG * a, c = T.tj + TG * b;
+      if (r < n && c < n)
+        g[(size_t)c * n + r] = r > c ? T.m[a][b] * rs[a] : (r == c ? rs[a] : 0.0);
+    }
 }
 
 // Inverse of X = L R (n x n) in place, partial pivoting; log|det X| and its
