@@ -310,6 +310,20 @@ def test_fixed_field_pass_odd_lattice(prec, kw):
     check_fixed_field(rect(prec, **kw), prec)
 
 
+# doped lattices whose particle numbers per spin fall in the register-tile
+# widths of the checkpoint factorisations (16 x 16 threads, ceil(n / 16)
+# columns each) that no other case meets: 33-48, 81-96 and 113-128.  At
+# n = 128, the largest width, the fused segment update and the propagation
+# also span all eight 16-column blocks.  The ramp closes the trial's shell.
+WIDTHS = [dict(L=8, n=40), dict(L=12, n=90), dict(L=12, n=128)]
+
+
+@pytest.mark.parametrize("kw", WIDTHS)
+def test_fixed_field_pass_every_factorisation_width(kw):
+    w = small("fp64", l_half=3, n_s=2, k=32, U=3.0, ramp=0.1, **kw)
+    check_fixed_field(w, "fp64")
+
+
 def honey(prec, l1, l2, U=4.0, l_half=5, n_s=3, k=8):
     """Half-filled l1 x l2 honeycomb lattice (2 l1 l2 sites), the paper's
     Hubbard lattice (Eq. 2)."""
