@@ -491,7 +491,7 @@ void k_chol_inv_rt(const ChainDev* __restrict__ chains) {
     __syncthreads();
     const double u = rk[jb][j];
     // not positive definite (or NaN): flag, take no multipliers at this
-    // step and R_jj = 1, so that every value stays finite
+    // step and R_jj = 1, so that a finite matrix keeps every value finite
     const bool ok = u > 0.0;
     if (!ok) bad = true;
     if (tid == 0) pabs[j] = ok ? u : 1.0;
