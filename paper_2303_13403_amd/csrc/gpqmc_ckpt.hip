@@ -586,6 +586,35 @@ __global__ __launch_bounds__(kThreads) void k_basis_to_fp64(const ChainDev* __re
   }
 }
 
+// Visits every (i, j) of the N x N matrices G0 (and G1, NM = 2) with G_ij read
+// by the caller and G_ji handed in: the matrices are walked in 32 x 32 tiles
+// whose transposes are staged in LDS, so that every global read is coalesced
+// (a plain loop over (i, j) reads G_ji with a stride of N).
+constexpr int kPairTile = 32;
+template <int NM, class F>
+__device__ void visit_pairs(int N, const GLOBAL double* __restrict__ G0,
+                            const GLOBAL double* __restrict__ G1,
+                            double (*tt)[kPairTile][kPairTile + 1], F f) {
+  const int tid = threadIdx.x;
+  for (int i0 = 0; i0 < N; i0 += kPairTile)
+    for (int j0 = 0; j0 < N; j0 += kPairTile) {
+      __syncthreads();   // the previous tile is read
+      for (int t = tid; t < kPairTile * kPairTile; t += kThreads) {
+        const int a = t / kPairTile, b = t % kPairTile;
+        const int j = j0 + a, i = i0 + b;   // row j of G, along i
+        const bool ok = i < N && j < N;
+        tt[0][a][b] = ok ? G0[(size_t)j * N + i] : 0.0;
+        if (NM == 2) tt[1][a][b] = ok ? G1[(size_t)j * N + i] : 0.0;
+      }
+      __syncthreads();
+      for (int t = tid; t < kPairTile * kPairTile; t += kThreads) {
+        const int a = t / kPairTile, b = t % kPairTile;
+        const int i = i0 + a, j = j0 + b;
+        if (i < N && j < N) f(i, j, tt[0][b][a], NM == 2 ? tt[1][b][a] : 0.0);
+      }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // checkpoint bookkeeping (one workgroup per chain)
 // mode 0: checkpoint of a pass (sign check, drift);  1: final checkpoint of
@@ -604,6 +633,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const ChainDev* __restric
   ChainState* st = C.st;
   const int N = C.N, tid = threadIdx.x, nsp = C.nsp;
   __shared__ double red[4];
+  __shared__ double tt[2][kPairTile][kPairTile + 1];   // transposed tiles of the measurement
   for (int sp = 0; sp < nsp; ++sp) {
     const size_t sz = (size_t)N * C.n[sp];
     GLOBAL double* dst = gp(C.stack[sp] + (size_t)slot * sz);
@@ -710,13 +740,13 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const ChainDev* __restric
     const GLOBAL double* __restrict__ G = gp((const double*)C.G64[0]);
     const GLOBAL int8_t* __restrict__ eps = gp(C.eps);
     double ek = 0.0, cross = 0.0, mc = 0.0, ev = 0.0, nnb = 0.0;
-    for (int idx = tid; idx < N * N; idx += kThreads) {
-      const int i = idx / N, j = idx - i * N;
-      const double gb = (i == j ? 1.0 : 0.0) - G[(size_t)j * N + i];
+    visit_pairs<1>(N, G, nullptr, tt, [&](int i, int j, double gt, double) {
+      const size_t idx = (size_t)i * N + j;
+      const double gb = (i == j ? 1.0 : 0.0) - gt;
       const double k = C.Khop[idx];
       if (k != 0.0) ek += k * gb;
       cross += (double)eps[i] * (double)eps[j] * gb * G[idx];
-    }
+    });
     for (int i = tid; i < N; i += kThreads) mc += (double)eps[i] * (0.5 - G[(size_t)i * N + i]);
     for (int b = tid; b < C.n_bonds; b += kThreads) {
       const int i = C.bonds[2 * b], j = C.bonds[2 * b + 1];
@@ -758,17 +788,21 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const ChainDev* __restric
     const GLOBAL double* __restrict__ Gd = gp((const double*)C.G64[ph ? 0 : 1]);
     const GLOBAL int8_t* __restrict__ eps = gp(C.eps);
     double ek = 0.0, dsum = 0.0, spair = 0.0, mz = 0.0;
-    for (int idx = tid; idx < N * N; idx += kThreads) {
-      const int i = idx / N, j = idx - i * N;
+    auto wick = [&](int i, int j, double gut, double gdt) {
+      const size_t idx = (size_t)i * N + j;
       const double dij = i == j ? 1.0 : 0.0;
       const double ee = (double)eps[i] * (double)eps[j];
-      const double gu = Gu[idx], gut = Gu[(size_t)j * N + i];
+      const double gu = Gu[idx];
       const double gd = ph ? dij - ee * gut : Gd[idx];
-      const double gbu = dij - gut, gbd = ph ? ee * gu : dij - Gd[(size_t)j * N + i];
+      const double gbu = dij - gut, gbd = ph ? ee * gu : dij - gdt;
       const double k = C.Khop[idx];
       if (k != 0.0) ek += k * (gbu + gbd);
       spair += ee * (0.25 * (gbu * gu + gbd * gd) + 0.5 * (gbu * gd + gbd * gu));
-    }
+    };
+    if (ph)
+      visit_pairs<1>(N, Gu, nullptr, tt, wick);
+    else
+      visit_pairs<2>(N, Gu, Gd, tt, wick);
     for (int i = tid; i < N; i += kThreads) {
       const double nu = 1.0 - Gu[(size_t)i * N + i];
       const double nd = ph ? Gu[(size_t)i * N + i] : 1.0 - Gd[(size_t)i * N + i];
