@@ -2,13 +2,14 @@
 // (gfx950).  At a checkpoint the propagated N x n basis U is re-orthonormalised
 // in FP64 by Cholesky QR: U = Q T with T the Cholesky factor of U^T U and
 // Q = U T^{-1} (the Gram matrix and Q are batched MFMA GEMMs; the n x n
-// Cholesky factorisation and T^{-1} run here, in LDS).  Only span(Q) and the
-// exact factorisation U = Q T matter (the Green's function is invariant under
-// R -> R T), so one pass suffices: Q is orthonormal to O(eps cond(U)^2).  The
-// fresh Green's function
+// Cholesky factorisation and T^{-1} run here, in registers for n <= 128, else
+// in LDS or global memory).  Only span(Q) and the exact factorisation U = Q T
+// matter (the Green's function is invariant under R -> R T), so one pass
+// suffices: Q is orthonormal to O(eps cond(U)^2).  The fresh Green's function
 // G = 1 - R (L R)^{-1} L follows from the inverse of the n x n overlap L R
-// (Gauss-Jordan with partial pivoting, in LDS) and two more GEMMs; log|det|
-// and the sign of each factor are accumulated for the sign check.
+// (Gauss-Jordan with partial pivoting, placed like the Cholesky factor) and
+// two more GEMMs; log|det| and the sign of each factor are accumulated for the
+// sign check.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
