@@ -328,16 +328,14 @@ struct RegTile {
   }
 };
 
-// In-place inverse.  triangular: upper triangular input, no pivoting.  Returns
-// log|det| (to thread 0, over the nonzero pivots) and the sign (0: singular,
-// the tile is then unusable; to every thread);
-// colmap receives, for every column of the eliminated matrix, its column in
-// the inverse.
+// In-place inverse with partial pivoting.  Returns log|det| (to thread 0, over
+// the nonzero pivots) and the sign (0: singular, the tile is then unusable; to
+// every thread); colmap receives, for every column of the eliminated matrix,
+// its column in the inverse.
 template <int NB, int TG>
-__device__ void rt_invert(RegTile<NB, TG>& T, bool triangular, double (*rk)[kRtMax],
-                          double (*rp)[kRtMax], double (*ck)[kRtMax], double (*cv)[32],
-                          int (*ci)[32], int* piv, int* colmap, double* pabs, bool want_log,
-                          double& logabs, int& sgn) {
+__device__ void rt_invert(RegTile<NB, TG>& T, double (*rk)[kRtMax], double (*rp)[kRtMax],
+                          double (*ck)[kRtMax], double (*cv)[32], int (*ci)[32], int* piv,
+                          int* colmap, double* pabs, double& logabs, int& sgn) {
   const int n = T.n, tid = threadIdx.x;
   logabs = 0.0;
   sgn = 1;
@@ -347,44 +345,41 @@ __device__ void rt_invert(RegTile<NB, TG>& T, bool triangular, double (*rk)[kRtM
     const int kb = k & 1;
     T.put_row(k, rk[kb]);
     T.put_col(k, ck[kb]);
-    int p = k;
-    if (!triangular) {
-      // candidates of the owners of column k, one per row residue
-      const int bc = k / TG;
-      if (T.tj == k % TG) {
-        double best = -1.0;
-        int bi = k;
+    // candidates of the owners of column k, one per row residue
+    const int bc = k / TG;
+    if (T.tj == k % TG) {
+      double best = -1.0;
+      int bi = k;
 #pragma unroll
-        for (int b = 0; b < NB; ++b)
-          if (b == bc) {
+      for (int b = 0; b < NB; ++b)
+        if (b == bc) {
 #pragma unroll
-            for (int a = 0; a < NB; ++a) {
-              const double x = T.m[a][b];
-              const int r = T.ti + TG * a;
-              const bool take = (r >= k) & (r < n) & (fabs(x) > best);
-              best = take ? fabs(x) : best;
-              bi = take ? r : bi;
-            }
+          for (int a = 0; a < NB; ++a) {
+            const double x = T.m[a][b];
+            const int r = T.ti + TG * a;
+            const bool take = (r >= k) & (r < n) & (fabs(x) > best);
+            best = take ? fabs(x) : best;
+            bi = take ? r : bi;
           }
-        cv[kb][T.ti] = best;
-        ci[kb][T.ti] = bi;
-      }
-      __syncthreads();
-      // largest candidate, ties to the smallest row: a shuffle reduction over
-      // each group of TG lanes, which holds all TG candidates
-      double best = cv[kb][tid % TG];
-      int bi = ci[kb][tid % TG];
-#pragma unroll
-      for (int off = TG / 2; off > 0; off >>= 1) {
-        const double ob = __shfl_xor(best, off, TG);
-        const int oi = __shfl_xor(bi, off, TG);
-        const bool take = (ob > best) | ((ob == best) & (oi < bi));
-        best = take ? ob : best;
-        bi = take ? oi : bi;
-      }
-      p = __builtin_amdgcn_readfirstlane(bi);   // the same on every lane
-      if (p != k) T.put_row(p, rp[kb]);
+        }
+      cv[kb][T.ti] = best;
+      ci[kb][T.ti] = bi;
     }
+    __syncthreads();
+    // largest candidate, ties to the smallest row: a shuffle reduction over
+    // each group of TG lanes, which holds all TG candidates
+    double best = cv[kb][tid % TG];
+    int bi = ci[kb][tid % TG];
+#pragma unroll
+    for (int off = TG / 2; off > 0; off >>= 1) {
+      const double ob = __shfl_xor(best, off, TG);
+      const int oi = __shfl_xor(bi, off, TG);
+      const bool take = (ob > best) | ((ob == best) & (oi < bi));
+      best = take ? ob : best;
+      bi = take ? oi : bi;
+    }
+    const int p = __builtin_amdgcn_readfirstlane(bi);   // the same on every lane
+    if (p != k) T.put_row(p, rp[kb]);
     __syncthreads();
     const double* prow = (p == k) ? rk[kb] : rp[kb];
     const double pv = prow[k];
@@ -396,7 +391,7 @@ __device__ void rt_invert(RegTile<NB, TG>& T, bool triangular, double (*rk)[kRtM
     if (tid == 0) {
       // |pivot| (1 for a bad one); the logs are taken after the loop, off
       // the critical path of the elimination steps
-      if (want_log) pabs[k] = bad ? 1.0 : fabs(pv);
+      pabs[k] = bad ? 1.0 : fabs(pv);
       piv[k] = p;
     }
     if (pv < 0) sgn = -sgn;
@@ -407,24 +402,21 @@ __device__ void rt_invert(RegTile<NB, TG>& T, bool triangular, double (*rk)[kRtM
   if (tid == 0) {
     // columns of the result: undo the row interchanges as column
     // interchanges in reverse order; colmap[c] = destination of column c
-    if (!triangular)
-      for (int k = n - 1; k >= 0; --k) {
-        const int q = piv[k];
-        const int t = colmap[k];
-        colmap[k] = colmap[q];
-        colmap[q] = t;
-      }
+    for (int k = n - 1; k >= 0; --k) {
+      const int q = piv[k];
+      const int t = colmap[k];
+      colmap[k] = colmap[q];
+      colmap[q] = t;
+    }
     // colmap now holds the source column of each destination; invert it
     for (int c = 0; c < n; ++c) piv[colmap[c]] = c;
     for (int c = 0; c < n; ++c) colmap[c] = piv[c];
   }
-  if (want_log) {
-    // log|pivot| on n threads at once, summed in pivot order by thread 0
-    for (int c = tid; c < n; c += blockDim.x) pabs[c] = log(pabs[c]);
-    __syncthreads();
-    if (tid == 0)
-      for (int c = 0; c < n; ++c) logabs += pabs[c];
-  }
+  // log|pivot| on n threads at once, summed in pivot order by thread 0
+  for (int c = tid; c < n; c += blockDim.x) pabs[c] = log(pabs[c]);
+  __syncthreads();
+  if (tid == 0)
+    for (int c = 0; c < n; ++c) logabs += pabs[c];
   __syncthreads();
 }
 
@@ -567,7 +559,7 @@ void k_gj_inv_rt(const ChainDev* __restrict__ chains) {
   T.load(gp(C.Xm[sp]), n);
   double logabs;
   int sgn;
-  rt_invert<NB, TG>(T, false, rk, rp, ck, cv, ci, piv, colmap, pabs, true, logabs, sgn);
+  rt_invert<NB, TG>(T, rk, rp, ck, cv, ci, piv, colmap, pabs, logabs, sgn);
   if (sgn != 0) rt_store<NB, TG>(T, gp(C.Xm[sp]), colmap, false);
   if (tid == 0) {
     C.st->x_log[sp] = logabs;
