@@ -14,6 +14,10 @@ stream) are applied n times to the 16x16 and 12x12 workloads' trial bases:
   before 30 slices, so the interval has a ceiling about three times above
   the one used, which the library flags (a Gram matrix that is not positive
   definite sets the singular flag) rather than repairs.
+
+The checkpoint kernel forms R and R^{-1} in one elimination pass (W = L U
+without pivoting, L^{-1} built in the eliminated slots); the identities it
+relies on are checked here step by step against numpy's Cholesky factor.
 """
 import numpy as np
 import pytest
@@ -58,3 +62,58 @@ def test_cholesky_qr_holds_at_the_configured_interval(name, sigma):
     assert EPS * c30 ** 2 > 1e-3, f"{name}: cond {c30:.3g} after 30 slices"
     conds = [c for c, _ in steps]
     assert all(b > a for a, b in zip(conds[4::5], conds[9::5])), "cond grows along the pass"
+
+
+def _eliminate_in_place(W):
+    """The checkpoint kernel's single pass over the Gram matrix, step by step:
+    below each pivot, row r -= l_rj row j over every column (the trailing block
+    and the L^{-1} columns already formed), then slot (r, j) <- -l_rj; the
+    multipliers come from row j (the trailing block is symmetric).  Returns
+    the tile and the pivots U_jj (1 where a pivot is not positive)."""
+    m = np.array(W, dtype=np.float64)
+    n = len(m)
+    piv = np.ones(n)
+    for j in range(n):
+        row = m[j].copy()
+        u = row[j]
+        ok = u > 0.0
+        piv[j] = u if ok else 1.0
+        below = np.arange(n) > j
+        rl = np.where(below, row * (1.0 / u if ok else 0.0), 0.0)
+        m -= np.outer(rl, row)
+        m[below, j] = -rl[below]
+    return m, piv
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 40, 112, 128])
+def test_single_pass_cholesky_inverse_identity(n):
+    """W = L U without pivoting, with L^{-1} kept in the eliminated slots:
+    R = diag(U)^{-1/2} U is the Cholesky factor (W = R^T R) and
+    R^{-1} = (L^{-1})^T diag(U)^{-1/2}; log det R = (1/2) sum log U_jj."""
+    rng = np.random.default_rng(n)
+    M = rng.standard_normal((2 * n + 3, n))
+    W = M.T @ M
+    m, piv = _eliminate_in_place(W)
+    Linv = np.tril(m, -1) + np.eye(n)
+    U = np.triu(m)
+    R = U / np.sqrt(piv)[:, None]
+    Rinv = Linv.T / np.sqrt(piv)[None, :]
+    R_ref = np.linalg.cholesky(W).T
+    assert np.allclose(R, R_ref, rtol=0, atol=1e-12 * np.abs(R_ref).max())
+    Rinv_ref = np.linalg.inv(R_ref)
+    assert np.abs(Rinv - Rinv_ref).max() < 1e-12 * np.abs(Rinv_ref).max()
+    assert np.abs(Rinv @ R - np.eye(n)).max() < 1e-12
+    assert abs(0.5 * np.log(piv).sum() - np.log(np.diag(R_ref)).sum()) < 1e-12 * max(1.0, n)
+
+
+def test_single_pass_cholesky_stays_finite_without_definiteness():
+    """A finite symmetric matrix that is not positive definite (the second
+    pivot is 1 - 4 = -3): the pass takes no multipliers at that step and
+    reports the pivot as 1, so every entry stays finite (the kernel flags
+    the chain)."""
+    W = np.array([[1.0, 2.0, 0.5],
+                  [2.0, 1.0, 0.3],
+                  [0.5, 0.3, 2.0]])
+    m, piv = _eliminate_in_place(W)
+    assert piv[0] == 1.0 and piv[1] == 1.0 and piv[2] > 0.0
+    assert np.isfinite(m).all()
